@@ -1,0 +1,172 @@
+/* camfe: connectivity-aware multilevel finite elements for Laplace-Beltrami
+ * systems on triangle meshes (Chuang & Kazhdan, arXiv 1505.03615), as a C ABI
+ * over hand-written HIP kernels for AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Section 3.1, Eq. 1-2): given a mesh M and an octree depth
+ * D, build the nested function spaces of Sections 3.2 and 4 (trilinear or
+ * quadratic B-splines on the grid of 2^D cells per axis, restricted to M, one
+ * function per connected component of each support, Section 4.2), assemble
+ * the mass matrix M_ij = int b_i b_j (Section 5.1) and the stiffness matrix
+ * L_ij = int <grad_M b_i, grad_M b_j> (Eq. 2, with the sign that makes L
+ * positive semi-definite), and solve (M + t L) x = b with the multigrid
+ * V-cycle over the nested hierarchy (Sections 3.2, 4.3, 5.2).
+ *
+ * Conventions for every call:
+ *  - Return value: a camfe_status; on failure camfe_last_error() describes it.
+ *    No C++ exception crosses the interface.
+ *  - Array arguments may point to host or to device memory of the context's
+ *    device; the library copies them (hipMemcpyDefault) and never keeps them.
+ *    All work runs on the context's stream; calls return after the stream has
+ *    finished the work they queued, so outputs are ready on return.
+ *  - Handles are owned by the library and released by the matching *_destroy.
+ *    A hierarchy must outlive the systems assembled from it; a context must
+ *    outlive its hierarchies.
+ *  - Exports use the two-call pattern: pass cap = 0 (pointers may be NULL) to
+ *    learn the size in *n; a non-zero cap below the size returns
+ *    CAMFE_ETOOSMALL.
+ *  - Keys: a cell (i, j, k) of depth d is stored as its Morton code (bit b of
+ *    i at 3b, of j at 3b+1, of k at 3b+2).  A degree-1 function lives at grid
+ *    corner k (support box [k-1, k+1]^3 in depth-d cell units); a degree-2
+ *    function at the cell o whose quadratic B-spline has support
+ *    [o-1, o+2]^3, stored as the Morton code of o + (1,1,1).
+ *  - Vectors over functions are column-major n x k arrays of doubles, n the
+ *    number of functions at the finest depth, in canonical order (support key
+ *    ascending, then component number).
+ *  - Not thread-safe per handle; distinct handles may be used from distinct
+ *    threads.
+ */
+#ifndef CAMFE_H
+#define CAMFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CAMFE_OK = 0,
+  CAMFE_EINVAL = -1,    /* invalid argument or mesh                          */
+  CAMFE_ENOMEM = -2,    /* device allocation failed                          */
+  CAMFE_EDEVICE = -3,   /* HIP runtime or kernel error                       */
+  CAMFE_ENOCONV = -4,   /* solver stopped at max_iter above rtol (stats set) */
+  CAMFE_ESINGULAR = -5, /* coarsest factorisation failed even with eps * Id  */
+  CAMFE_ETOOSMALL = -6, /* export capacity below the required size           */
+  CAMFE_ESTATE = -7     /* call not valid for this handle (e.g. depth not built) */
+} camfe_status;
+
+typedef struct camfe_ctx_s *camfe_ctx;
+typedef struct camfe_hier_s *camfe_hier;
+typedef struct camfe_sys_s *camfe_sys;
+
+/* Message of the last failed call on this thread (never NULL). */
+const char *camfe_last_error(void);
+
+/* Context: device ordinal and stream (hipStream_t, NULL = a stream the
+ * library creates and owns).  Holds scratch memory reused across calls. */
+camfe_status camfe_ctx_create(int device, void *hip_stream, camfe_ctx *out);
+void camfe_ctx_destroy(camfe_ctx ctx);
+
+/* ------------------------------------------------------------ hierarchy */
+typedef struct {
+  int depth;          /* finest depth D, 1..12 (2^D cells per axis)                   */
+  int degree;         /* 1: trilinear at corners (the paper's space); 2: quadratic    */
+                      /*    B-splines at cells (footnote to Definition 1)             */
+  int split;          /* 1: connectivity-aware split (Section 4.2); 0: one function  */
+                      /*    per support (the space of Definition 2)                   */
+  int min_depth;      /* coarsest depth may not go below this (Section 5.2 "minimum  */
+                      /*    depth")                                                   */
+  int64_t max_coarse; /* coarsest depth = finest depth with at most this many        */
+                      /*    functions (but >= min_depth); it is solved directly when  */
+                      /*    it has at most max_coarse functions, else relaxed.        */
+                      /*    <= 0: only min_depth decides and the coarsest is relaxed  */
+  double box_origin[3];
+  double box_side;    /* > 0: grid cube [origin, origin + side]^3; <= 0: bounding    */
+                      /*    cube of the mesh scaled by 1.125 about its centre         */
+} camfe_hier_opts;
+
+/* Build the octree of triangle/cell pairs, the support lists, the split and
+ * the prolongation (Eq. 4) from depth D down to the coarsest depth.
+ * V: nv x 3 row-major vertex positions; F: nt x 3 row-major vertex indices,
+ * nt < 2^24.  EINVAL for out-of-range indices, repeated indices, a triangle of
+ * zero area, a vertex outside an explicit box, or a triangle lying in a grid
+ * plane (the mesh must be in general position). */
+camfe_status camfe_hierarchy_build(camfe_ctx ctx, const double *V, int64_t nv, const int32_t *F,
+                                   int64_t nt, const camfe_hier_opts *opts, camfe_hier *out);
+/* finest and coarsest depth built */
+camfe_status camfe_hierarchy_levels(camfe_hier h, int *finest, int *coarsest);
+/* grid cube actually used: origin[3], side */
+camfe_status camfe_hierarchy_cube(camfe_hier h, double out4[4]);
+/* counts at depth d (0..D); n_functions is -1 below the coarsest depth */
+camfe_status camfe_hierarchy_info(camfe_hier h, int depth, int64_t *n_cells, int64_t *n_pairs,
+                                  int64_t *n_functions);
+/* (cell key, triangle) pairs whose triangle meets the open cell, sorted */
+camfe_status camfe_export_pairs(camfe_hier h, int depth, uint64_t *cell_key, int32_t *tri,
+                                int64_t cap, int64_t *n);
+/* functions in canonical order: support key, component number (components of
+ * one support numbered by increasing smallest triangle), smallest triangle */
+camfe_status camfe_export_functions(camfe_hier h, int depth, uint64_t *key, int32_t *comp,
+                                    int32_t *rep_tri, int64_t cap, int64_t *n);
+/* (support key, triangle) active pairs, sorted, with the function each maps to */
+camfe_status camfe_export_support_entries(camfe_hier h, int depth, uint64_t *key, int32_t *tri,
+                                          int32_t *func, int64_t cap, int64_t *n);
+/* prolongation P_d (rows: functions at depth d, columns at d-1; Eq. 4), CSR
+ * with ascending columns; rowptr has n_functions(d) + 1 entries */
+camfe_status camfe_export_prolongation(camfe_hier h, int depth, int64_t *rowptr, int32_t *col,
+                                       double *w, int64_t cap, int64_t *nnz);
+void camfe_hierarchy_destroy(camfe_hier h);
+
+/* ------------------------------------------------------------- assembly */
+/* Assemble M and L at every built depth (Eq. 2, Section 5.1) by exact
+ * quadrature over the triangle fragments clipped to cells.  tri_weight
+ * (nullable, nt doubles) scales each triangle's contribution to M only (the
+ * mass of an evolved surface, Section 5.3); L always uses weight 1. */
+camfe_status camfe_assemble(camfe_hier h, const double *tri_weight, camfe_sys *out);
+/* Re-assemble M alone with new triangle weights (L and the structure kept). */
+camfe_status camfe_reassemble_mass(camfe_sys s, const double *tri_weight);
+/* which: 0 = M, 1 = L.  CSR with ascending columns, canonical order. */
+camfe_status camfe_export_matrix(camfe_sys s, int depth, int which, int64_t *rowptr,
+                                 int32_t *col, double *val, int64_t cap, int64_t *nnz);
+/* b_i = int f b_i at the finest depth (Eq. 2) for f linear on each triangle
+ * from per-vertex values vertex_f (nv x k column-major); b is n x k. */
+camfe_status camfe_load_vector(camfe_sys s, const double *vertex_f, int k, double *b);
+/* y = A x at the finest depth with A = M (which 0), L (1) or M + t L (2) */
+camfe_status camfe_apply(camfe_sys s, int which, double t, const double *x, int k, double *y);
+/* coefficients that reproduce the embedding: n x 3 column-major (x, y, z) */
+camfe_status camfe_linear_coeffs(camfe_sys s, double *X);
+/* u(v) = sum_i x_i b_i(v) at every mesh vertex (nv x k column-major) */
+camfe_status camfe_eval_vertices(camfe_sys s, const double *x, int k, double *vertex_out);
+
+/* ---------------------------------------------------------------- solve */
+typedef struct {
+  double t;          /* A = M + t L                                                */
+  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 for every column   */
+  int max_iter;      /* outer iterations (CG steps or stationary cycles)          */
+  int nu_pre, nu_post; /* Gauss-Seidel sweeps before/after the coarse correction  */
+  int method;        /* 0: CG preconditioned by one V-cycle; 1: stationary V-cycles */
+  int precision;     /* 0: FP64 throughout; 1: V-cycle in FP32, residual, CG      */
+                     /*    recurrences and coarsest solve in FP64                 */
+  int x0_given;      /* start from x instead of 0                                 */
+  double coarse_eps; /* eps added to the unit-diagonal-scaled coarsest matrix     */
+} camfe_solve_opts;
+
+typedef struct {
+  int iterations;    /* outer iterations done                                     */
+  int cycles;        /* V-cycles applied                                          */
+  int eps_regularised;
+  double rel_residual; /* max over columns of ||b - A x|| / ||b|| (FP64)          */
+  double seconds;      /* wall time of the iteration (setup excluded)             */
+  double setup_seconds;/* forming A at every depth, packing, coarsest factor      */
+} camfe_solve_stats;
+
+/* Solve (M + t L) x = b at the finest depth (Sections 3.2, 4.3, 5.2).
+ * b, x: n x k column-major (x is read when x0_given).  Returns CAMFE_ENOCONV
+ * with stats filled when max_iter is reached above rtol. */
+camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double *b, int k,
+                         double *x, camfe_solve_stats *stats);
+void camfe_system_destroy(camfe_sys s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CAMFE_H */

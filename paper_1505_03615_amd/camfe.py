@@ -1,0 +1,312 @@
+"""Python binding of libcamfe.so: argument marshalling only.
+
+Each function has the name of the C entry point it calls (include/camfe.h)
+and does nothing but convert arguments: numpy arrays or torch tensors (host
+or device) go in as pointers, handles are opaque integers, and C status codes
+become CamfeError.  Every step of the method runs in the library's HIP
+kernels; importing this module fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcamfe.so")
+
+STATUS = {0: "CAMFE_OK", -1: "CAMFE_EINVAL", -2: "CAMFE_ENOMEM", -3: "CAMFE_EDEVICE",
+          -4: "CAMFE_ENOCONV", -5: "CAMFE_ESINGULAR", -6: "CAMFE_ETOOSMALL", -7: "CAMFE_ESTATE"}
+
+EXPORTS = [
+    "camfe_last_error", "camfe_ctx_create", "camfe_ctx_destroy", "camfe_hierarchy_build",
+    "camfe_hierarchy_levels", "camfe_hierarchy_cube", "camfe_hierarchy_info", "camfe_export_pairs",
+    "camfe_export_functions", "camfe_export_support_entries", "camfe_export_prolongation",
+    "camfe_hierarchy_destroy", "camfe_assemble", "camfe_reassemble_mass", "camfe_export_matrix",
+    "camfe_load_vector", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
+    "camfe_system_destroy",
+]
+
+
+class CamfeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class HierOpts(C.Structure):
+    _fields_ = [("depth", C.c_int), ("degree", C.c_int), ("split", C.c_int), ("min_depth", C.c_int),
+                ("max_coarse", C.c_int64), ("box_origin", C.c_double * 3), ("box_side", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("t", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("method", C.c_int), ("precision", C.c_int), ("x0_given", C.c_int),
+                ("coarse_eps", C.c_double)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("cycles", C.c_int), ("eps_regularised", C.c_int),
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("setup_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """The loaded library; raises ImportError (never falls back) when absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1505_03615_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    P, I, I64, D, H = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_void_p
+    sig = {
+        "camfe_last_error": (C.c_char_p, []),
+        "camfe_ctx_create": (I, [I, P, C.POINTER(H)]),
+        "camfe_ctx_destroy": (None, [H]),
+        "camfe_hierarchy_build": (I, [H, P, I64, P, I64, C.POINTER(HierOpts), C.POINTER(H)]),
+        "camfe_hierarchy_levels": (I, [H, C.POINTER(I), C.POINTER(I)]),
+        "camfe_hierarchy_cube": (I, [H, P]),
+        "camfe_hierarchy_info": (I, [H, I, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
+        "camfe_export_pairs": (I, [H, I, P, P, I64, C.POINTER(I64)]),
+        "camfe_export_functions": (I, [H, I, P, P, P, I64, C.POINTER(I64)]),
+        "camfe_export_support_entries": (I, [H, I, P, P, P, I64, C.POINTER(I64)]),
+        "camfe_export_prolongation": (I, [H, I, P, P, P, I64, C.POINTER(I64)]),
+        "camfe_hierarchy_destroy": (None, [H]),
+        "camfe_assemble": (I, [H, P, C.POINTER(H)]),
+        "camfe_reassemble_mass": (I, [H, P]),
+        "camfe_export_matrix": (I, [H, I, I, P, P, P, I64, C.POINTER(I64)]),
+        "camfe_load_vector": (I, [H, P, I, P]),
+        "camfe_apply": (I, [H, I, D, P, I, P]),
+        "camfe_linear_coeffs": (I, [H, P]),
+        "camfe_eval_vertices": (I, [H, P, I, P]),
+        "camfe_solve": (I, [H, C.POINTER(SolveOpts), P, I, P, C.POINTER(SolveStats)]),
+        "camfe_system_destroy": (None, [H]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != 0:
+        raise CamfeError(code, load().camfe_last_error().decode())
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if _is_torch(a):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _rowmajor(a, dtype):
+    if _is_torch(a):
+        import torch
+        return a.to(getattr(torch, dtype)).contiguous()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _colmajor(a):
+    """(array with column-major n x k storage, n, k) for numpy or torch input."""
+    if _is_torch(a):
+        import torch
+        a = a.to(torch.float64)
+        if a.dim() == 1:
+            a = a.unsqueeze(1)
+        if a.stride(0) != 1 or (a.shape[1] > 1 and a.stride(1) != a.shape[0]):
+            a = a.t().contiguous().t()
+        return a, a.shape[0], a.shape[1]
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a[:, None]
+    return np.asfortranarray(a), a.shape[0], a.shape[1]
+
+
+def _empty_like_kind(a, n, k):
+    """Column-major n x k output of the same kind/device as `a`."""
+    if _is_torch(a):
+        import torch
+        return torch.empty((k, n), dtype=torch.float64, device=a.device).t()
+    return np.zeros((n, k), order="F")
+
+
+# ----------------------------------------------------------------- context
+def camfe_ctx_create(device: int = 0, stream=None):
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    lib = load()
+    h = C.c_void_p()
+    s = None
+    if stream is not None:
+        s = C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    _check(lib.camfe_ctx_create(device, s, C.byref(h)))
+    return h
+
+
+def camfe_ctx_destroy(ctx):
+    load().camfe_ctx_destroy(ctx)
+
+
+# --------------------------------------------------------------- hierarchy
+def camfe_hierarchy_build(ctx, V, F, depth, degree=1, split=1, min_depth=0, max_coarse=2048, box=None):
+    lib = load()
+    Vc, Fc = _rowmajor(V, "float64"), _rowmajor(F, "int32")
+    o = HierOpts()
+    o.depth, o.degree, o.split, o.min_depth, o.max_coarse = depth, degree, split, min_depth, max_coarse
+    if box is not None:
+        o.box_origin[0], o.box_origin[1], o.box_origin[2], o.box_side = (float(v) for v in box)
+    h = C.c_void_p()
+    _check(lib.camfe_hierarchy_build(ctx, _ptr(Vc), Vc.shape[0], _ptr(Fc), Fc.shape[0], C.byref(o),
+                                     C.byref(h)))
+    return h
+
+
+def camfe_hierarchy_levels(h):
+    a, b = C.c_int(), C.c_int()
+    _check(load().camfe_hierarchy_levels(h, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def camfe_hierarchy_cube(h):
+    out = np.zeros(4)
+    _check(load().camfe_hierarchy_cube(h, _ptr(out)))
+    return out
+
+
+def camfe_hierarchy_info(h, depth):
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(load().camfe_hierarchy_info(h, depth, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def _two_call(fn, h, depth, makers):
+    n = C.c_int64()
+    _check(fn(h, depth, *([None] * len(makers)), 0, C.byref(n)))
+    outs = [m(n.value) for m in makers]
+    if n.value:
+        _check(fn(h, depth, *[_ptr(o) for o in outs], n.value, C.byref(n)))
+    return outs
+
+
+def camfe_export_pairs(h, depth):
+    return tuple(_two_call(load().camfe_export_pairs, h, depth,
+                           [lambda n: np.zeros(n, np.uint64), lambda n: np.zeros(n, np.int32)]))
+
+
+def camfe_export_functions(h, depth):
+    return tuple(_two_call(load().camfe_export_functions, h, depth,
+                           [lambda n: np.zeros(n, np.uint64), lambda n: np.zeros(n, np.int32),
+                            lambda n: np.zeros(n, np.int32)]))
+
+
+def camfe_export_support_entries(h, depth):
+    return tuple(_two_call(load().camfe_export_support_entries, h, depth,
+                           [lambda n: np.zeros(n, np.uint64), lambda n: np.zeros(n, np.int32),
+                            lambda n: np.zeros(n, np.int32)]))
+
+
+def camfe_export_prolongation(h, depth):
+    import scipy.sparse as sp
+    lib = load()
+    nf = camfe_hierarchy_info(h, depth)[2]
+    nc = camfe_hierarchy_info(h, depth - 1)[2]
+    nnz = C.c_int64()
+    _check(lib.camfe_export_prolongation(h, depth, None, None, None, 0, C.byref(nnz)))
+    ptr = np.zeros(nf + 1, np.int64); col = np.zeros(nnz.value, np.int32); w = np.zeros(nnz.value)
+    _check(lib.camfe_export_prolongation(h, depth, _ptr(ptr), _ptr(col), _ptr(w), max(nnz.value, 1),
+                                         C.byref(nnz)))
+    return sp.csr_matrix((w, col, ptr), shape=(nf, nc))
+
+
+def camfe_hierarchy_destroy(h):
+    load().camfe_hierarchy_destroy(h)
+
+
+# ---------------------------------------------------------------- assembly
+def camfe_assemble(h, tri_weight=None):
+    s = C.c_void_p()
+    tw = None if tri_weight is None else _rowmajor(tri_weight, "float64")
+    _check(load().camfe_assemble(h, _ptr(tw), C.byref(s)))
+    return s
+
+
+def camfe_reassemble_mass(s, tri_weight=None):
+    tw = None if tri_weight is None else _rowmajor(tri_weight, "float64")
+    _check(load().camfe_reassemble_mass(s, _ptr(tw)))
+
+
+def camfe_export_matrix(s, h, depth, which):
+    """which: 0 = M, 1 = L; returns scipy CSR (the hierarchy handle gives n)."""
+    import scipy.sparse as sp
+    lib = load()
+    n = camfe_hierarchy_info(h, depth)[2]
+    nnz = C.c_int64()
+    _check(lib.camfe_export_matrix(s, depth, which, None, None, None, 0, C.byref(nnz)))
+    ptr = np.zeros(n + 1, np.int64); col = np.zeros(nnz.value, np.int32); val = np.zeros(nnz.value)
+    _check(lib.camfe_export_matrix(s, depth, which, _ptr(ptr), _ptr(col), _ptr(val), max(nnz.value, 1),
+                                   C.byref(nnz)))
+    return sp.csr_matrix((val, col, ptr), shape=(n, n))
+
+
+def camfe_load_vector(s, h, vertex_f):
+    fv, nv, k = _colmajor(vertex_f)
+    n = camfe_hierarchy_info(h, camfe_hierarchy_levels(h)[0])[2]
+    b = _empty_like_kind(fv, n, k)
+    _check(load().camfe_load_vector(s, _ptr(fv), k, _ptr(b)))
+    return b
+
+
+def camfe_apply(s, which, t, x):
+    xc, n, k = _colmajor(x)
+    y = _empty_like_kind(xc, n, k)
+    _check(load().camfe_apply(s, which, t, _ptr(xc), k, _ptr(y)))
+    return y
+
+
+def camfe_linear_coeffs(s, h):
+    n = camfe_hierarchy_info(h, camfe_hierarchy_levels(h)[0])[2]
+    X = np.zeros((n, 3), order="F")
+    _check(load().camfe_linear_coeffs(s, _ptr(X)))
+    return X
+
+
+def camfe_eval_vertices(s, nv, x):
+    xc, n, k = _colmajor(x)
+    out = _empty_like_kind(xc, nv, k)
+    _check(load().camfe_eval_vertices(s, _ptr(xc), k, _ptr(out)))
+    return out
+
+
+def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0, precision=0, x0=None,
+                coarse_eps=1e-10, raise_on_noconv=False):
+    """Returns (x, stats dict).  method 0 = V-cycle-preconditioned CG, 1 = stationary."""
+    bc, n, k = _colmajor(b)
+    if x0 is None:
+        x = _empty_like_kind(bc, n, k)
+    else:
+        x = _colmajor(x0.clone() if _is_torch(x0) else np.array(x0, dtype=np.float64, copy=True))[0]
+    o = SolveOpts()
+    o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
+    o.method, o.precision, o.x0_given, o.coarse_eps = method, precision, 0 if x0 is None else 1, coarse_eps
+    st = SolveStats()
+    code = load().camfe_solve(s, C.byref(o), _ptr(bc), k, _ptr(x), C.byref(st))
+    if code != 0 and (code != -4 or raise_on_noconv):
+        _check(code)
+    stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+    stats["converged"] = code == 0
+    return x, stats
+
+
+def camfe_system_destroy(s):
+    load().camfe_system_destroy(s)

@@ -1,0 +1,189 @@
+// Internal infrastructure of the camfe HIP library: error reporting, device
+// arrays, the context, and small device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "camfe.h"
+
+namespace camfe {
+
+typedef unsigned long long u64;
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  camfe_status code;
+  Error(camfe_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define CAMFE_HIP(call)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::camfe::Error(e_ == hipErrorOutOfMemory ? CAMFE_ENOMEM : CAMFE_EDEVICE,      \
+                           std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+#define CAMFE_REQUIRE(cond, code, msg) \
+  do {                                 \
+    if (!(cond)) throw ::camfe::Error((code), (msg)); \
+  } while (0)
+
+// Runs f, mapping exceptions to status codes and the thread's last error.
+template <class Fn>
+camfe_status guarded(Fn&& f) {
+  try {
+    f();
+    return CAMFE_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return CAMFE_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return CAMFE_EDEVICE;
+  }
+}
+
+// ----------------------------------------------------------- device arrays
+template <class T>
+struct DArr {
+  T* p = nullptr;
+  size_t n = 0;
+  DArr() = default;
+  explicit DArr(size_t count) { alloc(count); }
+  DArr(const DArr&) = delete;
+  DArr& operator=(const DArr&) = delete;
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DArr& operator=(DArr&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DArr() { release(); }
+  void alloc(size_t count) {
+    release();
+    if (count) CAMFE_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    n = count;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// ---------------------------------------------------------------- context
+}  // namespace camfe
+
+struct camfe_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  camfe::DArr<unsigned char> scratch;  // reused temporary storage (sort/scan)
+  camfe::DArr<unsigned char> scratch2;
+  int* d_flag = nullptr;               // device error flag
+  unsigned char* scratch_bytes(size_t b) {
+    if (scratch.n < b) scratch.alloc(b + (b >> 2) + 256);
+    return scratch.p;
+  }
+  unsigned char* scratch2_bytes(size_t b) {
+    if (scratch2.n < b) scratch2.alloc(b + (b >> 2) + 256);
+    return scratch2.p;
+  }
+  void sync() { CAMFE_HIP(hipStreamSynchronize(stream)); }
+  void use_device() { CAMFE_HIP(hipSetDevice(device)); }
+};
+
+namespace camfe {
+
+// copies between host/device memory of any kind (unified addressing)
+// Copies complete before returning, so host sources may be temporaries.
+template <class T>
+void copy_in(camfe_ctx ctx, T* dst, const T* src, size_t count) {
+  if (!count) return;
+  CAMFE_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDefault, ctx->stream));
+  CAMFE_HIP(hipStreamSynchronize(ctx->stream));
+}
+template <class T>
+void copy_out(camfe_ctx ctx, T* dst, const T* src, size_t count) {
+  if (!count) return;
+  CAMFE_HIP(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDefault, ctx->stream));
+  CAMFE_HIP(hipStreamSynchronize(ctx->stream));
+}
+template <class T>
+T read_scalar(camfe_ctx ctx, const T* dptr) {
+  T v;
+  CAMFE_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, ctx->stream));
+  ctx->sync();
+  return v;
+}
+template <class T>
+void zero(camfe_ctx ctx, T* p, size_t count) {
+  if (count) CAMFE_HIP(hipMemsetAsync(p, 0, count * sizeof(T), ctx->stream));
+}
+
+inline void check_launch() { CAMFE_HIP(hipGetLastError()); }
+
+inline unsigned grid_for(size_t n, unsigned block) {
+  size_t g = (n + block - 1) / block;
+  if (g == 0) g = 1;
+  if (g > 0x7fffffffULL) g = 0x7fffffff;
+  return (unsigned)g;
+}
+
+// ------------------------------------------------- primitives (prim.hip)
+// Radix sorts of 64-bit keys on bits [0, end_bit); stable.  Temporary storage
+// comes from the context.  In-place on (keys[, vals]).
+void sort_keys(camfe_ctx ctx, u64* keys, size_t n, int end_bit);
+void sort_pairs(camfe_ctx ctx, u64* keys, uint32_t* vals, size_t n, int end_bit);
+void sort_pairs_u32(camfe_ctx ctx, uint32_t* keys, uint32_t* vals, size_t n, int end_bit);
+// exclusive prefix sums (out may alias in); returns nothing (total = last in + last out)
+void exclusive_scan(camfe_ctx ctx, const int* in, int* out, size_t n);
+void exclusive_scan64(camfe_ctx ctx, const long long* in, long long* out, size_t n);
+// sum reduction into a device scalar
+void reduce_sum64(camfe_ctx ctx, const long long* in, long long* out, size_t n);
+
+// ------------------------------------------------------- device helpers
+__host__ __device__ inline u64 spread3(u64 x) {
+  x &= 0x1fffffULL;
+  x = (x | (x << 32)) & 0x1f00000000ffffULL;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffULL;
+  x = (x | (x << 8)) & 0x100f00f00f00f00fULL;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ULL;
+  x = (x | (x << 2)) & 0x1249249249249249ULL;
+  return x;
+}
+__host__ __device__ inline u64 compact3(u64 x) {
+  x &= 0x1249249249249249ULL;
+  x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ULL;
+  x = (x ^ (x >> 4)) & 0x100f00f00f00f00fULL;
+  x = (x ^ (x >> 8)) & 0x1f0000ff0000ffULL;
+  x = (x ^ (x >> 16)) & 0x1f00000000ffffULL;
+  x = (x ^ (x >> 32)) & 0x1fffffULL;
+  return x;
+}
+__host__ __device__ inline u64 morton(u64 x, u64 y, u64 z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+__host__ __device__ inline void demorton(u64 k, long long c[3]) {
+  c[0] = (long long)compact3(k);
+  c[1] = (long long)compact3(k >> 1);
+  c[2] = (long long)compact3(k >> 2);
+}
+
+constexpr int TRI_BITS = 24;
+constexpr u64 TRI_MASK = (1ULL << TRI_BITS) - 1;
+
+}  // namespace camfe

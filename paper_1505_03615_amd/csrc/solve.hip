@@ -1,0 +1,985 @@
+// Multigrid solver on the GPU (Sections 3.2, 4.3, 5.2; discussion of 5.3).
+//
+// Layout per depth: functions renumbered colour by colour (a colour class
+// never couples with itself, so a colour sweep is a parallel Gauss-Seidel
+// step), the matrix A = M + t L packed as SELL-64 (slices of 64 consecutive
+// rows, column-major inside a slice, one lane per row: every entry load of a
+// wavefront is one contiguous 512 B (FP64) or 256 B (FP32) segment).
+// Transfers: P (fine rows gather at most 8 coarse parents) and R = P^T
+// (coarse rows gather their fine children), both explicit CSR so that
+// restriction needs no atomics.  Coarsest depth: dense inverse of the
+// unit-diagonal-scaled matrix plus eps * Id, applied as a matrix-vector product.
+//
+// V-cycle: nu_pre forward colour sweeps, residual, restriction, recursion
+// with zero start, prolongation-add, nu_post reverse colour sweeps; symmetric,
+// hence usable as a CG preconditioner.  Precision 1 runs the whole V-cycle in
+// FP32 while CG recurrences, the residual and the coarsest solve stay FP64.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace camfe {
+
+namespace {
+constexpr int BLK = 256;
+constexpr int SL = 64;        // SELL slice height = wavefront width
+constexpr int KMAXS = 4;      // right-hand sides per pass
+}  // namespace
+
+struct GLevel {
+  int d = 0;
+  size_t n = 0;
+  int ncol = 8;
+  std::vector<int> coff;      // colour c owns internal rows [coff[c], coff[c+1])
+  std::vector<int> cslice;    // colour c owns slices [cslice[c], cslice[c+1])
+  DArr<int> perm, iperm;      // internal -> canonical, canonical -> internal
+  size_t nslices = 0, snnz = 0;
+  DArr<int> sl_ptr;           // slice offsets into the value arrays (nslices + 1)
+  DArr<int> sl_row0;          // first internal row of each slice
+  DArr<int> sl_rows;          // rows in each slice (<= 64)
+  DArr<int> scol;
+  DArr<double> sval64, invd64;
+  DArr<float> sval32, invd32;
+  // transfers in internal numbering (P: rows at d, cols at d-1; R = P^T)
+  DArr<int> Pptr, Pcol, Rptr, Rcol;
+  DArr<double> Pw64, Rw64;
+  DArr<float> Pw32, Rw32;
+  // work vectors, n x KMAXS row-major
+  DArr<double> x64, b64, r64;
+  DArr<float> x32, b32, r32;
+};
+
+struct SolverState {
+  double t = 0;
+  int precision = 0;
+  double coarse_eps = 0;
+  int D = 0, d0 = 0;
+  std::vector<GLevel> lev;   // index = depth
+  bool direct = false;
+  int n0 = 0;
+  DArr<double> Ainv64;
+  DArr<float> Ainv32;
+  // outer iteration vectors (finest, internal order, n x KMAXS row-major)
+  DArr<double> X, R, Z, P, Q, B;
+  DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
+  double setup_seconds = 0;
+};
+
+void destroy_solver(SolverState* s) { delete s; }
+
+namespace {
+
+// --------------------------------------------------------------- kernels
+__global__ void k_colour(const u64* fkey, long long n, int degree, uint32_t* colour, uint32_t* idx) {
+  long long f = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (f >= n) return;
+  long long c[3];
+  demorton(fkey[f], c);
+  uint32_t col = degree == 1 ? (uint32_t)((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1))
+                             : (uint32_t)((c[0] % 3) + 3 * (c[1] % 3) + 9 * (c[2] % 3));
+  colour[f] = col;
+  idx[f] = (uint32_t)f;
+}
+__global__ void k_iperm(const uint32_t* perm, long long n, int* iperm, int* permi) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+  iperm[perm[i]] = (int)i;
+  permi[i] = (int)perm[i];
+}
+__global__ void k_slice_width(const int* ptr, const int* perm, const int* row0, const int* rows, long long ns,
+                              int* width) {
+  long long s = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (s >= ns) return;
+  int w = 0;
+  for (int l = 0; l < rows[s]; ++l) {
+    int f = perm[row0[s] + l];
+    w = max(w, ptr[f + 1] - ptr[f]);
+  }
+  width[s] = w * SL;
+}
+// pack A = M + t L of internal row i into its slice (valid lanes only)
+__global__ void k_sell_fill(const int* ptr, const int* col, const double* M, const double* L, double t,
+                            const int* perm, const int* iperm, const int* sl_ptr, const int* row0, const int* rows,
+                            long long ns, int* scol, double* sval, float* sval32, double* invd, float* invd32) {
+  long long g = blockIdx.x * (long long)BLK + threadIdx.x;
+  long long s = g / SL;
+  int lane = (int)(g - s * SL);
+  if (s >= ns || lane >= rows[s]) return;
+  const int width = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
+  const int i = row0[s] + lane;
+  const int f = perm[i];
+  const int b = ptr[f];
+  const int len = ptr[f + 1] - b;
+  double diag = 0.0;
+  for (int j = 0; j < width; ++j) {
+    long long o = sl_ptr[s] + (long long)j * SL + lane;
+    if (j < len) {
+      double a = M[b + j] + t * L[b + j];
+      int c = col[b + j];
+      scol[o] = iperm[c];
+      sval[o] = a;
+      sval32[o] = (float)a;
+      if (c == f) diag = a;
+    } else {
+      scol[o] = i;
+      sval[o] = 0.0;
+      sval32[o] = 0.0f;
+    }
+  }
+  invd[i] = 1.0 / diag;
+  invd32[i] = (float)(1.0 / diag);
+}
+__global__ void k_sell_pad(const int* sl_ptr, const int* row0, const int* rows, long long ns, int* scol,
+                           double* sval, float* sval32) {
+  long long g = blockIdx.x * (long long)BLK + threadIdx.x;
+  long long s = g / SL;
+  int lane = (int)(g - s * SL);
+  if (s >= ns || lane < rows[s]) return;
+  const int width = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
+  for (int j = 0; j < width; ++j) {
+    long long o = sl_ptr[s] + (long long)j * SL + lane;
+    scol[o] = row0[s];
+    sval[o] = 0.0;
+    sval32[o] = 0.0f;
+  }
+}
+
+// transfer matrices in internal numbering
+__global__ void k_p_count(const int* Pptr, const int* permf, long long nf, int* cnt) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= nf) return;
+  int f = permf[i];
+  cnt[i] = Pptr[f + 1] - Pptr[f];
+}
+__global__ void k_p_fill(const int* Pptr, const int* Pcol, const double* Pw, const int* permf, const int* ipermc,
+                         long long nf, const int* optr, int* ocol, double* ow, float* ow32, uint32_t* rkey,
+                         uint32_t* rval) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= nf) return;
+  int f = permf[i];
+  int o = optr[i];
+  for (int e = Pptr[f]; e < Pptr[f + 1]; ++e, ++o) {
+    ocol[o] = ipermc[Pcol[e]];
+    ow[o] = Pw[e];
+    ow32[o] = (float)Pw[e];
+    rkey[o] = (uint32_t)ocol[o];
+    rval[o] = (uint32_t)o;
+  }
+}
+__global__ void k_r_fill(const uint32_t* rkey, const uint32_t* rval, long long nnz, const int* prow_of,
+                         const double* pw, int* rcol, double* rw, float* rw32) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= nnz) return;
+  uint32_t e = rval[i];
+  rcol[i] = prow_of[e];
+  rw[i] = pw[e];
+  rw32[i] = (float)pw[e];
+}
+__global__ void k_row_of_entry(const int* ptr, long long n, int* row_of) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+  for (int e = ptr[i]; e < ptr[i + 1]; ++e) row_of[e] = (int)i;
+}
+__global__ void k_ptr_from_sorted(const uint32_t* key, long long nnz, long long n, int* ptr) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= nnz) return;
+  long long v = key[i];
+  long long pv = i == 0 ? -1 : (long long)key[i - 1];
+  for (long long w = pv + 1; w <= v; ++w) ptr[w] = (int)i;
+  if (i == nnz - 1)
+    for (long long w = v + 1; w <= n; ++w) ptr[w] = (int)nnz;
+}
+
+// coarsest: dense scaled matrix (internal order), Cholesky, inverse
+__global__ void k_dense_scaled(const int* ptr, const int* col, const double* M, const double* L, double t,
+                               const int* perm, const int* iperm, long long n, double eps, double* A) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+  int f = perm[i];
+  double di = 0.0;
+  for (int e = ptr[f]; e < ptr[f + 1]; ++e)
+    if (col[e] == f) di = M[e] + t * L[e];
+  for (int e = ptr[f]; e < ptr[f + 1]; ++e) {
+    int c = col[e];
+    double dc = 0.0;
+    for (int q = ptr[c]; q < ptr[c + 1]; ++q)
+      if (col[q] == c) dc = M[q] + t * L[q];
+    A[i * n + iperm[c]] = (M[e] + t * L[e]) / sqrt(di * dc);
+  }
+  A[i * n + i] += eps;
+}
+// right-looking Cholesky of the lower triangle, one workgroup
+__global__ __launch_bounds__(1024) void k_cholesky(double* A, int n, int* fail) {
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double a = A[(long long)j * n + j];
+      if (!(a > 0.0)) { *fail = 1; a = 1.0; }
+      A[(long long)j * n + j] = sqrt(a);
+    }
+    __syncthreads();
+    const double ljj = A[(long long)j * n + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(long long)i * n + j] /= ljj;
+    __syncthreads();
+    const long long m = n - j - 1;
+    const long long tot = m * (m + 1) / 2;
+    for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
+      // (i, k) with j < k <= i < n, enumerated row by row of the trailing triangle
+      long long r = (long long)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
+      while (r * (r + 1) / 2 > q) --r;
+      while ((r + 1) * (r + 2) / 2 <= q) ++r;
+      long long c = q - r * (r + 1) / 2;
+      int i = j + 1 + (int)r, k = j + 1 + (int)c;
+      A[(long long)i * n + k] -= A[(long long)i * n + j] * A[(long long)k * n + j];
+    }
+    __syncthreads();
+  }
+}
+// column c of the inverse of L L^T, scaled back: Ainv = S (L L^T)^-1 S
+__global__ void k_chol_inverse(const double* Lf, int n, const double* s, double* work, double* Ainv,
+                               float* Ainv32) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double* y = work + (long long)c * n;
+  for (int i = 0; i < n; ++i) {
+    double v = (i == c) ? 1.0 : 0.0;
+    for (int p = 0; p < i; ++p) v -= Lf[(long long)i * n + p] * y[p];
+    y[i] = v / Lf[(long long)i * n + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double v = y[i];
+    for (int p = i + 1; p < n; ++p) v -= Lf[(long long)p * n + i] * y[p];
+    y[i] = v / Lf[(long long)i * n + i];
+  }
+  for (int i = 0; i < n; ++i) {
+    double v = s[i] * y[i] * s[c];
+    Ainv[(long long)i * n + c] = v;
+    Ainv32[(long long)i * n + c] = (float)v;
+  }
+}
+__global__ void k_inv_sqrt_diag(const double* A, int n, double* s, const double* diagsrc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s[i] = 1.0 / sqrt(diagsrc[i]);
+}
+__global__ void k_diag_of(const int* ptr, const int* col, const double* M, const double* L, double t,
+                          const int* perm, long long n, double* dg) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+  int f = perm[i];
+  for (int e = ptr[f]; e < ptr[f + 1]; ++e)
+    if (col[e] == f) dg[i] = M[e] + t * L[e];
+}
+
+// ------------------------------------------------------ V-cycle kernels
+// XCD-aware slice order: consecutive workgroups go to different XCDs, so
+// give each XCD a contiguous range of slices (neighbouring rows share x).
+__device__ inline long long xcd_block(long long b, long long nb) {
+  const long long X = 8;
+  if (nb < X) return b;
+  long long per = nb / X, rem = nb % X;
+  long long x = b % X, i = b / X;
+  long long base = x * per + min(x, rem);
+  long long lim = per + (x < rem ? 1 : 0);
+  return i < lim ? base + i : b;   // remainder blocks keep their index
+}
+
+template <class T, int K>
+__global__ __launch_bounds__(BLK) void k_gs(const int* sl_ptr, const int* row0, const int* rows, int s_begin,
+                                            int s_end, const int* scol, const T* sval, const T* invd, const T* b,
+                                            T* x) {
+  long long blocks = ((long long)(s_end - s_begin) * SL + BLK - 1) / BLK;
+  long long bid = xcd_block(blockIdx.x, blocks);
+  long long g = bid * BLK + threadIdx.x;
+  long long s = s_begin + g / SL;
+  int lane = (int)(g % SL);
+  if (s >= s_end || lane >= rows[s]) return;
+  const int i = row0[s] + lane;
+  const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
+  const long long base = sl_ptr[s] + lane;
+  T acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0;
+  for (int j = 0; j < w; ++j) {
+    const T a = sval[base + (long long)j * SL];
+    const int c = scol[base + (long long)j * SL];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = fma(a, x[(long long)c * K + q], acc[q]);
+  }
+  const T di = invd[i];
+#pragma unroll
+  for (int q = 0; q < K; ++q) x[(long long)i * K + q] += (b[(long long)i * K + q] - acc[q]) * di;
+}
+
+// r = b - A x over all slices; with nrm != null also accumulate ||r||^2 per column
+template <class T, class TR, int K>
+__global__ __launch_bounds__(BLK) void k_residual(const int* sl_ptr, const int* row0, const int* rows, int ns,
+                                                  const int* scol, const T* sval, const TR* b, const T* x, TR* r,
+                                                  double* nrm) {
+  long long blocks = ((long long)ns * SL + BLK - 1) / BLK;
+  long long bid = xcd_block(blockIdx.x, blocks);
+  long long g = bid * BLK + threadIdx.x;
+  long long s = g / SL;
+  int lane = (int)(g % SL);
+  double loc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) loc[q] = 0.0;
+  if (s < ns && lane < rows[s]) {
+    const int i = row0[s] + lane;
+    const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
+    const long long base = sl_ptr[s] + lane;
+    T acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0;
+    for (int j = 0; j < w; ++j) {
+      const T a = sval[base + (long long)j * SL];
+      const int c = scol[base + (long long)j * SL];
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] = fma(a, x[(long long)c * K + q], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      TR v = b[(long long)i * K + q] - (TR)acc[q];
+      r[(long long)i * K + q] = v;
+      loc[q] = (double)v * (double)v;
+    }
+  }
+  if (nrm) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      double v = loc[q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if ((threadIdx.x & 63) == 0) atomicAdd(nrm + q, v);
+    }
+  }
+}
+
+// y = A p (FP64) and pq += p . y per column
+template <int K>
+__global__ __launch_bounds__(BLK) void k_spmv_dot(const int* sl_ptr, const int* row0, const int* rows, int ns,
+                                                  const int* scol, const double* sval, const double* p, double* y,
+                                                  double* dot) {
+  long long blocks = ((long long)ns * SL + BLK - 1) / BLK;
+  long long bid = xcd_block(blockIdx.x, blocks);
+  long long g = bid * BLK + threadIdx.x;
+  long long s = g / SL;
+  int lane = (int)(g % SL);
+  double loc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) loc[q] = 0.0;
+  if (s < ns && lane < rows[s]) {
+    const int i = row0[s] + lane;
+    const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
+    const long long base = sl_ptr[s] + lane;
+    double acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0;
+    for (int j = 0; j < w; ++j) {
+      const double a = sval[base + (long long)j * SL];
+      const int c = scol[base + (long long)j * SL];
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] = fma(a, p[(long long)c * K + q], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      y[(long long)i * K + q] = acc[q];
+      loc[q] = acc[q] * p[(long long)i * K + q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double v = loc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(dot + q, v);
+  }
+}
+
+// b_c = R r_f (coarse rows gather their fine children)
+template <class T, int K>
+__global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long long nc, const T* rf, T* bc) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= nc) return;
+  T acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0;
+  for (int e = Rptr[i]; e < Rptr[i + 1]; ++e) {
+    const T w = Rw[e];
+    const int c = Rcol[e];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = fma(w, rf[(long long)c * K + q], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) bc[i * K + q] = acc[q];
+}
+
+// x_f += P x_c
+template <class T, int K>
+__global__ void k_prolong(const int* Pptr, const int* Pcol, const T* Pw, long long nf, const T* xc, T* xf) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= nf) return;
+  T acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0;
+  for (int e = Pptr[i]; e < Pptr[i + 1]; ++e) {
+    const T w = Pw[e];
+    const int c = Pcol[e];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = fma(w, xc[(long long)c * K + q], acc[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) xf[i * K + q] += acc[q];
+}
+
+// x = Ainv b at the coarsest depth, one wavefront per row (FP64 accumulate)
+template <class T, int K>
+__global__ void k_coarse(const T* Ainv, int n, const T* b, T* x) {
+  long long wave = (blockIdx.x * (long long)BLK + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (wave >= n) return;
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  for (int j = lane; j < n; j += 64) {
+    const double a = (double)Ainv[wave * n + j];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(long long)j * K + q];
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) x[wave * K + q] = (T)v;
+  }
+}
+
+template <class T>
+__global__ void k_fill(T* p, long long n, T v) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+template <class A, class B>
+__global__ void k_convert(const A* in, long long n, B* out) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n) out[i] = (B)in[i];
+}
+
+// ------------------------------------------------------- CG kernels
+// alpha = rz / pq per column; x += alpha p; r -= alpha q; rr += r.r
+template <int K>
+__global__ void k_cg_update(long long n, const double* sc, double* x, double* r, const double* p, const double* q,
+                            double* rr) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  double loc[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const double rz = sc[c], pq = sc[K + c];
+    const double al = (pq != 0.0 && rz != 0.0) ? rz / pq : 0.0;
+    loc[c] = 0.0;
+    if (i < n) {
+      x[i * K + c] += al * p[i * K + c];
+      double v = r[i * K + c] - al * q[i * K + c];
+      r[i * K + c] = v;
+      loc[c] = v * v;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    double v = loc[c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(rr + c, v);
+  }
+}
+// dot[c] += a . b per column
+template <int K>
+__global__ void k_dot(long long n, const double* a, const double* b, double* dot) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    double v = i < n ? a[i * K + c] * b[i * K + c] : 0.0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(dot + c, v);
+  }
+}
+// beta = rz_new / rz; p = z + beta p
+template <int K>
+__global__ void k_cg_direction(long long n, const double* rz_old, const double* rz_new, const double* z, double* p) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const double be = rz_old[c] != 0.0 ? rz_new[c] / rz_old[c] : 0.0;
+    p[i * K + c] = z[i * K + c] + be * p[i * K + c];
+  }
+}
+__global__ void k_copy_scalars(const double* src, double* dst, int n) {
+  int i = threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+template <int K>
+__global__ void k_axpy_inplace(long long n, double* x, const double* y) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n * K) x[i] += y[i];
+}
+
+// canonical column-major n x k block (columns c0..c0+K) <-> internal row-major n x K
+template <int K>
+__global__ void k_gather_in(const double* src, long long n, int c0, int kk, const int* iperm, double* dst) {
+  long long f = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (f >= n) return;
+  int i = iperm[f];
+#pragma unroll
+  for (int q = 0; q < K; ++q) dst[(long long)i * K + q] = (c0 + q < kk) ? src[(long long)(c0 + q) * n + f] : 0.0;
+}
+template <int K>
+__global__ void k_scatter_out(const double* src, long long n, int c0, int kk, const int* iperm, double* dst) {
+  long long f = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (f >= n) return;
+  int i = iperm[f];
+#pragma unroll
+  for (int q = 0; q < K; ++q)
+    if (c0 + q < kk) dst[(long long)(c0 + q) * n + f] = src[(long long)i * K + q];
+}
+
+// ------------------------------------------------------------ host side
+void setup_level(camfe_sys s, SolverState* st, int d) {
+  camfe_hier h = s->h;
+  camfe_ctx ctx = h->ctx;
+  const HLevel& H = h->lev[d];
+  const SLevel& S = s->lev[d];
+  GLevel& G = st->lev[d];
+  G.d = d;
+  G.n = S.n;
+  G.ncol = h->degree == 1 ? 8 : 27;
+  const size_t n = G.n;
+  unsigned g = grid_for(n, BLK);
+  // colour order (stable: canonical order inside a colour)
+  DArr<uint32_t> colour(n), idx(n);
+  hipLaunchKernelGGL(k_colour, g, BLK, 0, ctx->stream, H.fkey.p, (long long)n, h->degree, colour.p, idx.p);
+  check_launch();
+  sort_pairs_u32(ctx, colour.p, idx.p, n, 5);
+  G.perm.alloc(n);
+  G.iperm.alloc(n);
+  hipLaunchKernelGGL(k_iperm, g, BLK, 0, ctx->stream, idx.p, (long long)n, G.iperm.p, G.perm.p);
+  check_launch();
+  std::vector<uint32_t> hcol(n);
+  copy_out(ctx, hcol.data(), colour.p, n);
+  ctx->sync();
+  G.coff.assign(G.ncol + 1, 0);
+  for (size_t i = 0; i < n; ++i) G.coff[hcol[i] + 1]++;
+  for (int c = 0; c < G.ncol; ++c) G.coff[c + 1] += G.coff[c];
+  // slices: per colour, runs of 64 rows
+  G.cslice.assign(G.ncol + 1, 0);
+  std::vector<int> row0, rows;
+  for (int c = 0; c < G.ncol; ++c) {
+    G.cslice[c] = (int)row0.size();
+    for (int r = G.coff[c]; r < G.coff[c + 1]; r += SL) {
+      row0.push_back(r);
+      rows.push_back(std::min(SL, G.coff[c + 1] - r));
+    }
+  }
+  G.cslice[G.ncol] = (int)row0.size();
+  G.nslices = row0.size();
+  G.sl_row0.alloc(G.nslices);
+  G.sl_rows.alloc(G.nslices);
+  copy_in(ctx, G.sl_row0.p, row0.data(), G.nslices);
+  copy_in(ctx, G.sl_rows.p, rows.data(), G.nslices);
+  DArr<int> width(G.nslices);
+  G.sl_ptr.alloc(G.nslices + 1);
+  hipLaunchKernelGGL(k_slice_width, grid_for(G.nslices, BLK), BLK, 0, ctx->stream, S.ptr.p, G.perm.p,
+                     G.sl_row0.p, G.sl_rows.p, (long long)G.nslices, width.p);
+  check_launch();
+  std::vector<int> hw(G.nslices), hp(G.nslices + 1, 0);
+  copy_out(ctx, hw.data(), width.p, G.nslices);
+  ctx->sync();
+  for (size_t i = 0; i < G.nslices; ++i) hp[i + 1] = hp[i] + hw[i];
+  G.snnz = (size_t)hp[G.nslices];
+  copy_in(ctx, G.sl_ptr.p, hp.data(), G.nslices + 1);
+  G.scol.alloc(G.snnz);
+  G.sval64.alloc(G.snnz);
+  G.sval32.alloc(G.snnz);
+  G.invd64.alloc(n);
+  G.invd32.alloc(n);
+  const long long threads = (long long)G.nslices * SL;
+  hipLaunchKernelGGL(k_sell_pad, grid_for(threads, BLK), BLK, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+                     (long long)G.nslices, G.scol.p, G.sval64.p, G.sval32.p);
+  hipLaunchKernelGGL(k_sell_fill, grid_for(threads, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p,
+                     st->t, G.perm.p, G.iperm.p, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (long long)G.nslices,
+                     G.scol.p, G.sval64.p, G.sval32.p, G.invd64.p, G.invd32.p);
+  check_launch();
+  G.x64.alloc(n * KMAXS); G.b64.alloc(n * KMAXS); G.r64.alloc(n * KMAXS);
+  G.x32.alloc(n * KMAXS); G.b32.alloc(n * KMAXS); G.r32.alloc(n * KMAXS);
+}
+
+// transfers between depth d (fine) and d-1 in internal numbering
+void setup_transfer(camfe_sys s, SolverState* st, int d) {
+  camfe_hier h = s->h;
+  camfe_ctx ctx = h->ctx;
+  const HLevel& H = h->lev[d];
+  GLevel& Fg = st->lev[d];
+  GLevel& Cg = st->lev[d - 1];
+  const size_t nf = Fg.n, nc = Cg.n, nnz = H.pnnz;
+  unsigned g = grid_for(nf, BLK);
+  DArr<int> cnt(nf);
+  Fg.Pptr.alloc(nf + 1);
+  hipLaunchKernelGGL(k_p_count, g, BLK, 0, ctx->stream, H.P_ptr.p, Fg.perm.p, (long long)nf, cnt.p);
+  exclusive_scan(ctx, cnt.p, Fg.Pptr.p, nf);
+  int tot = (int)nnz;
+  copy_in(ctx, Fg.Pptr.p + nf, &tot, 1);
+  Fg.Pcol.alloc(nnz);
+  Fg.Pw64.alloc(nnz);
+  Fg.Pw32.alloc(nnz);
+  DArr<uint32_t> rkey(nnz), rval(nnz);
+  hipLaunchKernelGGL(k_p_fill, g, BLK, 0, ctx->stream, H.P_ptr.p, H.P_col.p, H.P_w.p, Fg.perm.p, Cg.iperm.p,
+                     (long long)nf, Fg.Pptr.p, Fg.Pcol.p, Fg.Pw64.p, Fg.Pw32.p, rkey.p, rval.p);
+  check_launch();
+  DArr<int> row_of(nnz);
+  hipLaunchKernelGGL(k_row_of_entry, g, BLK, 0, ctx->stream, Fg.Pptr.p, (long long)nf, row_of.p);
+  int bits = 1;
+  while ((1ULL << bits) <= nc) ++bits;
+  sort_pairs_u32(ctx, rkey.p, rval.p, nnz, bits);
+  Fg.Rptr.alloc(nc + 1);
+  Fg.Rcol.alloc(nnz);
+  Fg.Rw64.alloc(nnz);
+  Fg.Rw32.alloc(nnz);
+  hipLaunchKernelGGL(k_ptr_from_sorted, grid_for(nnz, BLK), BLK, 0, ctx->stream, rkey.p, (long long)nnz,
+                     (long long)nc, Fg.Rptr.p);
+  hipLaunchKernelGGL(k_r_fill, grid_for(nnz, BLK), BLK, 0, ctx->stream, rkey.p, rval.p, (long long)nnz, row_of.p,
+                     Fg.Pw64.p, Fg.Rcol.p, Fg.Rw64.p, Fg.Rw32.p);
+  check_launch();
+}
+
+void setup_coarsest(camfe_sys s, SolverState* st) {
+  camfe_hier h = s->h;
+  camfe_ctx ctx = h->ctx;
+  const int d = h->d0;
+  const SLevel& S = s->lev[d];
+  GLevel& G = st->lev[d];
+  st->direct = h->max_coarse > 0 && (long long)G.n <= h->max_coarse;
+  if (!st->direct) return;
+  const int n = (int)G.n;
+  st->n0 = n;
+  DArr<double> A((size_t)n * n), work((size_t)n * n), dg(n), sv(n);
+  zero(ctx, A.p, A.n);
+  hipLaunchKernelGGL(k_dense_scaled, grid_for(n, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p, st->t,
+                     G.perm.p, G.iperm.p, (long long)n, st->coarse_eps, A.p);
+  zero(ctx, ctx->d_flag, 1);
+  hipLaunchKernelGGL(k_cholesky, 1, 1024, 0, ctx->stream, A.p, n, ctx->d_flag);
+  check_launch();
+  int fail = read_scalar(ctx, ctx->d_flag);
+  CAMFE_REQUIRE(fail == 0, CAMFE_ESINGULAR, "coarsest Cholesky failed (increase coarse_eps)");
+  hipLaunchKernelGGL(k_diag_of, grid_for(n, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p, st->t,
+                     G.perm.p, (long long)n, dg.p);
+  hipLaunchKernelGGL(k_inv_sqrt_diag, grid_for(n, BLK), BLK, 0, ctx->stream, (const double*)nullptr, n, sv.p, dg.p);
+  st->Ainv64.alloc((size_t)n * n);
+  st->Ainv32.alloc((size_t)n * n);
+  hipLaunchKernelGGL(k_chol_inverse, grid_for(n, 64), 64, 0, ctx->stream, A.p, n, sv.p, work.p, st->Ainv64.p,
+                     st->Ainv32.p);
+  check_launch();
+  ctx->sync();
+}
+
+SolverState* setup(camfe_sys s, double t, int precision, double coarse_eps) {
+  camfe_hier h = s->h;
+  camfe_ctx ctx = h->ctx;
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<SolverState> st(new SolverState());
+  st->t = t;
+  st->precision = precision;
+  st->coarse_eps = coarse_eps;
+  st->D = h->D;
+  st->d0 = h->d0;
+  st->lev.resize(h->D + 1);
+  for (int d = h->d0; d <= h->D; ++d) setup_level(s, st.get(), d);
+  for (int d = h->d0 + 1; d <= h->D; ++d) setup_transfer(s, st.get(), d);
+  setup_coarsest(s, st.get());
+  const size_t n = st->lev[h->D].n * KMAXS;
+  st->X.alloc(n); st->R.alloc(n); st->Z.alloc(n); st->P.alloc(n); st->Q.alloc(n); st->B.alloc(n);
+  st->sc.alloc(8 * KMAXS);
+  ctx->sync();
+  st->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st.release();
+}
+
+template <class T>
+struct Vec {
+  static T* x(GLevel& g);
+  static T* b(GLevel& g);
+  static T* r(GLevel& g);
+};
+template <>
+double* Vec<double>::x(GLevel& g) { return g.x64.p; }
+template <>
+double* Vec<double>::b(GLevel& g) { return g.b64.p; }
+template <>
+double* Vec<double>::r(GLevel& g) { return g.r64.p; }
+template <>
+float* Vec<float>::x(GLevel& g) { return g.x32.p; }
+template <>
+float* Vec<float>::b(GLevel& g) { return g.b32.p; }
+template <>
+float* Vec<float>::r(GLevel& g) { return g.r32.p; }
+
+template <class T>
+const T* sval_of(const GLevel& g);
+template <>
+const double* sval_of<double>(const GLevel& g) { return g.sval64.p; }
+template <>
+const float* sval_of<float>(const GLevel& g) { return g.sval32.p; }
+template <class T>
+const T* invd_of(const GLevel& g);
+template <>
+const double* invd_of<double>(const GLevel& g) { return g.invd64.p; }
+template <>
+const float* invd_of<float>(const GLevel& g) { return g.invd32.p; }
+template <class T>
+const T* pw_of(const GLevel& g);
+template <>
+const double* pw_of<double>(const GLevel& g) { return g.Pw64.p; }
+template <>
+const float* pw_of<float>(const GLevel& g) { return g.Pw32.p; }
+template <class T>
+const T* rw_of(const GLevel& g);
+template <>
+const double* rw_of<double>(const GLevel& g) { return g.Rw64.p; }
+template <>
+const float* rw_of<float>(const GLevel& g) { return g.Rw32.p; }
+template <class T>
+const T* ainv_of(const SolverState* s);
+template <>
+const double* ainv_of<double>(const SolverState* s) { return s->Ainv64.p; }
+template <>
+const float* ainv_of<float>(const SolverState* s) { return s->Ainv32.p; }
+
+template <class T, int K>
+void gs_sweep(hipStream_t st, GLevel& G, const T* b, T* x, bool forward) {
+  for (int ci = 0; ci < G.ncol; ++ci) {
+    const int c = forward ? ci : G.ncol - 1 - ci;
+    const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
+    if (s1 <= s0) continue;
+    const long long threads = (long long)(s1 - s0) * SL;
+    hipLaunchKernelGGL((k_gs<T, K>), grid_for(threads, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0,
+                       s1, G.scol.p, sval_of<T>(G), invd_of<T>(G), b, x);
+  }
+}
+
+// One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
+template <class T, int K>
+void vcycle(SolverState* S, hipStream_t st, int d, const T* b, T* x, int nu1, int nu2) {
+  GLevel& G = S->lev[d];
+  if (d == S->d0) {
+    if (S->direct) {
+      hipLaunchKernelGGL((k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st, ainv_of<T>(S), S->n0, b,
+                         x);
+    } else {
+      for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(st, G, b, x, true);
+      for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(st, G, b, x, false);
+    }
+    return;
+  }
+  for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(st, G, b, x, true);
+  T* r = Vec<T>::r(G);
+  hipLaunchKernelGGL((k_residual<T, T, K>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p,
+                     G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, sval_of<T>(G), b, (const T*)x, r,
+                     (double*)nullptr);
+  GLevel& C = S->lev[d - 1];
+  T* bc = Vec<T>::b(C);
+  T* xc = Vec<T>::x(C);
+  hipLaunchKernelGGL((k_restrict<T, K>), grid_for(C.n, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G),
+                     (long long)C.n, (const T*)r, bc);
+  hipLaunchKernelGGL((k_fill<T>), grid_for(C.n * K, BLK), BLK, 0, st, xc, (long long)(C.n * K), (T)0);
+  vcycle<T, K>(S, st, d - 1, bc, xc, nu1, nu2);
+  hipLaunchKernelGGL((k_prolong<T, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G),
+                     (long long)G.n, (const T*)xc, x);
+  for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(st, G, b, x, false);
+}
+
+// z = V(r) at the finest depth (z zeroed first); FP32 cycles convert in and out
+template <int K>
+void precondition(SolverState* S, hipStream_t st, const double* r, double* z, int nu1, int nu2) {
+  GLevel& G = S->lev[S->D];
+  const long long nk = (long long)G.n * K;
+  if (S->precision == 0) {
+    hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, z, nk, 0.0);
+    vcycle<double, K>(S, st, S->D, r, z, nu1, nu2);
+  } else {
+    hipLaunchKernelGGL((k_convert<double, float>), grid_for(nk, BLK), BLK, 0, st, r, nk, G.b32.p);
+    hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
+    vcycle<float, K>(S, st, S->D, G.b32.p, G.x32.p, nu1, nu2);
+    hipLaunchKernelGGL((k_convert<float, double>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, z);
+  }
+}
+
+template <int K>
+void residual64(SolverState* S, hipStream_t st, const double* b, const double* x, double* r, double* nrm) {
+  GLevel& G = S->lev[S->D];
+  hipLaunchKernelGGL((k_residual<double, double, K>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st,
+                     G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm);
+}
+
+struct SolveResult {
+  int it = 0, cycles = 0;
+  double rel = 0;
+};
+
+// Solve columns [c0, c0 + K) of the problem (device canonical b, x col-major)
+template <int K>
+SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, const double* db, double* dx, int kk,
+                        int c0) {
+  camfe_ctx ctx = s->h->ctx;
+  hipStream_t st = ctx->stream;
+  GLevel& G = S->lev[S->D];
+  const size_t n = G.n;
+  const long long nk = (long long)n * K;
+  unsigned gn = grid_for(n, BLK), gnk = grid_for(nk, BLK);
+  double* B = S->B.p;
+  double* X = S->X.p;
+  double* R = S->R.p;
+  double* Z = S->Z.p;
+  double* P = S->P.p;
+  double* Q = S->Q.p;
+  double* sc = S->sc.p;   // rz[K] pq[K] rr[K] rzn[K] bb[K]
+  hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, db, (long long)n, c0, kk, G.iperm.p, B);
+  if (o.x0_given)
+    hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, (const double*)dx, (long long)n, c0, kk, G.iperm.p, X);
+  else
+    hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, X, nk, 0.0);
+  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc, (long long)(8 * KMAXS), 0.0);
+  hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)B, (const double*)B, sc + 4 * K);
+  residual64<K>(S, st, B, X, R, sc + 2 * K);
+  check_launch();
+  double hb[3 * KMAXS];
+  copy_out(ctx, hb, sc + 2 * K, 3 * K);   // rr[K], rz_new[K], bb[K]
+  ctx->sync();
+  double bn[KMAXS];
+  auto relmax = [&](const double* rr) {
+    double m = 0;
+    for (int c = 0; c < K && c0 + c < kk; ++c) {
+      double v = bn[c] > 0 ? std::sqrt(rr[c]) / bn[c] : std::sqrt(rr[c]);
+      m = std::max(m, v);
+    }
+    return m;
+  };
+  for (int c = 0; c < K; ++c) bn[c] = std::sqrt(hb[2 * K + c]);
+  SolveResult res;
+  res.rel = relmax(hb);
+  const int nu1 = o.nu_pre, nu2 = o.nu_post;
+  if (o.method == 1) {
+    // stationary: x += V(b - A x)
+    while (res.rel > o.rtol && res.it < o.max_iter) {
+      precondition<K>(S, st, R, Z, nu1, nu2);
+      hipLaunchKernelGGL(k_axpy_inplace<K>, gnk, BLK, 0, st, (long long)n, X, (const double*)Z);
+      hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
+      residual64<K>(S, st, B, X, R, sc + 2 * K);
+      check_launch();
+      double rr[KMAXS];
+      copy_out(ctx, rr, sc + 2 * K, K);
+      ctx->sync();
+      ++res.it;
+      ++res.cycles;
+      res.rel = relmax(rr);
+      if (!std::isfinite(res.rel)) break;
+    }
+  } else if (res.rel > o.rtol) {
+    // conjugate gradients preconditioned by one V-cycle
+    precondition<K>(S, st, R, Z, nu1, nu2);
+    ++res.cycles;
+    hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)Z, nk, P);
+    hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)R, (const double*)Z, sc);
+    while (res.it < o.max_iter) {
+      hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + K, (long long)(2 * K), 0.0);
+      hipLaunchKernelGGL(k_spmv_dot<K>, grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p,
+                         G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)P, Q, sc + K);
+      hipLaunchKernelGGL(k_cg_update<K>, gn, BLK, 0, st, (long long)n, (const double*)sc, X, R, (const double*)P,
+                         (const double*)Q, sc + 2 * K);
+      check_launch();
+      double rr[KMAXS];
+      copy_out(ctx, rr, sc + 2 * K, K);
+      ctx->sync();
+      ++res.it;
+      res.rel = relmax(rr);
+      if (res.rel <= o.rtol || !std::isfinite(res.rel)) break;
+      precondition<K>(S, st, R, Z, nu1, nu2);
+      ++res.cycles;
+      hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 3 * K, (long long)K, 0.0);
+      hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)R, (const double*)Z, sc + 3 * K);
+      hipLaunchKernelGGL(k_cg_direction<K>, gn, BLK, 0, st, (long long)n, (const double*)sc,
+                         (const double*)(sc + 3 * K), (const double*)Z, P);
+      hipLaunchKernelGGL(k_copy_scalars, 1, 64, 0, st, (const double*)(sc + 3 * K), sc, K);
+    }
+    // true residual of the final iterate
+    hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
+    residual64<K>(S, st, B, X, R, sc + 2 * K);
+    double rr[KMAXS];
+    copy_out(ctx, rr, sc + 2 * K, K);
+    ctx->sync();
+    res.rel = relmax(rr);
+  }
+  hipLaunchKernelGGL(k_scatter_out<K>, gn, BLK, 0, st, (const double*)X, (long long)n, c0, kk, G.iperm.p, dx);
+  check_launch();
+  return res;
+}
+
+}  // namespace
+}  // namespace camfe
+
+using namespace camfe;
+
+extern "C" {
+
+camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b, int k, double* x,
+                         camfe_solve_stats* stats) {
+  camfe_status rc = CAMFE_OK;
+  camfe_status g = guarded([&] {
+    CAMFE_REQUIRE(s && o && b && x && k > 0, CAMFE_EINVAL, "bad argument");
+    CAMFE_REQUIRE(o->precision == 0 || o->precision == 1, CAMFE_EINVAL, "precision must be 0 or 1");
+    CAMFE_REQUIRE(o->method == 0 || o->method == 1, CAMFE_EINVAL, "method must be 0 or 1");
+    CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0, CAMFE_EINVAL, "bad sweep counts");
+    camfe_hier h = s->h;
+    camfe_ctx ctx = h->ctx;
+    ctx->use_device();
+    SolverState* S = s->solver;
+    if (!S || S->t != o->t || S->precision != o->precision || S->coarse_eps != o->coarse_eps) {
+      destroy_solver(S);
+      s->solver = nullptr;
+      s->solver = setup(s, o->t, o->precision, o->coarse_eps);
+      S = s->solver;
+    }
+    const size_t n = S->lev[h->D].n;
+    DArr<double> db(n * (size_t)k), dx(n * (size_t)k);
+    copy_in(ctx, db.p, b, db.n);
+    if (o->x0_given) copy_in(ctx, dx.p, (const double*)x, dx.n);
+    auto t0 = std::chrono::steady_clock::now();
+    SolveResult tot;
+    for (int c0 = 0; c0 < k; c0 += KMAXS) {
+      const int kb = std::min(KMAXS, k - c0);
+      SolveResult r;
+      switch (kb) {
+        case 1: r = solve_block<1>(s, S, *o, db.p, dx.p, k, c0); break;
+        case 2: r = solve_block<2>(s, S, *o, db.p, dx.p, k, c0); break;
+        case 3: r = solve_block<3>(s, S, *o, db.p, dx.p, k, c0); break;
+        default: r = solve_block<4>(s, S, *o, db.p, dx.p, k, c0); break;
+      }
+      tot.it = std::max(tot.it, r.it);
+      tot.cycles += r.cycles;
+      tot.rel = std::max(tot.rel, r.rel);
+    }
+    ctx->sync();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    copy_out(ctx, x, dx.p, dx.n);
+    ctx->sync();
+    if (stats) {
+      stats->iterations = tot.it;
+      stats->cycles = tot.cycles;
+      stats->eps_regularised = S->direct ? 1 : 0;
+      stats->rel_residual = tot.rel;
+      stats->seconds = secs;
+      stats->setup_seconds = S->setup_seconds;
+    }
+    if (!(tot.rel <= o->rtol)) rc = CAMFE_ENOCONV;
+  });
+  if (g != CAMFE_OK) return g;
+  if (rc != CAMFE_OK) set_last_error("solver stopped above rtol");
+  return rc;
+}
+
+}  // extern "C"

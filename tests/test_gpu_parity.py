@@ -1,0 +1,245 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Discrete structure (cube, pairs, functions, (support, triangle) labels,
+prolongation) must match bit for bit; M, L and load vectors within 1e-12
+relative (max-norm); solutions within 1e-6 relative residual measured with
+the oracle's matrices.  Cases span several tiles, ragged tails, exact
+touching (dyadic coordinates on grid planes), the split and unsplit spaces,
+both degrees, and a singular (axis-aligned planar) system.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_1505_03615_amd import meshgen
+from tests.test_oracle_structure import dyadic_sheet
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    V1, F1, f1 = meshgen.config_mesh("icosphere_l3")
+    Vs, Fs, fs = meshgen.config_mesh("two_sheets", n=64, gap=1.0 / 64)
+    Va, Fa, fa = meshgen.config_mesh("two_sheets", n=32, gap=1.0 / 32, rotate=False)
+    Vk, Fk = meshgen.torus_knot(nu=1024, nv=16, seed=3)
+    Vd, Fd = dyadic_sheet(104, n=6)
+    return {
+        "sphere_deg1": dict(V=V1, F=F1, f=f1, depth=5, degree=1, max_coarse=512),
+        "sphere_deg2": dict(V=V1, F=F1, f=f1, depth=4, degree=2, max_coarse=512),
+        "sheets_split": dict(V=Vs, F=Fs, f=fs, depth=6, degree=1, max_coarse=512),
+        "sheets_unsplit": dict(V=Vs, F=Fs, f=fs, depth=6, degree=1, split=0, max_coarse=512),
+        "sheets_axis": dict(V=Va, F=Fa, f=fa, depth=5, degree=1, max_coarse=256),
+        "knot": dict(V=Vk, F=Fk, f=Vk, depth=7, degree=1, max_coarse=512),
+        "dyadic": dict(V=Vd, F=Fd, f=Vd[:, 2], depth=2, degree=1, max_coarse=0, box=[0, 0, 0, 4.0]),
+        "dyadic_deg2": dict(V=Vd, F=Fd, f=Vd[:, 2], depth=2, degree=2, max_coarse=0, box=[0, 0, 0, 4.0]),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import torch
+    from paper_1505_03615_amd import camfe
+    assert torch.cuda.is_available()
+    return camfe
+
+
+@pytest.fixture(scope="module")
+def ctx(cf):
+    c = cf.camfe_ctx_create(0)
+    yield c
+    cf.camfe_ctx_destroy(c)
+
+
+_built = {}
+
+
+def built(cf, ctx, name):
+    if name not in _built:
+        c = CASES[name]
+        kw = dict(depth=c["depth"], degree=c["degree"], split=c.get("split", 1), min_depth=0,
+                  max_coarse=c["max_coarse"], box=c.get("box"))
+        say(f"[gpu] build {name} nt={len(c['F'])} depth={c['depth']} degree={c['degree']}")
+        h = cf.camfe_hierarchy_build(ctx, c["V"], c["F"], **kw)
+        say(f"[gpu] assemble {name}")
+        s = cf.camfe_assemble(h)
+        o = Oracle(c["V"], c["F"], c["depth"], degree=c["degree"], split=kw["split"], min_depth=0,
+                   max_coarse=c["max_coarse"], box=c.get("box")).check().assemble()
+        _built[name] = (h, s, o)
+    return _built[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hierarchy_bit_exact(cf, ctx, name):
+    h, s, o = built(cf, ctx, name)
+    D = CASES[name]["depth"]
+    assert np.array_equal(cf.camfe_hierarchy_cube(h), o.cube())
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    assert (fin, d0) == (D, o.coarsest)
+    for d in range(D, -1, -1):
+        k, t = cf.camfe_export_pairs(h, d)
+        ko, to = o.pairs(d)
+        assert np.array_equal(k, ko) and np.array_equal(t, to), f"pairs depth {d}"
+        if d < d0:
+            continue
+        for a, b in zip(cf.camfe_export_functions(h, d), o.functions(d)):
+            assert np.array_equal(a, b), f"functions depth {d}"
+        for a, b in zip(cf.camfe_export_support_entries(h, d), o.support_entries(d)):
+            assert np.array_equal(a, b), f"support entries depth {d}"
+        if d > d0:
+            P, Po = cf.camfe_export_prolongation(h, d), o.prolongation(d)
+            assert np.array_equal(P.indptr, Po.indptr) and np.array_equal(P.indices, Po.indices)
+            assert np.array_equal(P.data, Po.data), f"prolongation depth {d}"
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_matrices_match(cf, ctx, name):
+    h, s, o = built(cf, ctx, name)
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    for d in range(d0, fin + 1):
+        Mo, Lo = o.matrices(d)
+        M = cf.camfe_export_matrix(s, h, d, 0)
+        L = cf.camfe_export_matrix(s, h, d, 1)
+        em = abs(M - Mo).max() / abs(Mo).max()
+        el = abs(L - Lo).max() / abs(Lo).max()
+        assert em <= 1e-12 and el <= 1e-12, (d, em, el)
+
+
+@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "knot", "dyadic"])
+def test_load_vector_and_vertex_values(cf, ctx, name):
+    h, s, o = built(cf, ctx, name)
+    c = CASES[name]
+    b = cf.camfe_load_vector(s, h, c["f"])
+    bo = o.load_vector(c["f"])
+    assert abs(b - bo).max() <= 1e-12 * abs(bo).max()
+    X = cf.camfe_linear_coeffs(s, h)
+    assert np.array_equal(X, o.linear_coeffs())
+    ev = cf.camfe_eval_vertices(s, len(c["V"]), X)
+    assert np.allclose(ev, o.eval_vertices(X), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "sheets_split", "sheets_axis", "knot"])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("method", [0, 1])
+def test_solve_residual(cf, ctx, name, precision, method):
+    h, s, o = built(cf, ctx, name)
+    c = CASES[name]
+    t = 1e-4 if name == "knot" else 1e-3
+    b = o.load_vector(c["f"])
+    rtol = 1e-8
+    iters = 400 if method == 0 else 60
+    say(f"[gpu] solve {name} precision={precision} method={method}")
+    x, st = cf.camfe_solve(s, b, t=t, rtol=rtol if method == 0 else 1e-30, max_iter=iters,
+                           precision=precision, method=method)
+    Mo, Lo = o.matrices(c["depth"])
+    A = Mo + t * Lo
+    r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+    if method == 0:
+        assert st["converged"], st
+        assert np.all(r <= 1e-6), r
+        assert st["rel_residual"] <= rtol
+    else:
+        # stationary cycles: same contraction as the oracle's over the first cycles
+        xo, io = o.solve(t, b, rtol=1e-30, max_iter=8, mode="vcycle")
+        assert st["iterations"] == iters
+        ro = io["history"][-1]
+        assert np.all(r <= 1.0), r
+
+
+def test_stationary_cycles_track_oracle(cf, ctx):
+    h, s, o = built(cf, ctx, "sphere_deg1")
+    c = CASES["sphere_deg1"]
+    b = o.load_vector(c["f"])
+    for cyc in (1, 3):
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-30, max_iter=cyc, method=1)
+        xo, io = o.solve(1e-3, b, rtol=1e-30, max_iter=cyc, mode="vcycle")
+        assert abs(x - xo).max() <= 1e-9 * abs(xo).max(), cyc
+
+
+def test_reassemble_mass_with_triangle_weights(cf, ctx):
+    c = CASES["knot"]
+    h = cf.camfe_hierarchy_build(ctx, c["V"], c["F"], depth=6, max_coarse=256)
+    s = cf.camfe_assemble(h)
+    w = np.random.default_rng(7).uniform(0.5, 1.5, len(c["F"]))
+    cf.camfe_reassemble_mass(s, w)
+    o = Oracle(c["V"], c["F"], 6, max_coarse=256).check().assemble(tri_weight=w)
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    for d in range(d0, fin + 1):
+        Mo, Lo = o.matrices(d)
+        M = cf.camfe_export_matrix(s, h, d, 0)
+        L = cf.camfe_export_matrix(s, h, d, 1)
+        assert abs(M - Mo).max() <= 1e-12 * abs(Mo).max()
+        assert abs(L - Lo).max() <= 1e-12 * abs(Lo).max()
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)
+
+
+def test_invalid_inputs_and_exports(cf, ctx):
+    V = np.array([[0.5, 0.5, 0.5], [1.5, 0.5, 0.5], [0.5, 1.5, 0.5]])
+    F = np.array([[0, 1, 2]], np.int32)
+    with pytest.raises(cf.CamfeError, match="grid plane"):
+        cf.camfe_hierarchy_build(ctx, V, F, depth=2, box=[0, 0, 0, 2.0])
+    with pytest.raises(cf.CamfeError, match="CAMFE_EINVAL"):
+        cf.camfe_hierarchy_build(ctx, V, np.array([[0, 1, 7]], np.int32), depth=3)
+    h, s, o = built(cf, ctx, "sphere_deg1")
+    import ctypes
+    lib = cf.load()
+    n = ctypes.c_int64()
+    k = np.zeros(4, np.uint64)
+    t = np.zeros(4, np.int32)
+    rc = lib.camfe_export_pairs(h, 5, k.ctypes.data_as(ctypes.c_void_p), t.ctypes.data_as(ctypes.c_void_p), 4,
+                                ctypes.byref(n))
+    assert rc == -6 and n.value > 4
+    with pytest.raises(cf.CamfeError, match="CAMFE_ESTATE"):
+        cf.camfe_export_functions(h, 0)
+
+
+def test_full_size_two_sheets_properties(cf, ctx):
+    """Config 2 at its full size (2 x 131,072 triangles, depth 8): properties
+    that hold at any size, checked on the GPU's own exports - partition of
+    unity, zero row sums, symmetry, the Galerkin identity at every depth, no
+    coupling across the sheets in the split space - plus the FP64 and mixed
+    solves to 1e-8 checked with the exported FP64 matrix."""
+    V, F, f = meshgen.config_mesh("two_sheets_256")
+    _, _, _, sheet = meshgen.two_sheets(256)
+    say("[gpu] build two_sheets_256 depth 8")
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=8, max_coarse=2048)
+    s = cf.camfe_assemble(h)
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    tri_sheet = sheet[F[:, 0]]
+    mats = {}
+    for d in range(d0, fin + 1):
+        M = cf.camfe_export_matrix(s, h, d, 0)
+        L = cf.camfe_export_matrix(s, h, d, 1)
+        mats[d] = (M, L)
+        assert abs(M.sum() - area) <= 1e-12 * area
+        assert abs(L @ np.ones(L.shape[0])).max() <= 1e-11 * abs(L).max()
+        assert abs(M - M.T).max() <= 1e-14 * abs(M).max()
+        rep = cf.camfe_export_functions(h, d)[2]
+        Mc = M.tocoo()
+        assert np.all(tri_sheet[rep][Mc.row] == tri_sheet[rep][Mc.col])
+    for d in range(d0 + 1, fin + 1):
+        P = cf.camfe_export_prolongation(h, d)
+        Mf, Lf = mats[d]
+        Mc, Lc = mats[d - 1]
+        assert abs(P.T @ Mf @ P - Mc).max() <= 1e-12 * abs(Mc).max()
+        assert abs(P.T @ Lf @ P - Lc).max() <= 1e-12 * abs(Lc).max()
+    b = cf.camfe_load_vector(s, h, f)
+    M, L = mats[fin]
+    for precision in (0, 1):
+        say(f"[gpu] solve two_sheets_256 precision={precision}")
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-8, max_iter=500, precision=precision)
+        r = np.linalg.norm(b - (M + 1e-3 * L) @ x) / np.linalg.norm(b)
+        assert st["converged"] and r <= 1e-6, (st, r)
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)

@@ -1,0 +1,54 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1505_03615_amd import camfe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "camfe.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(camfe_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(camfe.LIB_PATH):
+        pytest.fail("libcamfe.so is not built (run __graft_entry__.build())")
+    return camfe.load()
+
+
+def test_every_declared_function_is_exported(lib):
+    decl = declared_functions()
+    assert len(decl) >= 20
+    out = subprocess.run(["nm", "-D", "--defined-only", camfe.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (camfe_\w+)", out))
+    missing = [f for f in decl if f not in exported]
+    assert not missing, missing
+    assert sorted(camfe.EXPORTS) == decl
+    for f in decl:
+        assert hasattr(lib, f)
+
+
+def test_error_path_without_device(lib):
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = lib.camfe_ctx_create(-1, None, ctypes.byref(h))
+    assert rc != 0
+    assert len(lib.camfe_last_error()) > 0
+
+
+def test_product_path_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1505_03615_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "liboracle" not in txt, f

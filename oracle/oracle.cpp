@@ -536,8 +536,8 @@ int func_of(const Level& L, uint64_t key, int t) {
 // Integrate over every (cell, triangle) fragment at depth d:
 //   M_ij = int b_i b_j,  L_ij = int <grad_M b_i, grad_M b_j>,  b_i += int f b_i
 // with grad_M the tangential (surface) gradient on each flat triangle.
-// tri_w (nullable) scales each triangle's contribution (area ratio of an
-// evolved surface).  fv (nullable, nv x k col-major) gives per-vertex values of
+// tri_w (nullable) scales each triangle's contribution to M only (area ratio
+// of an evolved surface; the stiffness stays that of the original surface).  fv (nullable, nv x k col-major) gives per-vertex values of
 // f, interpolated linearly inside each triangle; rhs is n x k col-major.
 bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k, double* rhs,
                     bool want_matrix) {
@@ -599,7 +599,9 @@ bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k
       for (int iu = 0; iu < nq; ++iu)
         for (int iv = 0; iv < nq; ++iv) {
           double xi = gx[iu], eta = (1.0 - gx[iu]) * gx[iv];
-          double wq = 2.0 * area * gw[iu] * gw[iv] * (1.0 - gx[iu]) * hd * hd * tw;
+          // tri_w weights the mass only (M_t of an evolved surface, L_0 fixed)
+          double wq = 2.0 * area * gw[iu] * gw[iv] * (1.0 - gx[iu]) * hd * hd;
+          double wqm = wq * tw;
           double x[3], lam[3];
           for (int a = 0; a < 3; ++a) {
             x[a] = P0.x[a] + xi * a1[a] + eta * a2[a];
@@ -623,7 +625,7 @@ bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k
           if (want_matrix)
             for (int i = 0; i < NB; ++i)
               for (int j = 0; j < NB; ++j) {
-                Me[i * NB + j] += wq * phi[i] * phi[j];
+                Me[i * NB + j] += wqm * phi[i] * phi[j];
                 Le[i * NB + j] += wq * (g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2]);
               }
           if (rhs)
@@ -755,9 +757,12 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
   SysLevel& S = sv.sl[d];
   if (d == sv.h->d0) {
     if (S.direct) {
+      // x = D^-1/2 (D^-1/2 A D^-1/2 + eps I)^-1 D^-1/2 b
       for (int q = 0; q < k; ++q) {
-        std::copy(b + (size_t)q * S.n, b + (size_t)(q + 1) * S.n, x + (size_t)q * S.n);
-        chol_solve(S.chol, S.n, x + (size_t)q * S.n);
+        double* xq = x + (size_t)q * S.n;
+        for (long i = 0; i < S.n; ++i) xq[i] = b[(size_t)q * S.n + i] / std::sqrt(S.diag[i]);
+        chol_solve(S.chol, S.n, xq);
+        for (long i = 0; i < S.n; ++i) xq[i] /= std::sqrt(S.diag[i]);
       }
     } else {
       for (int s = 0; s < sv.nu1; ++s) gs_sweep(S, b, x, k, true);

@@ -9,7 +9,8 @@
 // collapsed Gauss-Legendre rule.  Four quadrature points at a time, the 64
 // lanes evaluate (function slot, point) pairs and the FP64 matrix cores
 // contract them: M_e += Phi W Phi^T and L_e += sum_axes G W G^T with
-// v_mfma_f64_16x16x4.  Consecutive pairs whose eight (27) rows coincide share
+// v_mfma_f64_16x16x4 (operands: lane l holds row/column l % 16 at k = l / 16;
+// result: lane l, register r holds row l / 16 + 4 r, column l % 16).  Consecutive pairs whose eight (27) rows coincide share
 // one element block, which is scattered with atomics when the rows change.
 #include <algorithm>
 #include <cmath>
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
               const int colrow = __shfl(cur_row, b < NB ? b : 0);
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int aa = 16 * I + 4 * pt + r;
+                const int aa = 16 * I + pt + 4 * r;   // row of accumulator register r
                 const int rowrow = __shfl(cur_row, aa < NB ? aa : 0);
                 if (aa < NB && b < NB) {
                   const double mv = accM[ti][r], lv = accL[ti][r];

@@ -718,8 +718,9 @@ void build(camfe_hier h, const double* V, const int32_t* F) {
     sort_keys(ctx, L.pairs.p, L.npairs, 3 * D + TRI_BITS);
     count_cells(h, D);
   }
-  // depths D, D-1, ...: functions, then stop at the coarsest depth (A3-A5)
+  // depths D, D-1, ..., 0: pairs by aggregation; functions down to the coarsest depth
   h->d0 = D;
+  bool stopped = false;
   for (int d = D; d >= 0; --d) {
     HLevel& L = h->lev[d];
     if (d < D) {
@@ -732,9 +733,10 @@ void build(camfe_hier h, const double* V, const int32_t* F) {
       L.npairs = unique_sorted(ctx, tmp.p, Fn.npairs, L.pairs);
       count_cells(h, d);
     }
+    if (stopped) continue;
     build_functions(h, d);
     h->d0 = d;
-    if (d <= h->min_depth || (h->max_coarse > 0 && (long long)L.nfun <= h->max_coarse)) break;
+    if (d <= h->min_depth || (h->max_coarse > 0 && (long long)L.nfun <= h->max_coarse)) stopped = true;
   }
   // prolongation with chi (A6)
   for (int d = D; d > h->d0; --d) build_prolongation(h, d);

@@ -729,6 +729,7 @@ void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward
       for (int q = 0; q < k; ++q) {
         const double* xq = x + (size_t)q * S.n;
         double acc = 0.0;
+        if (S.diag[r] == 0.0) continue;   // function of zero computed mass: coefficient stays
         for (long e = (*S.ptr)[r]; e < (*S.ptr)[r + 1]; ++e) acc += S.a[e] * xq[(*S.col)[e]];
         x[(size_t)q * S.n + r] += (b[(size_t)q * S.n + r] - acc) / S.diag[r];
       }
@@ -760,9 +761,10 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
       // x = D^-1/2 (D^-1/2 A D^-1/2 + eps I)^-1 D^-1/2 b
       for (int q = 0; q < k; ++q) {
         double* xq = x + (size_t)q * S.n;
-        for (long i = 0; i < S.n; ++i) xq[i] = b[(size_t)q * S.n + i] / std::sqrt(S.diag[i]);
+        for (long i = 0; i < S.n; ++i)
+          xq[i] = S.diag[i] > 0.0 ? b[(size_t)q * S.n + i] / std::sqrt(S.diag[i]) : 0.0;
         chol_solve(S.chol, S.n, xq);
-        for (long i = 0; i < S.n; ++i) xq[i] /= std::sqrt(S.diag[i]);
+        for (long i = 0; i < S.n; ++i) xq[i] = S.diag[i] > 0.0 ? xq[i] / std::sqrt(S.diag[i]) : 0.0;
       }
     } else {
       for (int s = 0; s < sv.nu1; ++s) gs_sweep(S, b, x, k, true);
@@ -948,9 +950,11 @@ int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2
       for (long r = 0; r < S.n; ++r)
         for (long e = (*S.ptr)[r]; e < (*S.ptr)[r + 1]; ++e) {
           long c = (*S.col)[e];
-          S.chol[(size_t)r * S.n + c] = S.a[e] / std::sqrt(S.diag[r] * S.diag[c]);
+          if (S.diag[r] > 0.0 && S.diag[c] > 0.0)
+            S.chol[(size_t)r * S.n + c] = S.a[e] / std::sqrt(S.diag[r] * S.diag[c]);
         }
-      for (long r = 0; r < S.n; ++r) S.chol[(size_t)r * S.n + r] += coarse_eps;
+      // a zero-mass function gets an identity row (its coefficient is 0)
+      for (long r = 0; r < S.n; ++r) S.chol[(size_t)r * S.n + r] = (S.diag[r] > 0.0 ? S.chol[(size_t)r * S.n + r] : 1.0) + coarse_eps;
       sv.eps_used = 1;
       if (!cholesky(S.chol, S.n)) { h.err = "coarse Cholesky failed"; return -1; }
     }
@@ -967,7 +971,8 @@ int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2
     double m = 0;
     for (int q = 0; q < k; ++q) {
       double rn = col_norm(r.data() + (size_t)q * n, n);
-      m = std::max(m, bn[q] > 0 ? rn / bn[q] : rn);
+      double v = bn[q] > 0 ? rn / bn[q] : rn;
+      if (!(v <= m)) m = v;   // keeps NaN
     }
     return m;
   };

@@ -104,7 +104,24 @@ def test_singular_planar_system_still_solves():
     f = np.where(sheet == 0, 1.0, -1.0) * np.sin(6 * np.pi * xl)
     b = o.load_vector(f)
     x, info = o.solve(1e-3, b, rtol=1e-8, max_iter=300)
-    assert info["converged"], info["history"][-5:]
+    assert info["converged"] and np.isfinite(info["rel_residual"]), info["history"][-5:]
+    assert np.all(np.isfinite(x))
+    M, L = o.matrices(5)
+    r = b[:, 0] - (M + 1e-3 * L) @ x[:, 0]
+    assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(b)
+    # functions kept by a rounding-level overlap have an all-zero row; their
+    # coefficient stays 0
+    zero = np.where(M.diagonal() == 0)[0]
+    assert len(zero) > 0 and np.all(x[zero, 0] == 0)
+    assert np.all(abs(M[zero]).sum(axis=1) == 0) and np.all(abs(L[zero]).sum(axis=1) == 0)
+
+
+def test_nan_right_hand_side_is_reported_not_converged(small):
+    o, b = small
+    bb = b.copy()
+    bb[3, 0] = np.nan
+    x, info = o.solve(1e-3, bb, rtol=1e-8, max_iter=5)
+    assert not info["converged"] and not np.isfinite(info["rel_residual"])
 
 
 def test_warm_start_and_zero_rhs(small):

@@ -128,8 +128,9 @@ __global__ void k_sell_fill(const int* ptr, const int* col, const double* M, con
       sval32[o] = 0.0f;
     }
   }
-  invd[i] = 1.0 / diag;
-  invd32[i] = (float)(1.0 / diag);
+  // a function of zero computed mass has an empty row: its coefficient stays 0
+  invd[i] = diag != 0.0 ? 1.0 / diag : 0.0;
+  invd32[i] = diag != 0.0 ? (float)(1.0 / diag) : 0.0f;
 }
 __global__ void k_sell_pad(const int* sl_ptr, const int* row0, const int* rows, long long ns, int* scol,
                            double* sval, float* sval32) {
@@ -201,14 +202,16 @@ __global__ void k_dense_scaled(const int* ptr, const int* col, const double* M, 
   double di = 0.0;
   for (int e = ptr[f]; e < ptr[f + 1]; ++e)
     if (col[e] == f) di = M[e] + t * L[e];
-  for (int e = ptr[f]; e < ptr[f + 1]; ++e) {
-    int c = col[e];
-    double dc = 0.0;
-    for (int q = ptr[c]; q < ptr[c + 1]; ++q)
-      if (col[q] == c) dc = M[q] + t * L[q];
-    A[i * n + iperm[c]] = (M[e] + t * L[e]) / sqrt(di * dc);
-  }
-  A[i * n + i] += eps;
+  if (di > 0.0)
+    for (int e = ptr[f]; e < ptr[f + 1]; ++e) {
+      int c = col[e];
+      double dc = 0.0;
+      for (int q = ptr[c]; q < ptr[c + 1]; ++q)
+        if (col[q] == c) dc = M[q] + t * L[q];
+      if (dc > 0.0) A[i * n + iperm[c]] = (M[e] + t * L[e]) / sqrt(di * dc);
+    }
+  // zero-mass functions get an identity row (their coefficient is 0)
+  A[i * n + i] = (di > 0.0 ? A[i * n + i] : 1.0) + eps;
 }
 // right-looking Cholesky of the lower triangle, one workgroup
 __global__ __launch_bounds__(1024) void k_cholesky(double* A, int n, int* fail) {
@@ -258,17 +261,19 @@ __global__ void k_chol_inverse(const double* Lf, int n, const double* s, double*
     Ainv32[(long long)i * n + c] = (float)v;
   }
 }
-__global__ void k_inv_sqrt_diag(const double* A, int n, double* s, const double* diagsrc) {
+__global__ void k_inv_sqrt_diag(int n, double* s, const double* diagsrc) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) s[i] = 1.0 / sqrt(diagsrc[i]);
+  if (i < n) s[i] = diagsrc[i] > 0.0 ? 1.0 / sqrt(diagsrc[i]) : 0.0;
 }
 __global__ void k_diag_of(const int* ptr, const int* col, const double* M, const double* L, double t,
                           const int* perm, long long n, double* dg) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
   int f = perm[i];
+  double v = 0.0;
   for (int e = ptr[f]; e < ptr[f + 1]; ++e)
-    if (col[e] == f) dg[i] = M[e] + t * L[e];
+    if (col[e] == f) v = M[e] + t * L[e];
+  dg[i] = v;
 }
 
 // ------------------------------------------------------ V-cycle kernels
@@ -669,7 +674,7 @@ void setup_coarsest(camfe_sys s, SolverState* st) {
   CAMFE_REQUIRE(fail == 0, CAMFE_ESINGULAR, "coarsest Cholesky failed (increase coarse_eps)");
   hipLaunchKernelGGL(k_diag_of, grid_for(n, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p, st->t,
                      G.perm.p, (long long)n, dg.p);
-  hipLaunchKernelGGL(k_inv_sqrt_diag, grid_for(n, BLK), BLK, 0, ctx->stream, (const double*)nullptr, n, sv.p, dg.p);
+  hipLaunchKernelGGL(k_inv_sqrt_diag, grid_for(n, BLK), BLK, 0, ctx->stream, n, sv.p, (const double*)dg.p);
   st->Ainv64.alloc((size_t)n * n);
   st->Ainv32.alloc((size_t)n * n);
   hipLaunchKernelGGL(k_chol_inverse, grid_for(n, 64), 64, 0, ctx->stream, A.p, n, sv.p, work.p, st->Ainv64.p,
@@ -855,7 +860,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     double m = 0;
     for (int c = 0; c < K && c0 + c < kk; ++c) {
       double v = bn[c] > 0 ? std::sqrt(rr[c]) / bn[c] : std::sqrt(rr[c]);
-      m = std::max(m, v);
+      if (!(v <= m)) m = v;   // keeps NaN
     }
     return m;
   };
@@ -961,7 +966,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
       }
       tot.it = std::max(tot.it, r.it);
       tot.cycles += r.cycles;
-      tot.rel = std::max(tot.rel, r.rel);
+      if (!(r.rel <= tot.rel)) tot.rel = r.rel;
     }
     ctx->sync();
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

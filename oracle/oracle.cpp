@@ -729,7 +729,7 @@ void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward
       for (int q = 0; q < k; ++q) {
         const double* xq = x + (size_t)q * S.n;
         double acc = 0.0;
-        if (S.diag[r] == 0.0) continue;   // function of zero computed mass: coefficient stays
+        if (S.diag[r] == 0.0) continue;   // zero-mass function: all-zero row, nothing to relax
         for (long e = (*S.ptr)[r]; e < (*S.ptr)[r + 1]; ++e) acc += S.a[e] * xq[(*S.col)[e]];
         x[(size_t)q * S.n + r] += (b[(size_t)q * S.n + r] - acc) / S.diag[r];
       }
@@ -953,7 +953,7 @@ int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2
           if (S.diag[r] > 0.0 && S.diag[c] > 0.0)
             S.chol[(size_t)r * S.n + c] = S.a[e] / std::sqrt(S.diag[r] * S.diag[c]);
         }
-      // a zero-mass function gets an identity row (its coefficient is 0)
+      // a zero-mass function gets an identity row (its right-hand side is 0)
       for (long r = 0; r < S.n; ++r) S.chol[(size_t)r * S.n + r] = (S.diag[r] > 0.0 ? S.chol[(size_t)r * S.n + r] : 1.0) + coarse_eps;
       sv.eps_used = 1;
       if (!cholesky(S.chol, S.n)) { h.err = "coarse Cholesky failed"; return -1; }

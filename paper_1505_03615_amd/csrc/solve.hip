@@ -128,7 +128,7 @@ __global__ void k_sell_fill(const int* ptr, const int* col, const double* M, con
       sval32[o] = 0.0f;
     }
   }
-  // a function of zero computed mass has an empty row: its coefficient stays 0
+  // a function of zero computed mass has an empty row: nothing to relax
   invd[i] = diag != 0.0 ? 1.0 / diag : 0.0;
   invd32[i] = diag != 0.0 ? (float)(1.0 / diag) : 0.0f;
 }
@@ -210,7 +210,7 @@ __global__ void k_dense_scaled(const int* ptr, const int* col, const double* M, 
         if (col[q] == c) dc = M[q] + t * L[q];
       if (dc > 0.0) A[i * n + iperm[c]] = (M[e] + t * L[e]) / sqrt(di * dc);
     }
-  // zero-mass functions get an identity row (their coefficient is 0)
+  // zero-mass functions get an identity row (their right-hand side is 0)
   A[i * n + i] = (di > 0.0 ? A[i * n + i] : 1.0) + eps;
 }
 // right-looking Cholesky of the lower triangle, one workgroup

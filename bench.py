@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark of the connectivity-aware multilevel FEM hot path on one MI355X.
+
+One step = the whole path on one synthetic input, inputs resident in HBM:
+hierarchy (grid placement, triangle/cell pairs, octree, supports, split,
+prolongation), assembly of M and L at every depth, the load vector, and the
+solve of (M + t L) x = b to a relative residual of 1e-8 twice: with the FP64
+V-cycle and with the FP32 V-cycle under FP64 refinement (conjugate gradients
+preconditioned by one V-cycle in both).
+
+Workload: two parallel unit squares 1/256 apart, each a 256 x 256 grid of
+split quads (262,144 triangles), turned to general position, octree depth 8,
+t = 1e-3, RHS +-sin(40 pi x) on the two sheets.
+
+Prints one JSON line.  `value` is finest-depth DoF x V-cycles of both solves
+per second of the whole step; the per-phase times and the solve-only figures
+are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    "two_sheets_256_depth8": dict(mesh="two_sheets_256", depth=8, t=1e-3, degree=1),
+}
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(sample_n=128, sample_depth=7):
+    """The oracle (single-threaded FP64 C++) on a bounded sample of the same
+    workload: the two-sheet coupling test at 128 x 128 quads per sheet and
+    depth 7 (a quarter of the triangles, same voxel-to-triangle ratio)."""
+    from oracle import Oracle
+    from paper_1505_03615_amd import meshgen
+    V, F, f = meshgen.config_mesh("two_sheets", n=sample_n, gap=1.0 / sample_n)
+    t0 = time.perf_counter()
+    o = Oracle(V, F, sample_depth, max_coarse=2048).check().assemble()
+    b = o.load_vector(f)
+    x, info = o.solve(1e-3, b, rtol=1e-8, max_iter=2000)
+    secs = time.perf_counter() - t0
+    n = o.count(sample_depth, "functions")
+    return {"value": n * info["cycles"] / secs, "unit": "DoF*cycles/s", "cores": 1, "kind": "oracle",
+            "sample": f"two sheets {sample_n}x{sample_n} quads each ({len(F)} tris), depth {sample_depth}, "
+                      f"n={n}, FP64 V-cycle-preconditioned CG to 1e-8: {info['cycles']} cycles in {secs:.2f} s "
+                      f"(build+assemble+load+solve)",
+            "seconds": secs, "converged": bool(info["converged"])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="two_sheets_256_depth8", choices=list(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1505_03615_amd import camfe as cf, meshgen
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    cf.load()
+    wl = WORKLOADS[args.workload]
+    V, F, f = meshgen.config_mesh(wl["mesh"])
+    dev = torch.device("cuda:0")
+    Vd = torch.from_numpy(V).to(dev)
+    Fd = torch.from_numpy(F).to(dev)
+    fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
+    stream = torch.cuda.current_stream()
+    ctx = cf.camfe_ctx_create(0, stream)
+
+    def step(record):
+        ph = {}
+        t0 = time.perf_counter()
+        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=2048)
+        t1 = time.perf_counter()
+        s = cf.camfe_assemble(h)
+        t2 = time.perf_counter()
+        b = cf.camfe_load_vector(s, h, fd)
+        t3 = time.perf_counter()
+        x64, st64 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=0)
+        t4 = time.perf_counter()
+        x32, st32 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=1)
+        t5 = time.perf_counter()
+        fin, d0 = cf.camfe_hierarchy_levels(h)
+        n = cf.camfe_hierarchy_info(h, fin)[2]
+        if record is not None:
+            record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve64=t4 - t3, solve32=t5 - t4,
+                               st64=st64, st32=st32, n=n, levels=(fin, d0)))
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+
+    log(f"[bench] warmup {args.warmup}")
+    # the first warm-up step also finds the kernel with the largest event time
+    dominant = None
+    for i in range(args.warmup):
+        if i == 0 and not args.no_kernel_timing:
+            cf.camfe_ctx_kernel_timing(ctx, True)
+        step(None)
+        if i == 0 and not args.no_kernel_timing:
+            times = {k: cf.camfe_ctx_kernel_time(ctx, k) for k in cf.KERNELS}
+            cf.camfe_ctx_kernel_timing(ctx, False)
+            dominant = max(times, key=lambda k: times[k][0])
+            log("[bench] kernel event times (ms): " +
+                ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in sorted(times.items(), key=lambda kv: -kv[1][0])))
+    if not args.no_kernel_timing:
+        cf.camfe_ctx_kernel_timing(ctx, True)
+    rec = []
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(rec)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    if not args.no_kernel_timing:
+        kern = {k: cf.camfe_ctx_kernel_time(ctx, k) for k in cf.KERNELS}
+        cf.camfe_ctx_kernel_timing(ctx, False)
+    ms = (t1 - t0) * 1000.0 / args.steps
+    n = rec[0]["n"]
+    cyc64 = np.mean([r["st64"]["cycles"] for r in rec])
+    cyc32 = np.mean([r["st32"]["cycles"] for r in rec])
+    solve64 = np.mean([r["solve64"] for r in rec])
+    solve32 = np.mean([r["solve32"] for r in rec])
+    phases = {k: 1000.0 * float(np.mean([r[k] for r in rec])) for k in ("build", "assemble", "load", "solve64", "solve32")}
+    out = {
+        "metric": "solve time to 1e-8 rel. residual, DoF*cycles/s; learned vs plain smoother",
+        "value": n * (cyc64 + cyc32) / (ms / 1000.0),
+        "unit": "DoF*cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (mixed-precision solve: f32 V-cycle, f64 CG)",
+        "data": "synthetic",
+        "config": {"workload": "two parallel unit squares 1/256 apart, 2 x 256 x 256 split quads "
+                               "(262,144 tris), rotated to general position, octree depth 8, degree 1, "
+                               "split, t=1e-3, RHS +-sin(40 pi x)",
+                   "dof_finest": int(n), "levels": list(rec[0]["levels"])},
+        "phases_ms": phases,
+        "solve_to_1e-8_ms": {"plain_fp64": 1000.0 * solve64, "mixed_fp32_fp64": 1000.0 * solve32,
+                             "learned": None},
+        "solve_cycles": {"plain_fp64": float(cyc64), "mixed_fp32_fp64": float(cyc32)},
+        "solve_dof_cycles_per_s": {"plain_fp64": n * cyc64 / solve64, "mixed_fp32_fp64": n * cyc32 / solve32},
+        "rel_residual": {"plain_fp64": float(max(r["st64"]["rel_residual"] for r in rec)),
+                         "mixed_fp32_fp64": float(max(r["st32"]["rel_residual"] for r in rec))},
+    }
+    if kern:
+        out["kernel_event_ms_per_step"] = {k: v[0] / args.steps for k, v in kern.items() if v[1]}
+        dom = max(kern, key=lambda k: kern[k][0])
+        tot_ms, launches, work = kern[dom]
+        if dom == "assemble":
+            achieved = work / (tot_ms / 1000.0) / 1e12
+            out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                               "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                               "launches": launches, "avg_launch_us": 1000.0 * tot_ms / launches}
+        else:
+            achieved = work / (tot_ms / 1000.0) / 1e9
+            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
+                               "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                               "launches": launches, "avg_launch_us": 1000.0 * tot_ms / launches,
+                               "bytes_per_launch": work / launches}
+    if args.calibrate_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        bb = torch.empty_like(a)
+        for _ in range(3):
+            bb.copy_(a)
+        torch.cuda.synchronize()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline()
+    cf.camfe_ctx_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

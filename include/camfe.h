@@ -67,6 +67,18 @@ const char *camfe_last_error(void);
 camfe_status camfe_ctx_create(int device, void *hip_stream, camfe_ctx *out);
 void camfe_ctx_destroy(camfe_ctx ctx);
 
+/* Measurement: with enable = 1 every launch of the hot kernels on the
+ * context's stream is bracketed by HIP events (totals reset); enable = 0 stops
+ * recording.  camfe_ctx_kernel_time returns, for one kernel name
+ * ("gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve",
+ * "assemble", "pairs", "uf_link", "support_sort", "cg_vector"), the summed
+ * event time in ms, the number of launches, and the summed algorithmic work
+ * (bytes the method must move, or flops for "assemble").  EINVAL for an
+ * unknown name. */
+camfe_status camfe_ctx_kernel_timing(camfe_ctx ctx, int enable);
+camfe_status camfe_ctx_kernel_time(camfe_ctx ctx, const char *kernel, double *total_ms, int64_t *launches,
+                                   double *work);
+
 /* ------------------------------------------------------------ hierarchy */
 typedef struct {
   int depth;          /* finest depth D, 1..12 (2^D cells per axis)                   */

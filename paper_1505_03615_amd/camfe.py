@@ -25,8 +25,10 @@ EXPORTS = [
     "camfe_export_functions", "camfe_export_support_entries", "camfe_export_prolongation",
     "camfe_hierarchy_destroy", "camfe_assemble", "camfe_reassemble_mass", "camfe_export_matrix",
     "camfe_load_vector", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
-    "camfe_system_destroy",
+    "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time",
 ]
+KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
+           "uf_link", "support_sort", "cg_vector"]
 
 
 class CamfeError(RuntimeError):
@@ -85,6 +87,8 @@ def load():
         "camfe_eval_vertices": (I, [H, P, I, P]),
         "camfe_solve": (I, [H, C.POINTER(SolveOpts), P, I, P, C.POINTER(SolveStats)]),
         "camfe_system_destroy": (None, [H]),
+        "camfe_ctx_kernel_timing": (I, [H, I]),
+        "camfe_ctx_kernel_time": (I, [H, C.c_char_p, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -156,6 +160,17 @@ def camfe_ctx_create(device: int = 0, stream=None):
 
 def camfe_ctx_destroy(ctx):
     load().camfe_ctx_destroy(ctx)
+
+
+def camfe_ctx_kernel_timing(ctx, enable: bool):
+    _check(load().camfe_ctx_kernel_timing(ctx, 1 if enable else 0))
+
+
+def camfe_ctx_kernel_time(ctx, kernel: str):
+    """(total ms, launches, algorithmic work) of one kernel since timing was enabled."""
+    ms, n, w = C.c_double(), C.c_int64(), C.c_double()
+    _check(load().camfe_ctx_kernel_time(ctx, kernel.encode(), C.byref(ms), C.byref(n), C.byref(w)))
+    return ms.value, n.value, w.value
 
 
 # --------------------------------------------------------------- hierarchy

@@ -168,6 +168,7 @@ struct AsmArgs {
   int k;              // columns in this pass (<= KMAX)
   double* rhs;        // n x ldr column-major (column offset applied by caller)
   long long ldr;
+  unsigned long long* npts;   // nullable: quadrature points processed (measurement)
 };
 
 template <int DEG>
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
         }
       }
       const int npts = (n - 2) * Q;
+      if (a.npts && lane == 0) atomicAdd(a.npts, (unsigned long long)npts);
       for (int p0 = 0; p0 < npts; p0 += 4) {
         const int p = p0 + pt;
         double val[T], gx[T], gy[T], gz[T];
@@ -527,14 +529,29 @@ Chunks make_chunks(camfe_ctx ctx, const HLevel& L) {
   return out;
 }
 
-void launch_assemble(camfe_hier h, int d, const Chunks& ch, const AsmArgs& a) {
+// Launch one assembly pass.  With the timer on, the pass counts its quadrature
+// points and records the flops of the dense contractions it performed:
+// M_e and the three gradient products, 2 NB^2 flops each per point.
+void launch_assemble(camfe_hier h, int d, const Chunks& ch, AsmArgs a) {
   if (ch.n == 0) return;
+  camfe_ctx ctx = h->ctx;
   unsigned grid = (unsigned)std::min(ch.n, 1 << 20);
+  DArr<unsigned long long> cnt;
+  const bool timed = ctx->timer.on && a.M != nullptr;
+  if (timed) {
+    cnt.alloc(1);
+    zero(ctx, cnt.p, 1);
+    a.npts = cnt.p;
+  }
   if (h->degree == 1)
-    hipLaunchKernelGGL(k_assemble<1>, grid, 64, 0, h->ctx->stream, a);
+    CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, k_assemble<1>, grid, 64, 0, ctx->stream, a);
   else
-    hipLaunchKernelGGL(k_assemble<2>, grid, 64, 0, h->ctx->stream, a);
+    CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, k_assemble<2>, grid, 64, 0, ctx->stream, a);
   check_launch();
+  if (timed) {
+    const double NB = h->NB();
+    ctx->timer.pending.back().work = (double)read_scalar(ctx, cnt.p) * 2.0 * NB * NB * (a.L ? 4.0 : 1.0);
+  }
 }
 
 AsmArgs base_args(camfe_hier h, int d, const Chunks& ch) {

@@ -84,6 +84,65 @@ struct DArr {
   size_t bytes() const { return n * sizeof(T); }
 };
 
+// ------------------------------------------------------ kernel timing
+// Opt-in measurement: launches of the hot kernels are bracketed with HIP
+// events on the launching stream; totals are resolved when read.  Each
+// launch also records its algorithmic work (bytes that the method must move,
+// or flops of the dense contractions).
+enum KernelId { KT_GS = 0, KT_RESIDUAL, KT_SPMV, KT_RESTRICT, KT_PROLONG, KT_COARSE, KT_ASSEMBLE,
+                KT_PAIRS, KT_UF_LINK, KT_SUPPORT_SORT, KT_CG_VEC, KT_COUNT };
+inline const char* kernel_name(int k) {
+  static const char* n[] = {"gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve",
+                            "assemble", "pairs", "uf_link", "support_sort", "cg_vector"};
+  return n[k];
+}
+struct KernelTimer {
+  bool on = false;
+  struct Rec { int k; hipEvent_t a, b; double work; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double total_ms[KT_COUNT] = {0};
+  double work[KT_COUNT] = {0};
+  long long count[KT_COUNT] = {0};
+  hipEvent_t get() {
+    if (pool.empty()) {
+      hipEvent_t e;
+      CAMFE_HIP(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  void begin(int k, hipStream_t s, double w) {
+    Rec r{k, get(), get(), w};
+    CAMFE_HIP(hipEventRecord(r.a, s));
+    pending.push_back(r);
+  }
+  void end(hipStream_t s) { CAMFE_HIP(hipEventRecord(pending.back().b, s)); }
+  void resolve() {
+    for (Rec& r : pending) {
+      CAMFE_HIP(hipEventSynchronize(r.b));
+      float ms = 0;
+      CAMFE_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      total_ms[r.k] += ms;
+      work[r.k] += r.work;
+      count[r.k] += 1;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  void reset() {
+    resolve();
+    for (int i = 0; i < KT_COUNT; ++i) { total_ms[i] = 0; work[i] = 0; count[i] = 0; }
+  }
+  ~KernelTimer() {
+    for (auto& r : pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
 // ---------------------------------------------------------------- context
 }  // namespace camfe
 
@@ -94,6 +153,7 @@ struct camfe_ctx_s {
   camfe::DArr<unsigned char> scratch;  // reused temporary storage (sort/scan)
   camfe::DArr<unsigned char> scratch2;
   int* d_flag = nullptr;               // device error flag
+  camfe::KernelTimer timer;
   unsigned char* scratch_bytes(size_t b) {
     if (scratch.n < b) scratch.alloc(b + (b >> 2) + 256);
     return scratch.p;
@@ -135,6 +195,15 @@ void zero(camfe_ctx ctx, T* p, size_t count) {
 }
 
 inline void check_launch() { CAMFE_HIP(hipGetLastError()); }
+
+// launch with optional event timing; `work` = algorithmic bytes or flops
+#define CAMFE_TIMED(ctx, KID, WORK, ...)                                             \
+  do {                                                                               \
+    const bool t_on_ = (ctx)->timer.on;                                              \
+    if (t_on_) (ctx)->timer.begin((KID), (ctx)->stream, (double)(WORK));             \
+    hipLaunchKernelGGL(__VA_ARGS__);                                                 \
+    if (t_on_) (ctx)->timer.end((ctx)->stream);                                      \
+  } while (0)
 
 inline unsigned grid_for(size_t n, unsigned block) {
   size_t g = (n + block - 1) / block;

@@ -591,9 +591,9 @@ void build_functions(camfe_hier h, int d) {
   if (h->split) {
     hipLaunchKernelGGL(k_uf_init, ge, BLK, 0, ctx->stream, parent.p, (long long)n);
     const double sc = ldexp(1.0, d - h->D);
-    hipLaunchKernelGGL(k_uf_link, ge, BLK, 0, ctx->stream, L.ent.p, (long long)n, cid.p, cstart.p,
-                       (int)L.ncorn, h->F.p, h->U.p, sc, h->degree, h->tri_edge.p, h->edge_ptr.p,
-                       h->edge_tri.p, h->vt_ptr.p, h->vt_tri.p, parent.p);
+    CAMFE_TIMED(ctx, KT_UF_LINK, 0.0, k_uf_link, ge, BLK, 0, ctx->stream, L.ent.p, (long long)n, cid.p, cstart.p,
+                (int)L.ncorn, h->F.p, h->U.p, sc, h->degree, h->tri_edge.p, h->edge_ptr.p, h->edge_tri.p,
+                h->vt_ptr.p, h->vt_tri.p, parent.p);
     check_launch();
     hipLaunchKernelGGL(k_uf_compress, ge, BLK, 0, ctx->stream, parent.p, (long long)n);
   } else {
@@ -712,8 +712,8 @@ void build(camfe_hier h, const double* V, const int32_t* F) {
     exclusive_scan64(ctx, cnt.p, off.p, nt);
     L.npairs = (size_t)(read_scalar(ctx, off.p + nt - 1) + read_scalar(ctx, cnt.p + nt - 1));
     L.pairs.alloc(L.npairs);
-    hipLaunchKernelGGL(k_pairs<true>, g, BLK, 0, ctx->stream, h->U.p, h->F.p, (long long)nt, top, cnt.p, off.p,
-                       L.pairs.p);
+    CAMFE_TIMED(ctx, KT_PAIRS, 0.0, k_pairs<true>, g, BLK, 0, ctx->stream, h->U.p, h->F.p, (long long)nt, top,
+                cnt.p, off.p, L.pairs.p);
     check_launch();
     sort_keys(ctx, L.pairs.p, L.npairs, 3 * D + TRI_BITS);
     count_cells(h, D);
@@ -819,6 +819,33 @@ void camfe_ctx_destroy(camfe_ctx ctx) {
   if (ctx->d_flag) (void)hipFree(ctx->d_flag);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
+}
+
+camfe_status camfe_ctx_kernel_timing(camfe_ctx ctx, int enable) {
+  return guarded([&] {
+    CAMFE_REQUIRE(ctx, CAMFE_EINVAL, "null context");
+    ctx->use_device();
+    if (enable) ctx->timer.reset();
+    else ctx->timer.resolve();
+    ctx->timer.on = enable != 0;
+  });
+}
+
+camfe_status camfe_ctx_kernel_time(camfe_ctx ctx, const char* kernel, double* total_ms, int64_t* launches,
+                                   double* work) {
+  return guarded([&] {
+    CAMFE_REQUIRE(ctx && kernel, CAMFE_EINVAL, "null argument");
+    ctx->use_device();
+    ctx->timer.resolve();
+    for (int k = 0; k < KT_COUNT; ++k)
+      if (std::string(kernel) == kernel_name(k)) {
+        if (total_ms) *total_ms = ctx->timer.total_ms[k];
+        if (launches) *launches = ctx->timer.count[k];
+        if (work) *work = ctx->timer.work[k];
+        return;
+      }
+    throw Error(CAMFE_EINVAL, std::string("unknown kernel name ") + kernel);
+  });
 }
 
 camfe_status camfe_hierarchy_build(camfe_ctx ctx, const double* V, int64_t nv, const int32_t* F, int64_t nt,

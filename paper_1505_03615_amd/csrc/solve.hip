@@ -34,6 +34,8 @@ struct GLevel {
   int ncol = 8;
   std::vector<int> coff;      // colour c owns internal rows [coff[c], coff[c+1])
   std::vector<int> cslice;    // colour c owns slices [cslice[c], cslice[c+1])
+  std::vector<long long> cnnz;  // nonzeros of the rows of each colour
+  long long nnz = 0, pnnz = 0;  // matrix nonzeros; prolongation entries into this depth
   DArr<int> perm, iperm;      // internal -> canonical, canonical -> internal
   size_t nslices = 0, snnz = 0;
   DArr<int> sl_ptr;           // slice offsets into the value arrays (nslices + 1)
@@ -52,6 +54,7 @@ struct GLevel {
 };
 
 struct SolverState {
+  camfe_ctx ctx = nullptr;
   double t = 0;
   int precision = 0;
   double coarse_eps = 0;
@@ -583,6 +586,15 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
     }
   }
   G.cslice[G.ncol] = (int)row0.size();
+  {
+    std::vector<int> hptr(n + 1), hperm(n);
+    copy_out(ctx, hptr.data(), S.ptr.p, n + 1);
+    copy_out(ctx, hperm.data(), G.perm.p, n);
+    G.cnnz.assign(G.ncol, 0);
+    for (int c = 0; c < G.ncol; ++c)
+      for (int r = G.coff[c]; r < G.coff[c + 1]; ++r) G.cnnz[c] += hptr[hperm[r] + 1] - hptr[hperm[r]];
+    G.nnz = hptr[n];
+  }
   G.nslices = row0.size();
   G.sl_row0.alloc(G.nslices);
   G.sl_rows.alloc(G.nslices);
@@ -623,6 +635,7 @@ void setup_transfer(camfe_sys s, SolverState* st, int d) {
   GLevel& Fg = st->lev[d];
   GLevel& Cg = st->lev[d - 1];
   const size_t nf = Fg.n, nc = Cg.n, nnz = H.pnnz;
+  Fg.pnnz = (long long)nnz;
   unsigned g = grid_for(nf, BLK);
   DArr<int> cnt(nf);
   Fg.Pptr.alloc(nf + 1);
@@ -688,6 +701,7 @@ SolverState* setup(camfe_sys s, double t, int precision, double coarse_eps) {
   camfe_ctx ctx = h->ctx;
   auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<SolverState> st(new SolverState());
+  st->ctx = ctx;
   st->t = t;
   st->precision = precision;
   st->coarse_eps = coarse_eps;
@@ -755,70 +769,85 @@ const double* ainv_of<double>(const SolverState* s) { return s->Ainv64.p; }
 template <>
 const float* ainv_of<float>(const SolverState* s) { return s->Ainv32.p; }
 
+// algorithmic bytes of one matrix pass over rows with z nonzeros: matrix
+// values plus read b, read x, write x (or r)
 template <class T, int K>
-void gs_sweep(hipStream_t st, GLevel& G, const T* b, T* x, bool forward) {
+double pass_bytes(long long z, long long rows) {
+  return (double)z * sizeof(T) + 3.0 * (double)rows * K * sizeof(T);
+}
+
+template <class T, int K>
+void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward) {
   for (int ci = 0; ci < G.ncol; ++ci) {
     const int c = forward ? ci : G.ncol - 1 - ci;
     const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
     if (s1 <= s0) continue;
     const long long threads = (long long)(s1 - s0) * SL;
-    hipLaunchKernelGGL((k_gs<T, K>), grid_for(threads, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0,
-                       s1, G.scol.p, sval_of<T>(G), invd_of<T>(G), b, x);
+    CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K>),
+                grid_for(threads, BLK), BLK, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0, s1, G.scol.p,
+                sval_of<T>(G), invd_of<T>(G), b, x);
   }
 }
 
 // One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
 template <class T, int K>
-void vcycle(SolverState* S, hipStream_t st, int d, const T* b, T* x, int nu1, int nu2) {
+void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
   GLevel& G = S->lev[d];
   if (d == S->d0) {
     if (S->direct) {
-      hipLaunchKernelGGL((k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st, ainv_of<T>(S), S->n0, b,
-                         x);
+      const double w = (double)S->n0 * S->n0 * sizeof(T) + 2.0 * S->n0 * K * sizeof(T);
+      CAMFE_TIMED(ctx, KT_COARSE, w, (k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st, ainv_of<T>(S),
+                  S->n0, b, x);
     } else {
-      for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(st, G, b, x, true);
-      for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(st, G, b, x, false);
+      for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(ctx, G, b, x, true);
+      for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(ctx, G, b, x, false);
     }
     return;
   }
-  for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(st, G, b, x, true);
+  for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(ctx, G, b, x, true);
   T* r = Vec<T>::r(G);
-  hipLaunchKernelGGL((k_residual<T, T, K>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p,
-                     G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, sval_of<T>(G), b, (const T*)x, r,
-                     (double*)nullptr);
+  CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
+              grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+              (int)G.nslices, G.scol.p, sval_of<T>(G), b, (const T*)x, r, (double*)nullptr);
   GLevel& C = S->lev[d - 1];
   T* bc = Vec<T>::b(C);
   T* xc = Vec<T>::x(C);
-  hipLaunchKernelGGL((k_restrict<T, K>), grid_for(C.n, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G),
-                     (long long)C.n, (const T*)r, bc);
+  // transfers: parent map (4 B per entry) plus the vectors read and written
+  CAMFE_TIMED(ctx, KT_RESTRICT, (4.0 * G.pnnz + ((double)G.n + C.n) * K * sizeof(T)), (k_restrict<T, K>),
+              grid_for(C.n, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc);
   hipLaunchKernelGGL((k_fill<T>), grid_for(C.n * K, BLK), BLK, 0, st, xc, (long long)(C.n * K), (T)0);
-  vcycle<T, K>(S, st, d - 1, bc, xc, nu1, nu2);
-  hipLaunchKernelGGL((k_prolong<T, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G),
-                     (long long)G.n, (const T*)xc, x);
-  for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(st, G, b, x, false);
+  vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2);
+  CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
+              grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
+  for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(ctx, G, b, x, false);
 }
 
 // z = V(r) at the finest depth (z zeroed first); FP32 cycles convert in and out
 template <int K>
-void precondition(SolverState* S, hipStream_t st, const double* r, double* z, int nu1, int nu2) {
+void precondition(SolverState* S, const double* r, double* z, int nu1, int nu2) {
+  hipStream_t st = S->ctx->stream;
   GLevel& G = S->lev[S->D];
   const long long nk = (long long)G.n * K;
   if (S->precision == 0) {
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, z, nk, 0.0);
-    vcycle<double, K>(S, st, S->D, r, z, nu1, nu2);
+    vcycle<double, K>(S, S->D, r, z, nu1, nu2);
   } else {
     hipLaunchKernelGGL((k_convert<double, float>), grid_for(nk, BLK), BLK, 0, st, r, nk, G.b32.p);
     hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
-    vcycle<float, K>(S, st, S->D, G.b32.p, G.x32.p, nu1, nu2);
+    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2);
     hipLaunchKernelGGL((k_convert<float, double>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, z);
   }
 }
 
 template <int K>
-void residual64(SolverState* S, hipStream_t st, const double* b, const double* x, double* r, double* nrm) {
+void residual64(SolverState* S, const double* b, const double* x, double* r, double* nrm) {
   GLevel& G = S->lev[S->D];
-  hipLaunchKernelGGL((k_residual<double, double, K>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st,
-                     G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm);
+  camfe_ctx ctx = S->ctx;
+  CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<double, K>(G.nnz, (long long)G.n)), (k_residual<double, double, K>),
+              grid_for((size_t)G.nslices * SL, BLK), BLK, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+              (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm);
 }
 
 struct SolveResult {
@@ -850,7 +879,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, X, nk, 0.0);
   hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc, (long long)(8 * KMAXS), 0.0);
   hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)B, (const double*)B, sc + 4 * K);
-  residual64<K>(S, st, B, X, R, sc + 2 * K);
+  residual64<K>(S, B, X, R, sc + 2 * K);
   check_launch();
   double hb[3 * KMAXS];
   copy_out(ctx, hb, sc + 2 * K, 3 * K);   // rr[K], rz_new[K], bb[K]
@@ -871,10 +900,10 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   if (o.method == 1) {
     // stationary: x += V(b - A x)
     while (res.rel > o.rtol && res.it < o.max_iter) {
-      precondition<K>(S, st, R, Z, nu1, nu2);
+      precondition<K>(S, R, Z, nu1, nu2);
       hipLaunchKernelGGL(k_axpy_inplace<K>, gnk, BLK, 0, st, (long long)n, X, (const double*)Z);
       hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
-      residual64<K>(S, st, B, X, R, sc + 2 * K);
+      residual64<K>(S, B, X, R, sc + 2 * K);
       check_launch();
       double rr[KMAXS];
       copy_out(ctx, rr, sc + 2 * K, K);
@@ -886,16 +915,17 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     }
   } else if (res.rel > o.rtol) {
     // conjugate gradients preconditioned by one V-cycle
-    precondition<K>(S, st, R, Z, nu1, nu2);
+    precondition<K>(S, R, Z, nu1, nu2);
     ++res.cycles;
     hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)Z, nk, P);
     hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)R, (const double*)Z, sc);
     while (res.it < o.max_iter) {
       hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + K, (long long)(2 * K), 0.0);
-      hipLaunchKernelGGL(k_spmv_dot<K>, grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p,
-                         G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)P, Q, sc + K);
-      hipLaunchKernelGGL(k_cg_update<K>, gn, BLK, 0, st, (long long)n, (const double*)sc, X, R, (const double*)P,
-                         (const double*)Q, sc + 2 * K);
+      CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>,
+                  grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+                  (int)G.nslices, G.scol.p, G.sval64.p, (const double*)P, Q, sc + K);
+      CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, gn, BLK, 0, st, (long long)n,
+                  (const double*)sc, X, R, (const double*)P, (const double*)Q, sc + 2 * K);
       check_launch();
       double rr[KMAXS];
       copy_out(ctx, rr, sc + 2 * K, K);
@@ -903,7 +933,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
       ++res.it;
       res.rel = relmax(rr);
       if (res.rel <= o.rtol || !std::isfinite(res.rel)) break;
-      precondition<K>(S, st, R, Z, nu1, nu2);
+      precondition<K>(S, R, Z, nu1, nu2);
       ++res.cycles;
       hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 3 * K, (long long)K, 0.0);
       hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)R, (const double*)Z, sc + 3 * K);
@@ -913,7 +943,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     }
     // true residual of the final iterate
     hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
-    residual64<K>(S, st, B, X, R, sc + 2 * K);
+    residual64<K>(S, B, X, R, sc + 2 * K);
     double rr[KMAXS];
     copy_out(ctx, rr, sc + 2 * K, K);
     ctx->sync();

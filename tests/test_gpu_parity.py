@@ -136,9 +136,9 @@ def test_solve_residual(cf, ctx, name, precision, method):
     t = 1e-4 if name == "knot" else 1e-3
     b = o.load_vector(c["f"])
     # the restricted quadratic space is nearly rank-deficient on flat facets
-    # and converges slowly; its bar is a looser tolerance
-    rtol = 1e-8 if c["degree"] == 1 else 1e-5
-    iters = 600 if method == 0 else 60
+    # and needs several hundred iterations
+    rtol = 1e-8
+    iters = (600 if c["degree"] == 1 else 1500) if method == 0 else 60
     say(f"[gpu] solve {name} precision={precision} method={method}")
     x, st = cf.camfe_solve(s, b, t=t, rtol=rtol if method == 0 else 1e-30, max_iter=iters,
                            precision=precision, method=method)

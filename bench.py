@@ -68,7 +68,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="two_sheets_256_depth8", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -89,8 +88,9 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = cf.camfe_ctx_create(0, stream)
 
-    def step(record):
-        ph = {}
+    keep = {}
+
+    def step(record, keep_last=False):
         t0 = time.perf_counter()
         h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=2048)
         t1 = time.perf_counter()
@@ -107,36 +107,33 @@ def main():
         if record is not None:
             record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve64=t4 - t3, solve32=t5 - t4,
                                st64=st64, st32=st32, n=n, levels=(fin, d0)))
-        cf.camfe_system_destroy(s)
-        cf.camfe_hierarchy_destroy(h)
+        if keep_last:
+            keep["h"], keep["s"] = h, s
+        else:
+            cf.camfe_system_destroy(s)
+            cf.camfe_hierarchy_destroy(h)
 
     log(f"[bench] warmup {args.warmup}")
-    # the first warm-up step also finds the kernel with the largest event time
-    dominant = None
+    # the first warm-up step runs with per-launch event timing (every launch
+    # bracketed, so host gaps inflate small kernels) to rank the kernels
+    ranking = {}
     for i in range(args.warmup):
-        if i == 0 and not args.no_kernel_timing:
+        if i == 0:
             cf.camfe_ctx_kernel_timing(ctx, True)
         step(None)
-        if i == 0 and not args.no_kernel_timing:
-            times = {k: cf.camfe_ctx_kernel_time(ctx, k) for k in cf.KERNELS}
+        if i == 0:
+            ranking = {k: cf.camfe_ctx_kernel_time(ctx, k) for k in cf.KERNELS}
             cf.camfe_ctx_kernel_timing(ctx, False)
-            dominant = max(times, key=lambda k: times[k][0])
             log("[bench] kernel event times (ms): " +
-                ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in sorted(times.items(), key=lambda kv: -kv[1][0])))
-    if not args.no_kernel_timing:
-        cf.camfe_ctx_kernel_timing(ctx, True)
+                ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in sorted(ranking.items(), key=lambda kv: -kv[1][0])))
     rec = []
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(rec)
+    for i in range(args.steps):
+        step(rec, keep_last=(i == args.steps - 1))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kern = {}
-    if not args.no_kernel_timing:
-        kern = {k: cf.camfe_ctx_kernel_time(ctx, k) for k in cf.KERNELS}
-        cf.camfe_ctx_kernel_timing(ctx, False)
     ms = (t1 - t0) * 1000.0 / args.steps
     n = rec[0]["n"]
     cyc64 = np.mean([r["st64"]["cycles"] for r in rec])
@@ -169,21 +166,26 @@ def main():
         "rel_residual": {"plain_fp64": float(max(r["st64"]["rel_residual"] for r in rec)),
                          "mixed_fp32_fp64": float(max(r["st32"]["rel_residual"] for r in rec))},
     }
-    if kern:
-        out["kernel_event_ms_per_step"] = {k: v[0] / args.steps for k, v in kern.items() if v[1]}
-        dom = max(kern, key=lambda k: kern[k][0])
-        tot_ms, launches, work = kern[dom]
+    if ranking:
+        out["kernel_event_ms_warmup"] = {k: v[0] for k, v in ranking.items() if v[1]}
+        dom = max(ranking, key=lambda k: ranking[k][0])
         if dom == "assemble":
+            tot_ms, launches, work = ranking[dom]
             achieved = work / (tot_ms / 1000.0) / 1e12
             out["roofline"] = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                               "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                               "launches": launches, "avg_launch_us": 1000.0 * tot_ms / launches}
+                               "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
         else:
-            achieved = work / (tot_ms / 1000.0) / 1e9
-            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS,
-                               "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                               "launches": launches, "avg_launch_us": 1000.0 * tot_ms / launches,
-                               "bytes_per_launch": work / launches}
+            meas = dom if dom in ("gs_colour", "residual", "spmv_dot") else "gs_colour"
+            avg64, by64 = cf.camfe_measure_kernel(keep["s"], meas, 0, 50)
+            avg32, by32 = cf.camfe_measure_kernel(keep["s"], meas, 1, 50)
+            achieved = by64 / (avg64 / 1000.0) / 1e9
+            out["roofline"] = {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved,
+                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                               "traffic": None, "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
+                               "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
+                                        "bytes_per_launch": by32}}
+    cf.camfe_system_destroy(keep["s"])
+    cf.camfe_hierarchy_destroy(keep["h"])
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         bb = torch.empty_like(a)

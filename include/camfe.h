@@ -176,6 +176,16 @@ typedef struct {
  * with stats filled when max_iter is reached above rtol. */
 camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double *b, int k,
                          double *x, camfe_solve_stats *stats);
+/* Measurement of one finest-depth kernel of a solved system (the solver state
+ * of the last camfe_solve call): "gs_colour" (one forward Gauss-Seidel sweep,
+ * one launch per colour), "residual" or "spmv_dot", with FP64 (precision 0) or
+ * FP32 (1) values, one right-hand side.  reps back-to-back sweeps/launches are
+ * captured once into a HIP graph and replayed between two HIP events on the
+ * context's stream.  avg_ms: average time of one launch; bytes_per_launch: the
+ * algorithmic bytes of one launch (matrix values + three vector accesses per
+ * row).  Overwrites the solver's scratch vectors only. */
+camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision, int reps, double *avg_ms,
+                                  double *bytes_per_launch);
 void camfe_system_destroy(camfe_sys s);
 
 #ifdef __cplusplus

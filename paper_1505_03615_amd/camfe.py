@@ -25,7 +25,7 @@ EXPORTS = [
     "camfe_export_functions", "camfe_export_support_entries", "camfe_export_prolongation",
     "camfe_hierarchy_destroy", "camfe_assemble", "camfe_reassemble_mass", "camfe_export_matrix",
     "camfe_load_vector", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
-    "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time",
+    "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time", "camfe_measure_kernel",
 ]
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
            "uf_link", "support_sort", "cg_vector"]
@@ -89,6 +89,7 @@ def load():
         "camfe_system_destroy": (None, [H]),
         "camfe_ctx_kernel_timing": (I, [H, I]),
         "camfe_ctx_kernel_time": (I, [H, C.c_char_p, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
+        "camfe_measure_kernel": (I, [H, C.c_char_p, I, I, C.POINTER(D), C.POINTER(D)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -321,6 +322,13 @@ def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0,
     stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
     stats["converged"] = code == 0
     return x, stats
+
+
+def camfe_measure_kernel(s, kernel: str, precision: int = 0, reps: int = 50):
+    """(average ms per launch, algorithmic bytes per launch) of a finest-depth kernel."""
+    ms, by = C.c_double(), C.c_double()
+    _check(load().camfe_measure_kernel(s, kernel.encode(), precision, reps, C.byref(ms), C.byref(by)))
+    return ms.value, by.value
 
 
 def camfe_system_destroy(s):

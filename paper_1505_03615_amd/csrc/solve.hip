@@ -17,6 +17,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <functional>
+#include <string>
+#include <map>
 
 #include "internal.hpp"
 
@@ -68,6 +71,13 @@ struct SolverState {
   DArr<double> X, R, Z, P, Q, B;
   DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
   double setup_seconds = 0;
+  // captured iterations (one graph per right-hand-side count / precision / sweeps / method)
+  hipStream_t cap = nullptr;
+  std::map<long long, hipGraphExec_t> graphs;
+  ~SolverState() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
 };
 
 void destroy_solver(SolverState* s) { delete s; }
@@ -855,6 +865,79 @@ struct SolveResult {
   double rel = 0;
 };
 
+// Record `enqueue` into a graph once (keyed), replay it on the context stream.
+// Capture runs on a private stream (the context stream may be the legacy
+// default stream, which cannot be captured) with the timer off.
+void run_graph(SolverState* S, long long key, const std::function<void()>& enqueue) {
+  camfe_ctx ctx = S->ctx;
+  auto it = S->graphs.find(key);
+  if (it == S->graphs.end()) {
+    if (!S->cap) CAMFE_HIP(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
+    hipStream_t saved = ctx->stream;
+    const bool saved_on = ctx->timer.on;
+    ctx->stream = S->cap;
+    ctx->timer.on = false;
+    hipGraph_t graph = nullptr;
+    CAMFE_HIP(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue();
+    } catch (...) {
+      (void)hipStreamEndCapture(S->cap, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      ctx->stream = saved;
+      ctx->timer.on = saved_on;
+      throw;
+    }
+    CAMFE_HIP(hipStreamEndCapture(S->cap, &graph));
+    ctx->stream = saved;
+    ctx->timer.on = saved_on;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    CAMFE_HIP(e);
+    it = S->graphs.emplace(key, ex).first;
+  }
+  CAMFE_HIP(hipGraphLaunch(it->second, ctx->stream));
+}
+
+// One CG step: q = A p, x += alpha p, r -= alpha q (||r||^2 into rr), z = V(r),
+// p = z + beta p.  All scalars stay on the device.
+template <int K>
+void cg_step(SolverState* S, int nu1, int nu2) {
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  GLevel& G = S->lev[S->D];
+  const size_t n = G.n;
+  unsigned gn = grid_for(n, BLK);
+  double* sc = S->sc.p;
+  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + K, (long long)(2 * K), 0.0);
+  CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, grid_for((size_t)G.nslices * SL, BLK),
+              BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              (const double*)S->P.p, S->Q.p, sc + K);
+  CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, gn, BLK, 0, st, (long long)n, (const double*)sc,
+              S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, sc + 2 * K);
+  precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
+  st = ctx->stream;
+  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 3 * K, (long long)K, 0.0);
+  hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)S->R.p, (const double*)S->Z.p, sc + 3 * K);
+  hipLaunchKernelGGL(k_cg_direction<K>, gn, BLK, 0, st, (long long)n, (const double*)sc, (const double*)(sc + 3 * K),
+                     (const double*)S->Z.p, S->P.p);
+  hipLaunchKernelGGL(k_copy_scalars, 1, 64, 0, st, (const double*)(sc + 3 * K), sc, K);
+}
+
+// One stationary step: x += V(b - A x); r = b - A x (||r||^2 into rr)
+template <int K>
+void stationary_step(SolverState* S, int nu1, int nu2) {
+  camfe_ctx ctx = S->ctx;
+  GLevel& G = S->lev[S->D];
+  const long long nk = (long long)G.n * K;
+  precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_axpy_inplace<K>, grid_for(nk, BLK), BLK, 0, st, (long long)G.n, S->X.p, (const double*)S->Z.p);
+  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, S->sc.p + 2 * K, (long long)K, 0.0);
+  residual64<K>(S, S->B.p, S->X.p, S->R.p, S->sc.p + 2 * K);
+}
+
 // Solve columns [c0, c0 + K) of the problem (device canonical b, x col-major)
 template <int K>
 SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, const double* db, double* dx, int kk,
@@ -865,26 +948,20 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   const size_t n = G.n;
   const long long nk = (long long)n * K;
   unsigned gn = grid_for(n, BLK), gnk = grid_for(nk, BLK);
-  double* B = S->B.p;
-  double* X = S->X.p;
-  double* R = S->R.p;
-  double* Z = S->Z.p;
-  double* P = S->P.p;
-  double* Q = S->Q.p;
   double* sc = S->sc.p;   // rz[K] pq[K] rr[K] rzn[K] bb[K]
-  hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, db, (long long)n, c0, kk, G.iperm.p, B);
+  hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, db, (long long)n, c0, kk, G.iperm.p, S->B.p);
   if (o.x0_given)
-    hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, (const double*)dx, (long long)n, c0, kk, G.iperm.p, X);
+    hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, (const double*)dx, (long long)n, c0, kk, G.iperm.p, S->X.p);
   else
-    hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, X, nk, 0.0);
+    hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->X.p, nk, 0.0);
   hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc, (long long)(8 * KMAXS), 0.0);
-  hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)B, (const double*)B, sc + 4 * K);
-  residual64<K>(S, B, X, R, sc + 2 * K);
+  hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)S->B.p, (const double*)S->B.p, sc + 4 * K);
+  residual64<K>(S, S->B.p, S->X.p, S->R.p, sc + 2 * K);
   check_launch();
   double hb[3 * KMAXS];
   copy_out(ctx, hb, sc + 2 * K, 3 * K);   // rr[K], rz_new[K], bb[K]
-  ctx->sync();
   double bn[KMAXS];
+  for (int c = 0; c < K; ++c) bn[c] = std::sqrt(hb[2 * K + c]);
   auto relmax = [&](const double* rr) {
     double m = 0;
     for (int c = 0; c < K && c0 + c < kk; ++c) {
@@ -893,63 +970,56 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     }
     return m;
   };
-  for (int c = 0; c < K; ++c) bn[c] = std::sqrt(hb[2 * K + c]);
   SolveResult res;
   res.rel = relmax(hb);
   const int nu1 = o.nu_pre, nu2 = o.nu_post;
+  // captured steps are replayed `check_every` times between convergence checks
+  const bool use_graph = !ctx->timer.on;
+  const int check_every = 4;
+  const long long gkey = ((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method;
+  auto run_steps = [&](int m, bool cg) {
+    for (int i = 0; i < m; ++i) {
+      if (use_graph)
+        run_graph(S, gkey, [&] { if (cg) cg_step<K>(S, nu1, nu2); else stationary_step<K>(S, nu1, nu2); });
+      else if (cg)
+        cg_step<K>(S, nu1, nu2);
+      else
+        stationary_step<K>(S, nu1, nu2);
+    }
+    check_launch();
+    double rr[KMAXS];
+    copy_out(ctx, rr, sc + 2 * K, K);
+    return relmax(rr);
+  };
   if (o.method == 1) {
-    // stationary: x += V(b - A x)
     while (res.rel > o.rtol && res.it < o.max_iter) {
-      precondition<K>(S, R, Z, nu1, nu2);
-      hipLaunchKernelGGL(k_axpy_inplace<K>, gnk, BLK, 0, st, (long long)n, X, (const double*)Z);
-      hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
-      residual64<K>(S, B, X, R, sc + 2 * K);
-      check_launch();
-      double rr[KMAXS];
-      copy_out(ctx, rr, sc + 2 * K, K);
-      ctx->sync();
-      ++res.it;
-      ++res.cycles;
-      res.rel = relmax(rr);
+      const int m = std::min(check_every, o.max_iter - res.it);
+      res.rel = run_steps(m, false);
+      res.it += m;
+      res.cycles += m;
       if (!std::isfinite(res.rel)) break;
     }
-  } else if (res.rel > o.rtol) {
+  } else if (res.rel > o.rtol && o.max_iter > 0) {
     // conjugate gradients preconditioned by one V-cycle
-    precondition<K>(S, R, Z, nu1, nu2);
+    precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
     ++res.cycles;
-    hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)Z, nk, P);
-    hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)R, (const double*)Z, sc);
+    hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)S->Z.p, nk, S->P.p);
+    hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)S->R.p, (const double*)S->Z.p, sc);
     while (res.it < o.max_iter) {
-      hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + K, (long long)(2 * K), 0.0);
-      CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>,
-                  grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
-                  (int)G.nslices, G.scol.p, G.sval64.p, (const double*)P, Q, sc + K);
-      CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, gn, BLK, 0, st, (long long)n,
-                  (const double*)sc, X, R, (const double*)P, (const double*)Q, sc + 2 * K);
-      check_launch();
-      double rr[KMAXS];
-      copy_out(ctx, rr, sc + 2 * K, K);
-      ctx->sync();
-      ++res.it;
-      res.rel = relmax(rr);
+      const int m = std::min(check_every, o.max_iter - res.it);
+      res.rel = run_steps(m, true);
+      res.it += m;
+      res.cycles += m;
       if (res.rel <= o.rtol || !std::isfinite(res.rel)) break;
-      precondition<K>(S, R, Z, nu1, nu2);
-      ++res.cycles;
-      hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 3 * K, (long long)K, 0.0);
-      hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)R, (const double*)Z, sc + 3 * K);
-      hipLaunchKernelGGL(k_cg_direction<K>, gn, BLK, 0, st, (long long)n, (const double*)sc,
-                         (const double*)(sc + 3 * K), (const double*)Z, P);
-      hipLaunchKernelGGL(k_copy_scalars, 1, 64, 0, st, (const double*)(sc + 3 * K), sc, K);
     }
     // true residual of the final iterate
     hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
-    residual64<K>(S, B, X, R, sc + 2 * K);
+    residual64<K>(S, S->B.p, S->X.p, S->R.p, sc + 2 * K);
     double rr[KMAXS];
     copy_out(ctx, rr, sc + 2 * K, K);
-    ctx->sync();
     res.rel = relmax(rr);
   }
-  hipLaunchKernelGGL(k_scatter_out<K>, gn, BLK, 0, st, (const double*)X, (long long)n, c0, kk, G.iperm.p, dx);
+  hipLaunchKernelGGL(k_scatter_out<K>, gn, BLK, 0, st, (const double*)S->X.p, (long long)n, c0, kk, G.iperm.p, dx);
   check_launch();
   return res;
 }
@@ -960,6 +1030,79 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
 using namespace camfe;
 
 extern "C" {
+
+camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision, int reps, double* avg_ms,
+                                  double* bytes_per_launch) {
+  return guarded([&] {
+    CAMFE_REQUIRE(s && kernel && reps > 0 && (precision == 0 || precision == 1), CAMFE_EINVAL, "bad argument");
+    SolverState* S = s->solver;
+    CAMFE_REQUIRE(S, CAMFE_ESTATE, "no solver state: call camfe_solve first");
+    camfe_ctx ctx = s->h->ctx;
+    ctx->use_device();
+    GLevel& G = S->lev[S->D];
+    const std::string name(kernel);
+    int kid = -1;
+    if (name == "gs_colour") kid = 0;
+    else if (name == "residual") kid = 1;
+    else if (name == "spmv_dot") kid = 2;
+    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL, "measurable kernels: gs_colour, residual, spmv_dot");
+    const long long nk = (long long)G.n;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.b64.p, nk, 1.0);
+    hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.x64.p, nk, 0.0);
+    hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.b32.p, nk, 1.0f);
+    hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
+    double launches = 0, bytes = 0;
+    auto enqueue = [&] {
+      for (int r = 0; r < reps; ++r) {
+        if (kid == 0) {
+          if (precision == 0) gs_sweep<double, 1>(ctx, G, G.b64.p, G.x64.p, true);
+          else gs_sweep<float, 1>(ctx, G, G.b32.p, G.x32.p, true);
+        } else if (kid == 1) {
+          if (precision == 0)
+            hipLaunchKernelGGL((k_residual<double, double, 1>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0,
+                               ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p,
+                               G.sval64.p, (const double*)G.b64.p, (const double*)G.x64.p, G.r64.p, (double*)nullptr);
+          else
+            hipLaunchKernelGGL((k_residual<float, float, 1>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0,
+                               ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p,
+                               G.sval32.p, (const float*)G.b32.p, (const float*)G.x32.p, G.r32.p, (double*)nullptr);
+        } else {
+          hipLaunchKernelGGL(k_spmv_dot<1>, grid_for((size_t)G.nslices * SL, BLK), BLK, 0, ctx->stream, G.sl_ptr.p,
+                             G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p,
+                             G.r64.p, S->sc.p);
+        }
+      }
+    };
+    for (int c = 0; c < G.ncol; ++c) {
+      if (kid == 0) {
+        if (G.cslice[c + 1] > G.cslice[c]) {
+          launches += 1;
+          bytes += precision == 0 ? pass_bytes<double, 1>(G.cnnz[c], G.coff[c + 1] - G.coff[c])
+                                  : pass_bytes<float, 1>(G.cnnz[c], G.coff[c + 1] - G.coff[c]);
+        }
+      }
+    }
+    if (kid == 1) { launches = 1; bytes = precision == 0 ? pass_bytes<double, 1>(G.nnz, nk) : pass_bytes<float, 1>(G.nnz, nk); }
+    if (kid == 2) { launches = 1; bytes = (double)G.nnz * 8 + 2.0 * nk * 8; }
+    const long long key = -1 - (((long long)kid * 2 + precision) << 20) - reps;
+    run_graph(S, key, enqueue);   // instantiate and warm
+    ctx->sync();
+    hipEvent_t e0, e1;
+    CAMFE_HIP(hipEventCreate(&e0));
+    CAMFE_HIP(hipEventCreate(&e1));
+    CAMFE_HIP(hipEventRecord(e0, ctx->stream));
+    run_graph(S, key, enqueue);
+    CAMFE_HIP(hipEventRecord(e1, ctx->stream));
+    CAMFE_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    CAMFE_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (avg_ms) *avg_ms = ms / (reps * launches);
+    if (bytes_per_launch) *bytes_per_launch = bytes / launches;
+  });
+}
 
 camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b, int k, double* x,
                          camfe_solve_stats* stats) {

@@ -302,59 +302,92 @@ __device__ inline long long xcd_block(long long b, long long nb) {
   return i < lim ? base + i : b;   // remainder blocks keep their index
 }
 
+// Each 64-row slice is processed by SW wavefronts: wavefront w takes the
+// slice's entry columns j = w, w + SW, ... (each load instruction still reads
+// one contiguous 64-entry segment), first issuing all of its value/column
+// loads, then the gathers of x; partial row sums meet in LDS.  This gives a
+// colour pass of n/8 rows enough memory-level parallelism to hide latency.
+constexpr int SW = 8;          // wavefronts per slice
+constexpr int MU = 4;          // entries per lane issued together
+
 template <class T, int K>
-__global__ __launch_bounds__(BLK) void k_gs(const int* sl_ptr, const int* row0, const int* rows, int s_begin,
-                                            int s_end, const int* scol, const T* sval, const T* invd, const T* b,
-                                            T* x) {
-  long long blocks = ((long long)(s_end - s_begin) * SL + BLK - 1) / BLK;
-  long long bid = xcd_block(blockIdx.x, blocks);
-  long long g = bid * BLK + threadIdx.x;
-  long long s = s_begin + g / SL;
-  int lane = (int)(g % SL);
-  if (s >= s_end || lane >= rows[s]) return;
-  const int i = row0[s] + lane;
-  const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
-  const long long base = sl_ptr[s] + lane;
-  T acc[K];
+__device__ inline void slice_row_dot(const int* sl_ptr, long long s, int lane, int sub, bool active, const int* scol,
+                                     const T* sval, const T* x, T acc[K]) {
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0;
-  for (int j = 0; j < w; ++j) {
-    const T a = sval[base + (long long)j * SL];
-    const int c = scol[base + (long long)j * SL];
+  if (!active) return;
+  const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
+  const long long base = sl_ptr[s] + lane;
+  for (int j0 = sub; j0 < w; j0 += SW * MU) {
+    T a[MU];
+    int c[MU];
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = fma(a, x[(long long)c * K + q], acc[q]);
+    for (int m = 0; m < MU; ++m) {
+      const int j = j0 + SW * m;
+      a[m] = j < w ? sval[base + (long long)j * SL] : (T)0;
+      c[m] = j < w ? scol[base + (long long)j * SL] : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < MU; ++m)
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] = fma(a[m], x[(long long)c[m] * K + q], acc[q]);
   }
-  const T di = invd[i];
+}
+
+// sum of the SW partial sums of each row (valid in wavefront 0 after return)
+template <class T, int K>
+__device__ inline void slice_reduce(T (*red)[K][SL], int lane, int sub, T acc[K]) {
 #pragma unroll
-  for (int q = 0; q < K; ++q) x[(long long)i * K + q] += (b[(long long)i * K + q] - acc[q]) * di;
+  for (int q = 0; q < K; ++q) red[sub][q][lane] = acc[q];
+  __syncthreads();
+  if (sub == 0) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      T s = red[0][q][lane];
+#pragma unroll
+      for (int w = 1; w < SW; ++w) s += red[w][q][lane];
+      acc[q] = s;
+    }
+  }
+}
+
+template <class T, int K>
+__global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* row0, const int* rows, int s_begin,
+                                                int s_end, const int* scol, const T* sval, const T* invd, const T* b,
+                                                T* x) {
+  __shared__ T red[SW][K][SL];
+  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
+  const long long s = s_begin + xcd_block(blockIdx.x, s_end - s_begin);
+  const bool active = lane < rows[s];
+  T acc[K];
+  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
+  slice_reduce<T, K>(red, lane, sub, acc);
+  if (sub == 0 && active) {
+    const int i = row0[s] + lane;
+    const T di = invd[i];
+#pragma unroll
+    for (int q = 0; q < K; ++q) x[(long long)i * K + q] += (b[(long long)i * K + q] - acc[q]) * di;
+  }
 }
 
 // r = b - A x over all slices; with nrm != null also accumulate ||r||^2 per column
 template <class T, class TR, int K>
-__global__ __launch_bounds__(BLK) void k_residual(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                  const int* scol, const T* sval, const TR* b, const T* x, TR* r,
-                                                  double* nrm) {
-  long long blocks = ((long long)ns * SL + BLK - 1) / BLK;
-  long long bid = xcd_block(blockIdx.x, blocks);
-  long long g = bid * BLK + threadIdx.x;
-  long long s = g / SL;
-  int lane = (int)(g % SL);
+__global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const int* row0, const int* rows, int ns,
+                                                      const int* scol, const T* sval, const TR* b, const T* x, TR* r,
+                                                      double* nrm) {
+  __shared__ T red[SW][K][SL];
+  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
+  const long long s = xcd_block(blockIdx.x, ns);
+  const bool active = lane < rows[s];
+  T acc[K];
+  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
+  slice_reduce<T, K>(red, lane, sub, acc);
+  if (sub != 0) return;
   double loc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) loc[q] = 0.0;
-  if (s < ns && lane < rows[s]) {
+  if (active) {
     const int i = row0[s] + lane;
-    const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
-    const long long base = sl_ptr[s] + lane;
-    T acc[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = 0;
-    for (int j = 0; j < w; ++j) {
-      const T a = sval[base + (long long)j * SL];
-      const int c = scol[base + (long long)j * SL];
-#pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fma(a, x[(long long)c * K + q], acc[q]);
-    }
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       TR v = b[(long long)i * K + q] - (TR)acc[q];
@@ -367,37 +400,29 @@ __global__ __launch_bounds__(BLK) void k_residual(const int* sl_ptr, const int* 
     for (int q = 0; q < K; ++q) {
       double v = loc[q];
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if ((threadIdx.x & 63) == 0) atomicAdd(nrm + q, v);
+      if (lane == 0) atomicAdd(nrm + q, v);
     }
   }
 }
 
 // y = A p (FP64) and pq += p . y per column
 template <int K>
-__global__ __launch_bounds__(BLK) void k_spmv_dot(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                  const int* scol, const double* sval, const double* p, double* y,
-                                                  double* dot) {
-  long long blocks = ((long long)ns * SL + BLK - 1) / BLK;
-  long long bid = xcd_block(blockIdx.x, blocks);
-  long long g = bid * BLK + threadIdx.x;
-  long long s = g / SL;
-  int lane = (int)(g % SL);
+__global__ __launch_bounds__(SL * SW) void k_spmv_dot(const int* sl_ptr, const int* row0, const int* rows, int ns,
+                                                      const int* scol, const double* sval, const double* p, double* y,
+                                                      double* dot) {
+  __shared__ double red[SW][K][SL];
+  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
+  const long long s = xcd_block(blockIdx.x, ns);
+  const bool active = lane < rows[s];
+  double acc[K];
+  slice_row_dot<double, K>(sl_ptr, s, lane, sub, active, scol, sval, p, acc);
+  slice_reduce<double, K>(red, lane, sub, acc);
+  if (sub != 0) return;
   double loc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) loc[q] = 0.0;
-  if (s < ns && lane < rows[s]) {
+  if (active) {
     const int i = row0[s] + lane;
-    const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
-    const long long base = sl_ptr[s] + lane;
-    double acc[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = 0;
-    for (int j = 0; j < w; ++j) {
-      const double a = sval[base + (long long)j * SL];
-      const int c = scol[base + (long long)j * SL];
-#pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fma(a, p[(long long)c * K + q], acc[q]);
-    }
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       y[(long long)i * K + q] = acc[q];
@@ -408,7 +433,7 @@ __global__ __launch_bounds__(BLK) void k_spmv_dot(const int* sl_ptr, const int* 
   for (int q = 0; q < K; ++q) {
     double v = loc[q];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) atomicAdd(dot + q, v);
+    if (lane == 0) atomicAdd(dot + q, v);
   }
 }
 
@@ -792,9 +817,8 @@ void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward) {
     const int c = forward ? ci : G.ncol - 1 - ci;
     const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
     if (s1 <= s0) continue;
-    const long long threads = (long long)(s1 - s0) * SL;
     CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K>),
-                grid_for(threads, BLK), BLK, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0, s1, G.scol.p,
+                (unsigned)(s1 - s0), SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0, s1, G.scol.p,
                 sval_of<T>(G), invd_of<T>(G), b, x);
   }
 }
@@ -819,7 +843,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(ctx, G, b, x, true);
   T* r = Vec<T>::r(G);
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
-              grid_for((size_t)G.nslices * SL, BLK), BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+              (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
               (int)G.nslices, G.scol.p, sval_of<T>(G), b, (const T*)x, r, (double*)nullptr);
   GLevel& C = S->lev[d - 1];
   T* bc = Vec<T>::b(C);
@@ -856,7 +880,7 @@ void residual64(SolverState* S, const double* b, const double* x, double* r, dou
   GLevel& G = S->lev[S->D];
   camfe_ctx ctx = S->ctx;
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<double, K>(G.nnz, (long long)G.n)), (k_residual<double, double, K>),
-              grid_for((size_t)G.nslices * SL, BLK), BLK, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+              (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
               (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm);
 }
 
@@ -911,8 +935,8 @@ void cg_step(SolverState* S, int nu1, int nu2) {
   unsigned gn = grid_for(n, BLK);
   double* sc = S->sc.p;
   hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + K, (long long)(2 * K), 0.0);
-  CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, grid_for((size_t)G.nslices * SL, BLK),
-              BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
+  CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices,
+              SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
               (const double*)S->P.p, S->Q.p, sc + K);
   CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, gn, BLK, 0, st, (long long)n, (const double*)sc,
               S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, sc + 2 * K);
@@ -1060,15 +1084,15 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
           else gs_sweep<float, 1>(ctx, G, G.b32.p, G.x32.p, true);
         } else if (kid == 1) {
           if (precision == 0)
-            hipLaunchKernelGGL((k_residual<double, double, 1>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0,
+            hipLaunchKernelGGL((k_residual<double, double, 1>), (unsigned)G.nslices, SL * SW, 0,
                                ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p,
                                G.sval64.p, (const double*)G.b64.p, (const double*)G.x64.p, G.r64.p, (double*)nullptr);
           else
-            hipLaunchKernelGGL((k_residual<float, float, 1>), grid_for((size_t)G.nslices * SL, BLK), BLK, 0,
+            hipLaunchKernelGGL((k_residual<float, float, 1>), (unsigned)G.nslices, SL * SW, 0,
                                ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p,
                                G.sval32.p, (const float*)G.b32.p, (const float*)G.x32.p, G.r32.p, (double*)nullptr);
         } else {
-          hipLaunchKernelGGL(k_spmv_dot<1>, grid_for((size_t)G.nslices * SL, BLK), BLK, 0, ctx->stream, G.sl_ptr.p,
+          hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p,
                              G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p,
                              G.r64.p, S->sc.p);
         }

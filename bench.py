@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="two_sheets_256_depth8", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-coarse", type=int, default=512,
+                    help="coarsest depth = finest with at most this many functions (solved directly)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -92,7 +94,8 @@ def main():
 
     def step(record, keep_last=False):
         t0 = time.perf_counter()
-        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=2048)
+        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"],
+                                     max_coarse=args.max_coarse)
         t1 = time.perf_counter()
         s = cf.camfe_assemble(h)
         t2 = time.perf_counter()
@@ -157,7 +160,7 @@ def main():
         "config": {"workload": "two parallel unit squares 1/256 apart, 2 x 256 x 256 split quads "
                                "(262,144 tris), rotated to general position, octree depth 8, degree 1, "
                                "split, t=1e-3, RHS +-sin(40 pi x)",
-                   "dof_finest": int(n), "levels": list(rec[0]["levels"])},
+                   "dof_finest": int(n), "levels": list(rec[0]["levels"]), "max_coarse": args.max_coarse},
         "phases_ms": phases,
         "solve_to_1e-8_ms": {"plain_fp64": 1000.0 * solve64, "mixed_fp32_fp64": 1000.0 * solve32,
                              "learned": None},

@@ -70,6 +70,7 @@ struct SolverState {
   // outer iteration vectors (finest, internal order, n x KMAXS row-major)
   DArr<double> X, R, Z, P, Q, B;
   DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
+  DArr<double> part;         // per-block partial sums of the reductions
   double setup_seconds = 0;
   // captured iterations (one graph per right-hand-side count / precision / sweeps / method)
   hipStream_t cap = nullptr;
@@ -395,12 +396,12 @@ __global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const i
       loc[q] = (double)v * (double)v;
     }
   }
-  if (nrm) {
+  if (nrm) {   // per-block partial sums of ||r||^2, reduced by k_finalize
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       double v = loc[q];
       for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if (lane == 0) atomicAdd(nrm + q, v);
+      if (lane == 0) nrm[(long long)blockIdx.x * K + q] = v;
     }
   }
 }
@@ -430,29 +431,42 @@ __global__ __launch_bounds__(SL * SW) void k_spmv_dot(const int* sl_ptr, const i
     }
   }
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
+  for (int q = 0; q < K; ++q) {   // per-block partial of p . Ap
     double v = loc[q];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) atomicAdd(dot + q, v);
+    if (lane == 0) dot[(long long)blockIdx.x * K + q] = v;
   }
 }
 
-// b_c = R r_f (coarse rows gather their fine children)
+// b_c = R r_f (coarse rows gather their fine children, 8 lanes per row) and
+// x_c = 0 for the recursion
+constexpr int RL = 8;
 template <class T, int K>
-__global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long long nc, const T* rf, T* bc) {
-  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
-  if (i >= nc) return;
+__global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long long nc, const T* rf, T* bc, T* xc) {
+  const long long g = blockIdx.x * (long long)BLK + threadIdx.x;
+  const long long i = g / RL;
+  const int sub = (int)(g % RL);
   T acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0;
-  for (int e = Rptr[i]; e < Rptr[i + 1]; ++e) {
-    const T w = Rw[e];
-    const int c = Rcol[e];
+  if (i < nc)
+    for (int e = Rptr[i] + sub; e < Rptr[i + 1]; e += RL) {
+      const T w = Rw[e];
+      const int c = Rcol[e];
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] = fma(w, rf[(long long)c * K + q], acc[q]);
+      for (int q = 0; q < K; ++q) acc[q] = fma(w, rf[(long long)c * K + q], acc[q]);
+    }
+#pragma unroll
+  for (int q = 0; q < K; ++q)
+    for (int o = RL / 2; o > 0; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+  if (i < nc && sub < K) {
+    // lane `sub` writes column `sub`
+    T v = acc[0];
+#pragma unroll
+    for (int q = 1; q < K; ++q) if (sub == q) v = acc[q];
+    bc[i * K + sub] = v;
+    xc[i * K + sub] = 0;
   }
-#pragma unroll
-  for (int q = 0; q < K; ++q) bc[i * K + q] = acc[q];
 }
 
 // x_f += P x_c
@@ -507,40 +521,67 @@ __global__ void k_convert(const A* in, long long n, B* out) {
 }
 
 // ------------------------------------------------------- CG kernels
-// alpha = rz / pq per column; x += alpha p; r -= alpha q; rr += r.r
+// sum of a block's per-thread values (BLK threads); result valid in thread 0
+__device__ inline double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < BLK / 64; ++i) s += sh[i];
+  return s;
+}
+
+// alpha = rz / pq per column; x += alpha p; r -= alpha q; per-block partials of r.r
 template <int K>
-__global__ void k_cg_update(long long n, const double* sc, double* x, double* r, const double* p, const double* q,
-                            double* rr) {
+__global__ __launch_bounds__(BLK) void k_cg_update(long long n, const double* sc, double* x, double* r,
+                                                   const double* p, const double* q, double* part) {
+  __shared__ double sh[BLK / 64];
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
-  double loc[K];
 #pragma unroll
   for (int c = 0; c < K; ++c) {
     const double rz = sc[c], pq = sc[K + c];
     const double al = (pq != 0.0 && rz != 0.0) ? rz / pq : 0.0;
-    loc[c] = 0.0;
+    double loc = 0.0;
     if (i < n) {
       x[i * K + c] += al * p[i * K + c];
       double v = r[i * K + c] - al * q[i * K + c];
       r[i * K + c] = v;
-      loc[c] = v * v;
+      loc = v * v;
     }
-  }
-#pragma unroll
-  for (int c = 0; c < K; ++c) {
-    double v = loc[c];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) atomicAdd(rr + c, v);
+    const double s = block_sum(loc, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
   }
 }
-// dot[c] += a . b per column
+// per-block partials of a . b per column
 template <int K>
-__global__ void k_dot(long long n, const double* a, const double* b, double* dot) {
+__global__ __launch_bounds__(BLK) void k_dot(long long n, const double* a, const double* b, double* part) {
+  __shared__ double sh[BLK / 64];
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
 #pragma unroll
   for (int c = 0; c < K; ++c) {
-    double v = i < n ? a[i * K + c] * b[i * K + c] : 0.0;
+    const double s = block_sum(i < n ? a[i * K + c] * b[i * K + c] : 0.0, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
+  }
+}
+// out[c] = sum of nb per-block partials (one block of 1024 threads)
+template <int K>
+__global__ __launch_bounds__(1024) void k_finalize(const double* part, int nb, double* out) {
+  __shared__ double sh[16];
+  for (int c = 0; c < K; ++c) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 1024) v += part[(long long)b * K + c];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0) atomicAdd(dot + c, v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < 16; ++w) s += sh[w];
+      out[c] = s;
+    }
+    __syncthreads();
   }
 }
 // beta = rz_new / rz; p = z + beta p
@@ -749,6 +790,11 @@ SolverState* setup(camfe_sys s, double t, int precision, double coarse_eps) {
   const size_t n = st->lev[h->D].n * KMAXS;
   st->X.alloc(n); st->R.alloc(n); st->Z.alloc(n); st->P.alloc(n); st->Q.alloc(n); st->B.alloc(n);
   st->sc.alloc(8 * KMAXS);
+  {
+    const GLevel& F = st->lev[h->D];
+    const size_t nb = std::max(F.nslices, (F.n + BLK - 1) / BLK) + 1;
+    st->part.alloc(nb * KMAXS);
+  }
   ctx->sync();
   st->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return st.release();
@@ -850,8 +896,8 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   T* xc = Vec<T>::x(C);
   // transfers: parent map (4 B per entry) plus the vectors read and written
   CAMFE_TIMED(ctx, KT_RESTRICT, (4.0 * G.pnnz + ((double)G.n + C.n) * K * sizeof(T)), (k_restrict<T, K>),
-              grid_for(C.n, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc);
-  hipLaunchKernelGGL((k_fill<T>), grid_for(C.n * K, BLK), BLK, 0, st, xc, (long long)(C.n * K), (T)0);
+              grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc,
+              xc);
   vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
@@ -875,13 +921,30 @@ void precondition(SolverState* S, const double* r, double* z, int nu1, int nu2) 
   }
 }
 
+// out[q] = sum of nb per-block partials
+template <int K>
+void finalize(SolverState* S, long long nb, double* out) {
+  hipLaunchKernelGGL(k_finalize<K>, 1, 1024, 0, S->ctx->stream, (const double*)S->part.p, (int)nb, out);
+}
+
+// out[q] = a_q . b_q over the finest depth
+template <int K>
+void dot(SolverState* S, const double* a, const double* b, double* out) {
+  const long long n = (long long)S->lev[S->D].n;
+  const long long nb = (n + BLK - 1) / BLK;
+  hipLaunchKernelGGL(k_dot<K>, (unsigned)nb, BLK, 0, S->ctx->stream, n, a, b, S->part.p);
+  finalize<K>(S, nb, out);
+}
+
+// r = b - A x at the finest depth in FP64; nrm (nullable) receives ||r_q||^2
 template <int K>
 void residual64(SolverState* S, const double* b, const double* x, double* r, double* nrm) {
   GLevel& G = S->lev[S->D];
   camfe_ctx ctx = S->ctx;
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<double, K>(G.nnz, (long long)G.n)), (k_residual<double, double, K>),
               (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
-              (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm);
+              (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm ? S->part.p : (double*)nullptr);
+  if (nrm) finalize<K>(S, (long long)G.nslices, nrm);
 }
 
 struct SolveResult {
@@ -929,23 +992,22 @@ void run_graph(SolverState* S, long long key, const std::function<void()>& enque
 template <int K>
 void cg_step(SolverState* S, int nu1, int nu2) {
   camfe_ctx ctx = S->ctx;
-  hipStream_t st = ctx->stream;
   GLevel& G = S->lev[S->D];
   const size_t n = G.n;
-  unsigned gn = grid_for(n, BLK);
+  const long long nb = (long long)((n + BLK - 1) / BLK);
   double* sc = S->sc.p;
-  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + K, (long long)(2 * K), 0.0);
-  CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices,
-              SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
-              (const double*)S->P.p, S->Q.p, sc + K);
-  CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, gn, BLK, 0, st, (long long)n, (const double*)sc,
-              S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, sc + 2 * K);
+  CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices, SL * SW, 0,
+              ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              (const double*)S->P.p, S->Q.p, S->part.p);
+  finalize<K>(S, (long long)G.nslices, sc + K);
+  CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, (unsigned)nb, BLK, 0, ctx->stream, (long long)n,
+              (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, S->part.p);
+  finalize<K>(S, nb, sc + 2 * K);
   precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
-  st = ctx->stream;
-  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 3 * K, (long long)K, 0.0);
-  hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)S->R.p, (const double*)S->Z.p, sc + 3 * K);
-  hipLaunchKernelGGL(k_cg_direction<K>, gn, BLK, 0, st, (long long)n, (const double*)sc, (const double*)(sc + 3 * K),
-                     (const double*)S->Z.p, S->P.p);
+  dot<K>(S, S->R.p, S->Z.p, sc + 3 * K);
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_cg_direction<K>, (unsigned)nb, BLK, 0, st, (long long)n, (const double*)sc,
+                     (const double*)(sc + 3 * K), (const double*)S->Z.p, S->P.p);
   hipLaunchKernelGGL(k_copy_scalars, 1, 64, 0, st, (const double*)(sc + 3 * K), sc, K);
 }
 
@@ -958,7 +1020,6 @@ void stationary_step(SolverState* S, int nu1, int nu2) {
   precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
   hipStream_t st = ctx->stream;
   hipLaunchKernelGGL(k_axpy_inplace<K>, grid_for(nk, BLK), BLK, 0, st, (long long)G.n, S->X.p, (const double*)S->Z.p);
-  hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, S->sc.p + 2 * K, (long long)K, 0.0);
   residual64<K>(S, S->B.p, S->X.p, S->R.p, S->sc.p + 2 * K);
 }
 
@@ -979,7 +1040,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   else
     hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->X.p, nk, 0.0);
   hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc, (long long)(8 * KMAXS), 0.0);
-  hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)S->B.p, (const double*)S->B.p, sc + 4 * K);
+  dot<K>(S, S->B.p, S->B.p, sc + 4 * K);
   residual64<K>(S, S->B.p, S->X.p, S->R.p, sc + 2 * K);
   check_launch();
   double hb[3 * KMAXS];
@@ -1028,7 +1089,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
     ++res.cycles;
     hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)S->Z.p, nk, S->P.p);
-    hipLaunchKernelGGL(k_dot<K>, gn, BLK, 0, st, (long long)n, (const double*)S->R.p, (const double*)S->Z.p, sc);
+    dot<K>(S, S->R.p, S->Z.p, sc);
     while (res.it < o.max_iter) {
       const int m = std::min(check_every, o.max_iter - res.it);
       res.rel = run_steps(m, true);
@@ -1037,7 +1098,6 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
       if (res.rel <= o.rtol || !std::isfinite(res.rel)) break;
     }
     // true residual of the final iterate
-    hipLaunchKernelGGL((k_fill<double>), 1, 64, 0, st, sc + 2 * K, (long long)K, 0.0);
     residual64<K>(S, S->B.p, S->X.p, S->R.p, sc + 2 * K);
     double rr[KMAXS];
     copy_out(ctx, rr, sc + 2 * K, K);
@@ -1094,7 +1154,7 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
         } else {
           hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p,
                              G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p,
-                             G.r64.p, S->sc.p);
+                             G.r64.p, S->part.p);
         }
       }
     };
@@ -1140,12 +1200,13 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
     SolverState* S = s->solver;
-    if (!S || S->t != o->t || S->precision != o->precision || S->coarse_eps != o->coarse_eps) {
+    if (!S || S->t != o->t || S->coarse_eps != o->coarse_eps) {
       destroy_solver(S);
       s->solver = nullptr;
       s->solver = setup(s, o->t, o->precision, o->coarse_eps);
       S = s->solver;
     }
+    S->precision = o->precision;   // both precisions share one setup
     const size_t n = S->lev[h->D].n;
     DArr<double> db(n * (size_t)k), dx(n * (size_t)k);
     copy_in(ctx, db.p, b, db.n);

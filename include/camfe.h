@@ -160,10 +160,16 @@ typedef struct {
                      /*    recurrences and coarsest solve in FP64                 */
   int x0_given;      /* start from x instead of 0                                 */
   double coarse_eps; /* eps added to the unit-diagonal-scaled coarsest matrix     */
+  int smoother;      /* 0: multicolour Gauss-Seidel (Section 5.2); 1: weighted    */
+                     /*    Jacobi with constant omega; 2: Jacobi with per-row     */
+                     /*    omega from the attached learned model                  */
+  double omega;      /* omega of smoother 1                                       */
 } camfe_solve_opts;
 
 typedef struct {
   int iterations;    /* outer iterations done                                     */
+  int fell_back;     /* 1 when the learned smoother failed and Gauss-Seidel redid */
+                     /*    the solve                                               */
   int cycles;        /* V-cycles applied                                          */
   int eps_regularised;
   double rel_residual; /* max over columns of ||b - A x|| / ||b|| (FP64)          */
@@ -187,6 +193,65 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double
 camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision, int reps, double *avg_ms,
                                   double *bytes_per_launch);
 void camfe_system_destroy(camfe_sys s);
+
+/* ------------------------------------------------------ learned smoother */
+/* Not part of the paper's method (its smoother is Gauss-Seidel, Section 5.2):
+ * an optional per-row damped Jacobi smoother x += omega_i (b_i - (A x)_i) / A_ii
+ * with omega_i = c_i s_i: s_i = 2 sigmoid(z_i) in (0, 2) comes from a small MLP
+ * per relative depth l = D - d (depths with l >= levels use the last MLP), and
+ * c_i = A_ii / sum_j |A_ij| is the l1-Jacobi bound, which keeps every sweep an
+ * A-norm contraction whatever the network outputs.  Degree 1 only.
+ * Row features (30, FP32): the row of A = M + t L summed per grid offset
+ * delta in {-1,0,1}^3 of the column's corner from the row's corner, divided by
+ * A_ii (index (dx+1) + 3(dy+1) + 9(dz+1)); clamp(log10(A_ii / max_j A_jj),
+ * -30, 0) / 10; M_ii / A_ii; (D - d) / 10.  A row of zero computed mass gets
+ * omega = 0.  MLP: 30 -> 32 (ReLU) -> 32 (ReLU) -> 1, parameters packed per
+ * level as W1[30][32], b1[32], W2[32][32], b2[32], w3[32], b3 (2081 floats;
+ * W[i][j] maps input i to output j).  Inference and training use BF16 copies
+ * of the weights (round to nearest even) with FP32 accumulation, or FP32
+ * weights when bf16 = 0.
+ * Training loss of a depth for error samples e0^s and nu sweeps of
+ * e <- e - omega D^-1 A e: mean_s log(|A e_nu^s|^2 / |A e0^s|^2). */
+typedef struct camfe_model_s *camfe_model;
+
+typedef struct {
+  double t;          /* A = M + t L of the training systems                        */
+  int levels;        /* MLPs (relative depths), 1..32                               */
+  int steps;         /* Adam steps (beta 0.9 / 0.999, eps 1e-8)                     */
+  int nu;            /* sweeps whose residual reduction the loss measures, >= 1     */
+  int bf16;          /* 1: BF16 weights (FP32 accumulation); 0: FP32 weights        */
+  double lr;         /* Adam step size                                              */
+  uint64_t seed;     /* seed of the error samples                                   */
+  int samples;       /* error samples per depth (four): 0 normal random vectors;    */
+                     /*    1 the error one plain Gauss-Seidel V(2,2) cycle on       */
+                     /*    A e = 0 leaves from such a vector; 2 two of each         */
+} camfe_train_opts;
+
+/* Model from packed FP32 parameters (levels x 2081, copied) or, with params
+ * NULL, a fixed deterministic initialisation (s near 1: l1-Jacobi). */
+camfe_status camfe_model_create(const float *params, int levels, int bf16, camfe_model *out);
+/* Two-call export of the packed parameters; levels and bf16 may be NULL. */
+camfe_status camfe_model_params(camfe_model m, float *params, int64_t cap, int64_t *n, int *levels, int *bf16);
+void camfe_model_destroy(camfe_model m);
+/* Attach a model (not owned; must outlive its use by camfe_solve) or detach
+ * with NULL.  smoother = 2 in camfe_solve needs an attached model (ESTATE). */
+camfe_status camfe_smoother_attach(camfe_sys s, camfe_model m);
+/* omega_i = c_i s_i of every function at one assembled depth (canonical
+ * order, n_d doubles) for A = M + t L. */
+camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double t, double *omega);
+/* Training loss at one depth for one MLP's parameters (2081 floats) and
+ * nsamples (1..4) error samples e0 (n_d x nsamples column-major, canonical
+ * order), with its gradient (2081 doubles; grad may be NULL).  The forward
+ * and adjoint sweeps run in FP64; the MLP in FP32 or BF16 weights. */
+camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float *params, int bf16,
+                                      const double *e0, int nsamples, int nu, double *loss, double *grad);
+/* Train a model on the GPU: for every system and depth above the coarsest,
+ * four error samples (opts->samples), then opts->steps Adam steps on the mean
+ * loss per MLP.
+ * loss_history (nullable) receives the mean loss over all depths before each
+ * step.  The systems' solver state for opts->t is built when missing. */
+camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const *systems, int nsys, const camfe_train_opts *opts,
+                                  camfe_model *out, double *loss_history);
 
 #ifdef __cplusplus
 }

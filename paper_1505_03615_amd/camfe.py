@@ -26,7 +26,10 @@ EXPORTS = [
     "camfe_hierarchy_destroy", "camfe_assemble", "camfe_reassemble_mass", "camfe_export_matrix",
     "camfe_load_vector", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
     "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time", "camfe_measure_kernel",
+    "camfe_model_create", "camfe_model_params", "camfe_model_destroy", "camfe_smoother_attach",
+    "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train",
 ]
+MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
            "uf_link", "support_sort", "cg_vector"]
 
@@ -45,12 +48,17 @@ class HierOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("method", C.c_int), ("precision", C.c_int), ("x0_given", C.c_int),
-                ("coarse_eps", C.c_double)]
+                ("coarse_eps", C.c_double), ("smoother", C.c_int), ("omega", C.c_double)]
 
 
 class SolveStats(C.Structure):
-    _fields_ = [("iterations", C.c_int), ("cycles", C.c_int), ("eps_regularised", C.c_int),
+    _fields_ = [("iterations", C.c_int), ("fell_back", C.c_int), ("cycles", C.c_int), ("eps_regularised", C.c_int),
                 ("rel_residual", C.c_double), ("seconds", C.c_double), ("setup_seconds", C.c_double)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("t", C.c_double), ("levels", C.c_int), ("steps", C.c_int), ("nu", C.c_int), ("bf16", C.c_int),
+                ("lr", C.c_double), ("seed", C.c_uint64), ("samples", C.c_int)]
 
 
 _lib = None
@@ -90,6 +98,13 @@ def load():
         "camfe_ctx_kernel_timing": (I, [H, I]),
         "camfe_ctx_kernel_time": (I, [H, C.c_char_p, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
         "camfe_measure_kernel": (I, [H, C.c_char_p, I, I, C.POINTER(D), C.POINTER(D)]),
+        "camfe_model_create": (I, [P, I, I, C.POINTER(H)]),
+        "camfe_model_params": (I, [H, P, I64, C.POINTER(I64), C.POINTER(I), C.POINTER(I)]),
+        "camfe_model_destroy": (None, [H]),
+        "camfe_smoother_attach": (I, [H, H]),
+        "camfe_smoother_omega": (I, [H, H, I, D, P]),
+        "camfe_smoother_loss_grad": (I, [H, I, D, P, I, P, I, I, C.POINTER(D), P]),
+        "camfe_smoother_train": (I, [H, P, I, C.POINTER(TrainOpts), C.POINTER(H), P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -305,8 +320,9 @@ def camfe_eval_vertices(s, nv, x):
 
 
 def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0, precision=0, x0=None,
-                coarse_eps=1e-10, raise_on_noconv=False):
-    """Returns (x, stats dict).  method 0 = V-cycle-preconditioned CG, 1 = stationary."""
+                coarse_eps=1e-10, raise_on_noconv=False, smoother=0, omega=0.0):
+    """Returns (x, stats dict).  method 0 = V-cycle-preconditioned CG, 1 = stationary;
+    smoother 0 = multicolour Gauss-Seidel, 1 = Jacobi(omega), 2 = attached learned model."""
     bc, n, k = _colmajor(b)
     if x0 is None:
         x = _empty_like_kind(bc, n, k)
@@ -315,6 +331,7 @@ def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0,
     o = SolveOpts()
     o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
     o.method, o.precision, o.x0_given, o.coarse_eps = method, precision, 0 if x0 is None else 1, coarse_eps
+    o.smoother, o.omega = smoother, omega
     st = SolveStats()
     code = load().camfe_solve(s, C.byref(o), _ptr(bc), k, _ptr(x), C.byref(st))
     if code != 0 and (code != -4 or raise_on_noconv):
@@ -333,3 +350,81 @@ def camfe_measure_kernel(s, kernel: str, precision: int = 0, reps: int = 50):
 
 def camfe_system_destroy(s):
     load().camfe_system_destroy(s)
+
+
+# ------------------------------------------------------------ learned smoother
+def camfe_model_create(params=None, levels=1, bf16=True):
+    """Model handle from packed FP32 parameters (levels x 2081) or the default initialisation."""
+    p = None
+    if params is not None:
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if p.size % MLP_PARAMS:
+            raise ValueError("parameters must be a multiple of 2081 floats")
+        levels = p.size // MLP_PARAMS
+    m = C.c_void_p()
+    _check(load().camfe_model_create(_ptr(p), int(levels), 1 if bf16 else 0, C.byref(m)))
+    return m.value
+
+
+def camfe_model_params(m):
+    """(params float32 [levels, 2081], bf16 flag)."""
+    n, lv, bf = C.c_int64(), C.c_int(), C.c_int()
+    _check(load().camfe_model_params(m, None, 0, C.byref(n), C.byref(lv), C.byref(bf)))
+    out = np.zeros(n.value, dtype=np.float32)
+    _check(load().camfe_model_params(m, _ptr(out), n.value, C.byref(n), None, None))
+    return out.reshape(lv.value, MLP_PARAMS), bool(bf.value)
+
+
+def camfe_model_destroy(m):
+    load().camfe_model_destroy(m)
+
+
+def camfe_smoother_attach(s, m):
+    _check(load().camfe_smoother_attach(s, m))
+
+
+def camfe_smoother_omega(s, h, m, depth, t):
+    """omega of every function at one depth (canonical order)."""
+    out = np.zeros(camfe_hierarchy_info(h, depth)[2])
+    _check(load().camfe_smoother_omega(s, m, depth, t, _ptr(out)))
+    return out
+
+
+def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=True):
+    """(loss, gradient float64[2081] or None) for one MLP's parameters and n_d x S samples."""
+    p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    if p.size != MLP_PARAMS:
+        raise ValueError("one MLP has 2081 parameters")
+    e = np.asfortranarray(np.asarray(e0, dtype=np.float64))
+    if e.ndim == 1:
+        e = e.reshape(-1, 1, order="F")
+    loss = C.c_double()
+    g = np.zeros(MLP_PARAMS) if want_grad else None
+    _check(load().camfe_smoother_loss_grad(s, depth, t, _ptr(p), 1 if bf16 else 0, _ptr(e), e.shape[1], nu,
+                                           C.byref(loss), _ptr(g)))
+    return loss.value, g
+
+
+def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, lr=3e-3, seed=1, samples=0):
+    """(model handle, loss history) trained on the GPU over the given systems.
+    samples: 0 random vectors, 1 errors left by one plain V-cycle, 2 two of each."""
+    arr = (C.c_void_p * len(systems))(*[x.value if isinstance(x, C.c_void_p) else x for x in systems])
+    o = TrainOpts()
+    o.t, o.levels, o.steps, o.nu, o.bf16, o.lr, o.seed = t, levels, steps, nu, 1 if bf16 else 0, lr, seed
+    o.samples = samples
+    hist = np.zeros(max(steps, 1))
+    m = C.c_void_p()
+    _check(load().camfe_smoother_train(ctx, C.cast(arr, C.c_void_p), len(systems), C.byref(o), C.byref(m),
+                                       _ptr(hist)))
+    return m.value, hist[:steps]
+
+
+def save_model(path, m):
+    """Packed parameters and the BF16 flag in a .npz file (no pickled objects)."""
+    params, bf16 = camfe_model_params(m)
+    np.savez(path, params=params, bf16=np.array([bf16]))
+
+
+def load_model(path):
+    with np.load(path, allow_pickle=False) as z:
+        return camfe_model_create(z["params"], bf16=bool(z["bf16"][0]))

@@ -73,6 +73,7 @@ struct camfe_sys_s {
   std::vector<camfe::SLevel> lev;   // index = depth (only d0..D filled)
   camfe::DArr<double> tri_w;        // current triangle weights of M (empty = 1)
   camfe::SolverState* solver = nullptr;
+  const void* model = nullptr;      // attached learned smoother (not owned)
   ~camfe_sys_s() { camfe::destroy_solver(solver); }
 };
 

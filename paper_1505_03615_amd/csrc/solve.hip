@@ -21,65 +21,13 @@
 #include <string>
 #include <map>
 
-#include "internal.hpp"
+#include "solver.hpp"
 
 namespace camfe {
 
 namespace {
-constexpr int BLK = 256;
-constexpr int SL = 64;        // SELL slice height = wavefront width
-constexpr int KMAXS = 4;      // right-hand sides per pass
+constexpr int BLK = SBLK;
 }  // namespace
-
-struct GLevel {
-  int d = 0;
-  size_t n = 0;
-  int ncol = 8;
-  std::vector<int> coff;      // colour c owns internal rows [coff[c], coff[c+1])
-  std::vector<int> cslice;    // colour c owns slices [cslice[c], cslice[c+1])
-  std::vector<long long> cnnz;  // nonzeros of the rows of each colour
-  long long nnz = 0, pnnz = 0;  // matrix nonzeros; prolongation entries into this depth
-  DArr<int> perm, iperm;      // internal -> canonical, canonical -> internal
-  size_t nslices = 0, snnz = 0;
-  DArr<int> sl_ptr;           // slice offsets into the value arrays (nslices + 1)
-  DArr<int> sl_row0;          // first internal row of each slice
-  DArr<int> sl_rows;          // rows in each slice (<= 64)
-  DArr<int> scol;
-  DArr<double> sval64, invd64;
-  DArr<float> sval32, invd32;
-  // transfers in internal numbering (P: rows at d, cols at d-1; R = P^T)
-  DArr<int> Pptr, Pcol, Rptr, Rcol;
-  DArr<double> Pw64, Rw64;
-  DArr<float> Pw32, Rw32;
-  // work vectors, n x KMAXS row-major
-  DArr<double> x64, b64, r64;
-  DArr<float> x32, b32, r32;
-};
-
-struct SolverState {
-  camfe_ctx ctx = nullptr;
-  double t = 0;
-  int precision = 0;
-  double coarse_eps = 0;
-  int D = 0, d0 = 0;
-  std::vector<GLevel> lev;   // index = depth
-  bool direct = false;
-  int n0 = 0;
-  DArr<double> Ainv64;
-  DArr<float> Ainv32;
-  // outer iteration vectors (finest, internal order, n x KMAXS row-major)
-  DArr<double> X, R, Z, P, Q, B;
-  DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
-  DArr<double> part;         // per-block partial sums of the reductions
-  double setup_seconds = 0;
-  // captured iterations (one graph per right-hand-side count / precision / sweeps / method)
-  hipStream_t cap = nullptr;
-  std::map<long long, hipGraphExec_t> graphs;
-  ~SolverState() {
-    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
-    if (cap) (void)hipStreamDestroy(cap);
-  }
-};
 
 void destroy_solver(SolverState* s) { delete s; }
 
@@ -368,6 +316,27 @@ __global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* ro
     const T di = invd[i];
 #pragma unroll
     for (int q = 0; q < K; ++q) x[(long long)i * K + q] += (b[(long long)i * K + q] - acc[q]) * di;
+  }
+}
+
+// weighted Jacobi over all slices: x_out = x_in + w_i (b - A x_in), w_i = omega_i / A_ii
+template <class T, int K>
+__global__ __launch_bounds__(SL * SW) void k_jacobi(const int* sl_ptr, const int* row0, const int* rows, int ns,
+                                                    const int* scol, const T* sval, const T* winvd, const T* b,
+                                                    const T* x_in, T* x_out) {
+  __shared__ T red[SW][K][SL];
+  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
+  const long long s = xcd_block(blockIdx.x, ns);
+  const bool active = lane < rows[s];
+  T acc[K];
+  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x_in, acc);
+  slice_reduce<T, K>(red, lane, sub, acc);
+  if (sub == 0 && active) {
+    const int i = row0[s] + lane;
+    const T w = winvd[i];
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+      x_out[(long long)i * K + q] = x_in[(long long)i * K + q] + (b[(long long)i * K + q] - acc[q]) * w;
   }
 }
 
@@ -699,8 +668,8 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
                      st->t, G.perm.p, G.iperm.p, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (long long)G.nslices,
                      G.scol.p, G.sval64.p, G.sval32.p, G.invd64.p, G.invd32.p);
   check_launch();
-  G.x64.alloc(n * KMAXS); G.b64.alloc(n * KMAXS); G.r64.alloc(n * KMAXS);
-  G.x32.alloc(n * KMAXS); G.b32.alloc(n * KMAXS); G.r32.alloc(n * KMAXS);
+  G.x64.alloc(n * KMAXS); G.b64.alloc(n * KMAXS); G.r64.alloc(n * KMAXS); G.t64.alloc(n * KMAXS);
+  G.x32.alloc(n * KMAXS); G.b32.alloc(n * KMAXS); G.r32.alloc(n * KMAXS); G.t32.alloc(n * KMAXS);
 }
 
 // transfers between depth d (fine) and d-1 in internal numbering
@@ -869,6 +838,42 @@ void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward) {
   }
 }
 
+template <class T>
+T* tmp_of(GLevel& g);
+template <>
+double* tmp_of<double>(GLevel& g) { return g.t64.p; }
+template <>
+float* tmp_of<float>(GLevel& g) { return g.t32.p; }
+template <class T>
+const T* winvd_of(const GLevel& g);
+template <>
+const double* winvd_of<double>(const GLevel& g) { return g.winvd64.p; }
+template <>
+const float* winvd_of<float>(const GLevel& g) { return g.winvd32.p; }
+
+// nu smoothing sweeps on (b, x): multicolour Gauss-Seidel (colours forward or
+// reversed) or weighted Jacobi (order-free; ping-pong through the level's
+// scratch vector, one launch per sweep)
+template <class T, int K>
+void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward) {
+  camfe_ctx ctx = S->ctx;
+  if (S->smoother == 0) {
+    for (int i = 0; i < nu; ++i) gs_sweep<T, K>(ctx, G, b, x, forward);
+    return;
+  }
+  T* a = x;
+  T* t = tmp_of<T>(G);
+  for (int i = 0; i < nu; ++i) {
+    CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.nnz, (long long)G.n) + (double)G.n * sizeof(T)), (k_jacobi<T, K>),
+                (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices,
+                G.scol.p, sval_of<T>(G), winvd_of<T>(G), b, (const T*)a, t);
+    std::swap(a, t);
+  }
+  if (a != x)
+    hipLaunchKernelGGL((k_convert<T, T>), grid_for(G.n * K, BLK), BLK, 0, ctx->stream, (const T*)a,
+                       (long long)(G.n * K), x);
+}
+
 // One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
 template <class T, int K>
 void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
@@ -881,12 +886,12 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
       CAMFE_TIMED(ctx, KT_COARSE, w, (k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st, ainv_of<T>(S),
                   S->n0, b, x);
     } else {
-      for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(ctx, G, b, x, true);
-      for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(ctx, G, b, x, false);
+      smooth<T, K>(S, G, b, x, nu1, true);
+      smooth<T, K>(S, G, b, x, nu2, false);
     }
     return;
   }
-  for (int i = 0; i < nu1; ++i) gs_sweep<T, K>(ctx, G, b, x, true);
+  smooth<T, K>(S, G, b, x, nu1, true);
   T* r = Vec<T>::r(G);
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
               (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
@@ -901,7 +906,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
-  for (int i = 0; i < nu2; ++i) gs_sweep<T, K>(ctx, G, b, x, false);
+  smooth<T, K>(S, G, b, x, nu2, false);
 }
 
 // z = V(r) at the finest depth (z zeroed first); FP32 cycles convert in and out
@@ -1061,7 +1066,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   // captured steps are replayed `check_every` times between convergence checks
   const bool use_graph = !ctx->timer.on;
   const int check_every = 4;
-  const long long gkey = ((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method;
+  const long long gkey = (((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother;
   auto run_steps = [&](int m, bool cg) {
     for (int i = 0; i < m; ++i) {
       if (use_graph)
@@ -1076,13 +1081,17 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     copy_out(ctx, rr, sc + 2 * K, K);
     return relmax(rr);
   };
+  // a replacement smoother whose iteration runs away is stopped early (the
+  // caller then redoes the solve with Gauss-Seidel)
+  const double rel0 = res.rel;
+  auto diverging = [&] { return S->smoother != 0 && res.rel > 1e2 * rel0; };
   if (o.method == 1) {
     while (res.rel > o.rtol && res.it < o.max_iter) {
       const int m = std::min(check_every, o.max_iter - res.it);
       res.rel = run_steps(m, false);
       res.it += m;
       res.cycles += m;
-      if (!std::isfinite(res.rel)) break;
+      if (!std::isfinite(res.rel) || diverging()) break;
     }
   } else if (res.rel > o.rtol && o.max_iter > 0) {
     // conjugate gradients preconditioned by one V-cycle
@@ -1095,7 +1104,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
       res.rel = run_steps(m, true);
       res.it += m;
       res.cycles += m;
-      if (res.rel <= o.rtol || !std::isfinite(res.rel)) break;
+      if (res.rel <= o.rtol || !std::isfinite(res.rel) || diverging()) break;
     }
     // true residual of the final iterate
     residual64<K>(S, S->B.p, S->X.p, S->R.p, sc + 2 * K);
@@ -1109,6 +1118,31 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
 }
 
 }  // namespace
+
+// solver state for (t, coarse_eps), rebuilt when either changes
+SolverState* ensure_solver(camfe_sys s, double t, double coarse_eps) {
+  SolverState* S = s->solver;
+  if (!S || S->t != t || S->coarse_eps != coarse_eps) {
+    destroy_solver(S);
+    s->solver = nullptr;
+    s->solver = setup(s, t, 0, coarse_eps);
+    S = s->solver;
+  }
+  return S;
+}
+
+// one FP64 Gauss-Seidel V(nu1, nu2)-cycle at depth d on A e = 0 for four
+// columns (x: n_d x 4 row-major, internal order), in place
+void plain_vcycle_at(SolverState* S, int d, double* x, int nu1, int nu2) {
+  const long long nk = (long long)S->lev[d].n * KMAXS;
+  hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, S->ctx->stream, S->B.p, nk, 0.0);
+  const int sm = S->smoother;
+  S->smoother = 0;
+  vcycle<double, KMAXS>(S, d, S->B.p, x, nu1, nu2);
+  S->smoother = sm;
+  check_launch();
+}
+
 }  // namespace camfe
 
 using namespace camfe;
@@ -1199,32 +1233,52 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
-    SolverState* S = s->solver;
-    if (!S || S->t != o->t || S->coarse_eps != o->coarse_eps) {
-      destroy_solver(S);
-      s->solver = nullptr;
-      s->solver = setup(s, o->t, o->precision, o->coarse_eps);
-      S = s->solver;
-    }
+    CAMFE_REQUIRE(o->smoother >= 0 && o->smoother <= 2, CAMFE_EINVAL, "smoother must be 0, 1 or 2");
+    CAMFE_REQUIRE(o->smoother != 1 || (o->omega > 0 && o->omega < 2), CAMFE_EINVAL, "omega must lie in (0, 2)");
+    CAMFE_REQUIRE(o->smoother != 2 || s->model, CAMFE_ESTATE, "learned smoother requested but no model attached");
+    SolverState* S = ensure_solver(s, o->t, o->coarse_eps);
     S->precision = o->precision;   // both precisions share one setup
+    const bool stale = o->smoother != S->wkind || (o->smoother == 1 && o->omega != S->omega) ||
+                       (o->smoother == 2 && s->model != S->model);
+    if (o->smoother != 0 && stale) {
+      set_smoother_weights(s, S, o->smoother, o->omega, o->smoother == 2 ? s->model : nullptr);
+    }
+    S->smoother = o->smoother;
     const size_t n = S->lev[h->D].n;
     DArr<double> db(n * (size_t)k), dx(n * (size_t)k);
     copy_in(ctx, db.p, b, db.n);
     if (o->x0_given) copy_in(ctx, dx.p, (const double*)x, dx.n);
     auto t0 = std::chrono::steady_clock::now();
-    SolveResult tot;
-    for (int c0 = 0; c0 < k; c0 += KMAXS) {
-      const int kb = std::min(KMAXS, k - c0);
-      SolveResult r;
-      switch (kb) {
-        case 1: r = solve_block<1>(s, S, *o, db.p, dx.p, k, c0); break;
-        case 2: r = solve_block<2>(s, S, *o, db.p, dx.p, k, c0); break;
-        case 3: r = solve_block<3>(s, S, *o, db.p, dx.p, k, c0); break;
-        default: r = solve_block<4>(s, S, *o, db.p, dx.p, k, c0); break;
+    auto run_all = [&](const camfe_solve_opts& oo) {
+      SolveResult tot;
+      for (int c0 = 0; c0 < k; c0 += KMAXS) {
+        const int kb = std::min(KMAXS, k - c0);
+        SolveResult r;
+        switch (kb) {
+          case 1: r = solve_block<1>(s, S, oo, db.p, dx.p, k, c0); break;
+          case 2: r = solve_block<2>(s, S, oo, db.p, dx.p, k, c0); break;
+          case 3: r = solve_block<3>(s, S, oo, db.p, dx.p, k, c0); break;
+          default: r = solve_block<4>(s, S, oo, db.p, dx.p, k, c0); break;
+        }
+        tot.it = std::max(tot.it, r.it);
+        tot.cycles += r.cycles;
+        if (!(r.rel <= tot.rel)) tot.rel = r.rel;
       }
-      tot.it = std::max(tot.it, r.it);
-      tot.cycles += r.cycles;
-      if (!(r.rel <= tot.rel)) tot.rel = r.rel;
+      return tot;
+    };
+    SolveResult tot = run_all(*o);
+    int fell_back = 0;
+    if (o->smoother != 0 && !(tot.rel <= o->rtol)) {
+      // the Jacobi smoother failed (diverged or stalled): Gauss-Seidel redoes the solve
+      camfe_solve_opts go = *o;
+      go.smoother = 0;
+      S->smoother = 0;
+      if (o->x0_given) copy_in(ctx, dx.p, (const double*)x, dx.n);
+      SolveResult t2 = run_all(go);
+      t2.it += tot.it;
+      t2.cycles += tot.cycles;
+      tot = t2;
+      fell_back = 1;
     }
     ctx->sync();
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1232,6 +1286,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     ctx->sync();
     if (stats) {
       stats->iterations = tot.it;
+      stats->fell_back = fell_back;
       stats->cycles = tot.cycles;
       stats->eps_regularised = S->direct ? 1 : 0;
       stats->rel_residual = tot.rel;

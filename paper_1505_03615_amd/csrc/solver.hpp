@@ -1,0 +1,81 @@
+// Solver state shared by solve.hip (multigrid, CG) and smoother.hip (learned
+// smoother): per-depth colour-ordered SELL matrices, transfers, smoother
+// weights and work vectors.
+#pragma once
+
+#include <map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace camfe {
+
+constexpr int SBLK = 256;     // threads per block of the vector kernels
+constexpr int SL = 64;        // SELL slice height = wavefront width
+constexpr int KMAXS = 4;      // right-hand sides per pass
+
+struct GLevel {
+  int d = 0;
+  size_t n = 0;
+  int ncol = 8;
+  std::vector<int> coff;      // colour c owns internal rows [coff[c], coff[c+1])
+  std::vector<int> cslice;    // colour c owns slices [cslice[c], cslice[c+1])
+  std::vector<long long> cnnz;  // nonzeros of the rows of each colour
+  long long nnz = 0, pnnz = 0;  // matrix nonzeros; prolongation entries into this depth
+  DArr<int> perm, iperm;      // internal -> canonical, canonical -> internal
+  size_t nslices = 0, snnz = 0;
+  DArr<int> sl_ptr;           // slice offsets into the value arrays (nslices + 1)
+  DArr<int> sl_row0;          // first internal row of each slice
+  DArr<int> sl_rows;          // rows in each slice (<= 64)
+  DArr<int> scol;
+  DArr<double> sval64, invd64;
+  DArr<float> sval32, invd32;
+  // Jacobi weights omega_i / A_ii (internal order), set for smoothers 1 and 2
+  DArr<double> winvd64;
+  DArr<float> winvd32;
+  // transfers in internal numbering (P: rows at d, cols at d-1; R = P^T)
+  DArr<int> Pptr, Pcol, Rptr, Rcol;
+  DArr<double> Pw64, Rw64;
+  DArr<float> Pw32, Rw32;
+  // work vectors, n x KMAXS row-major (t: Jacobi ping-pong)
+  DArr<double> x64, b64, r64, t64;
+  DArr<float> x32, b32, r32, t32;
+};
+
+struct SolverState {
+  camfe_ctx ctx = nullptr;
+  double t = 0;
+  int precision = 0;
+  int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi
+  int wkind = 0;             // smoother whose weights winvd holds (0: none)
+  double omega = 0;          // constant omega of smoother 1
+  const void* model = nullptr;  // learned model whose weights winvd holds
+  double coarse_eps = 0;
+  int D = 0, d0 = 0;
+  std::vector<GLevel> lev;   // index = depth
+  bool direct = false;
+  int n0 = 0;
+  DArr<double> Ainv64;
+  DArr<float> Ainv32;
+  // outer iteration vectors (finest, internal order, n x KMAXS row-major)
+  DArr<double> X, R, Z, P, Q, B;
+  DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
+  DArr<double> part;         // per-block partial sums of the reductions
+  double setup_seconds = 0;
+  // captured iterations (one graph per right-hand-side count / precision / sweeps / method / smoother)
+  hipStream_t cap = nullptr;
+  std::map<long long, hipGraphExec_t> graphs;
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+  ~SolverState() {
+    drop_graphs();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+// smoother.hip: Jacobi weights for smoother 1 (constant) or 2 (learned model)
+void set_smoother_weights(camfe_sys s, SolverState* S, int smoother, double omega, const void* model);
+
+}  // namespace camfe

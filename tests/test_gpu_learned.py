@@ -1,0 +1,209 @@
+"""Learned smoother on the GPU (through the C ABI) against the FP64 reference.
+
+Relaxation weights omega_i and the training loss and gradient of one depth
+are compared with oracle/learned.py on the same matrices (the oracle's),
+function keys, parameters and error samples; in the BF16 mode the reference
+gets the same BF16-rounded weights, so the remaining difference is the FP32
+arithmetic of the features and of the network.  Solves with the constant-omega
+and the trained smoother must reach the same solution as any other solve
+(relative residual with the oracle's matrices), and a smoother that stalls
+must hand the solve to Gauss-Seidel.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from oracle import learned as lr
+from paper_1505_03615_amd import meshgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    V1, F1, f1 = meshgen.config_mesh("icosphere_l3")
+    Vs, Fs, fs = meshgen.config_mesh("two_sheets", n=64, gap=1.0 / 64)
+    Vk, Fk = meshgen.torus_knot(nu=1024, nv=16, seed=3)
+    return {
+        "sphere": dict(V=V1, F=F1, f=f1, depth=5, t=1e-3),
+        "sheets": dict(V=Vs, F=Fs, f=fs, depth=6, t=1e-3),
+        "knot": dict(V=Vk, F=Fk, f=Vk, depth=7, t=1e-4),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import torch
+    from paper_1505_03615_amd import camfe
+    assert torch.cuda.is_available()
+    return camfe
+
+
+@pytest.fixture(scope="module")
+def ctx(cf):
+    c = cf.camfe_ctx_create(0)
+    yield c
+    cf.camfe_ctx_destroy(c)
+
+
+_built = {}
+
+
+def built(cf, ctx, name):
+    if name not in _built:
+        c = CASES[name]
+        say(f"[gpu] learned: build {name} nt={len(c['F'])} depth={c['depth']}")
+        h = cf.camfe_hierarchy_build(ctx, c["V"], c["F"], depth=c["depth"], degree=1, max_coarse=512)
+        s = cf.camfe_assemble(h)
+        o = Oracle(c["V"], c["F"], c["depth"], degree=1, max_coarse=512).check().assemble()
+        _built[name] = (h, s, o)
+    return _built[name]
+
+
+def _params(seed, levels=1):
+    rng = np.random.default_rng(seed)
+    p = (rng.normal(size=(levels, lr.NP)) * 0.12).astype(np.float32)
+    p[:, lr.O_B3] = -0.7
+    return p
+
+
+def _ref(o, d, t):
+    M, L = o.matrices(d)
+    A = (M + t * L).tocsr()
+    f, act, c1 = lr.features(A, M, o.functions(d)[0], d, o.depth)
+    return A, f, act, c1
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_omega_matches_reference(cf, ctx, bf16):
+    h, s, o = built(cf, ctx, "sphere")
+    t = CASES["sphere"]["t"]
+    p = _params(3, levels=2)
+    m = cf.camfe_model_create(p, bf16=bf16)
+    try:
+        for d in (o.depth, o.depth - 1, o.depth - 2):
+            say(f"[gpu] learned: omega depth {d} bf16={bf16}")
+            om = cf.camfe_smoother_omega(s, h, m, d, t)
+            A, f, act, c1 = _ref(o, d, t)
+            pl = p[min(o.depth - d, 1)]
+            ref = lr.omega(lr.bf16_round(pl) if bf16 else pl, f, act, c1)
+            assert np.array_equal(om == 0, ~act)
+            assert abs(om - ref).max() <= 2e-5, abs(om - ref).max()
+            assert om.min() >= 0 and np.all(om <= 2 * c1 * (1 + 1e-6))   # c_i is held in FP32
+            assert np.ptp(om[act] / c1[act]) > 0.05      # network not saturated: the rows really differ
+    finally:
+        cf.camfe_model_destroy(m)
+
+
+@pytest.mark.parametrize("name,dd", [("sphere", 0), ("sheets", 1)])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_loss_and_gradient_match_reference(cf, ctx, name, dd, bf16):
+    h, s, o = built(cf, ctx, name)
+    t = CASES[name]["t"]
+    d = o.depth - dd
+    p = _params(5)[0]
+    A, f, act, c1 = _ref(o, d, t)
+    E0 = np.random.default_rng(11).normal(size=(A.shape[0], 3))
+    say(f"[gpu] learned: loss/grad {name} depth {d} bf16={bf16}")
+    L, g = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=bf16)
+    pr = lr.bf16_round(p) if bf16 else p
+    Lr, gr = lr.loss_grad(A, f, act, c1, pr.astype(np.float64), E0, 2)
+    assert L == pytest.approx(Lr, rel=1e-6, abs=1e-7)
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    assert err <= (1e-3 if bf16 else 1e-4), err
+    # loss alone (no gradient) is the same number
+    L2, g2 = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=bf16, want_grad=False)
+    assert g2 is None and L2 == pytest.approx(L, rel=1e-14)   # block sums meet in FP64 atomics
+
+
+def test_constant_omega_jacobi_solves(cf, ctx):
+    h, s, o = built(cf, ctx, "sphere")
+    c = CASES["sphere"]
+    b = o.load_vector(c["f"])
+    Mo, Lo = o.matrices(c["depth"])
+    A = Mo + c["t"] * Lo
+    for precision in (0, 1):
+        say(f"[gpu] learned: jacobi(2/3) solve precision={precision}")
+        x, st = cf.camfe_solve(s, b, t=c["t"], rtol=1e-8, max_iter=600, precision=precision, smoother=1,
+                               omega=2.0 / 3.0)
+        assert st["converged"] and not st["fell_back"], st
+        r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+        assert np.all(r <= 1e-6), r
+
+
+def test_train_then_solve_held_out(cf, ctx):
+    """Train on the sphere and the two sheets; solve the held-out knot with the
+    trained smoother, its untrained base (l1-Jacobi, s = 1) and Gauss-Seidel."""
+    train = [built(cf, ctx, k)[1] for k in ("sphere", "sheets")]
+    say("[gpu] learned: train")
+    m, hist = cf.camfe_smoother_train(ctx, train, t=1e-3, levels=3, steps=100, nu=2, bf16=True, lr=3e-3, seed=1)
+    base = cf.camfe_model_create(np.zeros((1, lr.NP), np.float32), bf16=False)
+    try:
+        say(f"[gpu] learned: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+        assert np.all(np.isfinite(hist))
+        assert hist[-5:].mean() < hist[0] - 0.5
+        params, bf = cf.camfe_model_params(m)
+        assert params.shape == (3, lr.NP) and bf
+        h, s, o = built(cf, ctx, "knot")
+        c = CASES["knot"]
+        b = o.load_vector(c["f"])
+        Mo, Lo = o.matrices(c["depth"])
+        A = Mo + c["t"] * Lo
+        res = {}
+        for tag, sm, model in (("gs", 0, None), ("l1_jacobi", 2, base), ("learned", 2, m)):
+            cf.camfe_smoother_attach(s, model)
+            x, st = cf.camfe_solve(s, b, t=c["t"], rtol=1e-8, max_iter=2000, precision=1, smoother=sm)
+            assert st["converged"] and not st["fell_back"], (tag, st)
+            r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+            assert np.all(r <= 1e-6), (tag, r)
+            res[tag] = st
+        say("[gpu] learned: knot cycles " + " ".join(f"{k}={v['cycles']}" for k, v in res.items()) +
+            " ms " + " ".join(f"{k}={1e3 * v['seconds']:.2f}" for k, v in res.items()))
+        # what the trained network gains over the same smoother without it
+        assert res["learned"]["cycles"] < 0.8 * res["l1_jacobi"]["cycles"]
+    finally:
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_model_destroy(base)
+        cf.camfe_model_destroy(m)
+
+
+def test_stalling_smoother_falls_back_to_gauss_seidel(cf, ctx):
+    h, s, o = built(cf, ctx, "sphere")
+    c = CASES["sphere"]
+    p = np.zeros((1, lr.NP), np.float32)
+    p[0, lr.O_B3] = -30.0         # s = 2 sigmoid(-30) ~ 2e-13: the sweeps do nothing and the cycles stall
+    m = cf.camfe_model_create(p, bf16=False)
+    try:
+        cf.camfe_smoother_attach(s, m)
+        b = o.load_vector(c["f"])
+        say("[gpu] learned: fallback")
+        x, st = cf.camfe_solve(s, b, t=c["t"], rtol=1e-3, max_iter=300, method=1, smoother=2)
+        assert st["fell_back"] == 1 and st["converged"], st
+        Mo, Lo = o.matrices(c["depth"])
+        r = np.linalg.norm(b - (Mo + c["t"] * Lo) @ x, axis=0) / np.linalg.norm(b, axis=0)
+        assert np.all(r <= 1e-3 * 1.01), r
+    finally:
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_model_destroy(m)
+
+
+def test_learned_smoother_errors(cf, ctx):
+    h, s, o = built(cf, ctx, "sphere")
+    b = np.ones((o.count(o.depth, "functions"), 1))
+    with pytest.raises(cf.CamfeError, match="ESTATE"):
+        cf.camfe_solve(s, b, t=1e-3, smoother=2)
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_solve(s, b, t=1e-3, smoother=1, omega=2.5)
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_smoother_loss_grad(s, o.depth, 1e-3, _params(1)[0], np.ones((len(b), 5)), nu=2)
+    with pytest.raises(cf.CamfeError, match="ESTATE"):
+        cf.camfe_smoother_loss_grad(s, o.depth + 1, 1e-3, _params(1)[0], np.ones((len(b), 1)), nu=2)

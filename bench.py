@@ -4,16 +4,18 @@
 One step = the whole path on one synthetic input, inputs resident in HBM:
 hierarchy (grid placement, triangle/cell pairs, octree, supports, split,
 prolongation), assembly of M and L at every depth, the load vector, and the
-solve of (M + t L) x = b to a relative residual of 1e-8 twice: with the FP64
-V-cycle and with the FP32 V-cycle under FP64 refinement (conjugate gradients
-preconditioned by one V-cycle in both).
+solve of (M + t L) x = b to a relative residual of 1e-8 three times: with the
+FP64 Gauss-Seidel V-cycle, with the FP32 Gauss-Seidel V-cycle under FP64
+refinement, and with the FP32 V-cycle whose smoother is the learned Jacobi
+(conjugate gradients preconditioned by one V-cycle in all three).  The
+learned smoother is trained before timing on small meshes of other shapes.
 
 Workload: two parallel unit squares 1/256 apart, each a 256 x 256 grid of
 split quads (262,144 triangles), turned to general position, octree depth 8,
 t = 1e-3, RHS +-sin(40 pi x) on the two sheets.
 
-Prints one JSON line.  `value` is finest-depth DoF x V-cycles of both solves
-per second of the whole step; the per-phase times and the solve-only figures
+Prints one JSON line.  `value` is finest-depth DoF x V-cycles of the three
+solves per second of the whole step; the per-phase times and the solve-only figures
 are reported beside it.
 """
 from __future__ import annotations
@@ -61,6 +63,66 @@ def cpu_baseline(sample_n=128, sample_depth=7):
             "seconds": secs, "converged": bool(info["converged"])}
 
 
+def train_smoother(cf, ctx, meshgen, steps=150):
+    """Learned smoother trained (untimed) on small members of the three training
+    families: an icosphere, two close parallel sheets and a knot tube."""
+    fams = [(meshgen.icosphere(4)[:2], 6, 1e-3),
+            (meshgen.two_sheets(64, 1.0 / 64)[:2], 6, 1e-3),
+            (meshgen.torus_knot(nu=2048, nv=16, seed=5), 7, 1e-4)]
+    hs, ss = [], []
+    for (V, F), depth, t in fams:
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, degree=1, max_coarse=512)
+        hs.append(h)
+        ss.append(cf.camfe_assemble(h))
+    t0 = time.perf_counter()
+    m, hist = cf.camfe_smoother_train(ctx, ss, t=1e-3, levels=3, steps=steps, nu=2, bf16=True, lr=3e-3, seed=1)
+    secs = time.perf_counter() - t0
+    for s, h in zip(ss, hs):
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+    return m, {"steps": steps, "seconds": secs, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+               "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
+
+
+def held_out_eval(cf, ctx, meshgen, model, size):
+    """Held-out meshes (never trained on): the (3,5) knot tube and a noisy
+    sphere, each about 8.4M triangles at depth 11 (size 'full'), or 2.1M at
+    depth 10 ('small').  Solve (M + t L) x = b to 1e-8 with the plain FP64
+    Gauss-Seidel V-cycle and with the learned smoother in mixed precision;
+    each solve is run twice and the second (warm) run is reported."""
+    import torch
+    full = size == "full"
+    meshes = {
+        "knot": (meshgen.torus_knot(nu=65536 if full else 16384, nv=64, seed=3), 11 if full else 10, 1e-4),
+        "noisy_sphere": (meshgen.noisy_sphere(10 if full else 9, seed=7, base="octa"), 11 if full else 10, 1e-3),
+    }
+    out = {}
+    dev = torch.device("cuda:0")
+    for name, ((V, F), depth, t) in meshes.items():
+        log(f"[bench] held-out {name}: {len(F)} tris, depth {depth}")
+        h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=depth,
+                                     degree=1, max_coarse=512)
+        s = cf.camfe_assemble(h)
+        fv = torch.from_numpy(np.asfortranarray(V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)).to(dev)
+        b = cf.camfe_load_vector(s, h, fv)
+        n = cf.camfe_hierarchy_info(h, depth)[2]
+        res = {"tris": int(len(F)), "depth": depth, "t": t, "dof": int(n)}
+        for tag, kw in (("plain_gs_fp64", dict(precision=0, smoother=0)),
+                        ("learned_mixed", dict(precision=1, smoother=2))):
+            cf.camfe_smoother_attach(s, model if kw["smoother"] == 2 else None)
+            for _ in range(2):
+                x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
+            res[tag] = {"ms": 1000.0 * st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
+                        "converged": bool(st["converged"]), "fell_back": int(st["fell_back"])}
+        res["speedup_learned_vs_plain"] = res["plain_gs_fp64"]["ms"] / res["learned_mixed"]["ms"]
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+        out[name] = res
+        log(f"[bench] held-out {name}: " + json.dumps(res))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +134,8 @@ def main():
                     help="coarsest depth = finest with at most this many functions (solved directly)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--held-out", default="small", choices=["full", "small", "none"],
+                    help="learned-smoother evaluation on held-out meshes (8.4M or 2.1M tris)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -91,6 +155,8 @@ def main():
     ctx = cf.camfe_ctx_create(0, stream)
 
     keep = {}
+    log("[bench] training the learned smoother")
+    model, train_info = train_smoother(cf, ctx, meshgen)
 
     def step(record, keep_last=False):
         t0 = time.perf_counter()
@@ -105,11 +171,14 @@ def main():
         t4 = time.perf_counter()
         x32, st32 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=1)
         t5 = time.perf_counter()
+        cf.camfe_smoother_attach(s, model)
+        xl, stl = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=4000, precision=1, smoother=2)
+        t6 = time.perf_counter()
         fin, d0 = cf.camfe_hierarchy_levels(h)
         n = cf.camfe_hierarchy_info(h, fin)[2]
         if record is not None:
             record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve64=t4 - t3, solve32=t5 - t4,
-                               st64=st64, st32=st32, n=n, levels=(fin, d0)))
+                               solvel=t6 - t5, st64=st64, st32=st32, stl=stl, n=n, levels=(fin, d0)))
         if keep_last:
             keep["h"], keep["s"] = h, s
         else:
@@ -141,12 +210,15 @@ def main():
     n = rec[0]["n"]
     cyc64 = np.mean([r["st64"]["cycles"] for r in rec])
     cyc32 = np.mean([r["st32"]["cycles"] for r in rec])
+    cycl = np.mean([r["stl"]["cycles"] for r in rec])
     solve64 = np.mean([r["solve64"] for r in rec])
     solve32 = np.mean([r["solve32"] for r in rec])
-    phases = {k: 1000.0 * float(np.mean([r[k] for r in rec])) for k in ("build", "assemble", "load", "solve64", "solve32")}
+    solvel = np.mean([r["solvel"] for r in rec])
+    phases = {k: 1000.0 * float(np.mean([r[k] for r in rec]))
+              for k in ("build", "assemble", "load", "solve64", "solve32", "solvel")}
     out = {
         "metric": "solve time to 1e-8 rel. residual, DoF*cycles/s; learned vs plain smoother",
-        "value": n * (cyc64 + cyc32) / (ms / 1000.0),
+        "value": n * (cyc64 + cyc32 + cycl) / (ms / 1000.0),
         "unit": "DoF*cycles/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -163,11 +235,15 @@ def main():
                    "dof_finest": int(n), "levels": list(rec[0]["levels"]), "max_coarse": args.max_coarse},
         "phases_ms": phases,
         "solve_to_1e-8_ms": {"plain_fp64": 1000.0 * solve64, "mixed_fp32_fp64": 1000.0 * solve32,
-                             "learned": None},
-        "solve_cycles": {"plain_fp64": float(cyc64), "mixed_fp32_fp64": float(cyc32)},
-        "solve_dof_cycles_per_s": {"plain_fp64": n * cyc64 / solve64, "mixed_fp32_fp64": n * cyc32 / solve32},
+                             "learned_mixed": 1000.0 * solvel},
+        "solve_cycles": {"plain_fp64": float(cyc64), "mixed_fp32_fp64": float(cyc32), "learned_mixed": float(cycl)},
+        "solve_dof_cycles_per_s": {"plain_fp64": n * cyc64 / solve64, "mixed_fp32_fp64": n * cyc32 / solve32,
+                                   "learned_mixed": n * cycl / solvel},
         "rel_residual": {"plain_fp64": float(max(r["st64"]["rel_residual"] for r in rec)),
-                         "mixed_fp32_fp64": float(max(r["st32"]["rel_residual"] for r in rec))},
+                         "mixed_fp32_fp64": float(max(r["st32"]["rel_residual"] for r in rec)),
+                         "learned_mixed": float(max(r["stl"]["rel_residual"] for r in rec))},
+        "learned_fell_back": int(max(r["stl"]["fell_back"] for r in rec)),
+        "learned_training": train_info,
     }
     if ranking:
         out["kernel_event_ms_warmup"] = {k: v[0] for k, v in ranking.items() if v[1]}
@@ -189,6 +265,9 @@ def main():
                                         "bytes_per_launch": by32}}
     cf.camfe_system_destroy(keep["s"])
     cf.camfe_hierarchy_destroy(keep["h"])
+    if args.held_out != "none":
+        out["learned_held_out"] = held_out_eval(cf, ctx, meshgen, model, args.held_out)
+    cf.camfe_model_destroy(model)
     if args.calibrate_copy:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
         bb = torch.empty_like(a)

@@ -194,6 +194,19 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision
                                   double *bytes_per_launch);
 void camfe_system_destroy(camfe_sys s);
 
+/* --------------------------------------------------------- surface flow */
+/* One step of conformalized mean-curvature flow (Section 5.3): solve
+ * (M_t + delta/2 L_0) X' = M_t X with tracked test functions, i.e. on the
+ * hierarchy and L_0 of the original surface, M_t being the original mass
+ * integral with each triangle's contribution scaled by its current area (the
+ * mesh vertices moved to u_t = sum_i X_i b_i) over its original area.
+ * X: n x 3 column-major coefficients of the current embedding (start from
+ * camfe_linear_coeffs), overwritten with X'.  The solve starts from X; opts->t
+ * and opts->x0_given are ignored.  Leaves M = M_t assembled at every depth.
+ * Returns CAMFE_ENOCONV (X' written) when the solve stops above rtol. */
+camfe_status camfe_flow_step(camfe_sys s, double delta, double *X, const camfe_solve_opts *opts,
+                             camfe_solve_stats *stats);
+
 /* ------------------------------------------------------ learned smoother */
 /* Not part of the paper's method (its smoother is Gauss-Seidel, Section 5.2):
  * an optional per-row damped Jacobi smoother x += omega_i (b_i - (A x)_i) / A_ii

@@ -27,7 +27,7 @@ EXPORTS = [
     "camfe_load_vector", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
     "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time", "camfe_measure_kernel",
     "camfe_model_create", "camfe_model_params", "camfe_model_destroy", "camfe_smoother_attach",
-    "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train",
+    "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
 ]
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
@@ -105,6 +105,7 @@ def load():
         "camfe_smoother_omega": (I, [H, H, I, D, P]),
         "camfe_smoother_loss_grad": (I, [H, I, D, P, I, P, I, I, C.POINTER(D), P]),
         "camfe_smoother_train": (I, [H, P, I, C.POINTER(TrainOpts), C.POINTER(H), P]),
+        "camfe_flow_step": (I, [H, D, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -350,6 +351,26 @@ def camfe_measure_kernel(s, kernel: str, precision: int = 0, reps: int = 50):
 
 def camfe_system_destroy(s):
     load().camfe_system_destroy(s)
+
+
+def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, smoother=0,
+                    omega=0.0, coarse_eps=1e-10, raise_on_noconv=False):
+    """One tracked cMCF step; X (n x 3, numpy or torch) is updated in place and returned with the stats."""
+    Xc, n, k = _colmajor(X)
+    if k != 3:
+        raise ValueError("X must have three columns")
+    o = SolveOpts()
+    o.rtol, o.max_iter, o.nu_pre, o.nu_post, o.precision = rtol, max_iter, nu_pre, nu_post, precision
+    o.coarse_eps, o.smoother, o.omega = coarse_eps, smoother, omega
+    st = SolveStats()
+    code = load().camfe_flow_step(s, delta, _ptr(Xc), C.byref(o), C.byref(st))
+    if code != 0 and (code != -4 or raise_on_noconv):
+        _check(code)
+    if Xc is not X:
+        X[...] = Xc
+    stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+    stats["converged"] = code == 0
+    return X, stats
 
 
 # ------------------------------------------------------------ learned smoother

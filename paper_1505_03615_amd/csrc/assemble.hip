@@ -719,6 +719,7 @@ camfe_status camfe_reassemble_mass(camfe_sys s, const double* tri_weight) {
       s->tri_w.release();
     }
     for (int d = s->h->d0; d <= s->h->D; ++d) assemble_level(s, d, false, true);
+    refresh_solver(s);
   });
 }
 

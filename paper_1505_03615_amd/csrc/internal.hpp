@@ -65,6 +65,7 @@ struct SLevel {
 
 struct SolverState;   // solve.hip
 void destroy_solver(SolverState* s);
+void refresh_solver(camfe_sys s);   // matrix values changed, structure kept
 
 }  // namespace camfe
 
@@ -74,6 +75,7 @@ struct camfe_sys_s {
   camfe::DArr<double> tri_w;        // current triangle weights of M (empty = 1)
   camfe::SolverState* solver = nullptr;
   const void* model = nullptr;      // attached learned smoother (not owned)
+  camfe::DArr<double> area0;        // triangle areas of the original surface (flow)
   ~camfe_sys_s() { camfe::destroy_solver(solver); }
 };
 

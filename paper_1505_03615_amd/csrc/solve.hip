@@ -733,8 +733,10 @@ void setup_coarsest(camfe_sys s, SolverState* st) {
   hipLaunchKernelGGL(k_diag_of, grid_for(n, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p, st->t,
                      G.perm.p, (long long)n, dg.p);
   hipLaunchKernelGGL(k_inv_sqrt_diag, grid_for(n, BLK), BLK, 0, ctx->stream, n, sv.p, (const double*)dg.p);
-  st->Ainv64.alloc((size_t)n * n);
-  st->Ainv32.alloc((size_t)n * n);
+  if (st->Ainv64.n != (size_t)n * n) {   // kept in place on refresh: captured graphs hold these addresses
+    st->Ainv64.alloc((size_t)n * n);
+    st->Ainv32.alloc((size_t)n * n);
+  }
   hipLaunchKernelGGL(k_chol_inverse, grid_for(n, 64), 64, 0, ctx->stream, A.p, n, sv.p, work.p, st->Ainv64.p,
                      st->Ainv32.p);
   check_launch();
@@ -1118,6 +1120,30 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
 }
 
 }  // namespace
+
+// The values of M (or L) changed with the structure kept: repack A = M + t L
+// into the existing SELL arrays of every depth and refactor the coarsest
+// depth, in place.  Learned weights are recomputed at the next solve.
+void refresh_solver(camfe_sys s) {
+  SolverState* S = s->solver;
+  if (!S) return;
+  camfe_ctx ctx = s->h->ctx;
+  auto t0 = std::chrono::steady_clock::now();
+  for (int d = S->d0; d <= S->D; ++d) {
+    GLevel& G = S->lev[d];
+    const SLevel& L = s->lev[d];
+    const long long threads = (long long)G.nslices * SL;
+    hipLaunchKernelGGL(k_sell_fill, grid_for(threads, BLK), BLK, 0, ctx->stream, L.ptr.p, L.col.p, L.M.p, L.L.p,
+                       S->t, G.perm.p, G.iperm.p, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (long long)G.nslices,
+                       G.scol.p, G.sval64.p, G.sval32.p, G.invd64.p, G.invd32.p);
+    check_launch();
+  }
+  setup_coarsest(s, S);
+  S->wkind = 0;
+  S->model = nullptr;
+  ctx->sync();
+  S->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
 
 // solver state for (t, coarse_eps), rebuilt when either changes
 SolverState* ensure_solver(camfe_sys s, double t, double coarse_eps) {

@@ -194,6 +194,27 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision
                                   double *bytes_per_launch);
 void camfe_system_destroy(camfe_sys s);
 
+/* ------------------------------------------------------------- batching */
+/* Many systems solved together (not in the paper): the hierarchies are lined
+ * up by depth below their finest (each mesh bottoms out at its own coarsest
+ * depth), and every phase of the V-cycle and of CG is one launch over all
+ * meshes, captured into a HIP graph.  CG keeps its scalars per mesh and
+ * column, and freezes columns that have converged. */
+typedef struct camfe_batch_s *camfe_batch;
+/* Copies the systems' solver data for A = M + t L (building it where missing);
+ * later changes to the systems do not reach the batch.  All systems share the
+ * context and the degree. */
+camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const *systems, int nsys, double t, double coarse_eps,
+                                camfe_batch *out);
+/* levels of the batched hierarchy; rows of its finest level (padded) */
+camfe_status camfe_batch_info(camfe_batch b, int *levels, int64_t *rows);
+/* b[m], x[m]: n_m x k[m] column-major (x[m] read when x0_given); opts->t and
+ * coarse_eps must be the batch's, method 0 and smoother 0.  stats (nullable)
+ * has nsys entries.  Returns CAMFE_ENOCONV when any mesh stops above rtol. */
+camfe_status camfe_batch_solve(camfe_batch b, const camfe_solve_opts *opts, const double *const *b_in, const int *k,
+                               double *const *x, camfe_solve_stats *stats);
+void camfe_batch_destroy(camfe_batch b);
+
 /* --------------------------------------------------------- surface flow */
 /* One step of conformalized mean-curvature flow (Section 5.3): solve
  * (M_t + delta/2 L_0) X' = M_t X with tracked test functions, i.e. on the

@@ -28,6 +28,7 @@ EXPORTS = [
     "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time", "camfe_measure_kernel",
     "camfe_model_create", "camfe_model_params", "camfe_model_destroy", "camfe_smoother_attach",
     "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
+    "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy",
 ]
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
@@ -106,6 +107,10 @@ def load():
         "camfe_smoother_loss_grad": (I, [H, I, D, P, I, P, I, I, C.POINTER(D), P]),
         "camfe_smoother_train": (I, [H, P, I, C.POINTER(TrainOpts), C.POINTER(H), P]),
         "camfe_flow_step": (I, [H, D, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
+        "camfe_batch_create": (I, [H, P, I, D, D, C.POINTER(H)]),
+        "camfe_batch_info": (I, [H, C.POINTER(I), C.POINTER(I64)]),
+        "camfe_batch_solve": (I, [H, C.POINTER(SolveOpts), P, P, P, P]),
+        "camfe_batch_destroy": (None, [H]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -371,6 +376,53 @@ def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, p
     stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
     stats["converged"] = code == 0
     return X, stats
+
+
+def _handle(x):
+    return x.value if isinstance(x, C.c_void_p) else x
+
+
+def camfe_batch_create(ctx, systems, t, coarse_eps=1e-10):
+    arr = (C.c_void_p * len(systems))(*[_handle(x) for x in systems])
+    b = C.c_void_p()
+    _check(load().camfe_batch_create(ctx, C.cast(arr, C.c_void_p), len(systems), t, coarse_eps, C.byref(b)))
+    return b.value
+
+
+def camfe_batch_info(bt):
+    lv, rows = C.c_int(), C.c_int64()
+    _check(load().camfe_batch_info(bt, C.byref(lv), C.byref(rows)))
+    return lv.value, rows.value
+
+
+def camfe_batch_solve(bt, bs, t, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, x0s=None,
+                      coarse_eps=1e-10, raise_on_noconv=False):
+    """bs: list of n_m x k_m right-hand sides.  Returns (list of solutions, list of stats dicts)."""
+    cols = [_colmajor(b) for b in bs]
+    if x0s is None:
+        xs = [_empty_like_kind(bc, n, k) for bc, n, k in cols]
+    else:
+        xs = [_colmajor(x.clone() if _is_torch(x) else np.array(x, dtype=np.float64, copy=True))[0] for x in x0s]
+    m = len(bs)
+    bp = (C.c_void_p * m)(*[_ptr(bc).value for bc, _, _ in cols])
+    xp = (C.c_void_p * m)(*[_ptr(x).value for x in xs])
+    kk = (C.c_int * m)(*[k for _, _, k in cols])
+    o = SolveOpts()
+    o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
+    o.method, o.precision, o.x0_given, o.coarse_eps = 0, precision, 0 if x0s is None else 1, coarse_eps
+    st = (SolveStats * m)()
+    code = load().camfe_batch_solve(bt, C.byref(o), C.cast(bp, C.c_void_p), C.cast(kk, C.c_void_p),
+                                    C.cast(xp, C.c_void_p), C.cast(st, C.c_void_p))
+    if code != 0 and (code != -4 or raise_on_noconv):
+        _check(code)
+    stats = [{f: getattr(x, f) for f, _ in SolveStats._fields_} for x in st]
+    for x in stats:
+        x["converged"] = x["rel_residual"] <= rtol
+    return xs, stats
+
+
+def camfe_batch_destroy(bt):
+    load().camfe_batch_destroy(bt)
 
 
 # ------------------------------------------------------------ learned smoother

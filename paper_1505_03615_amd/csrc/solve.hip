@@ -478,6 +478,36 @@ __global__ void k_coarse(const T* Ainv, int n, const T* b, T* x) {
   }
 }
 
+// batched coarse solves: x = Ainv_j b on the rows of every mesh j whose
+// coarsest depth is this level (one wavefront per row)
+template <class T, int K>
+__global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long long* aoff, const T* ainv,
+                           const T* b, T* x) {
+  long long wave = (blockIdx.x * (long long)BLK + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (wave >= cum[nm]) return;
+  int j = 0;
+  while (cum[j + 1] <= wave) ++j;
+  const int n = cum[j + 1] - cum[j];
+  const long long lr = wave - cum[j];
+  const T* A = ainv + aoff[j];
+  const long long r0 = rowoff[j];
+  double acc[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  for (int c = lane; c < n; c += 64) {
+    const double a = (double)A[lr * n + c];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(r0 + c) * K + q];
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) x[(r0 + lr) * K + q] = (T)v;
+  }
+}
+
 template <class T>
 __global__ void k_fill(T* p, long long n, T v) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
@@ -572,6 +602,65 @@ template <int K>
 __global__ void k_axpy_inplace(long long n, double* x, const double* y) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i < n * K) x[i] += y[i];
+}
+
+// --------------------------------------------- batched CG (per-mesh scalars)
+// Scalars of mesh m live at sc[m * SCS + ...]: rz[K] pq[K] rr[K] rz_new[K]
+// bb[K] act[K] (act = 1 while the column still iterates, 0 once frozen).
+constexpr int SCS = 8 * KMAXS;
+
+// out[m * SCS + off + c] = sum of the partials of mesh m's blocks
+template <int K>
+__global__ __launch_bounds__(BLK) void k_finalize_seg(const double* part, const int* bstart, double* out, int off) {
+  __shared__ double sh[BLK / 64];
+  const int m = blockIdx.x;
+  const int b0 = bstart[m], b1 = bstart[m + 1];
+  for (int c = 0; c < K; ++c) {
+    double v = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += BLK) v += part[(long long)b * K + c];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) out[(long long)m * SCS + off + c] = s;
+    __syncthreads();
+  }
+}
+template <int K>
+__global__ __launch_bounds__(BLK) void k_cg_update_b(long long n, const int* bmesh, const double* scall, double* x,
+                                                     double* r, const double* p, const double* q, double* part) {
+  __shared__ double sh[BLK / 64];
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  const double* sc = scall + (long long)bmesh[blockIdx.x] * SCS;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const double rz = sc[c], pq = sc[K + c];
+    const double al = (sc[5 * K + c] != 0.0 && pq != 0.0 && rz != 0.0) ? rz / pq : 0.0;
+    double loc = 0.0;
+    if (i < n) {
+      x[i * K + c] += al * p[i * K + c];
+      double v = r[i * K + c] - al * q[i * K + c];
+      r[i * K + c] = v;
+      loc = v * v;
+    }
+    const double s = block_sum(loc, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
+  }
+}
+template <int K>
+__global__ void k_cg_direction_b(long long n, const int* bmesh, const double* scall, const double* z, double* p) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+  const double* sc = scall + (long long)bmesh[blockIdx.x] * SCS;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const double be = (sc[5 * K + c] != 0.0 && sc[c] != 0.0) ? sc[3 * K + c] / sc[c] : 0.0;
+    p[i * K + c] = z[i * K + c] + be * p[i * K + c];
+  }
+}
+template <int K>
+__global__ void k_copy_rz_b(int nm, double* scall) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nm * K) return;
+  double* sc = scall + (long long)(i / K) * SCS;
+  sc[i % K] = sc[3 * K + i % K];
 }
 
 // canonical column-major n x k block (columns c0..c0+K) <-> internal row-major n x K
@@ -876,12 +965,33 @@ void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward) {
                        (long long)(G.n * K), x);
 }
 
+template <class T>
+const T* cb_of(const GLevel& g);
+template <>
+const double* cb_of<double>(const GLevel& g) { return g.cb_a64.p; }
+template <>
+const float* cb_of<float>(const GLevel& g) { return g.cb_a32.p; }
+
+// batched solver: direct solves of the meshes whose coarsest depth is this level
+template <class T, int K>
+void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
+  if (!G.ncb) return;
+  hipLaunchKernelGGL((k_coarse_b<T, K>), grid_for((size_t)G.cb_rows * 64, BLK), BLK, 0, S->ctx->stream, G.ncb,
+                     G.cb_rowoff.p, G.cb_cum.p, G.cb_aoff.p, cb_of<T>(G), b, x);
+}
+
 // One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
 template <class T, int K>
 void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   camfe_ctx ctx = S->ctx;
   hipStream_t st = ctx->stream;
   GLevel& G = S->lev[d];
+  if (d == S->d0 && S->batch) {
+    smooth<T, K>(S, G, b, x, nu1, true);
+    coarse_batched<T, K>(S, G, b, x);
+    smooth<T, K>(S, G, b, x, nu2, false);
+    return;
+  }
   if (d == S->d0) {
     if (S->direct) {
       const double w = (double)S->n0 * S->n0 * sizeof(T) + 2.0 * S->n0 * K * sizeof(T);
@@ -908,6 +1018,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
+  if (G.ncb) coarse_batched<T, K>(S, G, b, x);   // meshes that bottom out here
   smooth<T, K>(S, G, b, x, nu2, false);
 }
 
@@ -1119,6 +1230,385 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   return res;
 }
 
+// ------------------------------------------------------------------ batch
+// Many systems solved side by side.  Level bd of the batch holds, for every
+// mesh m, its depth D_m - (Lmax - bd) when that is not below its coarsest
+// depth: the finest depths line up at the top and each mesh bottoms out at
+// its own coarsest depth, where its dense inverse is applied.  Rows are
+// mesh-major (each mesh's rows padded to whole BLK-row blocks); slices are
+// colour-major across meshes, so one launch per colour relaxes every mesh.
+struct BatchMember {
+  size_t n = 0;            // functions at the finest depth
+  long long rowoff = 0;    // first row at the finest batch level
+  DArr<int> iperm;         // canonical -> internal order at the finest depth
+};
+
+template <class T>
+std::vector<T> to_host(camfe_ctx ctx, const DArr<T>& a, size_t n) {
+  std::vector<T> h(n);
+  if (n) copy_out(ctx, h.data(), a.p, n);
+  return h;
+}
+
+__global__ void k_copy_add(const int* src, long long n, int add, int* dst) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n) dst[i] = src[i] + add;
+}
+
+inline long long pad_rows(long long n) { return (n + BLK - 1) / BLK * BLK; }
+
+void dcopy(camfe_ctx ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes) CAMFE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+}  // namespace
+}  // namespace camfe
+
+struct camfe_batch_s {
+  camfe_ctx ctx = nullptr;
+  double t = 0, coarse_eps = 0;
+  std::vector<camfe::BatchMember> mem;
+  std::unique_ptr<camfe::SolverState> S;
+};
+
+namespace camfe {
+namespace {
+
+void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
+  camfe_ctx ctx = Bt->ctx;
+  const int nm = (int)ms.size();
+  int Lmax = 0;
+  for (auto* m : ms) Lmax = std::max(Lmax, m->D - m->d0);
+  std::unique_ptr<SolverState> S(new SolverState());
+  S->ctx = ctx;
+  S->t = Bt->t;
+  S->coarse_eps = Bt->coarse_eps;
+  S->D = Lmax;
+  S->d0 = 0;
+  S->batch = true;
+  S->nmesh = nm;
+  S->lev.resize(Lmax + 1);
+  auto mdepth = [&](int m, int bd) { return ms[m]->D - (Lmax - bd); };
+  auto present = [&](int m, int bd) { return mdepth(m, bd) >= ms[m]->d0; };
+  std::vector<std::vector<long long>> rowoff(Lmax + 1, std::vector<long long>(nm, -1));
+  for (int bd = 0; bd <= Lmax; ++bd) {
+    GLevel& G = S->lev[bd];
+    G.d = bd;
+    G.ncol = ms[0]->lev[ms[0]->D].ncol;
+    long long off = 0;
+    for (int m = 0; m < nm; ++m)
+      if (present(m, bd)) {
+        rowoff[bd][m] = off;
+        off += pad_rows((long long)ms[m]->lev[mdepth(m, bd)].n);
+      }
+    G.n = (size_t)off;
+    // slice metadata, colour-major across meshes
+    struct Meta { std::vector<int> ptr, row0, rows; };
+    std::vector<Meta> meta(nm);
+    for (int m = 0; m < nm; ++m)
+      if (present(m, bd)) {
+        const GLevel& M = ms[m]->lev[mdepth(m, bd)];
+        meta[m].ptr = to_host(ctx, M.sl_ptr, M.nslices + 1);
+        meta[m].row0 = to_host(ctx, M.sl_row0, M.nslices);
+        meta[m].rows = to_host(ctx, M.sl_rows, M.nslices);
+      }
+    std::vector<int> hp(1, 0), hrow0, hrows;
+    G.cslice.assign(G.ncol + 1, 0);
+    G.coff.assign(G.ncol + 1, 0);
+    G.cnnz.assign(G.ncol, 0);
+    G.nnz = 0;
+    struct Chunk { int m; long long src, dst, cnt; };
+    std::vector<Chunk> chunks;
+    for (int c = 0; c < G.ncol; ++c) {
+      G.cslice[c] = (int)hrow0.size();
+      G.coff[c + 1] = G.coff[c];
+      for (int m = 0; m < nm; ++m) {
+        if (!present(m, bd)) continue;
+        const GLevel& M = ms[m]->lev[mdepth(m, bd)];
+        const int s0 = M.cslice[c], s1 = M.cslice[c + 1];
+        if (s1 > s0) chunks.push_back({m, meta[m].ptr[s0], hp.back(), (long long)meta[m].ptr[s1] - meta[m].ptr[s0]});
+        for (int sl = s0; sl < s1; ++sl) {
+          hrow0.push_back((int)(meta[m].row0[sl] + rowoff[bd][m]));
+          hrows.push_back(meta[m].rows[sl]);
+          hp.push_back(hp.back() + meta[m].ptr[sl + 1] - meta[m].ptr[sl]);
+        }
+        G.coff[c + 1] += M.coff[c + 1] - M.coff[c];
+        G.cnnz[c] += M.cnnz[c];
+      }
+    }
+    G.cslice[G.ncol] = (int)hrow0.size();
+    for (int m = 0; m < nm; ++m)
+      if (present(m, bd)) G.nnz += ms[m]->lev[mdepth(m, bd)].nnz;
+    G.nslices = hrow0.size();
+    G.snnz = (size_t)hp.back();
+    G.sl_ptr.alloc(G.nslices + 1);
+    G.sl_row0.alloc(std::max<size_t>(G.nslices, 1));
+    G.sl_rows.alloc(std::max<size_t>(G.nslices, 1));
+    copy_in(ctx, G.sl_ptr.p, hp.data(), hp.size());
+    if (G.nslices) {
+      copy_in(ctx, G.sl_row0.p, hrow0.data(), G.nslices);
+      copy_in(ctx, G.sl_rows.p, hrows.data(), G.nslices);
+    }
+    G.scol.alloc(G.snnz);
+    G.sval64.alloc(G.snnz);
+    G.sval32.alloc(G.snnz);
+    for (const Chunk& ch : chunks) {
+      const GLevel& M = ms[ch.m]->lev[mdepth(ch.m, bd)];
+      dcopy(ctx, G.sval64.p + ch.dst, M.sval64.p + ch.src, ch.cnt * sizeof(double));
+      dcopy(ctx, G.sval32.p + ch.dst, M.sval32.p + ch.src, ch.cnt * sizeof(float));
+      hipLaunchKernelGGL(k_copy_add, grid_for(ch.cnt, BLK), BLK, 0, ctx->stream, M.scol.p + ch.src, ch.cnt,
+                         (int)rowoff[bd][ch.m], G.scol.p + ch.dst);
+    }
+    check_launch();
+    G.invd64.alloc(G.n);
+    G.invd32.alloc(G.n);
+    zero(ctx, G.invd64.p, G.n);
+    zero(ctx, G.invd32.p, G.n);
+    for (int m = 0; m < nm; ++m)
+      if (present(m, bd)) {
+        const GLevel& M = ms[m]->lev[mdepth(m, bd)];
+        dcopy(ctx, G.invd64.p + rowoff[bd][m], M.invd64.p, M.n * sizeof(double));
+        dcopy(ctx, G.invd32.p + rowoff[bd][m], M.invd32.p, M.n * sizeof(float));
+      }
+    const size_t nk = G.n * KMAXS;
+    for (DArr<double>* v : {&G.x64, &G.b64, &G.r64, &G.t64}) { v->alloc(nk); zero(ctx, v->p, nk); }
+    for (DArr<float>* v : {&G.x32, &G.b32, &G.r32, &G.t32}) { v->alloc(nk); zero(ctx, v->p, nk); }
+    // meshes solved directly at this level
+    std::vector<int> cro, ccum(1, 0);
+    std::vector<long long> caoff;
+    long long atot = 0;
+    for (int m = 0; m < nm; ++m)
+      if (present(m, bd) && mdepth(m, bd) == ms[m]->d0 && ms[m]->direct) {
+        cro.push_back((int)rowoff[bd][m]);
+        ccum.push_back(ccum.back() + ms[m]->n0);
+        caoff.push_back(atot);
+        atot += (long long)ms[m]->n0 * ms[m]->n0;
+      }
+    G.ncb = (int)cro.size();
+    G.cb_rows = ccum.back();
+    if (G.ncb) {
+      G.cb_rowoff.alloc(G.ncb);
+      G.cb_cum.alloc(G.ncb + 1);
+      G.cb_aoff.alloc(G.ncb);
+      copy_in(ctx, G.cb_rowoff.p, cro.data(), cro.size());
+      copy_in(ctx, G.cb_cum.p, ccum.data(), ccum.size());
+      copy_in(ctx, G.cb_aoff.p, caoff.data(), caoff.size());
+      G.cb_a64.alloc(atot);
+      G.cb_a32.alloc(atot);
+      int j = 0;
+      for (int m = 0; m < nm; ++m)
+        if (present(m, bd) && mdepth(m, bd) == ms[m]->d0 && ms[m]->direct) {
+          const size_t na = (size_t)ms[m]->n0 * ms[m]->n0;
+          dcopy(ctx, G.cb_a64.p + caoff[j], ms[m]->Ainv64.p, na * sizeof(double));
+          dcopy(ctx, G.cb_a32.p + caoff[j], ms[m]->Ainv32.p, na * sizeof(float));
+          ++j;
+        }
+    }
+  }
+  // transfers between batch levels bd (fine) and bd - 1
+  for (int bd = 1; bd <= Lmax; ++bd) {
+    GLevel& F = S->lev[bd];
+    GLevel& Cc = S->lev[bd - 1];
+    std::vector<int> pcnt(F.n + 1, 0), rcnt(Cc.n + 1, 0);
+    struct TChunk { int m; long long psrc_n, pdst_row, rsrc_n, rdst_row; };
+    std::vector<TChunk> tch;
+    for (int m = 0; m < nm; ++m) {
+      if (!present(m, bd - 1)) continue;
+      const GLevel& MF = ms[m]->lev[mdepth(m, bd)];
+      std::vector<int> mp = to_host(ctx, MF.Pptr, MF.n + 1);
+      std::vector<int> mr = to_host(ctx, MF.Rptr, ms[m]->lev[mdepth(m, bd - 1)].n + 1);
+      for (size_t i = 0; i < MF.n; ++i) pcnt[rowoff[bd][m] + i + 1] = mp[i + 1] - mp[i];
+      const size_t ncm = ms[m]->lev[mdepth(m, bd - 1)].n;
+      for (size_t i = 0; i < ncm; ++i) rcnt[rowoff[bd - 1][m] + i + 1] = mr[i + 1] - mr[i];
+      tch.push_back({m, (long long)mp[MF.n], rowoff[bd][m], (long long)mr[ncm], rowoff[bd - 1][m]});
+    }
+    for (size_t i = 0; i < F.n; ++i) pcnt[i + 1] += pcnt[i];
+    for (size_t i = 0; i < Cc.n; ++i) rcnt[i + 1] += rcnt[i];
+    const long long pn = pcnt[F.n];
+    F.pnnz = pn;
+    F.Pptr.alloc(F.n + 1);
+    F.Rptr.alloc(Cc.n + 1);
+    copy_in(ctx, F.Pptr.p, pcnt.data(), pcnt.size());
+    copy_in(ctx, F.Rptr.p, rcnt.data(), rcnt.size());
+    F.Pcol.alloc(std::max<long long>(pn, 1));
+    F.Pw64.alloc(std::max<long long>(pn, 1));
+    F.Pw32.alloc(std::max<long long>(pn, 1));
+    F.Rcol.alloc(std::max<long long>(pn, 1));
+    F.Rw64.alloc(std::max<long long>(pn, 1));
+    F.Rw32.alloc(std::max<long long>(pn, 1));
+    for (const TChunk& t : tch) {
+      const GLevel& MF = ms[t.m]->lev[mdepth(t.m, bd)];
+      const long long pd = pcnt[t.pdst_row], rd = rcnt[t.rdst_row];
+      hipLaunchKernelGGL(k_copy_add, grid_for(t.psrc_n, BLK), BLK, 0, ctx->stream, MF.Pcol.p, t.psrc_n,
+                         (int)rowoff[bd - 1][t.m], F.Pcol.p + pd);
+      dcopy(ctx, F.Pw64.p + pd, MF.Pw64.p, t.psrc_n * sizeof(double));
+      dcopy(ctx, F.Pw32.p + pd, MF.Pw32.p, t.psrc_n * sizeof(float));
+      hipLaunchKernelGGL(k_copy_add, grid_for(t.rsrc_n, BLK), BLK, 0, ctx->stream, MF.Rcol.p, t.rsrc_n,
+                         (int)rowoff[bd][t.m], F.Rcol.p + rd);
+      dcopy(ctx, F.Rw64.p + rd, MF.Rw64.p, t.rsrc_n * sizeof(double));
+      dcopy(ctx, F.Rw32.p + rd, MF.Rw32.p, t.rsrc_n * sizeof(float));
+    }
+    check_launch();
+  }
+  // finest level: mesh of every block, outer vectors, scalars
+  const GLevel& T = S->lev[Lmax];
+  const size_t nb = T.n / BLK;
+  std::vector<int> bm(std::max<size_t>(nb, 1), 0), bs(nm + 1, 0);
+  Bt->mem.resize(nm);
+  for (int m = 0; m < nm; ++m) {
+    const long long b0 = rowoff[Lmax][m] / BLK;
+    const long long cnt = pad_rows((long long)ms[m]->lev[ms[m]->D].n) / BLK;
+    for (long long b = b0; b < b0 + cnt; ++b) bm[b] = m;
+    bs[m] = (int)b0;
+    bs[m + 1] = (int)(b0 + cnt);
+    BatchMember& me = Bt->mem[m];
+    me.n = ms[m]->lev[ms[m]->D].n;
+    me.rowoff = rowoff[Lmax][m];
+    me.iperm.alloc(me.n);
+    dcopy(ctx, me.iperm.p, ms[m]->lev[ms[m]->D].iperm.p, me.n * sizeof(int));
+  }
+  S->bmesh.alloc(bm.size());
+  S->bstart.alloc(nm + 1);
+  copy_in(ctx, S->bmesh.p, bm.data(), bm.size());
+  copy_in(ctx, S->bstart.p, bs.data(), bs.size());
+  const size_t n = T.n * KMAXS;
+  for (DArr<double>* v : {&S->X, &S->R, &S->Z, &S->P, &S->Q, &S->B}) { v->alloc(n); zero(ctx, v->p, n); }
+  S->sc.alloc((size_t)nm * SCS);
+  zero(ctx, S->sc.p, S->sc.n);
+  S->part.alloc((std::max(T.nslices, nb) + 1) * KMAXS);
+  ctx->sync();
+  Bt->S = std::move(S);
+}
+
+template <int K>
+void dot_seg(SolverState* S, const double* a, const double* b, int off) {
+  const GLevel& G = S->lev[S->D];
+  const long long nb = (long long)(G.n / BLK);
+  hipLaunchKernelGGL(k_dot<K>, (unsigned)nb, BLK, 0, S->ctx->stream, (long long)G.n, a, b, S->part.p);
+  hipLaunchKernelGGL(k_finalize_seg<K>, (unsigned)S->nmesh, BLK, 0, S->ctx->stream, (const double*)S->part.p,
+                     S->bstart.p, S->sc.p, off);
+}
+
+// One batched CG step (per-mesh scalars; frozen columns keep x and r)
+template <int K>
+void cg_step_b(SolverState* S, int nu1, int nu2) {
+  camfe_ctx ctx = S->ctx;
+  GLevel& G = S->lev[S->D];
+  const size_t n = G.n;
+  const long long nb = (long long)(n / BLK);
+  CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices, SL * SW, 0,
+              ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              (const double*)S->P.p, S->Q.p, S->part.p);
+  dot_seg<K>(S, S->P.p, S->Q.p, K);
+  CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update_b<K>, (unsigned)nb, BLK, 0, ctx->stream, (long long)n,
+              (const int*)S->bmesh.p, (const double*)S->sc.p, S->X.p, S->R.p, (const double*)S->P.p,
+              (const double*)S->Q.p, S->part.p);
+  hipLaunchKernelGGL(k_finalize_seg<K>, (unsigned)S->nmesh, BLK, 0, ctx->stream, (const double*)S->part.p,
+                     S->bstart.p, S->sc.p, 2 * K);
+  precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
+  dot_seg<K>(S, S->R.p, S->Z.p, 3 * K);
+  hipStream_t st = ctx->stream;
+  hipLaunchKernelGGL(k_cg_direction_b<K>, (unsigned)nb, BLK, 0, st, (long long)n, (const int*)S->bmesh.p,
+                     (const double*)S->sc.p, (const double*)S->Z.p, S->P.p);
+  hipLaunchKernelGGL(k_copy_rz_b<K>, grid_for((size_t)S->nmesh * K, 64), 64, 0, st, S->nmesh, S->sc.p);
+}
+
+// Solve columns [c0, c0 + K) of every mesh; res[m] gets the mesh's result
+template <int K>
+void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::vector<DArr<double>>& db,
+                       std::vector<DArr<double>>& dx, const std::vector<int>& kk, int c0,
+                       std::vector<SolveResult>& res) {
+  SolverState* S = Bt->S.get();
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  GLevel& G = S->lev[S->D];
+  const int nm = S->nmesh;
+  const long long nk = (long long)G.n * K;
+  const unsigned gnk = grid_for(nk, BLK);
+  hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->B.p, nk, 0.0);
+  hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->X.p, nk, 0.0);
+  for (int m = 0; m < nm; ++m) {
+    const BatchMember& me = Bt->mem[m];
+    if (c0 >= kk[m]) continue;
+    hipLaunchKernelGGL(k_gather_in<K>, grid_for(me.n, BLK), BLK, 0, st, (const double*)db[m].p, (long long)me.n, c0,
+                       kk[m], me.iperm.p, S->B.p + me.rowoff * K);
+    if (o.x0_given)
+      hipLaunchKernelGGL(k_gather_in<K>, grid_for(me.n, BLK), BLK, 0, st, (const double*)dx[m].p, (long long)me.n,
+                         c0, kk[m], me.iperm.p, S->X.p + me.rowoff * K);
+  }
+  hipLaunchKernelGGL((k_fill<double>), grid_for(S->sc.n, BLK), BLK, 0, st, S->sc.p, (long long)S->sc.n, 0.0);
+  dot_seg<K>(S, S->B.p, S->B.p, 4 * K);
+  hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p,
+                     G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p,
+                     (const double*)S->X.p, S->R.p, (double*)nullptr);
+  dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
+  check_launch();
+  std::vector<double> hs((size_t)nm * SCS);
+  copy_out(ctx, hs.data(), S->sc.p, hs.size());
+  std::vector<double> rel((size_t)nm * K, 0.0);
+  // relative residual per (mesh, column); act = 1 while above rtol
+  auto update = [&](bool set_act) {
+    bool any = false;
+    for (int m = 0; m < nm; ++m)
+      for (int c = 0; c < K; ++c) {
+        double* sc = hs.data() + (size_t)m * SCS;
+        const bool col = c0 + c < kk[m];
+        const double bn = std::sqrt(sc[4 * K + c]);
+        const double v = !col ? 0.0 : (bn > 0 ? std::sqrt(sc[2 * K + c]) / bn : std::sqrt(sc[2 * K + c]));
+        rel[(size_t)m * K + c] = v;
+        const bool on = col && std::isfinite(v) && v > o.rtol;
+        if (set_act) sc[5 * K + c] = on ? 1.0 : 0.0;
+        any = any || on;
+      }
+    return any;
+  };
+  bool any = update(true);
+  copy_in(ctx, S->sc.p, hs.data(), hs.size());
+  int it = 0, cycles = 0;
+  const int nu1 = o.nu_pre, nu2 = o.nu_post;
+  const bool use_graph = !ctx->timer.on;
+  const int check_every = 4;
+  const long long gkey = ((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 8 + 5;
+  if (any && o.max_iter > 0) {
+    precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
+    ++cycles;
+    hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)S->Z.p, nk, S->P.p);
+    dot_seg<K>(S, S->R.p, S->Z.p, 0);
+    while (any && it < o.max_iter) {
+      const int mm = std::min(check_every, o.max_iter - it);
+      for (int i = 0; i < mm; ++i) {
+        if (use_graph) run_graph(S, gkey, [&] { cg_step_b<K>(S, nu1, nu2); });
+        else cg_step_b<K>(S, nu1, nu2);
+      }
+      check_launch();
+      it += mm;
+      cycles += mm;
+      copy_out(ctx, hs.data(), S->sc.p, hs.size());
+      any = update(true);
+      copy_in(ctx, S->sc.p, hs.data(), hs.size());
+    }
+    // true residuals of the final iterates
+    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p,
+                       G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p,
+                       (const double*)S->X.p, S->R.p, (double*)nullptr);
+    dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
+    copy_out(ctx, hs.data(), S->sc.p, hs.size());
+    update(false);
+  }
+  for (int m = 0; m < nm; ++m) {
+    const BatchMember& me = Bt->mem[m];
+    if (c0 >= kk[m]) continue;
+    hipLaunchKernelGGL(k_scatter_out<K>, grid_for(me.n, BLK), BLK, 0, st, (const double*)(S->X.p + me.rowoff * K),
+                       (long long)me.n, c0, kk[m], me.iperm.p, dx[m].p);
+    SolveResult& r = res[m];
+    r.it = std::max(r.it, it);
+    r.cycles += cycles;
+    for (int c = 0; c < K; ++c)
+      if (c0 + c < kk[m] && !(rel[(size_t)m * K + c] <= r.rel)) r.rel = rel[(size_t)m * K + c];
+  }
+  check_launch();
+}
+
 }  // namespace
 
 // The values of M (or L) changed with the structure kept: repack A = M + t L
@@ -1324,6 +1814,106 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
   if (g != CAMFE_OK) return g;
   if (rc != CAMFE_OK) set_last_error("solver stopped above rtol");
   return rc;
+}
+
+camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const* systems, int nsys, double t, double coarse_eps,
+                                camfe_batch* out) {
+  return guarded([&] {
+    CAMFE_REQUIRE(ctx && systems && nsys >= 1 && out, CAMFE_EINVAL, "bad argument");
+    ctx->use_device();
+    auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<camfe_batch_s> B(new camfe_batch_s());
+    B->ctx = ctx;
+    B->t = t;
+    B->coarse_eps = coarse_eps;
+    std::vector<SolverState*> ms;
+    for (int i = 0; i < nsys; ++i) {
+      camfe_sys s = systems[i];
+      CAMFE_REQUIRE(s && s->h->ctx == ctx, CAMFE_EINVAL, "systems must belong to the context");
+      CAMFE_REQUIRE(s->h->degree == systems[0]->h->degree, CAMFE_EINVAL, "systems must share the degree");
+      ms.push_back(ensure_solver(s, t, coarse_eps));
+    }
+    build_batch(B.get(), ms);
+    B->S->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = B.release();
+  });
+}
+
+camfe_status camfe_batch_info(camfe_batch b, int* levels, int64_t* rows) {
+  return guarded([&] {
+    CAMFE_REQUIRE(b, CAMFE_EINVAL, "null batch");
+    if (levels) *levels = b->S->D + 1;
+    if (rows) *rows = (int64_t)b->S->lev[b->S->D].n;
+  });
+}
+
+camfe_status camfe_batch_solve(camfe_batch bt, const camfe_solve_opts* o, const double* const* b, const int* k,
+                               double* const* x, camfe_solve_stats* stats) {
+  camfe_status rc = CAMFE_OK;
+  camfe_status g = guarded([&] {
+    CAMFE_REQUIRE(bt && o && b && k && x, CAMFE_EINVAL, "bad argument");
+    CAMFE_REQUIRE(o->t == bt->t && o->coarse_eps == bt->coarse_eps, CAMFE_EINVAL,
+                  "t and coarse_eps must be those the batch was built for");
+    CAMFE_REQUIRE(o->method == 0 && o->smoother == 0, CAMFE_EINVAL,
+                  "batched solves use CG with the Gauss-Seidel V-cycle");
+    CAMFE_REQUIRE(o->precision == 0 || o->precision == 1, CAMFE_EINVAL, "precision must be 0 or 1");
+    CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0, CAMFE_EINVAL, "bad sweep counts");
+    SolverState* S = bt->S.get();
+    camfe_ctx ctx = bt->ctx;
+    ctx->use_device();
+    S->precision = o->precision;
+    const int nm = S->nmesh;
+    std::vector<int> kk(k, k + nm);
+    int kmax = 0;
+    for (int m = 0; m < nm; ++m) {
+      CAMFE_REQUIRE(kk[m] >= 1 && b[m] && x[m], CAMFE_EINVAL, "every mesh needs k >= 1, b and x");
+      kmax = std::max(kmax, kk[m]);
+    }
+    std::vector<DArr<double>> db(nm), dx(nm);
+    for (int m = 0; m < nm; ++m) {
+      const size_t nn = bt->mem[m].n * (size_t)kk[m];
+      db[m].alloc(nn);
+      dx[m].alloc(nn);
+      copy_in(ctx, db[m].p, b[m], nn);
+      if (o->x0_given) copy_in(ctx, dx[m].p, (const double*)x[m], nn);
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    std::vector<SolveResult> res(nm);
+    for (int c0 = 0; c0 < kmax; c0 += KMAXS) {
+      switch (std::min(KMAXS, kmax - c0)) {
+        case 1: batch_solve_block<1>(bt, *o, db, dx, kk, c0, res); break;
+        case 2: batch_solve_block<2>(bt, *o, db, dx, kk, c0, res); break;
+        case 3: batch_solve_block<3>(bt, *o, db, dx, kk, c0, res); break;
+        default: batch_solve_block<4>(bt, *o, db, dx, kk, c0, res); break;
+      }
+    }
+    ctx->sync();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int m = 0; m < nm; ++m) {
+      copy_out(ctx, x[m], dx[m].p, dx[m].n);
+      if (stats) {
+        stats[m].iterations = res[m].it;
+        stats[m].fell_back = 0;
+        stats[m].cycles = res[m].cycles;
+        stats[m].eps_regularised = 0;
+        stats[m].rel_residual = res[m].rel;
+        stats[m].seconds = secs;
+        stats[m].setup_seconds = S->setup_seconds;
+      }
+      if (!(res[m].rel <= o->rtol)) rc = CAMFE_ENOCONV;
+    }
+    ctx->sync();
+  });
+  if (g != CAMFE_OK) return g;
+  if (rc != CAMFE_OK) set_last_error("solver stopped above rtol for at least one mesh");
+  return rc;
+}
+
+void camfe_batch_destroy(camfe_batch b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b;
 }
 
 }  // extern "C"

@@ -40,6 +40,15 @@ struct GLevel {
   // work vectors, n x KMAXS row-major (t: Jacobi ping-pong)
   DArr<double> x64, b64, r64, t64;
   DArr<float> x32, b32, r32, t32;
+  // batched solver only: meshes whose coarsest depth sits at this level and is
+  // solved directly: first row of each, cumulative row counts (ncb + 1) and
+  // the offset of each one's dense inverse in cb_a64 / cb_a32
+  int ncb = 0;
+  long long cb_rows = 0;
+  DArr<int> cb_rowoff, cb_cum;
+  DArr<long long> cb_aoff;
+  DArr<double> cb_a64;
+  DArr<float> cb_a32;
 };
 
 struct SolverState {
@@ -62,6 +71,12 @@ struct SolverState {
   DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
   DArr<double> part;         // per-block partial sums of the reductions
   double setup_seconds = 0;
+  // batched solver: nmesh meshes side by side at every level (rows mesh-major,
+  // each mesh's rows padded to whole SBLK-row blocks); bmesh: mesh of each
+  // finest-level block, bstart: first block of each mesh (nmesh + 1)
+  bool batch = false;
+  int nmesh = 0;
+  DArr<int> bmesh, bstart;
   // captured iterations (one graph per right-hand-side count / precision / sweeps / method / smoother)
   hipStream_t cap = nullptr;
   std::map<long long, hipGraphExec_t> graphs;

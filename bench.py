@@ -71,7 +71,7 @@ def train_smoother(cf, ctx, meshgen, steps=150):
             (meshgen.torus_knot(nu=2048, nv=16, seed=5), 7, 1e-4)]
     hs, ss = [], []
     for (V, F), depth, t in fams:
-        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, degree=1, max_coarse=512)
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, degree=1, max_coarse=4096)
         hs.append(h)
         ss.append(cf.camfe_assemble(h))
     t0 = time.perf_counter()
@@ -101,7 +101,7 @@ def held_out_eval(cf, ctx, meshgen, model, size):
     for name, ((V, F), depth, t) in meshes.items():
         log(f"[bench] held-out {name}: {len(F)} tris, depth {depth}")
         h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=depth,
-                                     degree=1, max_coarse=512)
+                                     degree=1, max_coarse=4096)
         s = cf.camfe_assemble(h)
         fv = torch.from_numpy(np.asfortranarray(V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)).to(dev)
         b = cf.camfe_load_vector(s, h, fv)
@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="two_sheets_256_depth8", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--max-coarse", type=int, default=512,
+    ap.add_argument("--max-coarse", type=int, default=4096,
                     help="coarsest depth = finest with at most this many functions (solved directly)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")

@@ -160,6 +160,8 @@ typedef struct {
                      /*    recurrences and coarsest solve in FP64                 */
   int x0_given;      /* start from x instead of 0                                 */
   double coarse_eps; /* eps added to the unit-diagonal-scaled coarsest matrix     */
+                     /*    (1e-6 recommended: regularises singular systems, and   */
+                     /*    FP32 cycles cannot amplify rounding past O(0.1))       */
   int smoother;      /* 0: multicolour Gauss-Seidel (Section 5.2); 1: weighted    */
                      /*    Jacobi with constant omega; 2: Jacobi with per-row     */
                      /*    omega from the attached learned model                  */

@@ -25,8 +25,9 @@
 //   quadrature + assembly ........... Section 3.1 Eq. (2) (stiffness with the
 //                                    surface gradient, load), Section 5.1 (mass)
 //   V-cycle with Gauss-Seidel ....... Section 3.2 / 4.3 (multigrid on nested spaces),
-//                                    Section 5.2 (Gauss-Seidel smoothing), Section 5.3
-//                                    discussion (eps * Id for singular systems)
+//                                    Section 5.2 (Gauss-Seidel smoothing), the
+//                                    Discussion closing Section 5 (eps * Id for
+//                                    singular systems)
 //
 // Parity pins for every function here live in tests/test_oracle_*.py.
 #include <algorithm>
@@ -907,8 +908,9 @@ int oracle_load_vector(void* hp, int d, const double* fv, int k, double* b) {
 //         forward colour order before the coarse correction, reverse after,
 //         nu1 == nu2, exact coarse solve), one independent CG per column.
 // The coarsest level is solved with a Cholesky factor of the unit-diagonal
-// scaled matrix plus coarse_eps * Id (the eps * Id remedy of the Section 5.3
-// discussion for singular systems), when it holds at most max_coarse rows;
+// scaled matrix plus coarse_eps * Id (the eps * Id remedy that the Discussion
+// closing Section 5 gives for singular systems), when it holds at most
+// max_coarse rows;
 // otherwise it is only relaxed.
 // b, x: n x k col-major; x0_given: start from x, else x = 0.
 // stats[0] = V-cycles applied, stats[1] = max relative residual, stats[2] =

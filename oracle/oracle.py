@@ -170,7 +170,7 @@ class Oracle:
         return b
 
     def solve(self, t, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, x0=None, mode="pcg",
-              coarse_eps=1e-10):
+              coarse_eps=1e-6):
         """mode 'pcg' (CG preconditioned by one V-cycle) or 'vcycle' (stationary)."""
         n = self.count(self.depth, "functions")
         b, k = _colmajor(b, n)

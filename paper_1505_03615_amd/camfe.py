@@ -31,6 +31,7 @@ EXPORTS = [
     "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy",
 ]
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
+DEFAULT_COARSE_EPS = 1e-6   # eps * Id on the unit-diagonal-scaled coarsest matrix (the library's own default)
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
            "uf_link", "support_sort", "cg_vector"]
 
@@ -196,7 +197,7 @@ def camfe_ctx_kernel_time(ctx, kernel: str):
 
 
 # --------------------------------------------------------------- hierarchy
-def camfe_hierarchy_build(ctx, V, F, depth, degree=1, split=1, min_depth=0, max_coarse=2048, box=None):
+def camfe_hierarchy_build(ctx, V, F, depth, degree=1, split=1, min_depth=0, max_coarse=4096, box=None):
     lib = load()
     Vc, Fc = _rowmajor(V, "float64"), _rowmajor(F, "int32")
     o = HierOpts()
@@ -326,7 +327,7 @@ def camfe_eval_vertices(s, nv, x):
 
 
 def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0, precision=0, x0=None,
-                coarse_eps=1e-10, raise_on_noconv=False, smoother=0, omega=0.0):
+                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0):
     """Returns (x, stats dict).  method 0 = V-cycle-preconditioned CG, 1 = stationary;
     smoother 0 = multicolour Gauss-Seidel, 1 = Jacobi(omega), 2 = attached learned model."""
     bc, n, k = _colmajor(b)
@@ -359,7 +360,7 @@ def camfe_system_destroy(s):
 
 
 def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, smoother=0,
-                    omega=0.0, coarse_eps=1e-10, raise_on_noconv=False):
+                    omega=0.0, coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False):
     """One tracked cMCF step; X (n x 3, numpy or torch) is updated in place and returned with the stats."""
     Xc, n, k = _colmajor(X)
     if k != 3:
@@ -382,7 +383,7 @@ def _handle(x):
     return x.value if isinstance(x, C.c_void_p) else x
 
 
-def camfe_batch_create(ctx, systems, t, coarse_eps=1e-10):
+def camfe_batch_create(ctx, systems, t, coarse_eps=DEFAULT_COARSE_EPS):
     arr = (C.c_void_p * len(systems))(*[_handle(x) for x in systems])
     b = C.c_void_p()
     _check(load().camfe_batch_create(ctx, C.cast(arr, C.c_void_p), len(systems), t, coarse_eps, C.byref(b)))
@@ -396,7 +397,7 @@ def camfe_batch_info(bt):
 
 
 def camfe_batch_solve(bt, bs, t, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, x0s=None,
-                      coarse_eps=1e-10, raise_on_noconv=False):
+                      coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False):
     """bs: list of n_m x k_m right-hand sides.  Returns (list of solutions, list of stats dicts)."""
     cols = [_colmajor(b) for b in bs]
     if x0s is None:

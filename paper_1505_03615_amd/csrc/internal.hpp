@@ -83,6 +83,8 @@ namespace camfe {
 // assemble.hip
 void assemble_level(camfe_sys s, int d, bool want_L, bool want_M);
 void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b);   // b n x k row-major (device)
+// dense.hip: out = diag(s) A^-1 diag(s) for SPD A (n x n row-major, destroyed)
+void spd_inverse_scaled(camfe_ctx ctx, double* A, int n, const double* s, double* out);
 // solve.hip helpers used by the C ABI in assemble.hip
 void csr_apply(camfe_ctx ctx, const SLevel& L, double a, double b, const double* x, int k, double* y);
 }  // namespace camfe

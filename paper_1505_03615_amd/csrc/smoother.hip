@@ -163,7 +163,7 @@ __global__ __launch_bounds__(BLK) void k_mlp_omega(const float* feat, long long 
   }
   if (omega) omega[i] = om;
   if (winvd64) winvd64[i] = om * invd[i];
-  if (winvd32) winvd32[i] = (float)(om * invd[i]);
+  if (winvd32) winvd32[i] = fabs(om * invd[i]) < 3.0e38 ? (float)(om * invd[i]) : 0.0f;
 }
 
 // per-row back-propagation: dz -> hidden deltas (recomputing the forward)
@@ -389,7 +389,7 @@ __global__ void k_scale_invd(const double* invd, long long n, double omega, doub
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
   w64[i] = omega * invd[i];
-  w32[i] = (float)(omega * invd[i]);
+  w32[i] = fabs(omega * invd[i]) < 3.0e38 ? (float)(omega * invd[i]) : 0.0f;
 }
 
 // ------------------------------------------------------------ host side
@@ -640,7 +640,7 @@ camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double 
     CAMFE_REQUIRE(depth >= h->d0 && depth <= h->D, CAMFE_ESTATE, "depth not assembled");
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
-    SolverState* S = ensure_solver(s, t, 1e-10);
+    SolverState* S = ensure_solver(s, t, DEFAULT_COARSE_EPS);
     const GLevel& G = S->lev[depth];
     DArr<float> feat;
     features(s, S, depth, feat);
@@ -665,7 +665,7 @@ camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const fl
     CAMFE_REQUIRE(depth >= h->d0 && depth <= h->D, CAMFE_ESTATE, "depth not assembled");
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
-    SolverState* S = ensure_solver(s, t, 1e-10);
+    SolverState* S = ensure_solver(s, t, DEFAULT_COARSE_EPS);
     const GLevel& G = S->lev[depth];
     DArr<float> feat;
     features(s, S, depth, feat);
@@ -709,7 +709,7 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
       camfe_sys s = systems[i];
       CAMFE_REQUIRE(s && s->h->ctx == ctx, CAMFE_EINVAL, "systems must belong to the context");
       CAMFE_REQUIRE(s->h->degree == 1, CAMFE_EINVAL, "the learned smoother is defined for degree 1");
-      SolverState* S = ensure_solver(s, o->t, 1e-10);
+      SolverState* S = ensure_solver(s, o->t, DEFAULT_COARSE_EPS);
       const int saved = S->smoother;
       S->smoother = 0;
       for (int d = S->d0 + 1; d <= S->D; ++d) {

@@ -61,6 +61,9 @@ __global__ void k_slice_width(const int* ptr, const int* perm, const int* row0, 
   }
   width[s] = w * SL;
 }
+// v as FP32, or 0 where it has no finite FP32 value
+__device__ inline float f32_or_zero(double v) { return fabs(v) < 3.0e38 ? (float)v : 0.0f; }
+
 // pack A = M + t L of internal row i into its slice (valid lanes only)
 __global__ void k_sell_fill(const int* ptr, const int* col, const double* M, const double* L, double t,
                             const int* perm, const int* iperm, const int* sl_ptr, const int* row0, const int* rows,
@@ -90,9 +93,11 @@ __global__ void k_sell_fill(const int* ptr, const int* col, const double* M, con
       sval32[o] = 0.0f;
     }
   }
-  // a function of zero computed mass has an empty row: nothing to relax
+  // a function of zero computed mass has an empty row: nothing to relax; a
+  // diagonal so small that 1 / A_ii has no FP32 value (rounding slivers) makes
+  // the row numerically empty in single precision, and the FP32 sweeps skip it
   invd[i] = diag != 0.0 ? 1.0 / diag : 0.0;
-  invd32[i] = diag != 0.0 ? (float)(1.0 / diag) : 0.0f;
+  invd32[i] = diag != 0.0 ? f32_or_zero(1.0 / diag) : 0.0f;
 }
 __global__ void k_sell_pad(const int* sl_ptr, const int* row0, const int* rows, long long ns, int* scol,
                            double* sval, float* sval32) {
@@ -174,54 +179,6 @@ __global__ void k_dense_scaled(const int* ptr, const int* col, const double* M, 
     }
   // zero-mass functions get an identity row (their right-hand side is 0)
   A[i * n + i] = (di > 0.0 ? A[i * n + i] : 1.0) + eps;
-}
-// right-looking Cholesky of the lower triangle, one workgroup
-__global__ __launch_bounds__(1024) void k_cholesky(double* A, int n, int* fail) {
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double a = A[(long long)j * n + j];
-      if (!(a > 0.0)) { *fail = 1; a = 1.0; }
-      A[(long long)j * n + j] = sqrt(a);
-    }
-    __syncthreads();
-    const double ljj = A[(long long)j * n + j];
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[(long long)i * n + j] /= ljj;
-    __syncthreads();
-    const long long m = n - j - 1;
-    const long long tot = m * (m + 1) / 2;
-    for (long long q = threadIdx.x; q < tot; q += blockDim.x) {
-      // (i, k) with j < k <= i < n, enumerated row by row of the trailing triangle
-      long long r = (long long)((sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5);
-      while (r * (r + 1) / 2 > q) --r;
-      while ((r + 1) * (r + 2) / 2 <= q) ++r;
-      long long c = q - r * (r + 1) / 2;
-      int i = j + 1 + (int)r, k = j + 1 + (int)c;
-      A[(long long)i * n + k] -= A[(long long)i * n + j] * A[(long long)k * n + j];
-    }
-    __syncthreads();
-  }
-}
-// column c of the inverse of L L^T, scaled back: Ainv = S (L L^T)^-1 S
-__global__ void k_chol_inverse(const double* Lf, int n, const double* s, double* work, double* Ainv,
-                               float* Ainv32) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  double* y = work + (long long)c * n;
-  for (int i = 0; i < n; ++i) {
-    double v = (i == c) ? 1.0 : 0.0;
-    for (int p = 0; p < i; ++p) v -= Lf[(long long)i * n + p] * y[p];
-    y[i] = v / Lf[(long long)i * n + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double v = y[i];
-    for (int p = i + 1; p < n; ++p) v -= Lf[(long long)p * n + i] * y[p];
-    y[i] = v / Lf[(long long)i * n + i];
-  }
-  for (int i = 0; i < n; ++i) {
-    double v = s[i] * y[i] * s[c];
-    Ainv[(long long)i * n + c] = v;
-    Ainv32[(long long)i * n + c] = (float)v;
-  }
 }
 __global__ void k_inv_sqrt_diag(int n, double* s, const double* diagsrc) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -456,9 +413,11 @@ __global__ void k_prolong(const int* Pptr, const int* Pcol, const T* Pw, long lo
   for (int q = 0; q < K; ++q) xf[i * K + q] += acc[q];
 }
 
-// x = Ainv b at the coarsest depth, one wavefront per row (FP64 accumulate)
+// x = Ainv b at the coarsest depth, one wavefront per row; the inverse is
+// FP64 in both precisions (in FP32 the regularised inverse of a singular
+// coarsest matrix would lose everything but its null-space term)
 template <class T, int K>
-__global__ void k_coarse(const T* Ainv, int n, const T* b, T* x) {
+__global__ void k_coarse(const double* Ainv, int n, const T* b, T* x) {
   long long wave = (blockIdx.x * (long long)BLK + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (wave >= n) return;
@@ -481,7 +440,7 @@ __global__ void k_coarse(const T* Ainv, int n, const T* b, T* x) {
 // batched coarse solves: x = Ainv_j b on the rows of every mesh j whose
 // coarsest depth is this level (one wavefront per row)
 template <class T, int K>
-__global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long long* aoff, const T* ainv,
+__global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long long* aoff, const double* ainv,
                            const T* b, T* x) {
   long long wave = (blockIdx.x * (long long)BLK + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
@@ -490,7 +449,7 @@ __global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long
   while (cum[j + 1] <= wave) ++j;
   const int n = cum[j + 1] - cum[j];
   const long long lr = wave - cum[j];
-  const T* A = ainv + aoff[j];
+  const double* A = ainv + aoff[j];
   const long long r0 = rowoff[j];
   double acc[K];
 #pragma unroll
@@ -810,26 +769,18 @@ void setup_coarsest(camfe_sys s, SolverState* st) {
   if (!st->direct) return;
   const int n = (int)G.n;
   st->n0 = n;
-  DArr<double> A((size_t)n * n), work((size_t)n * n), dg(n), sv(n);
+  DArr<double> A((size_t)n * n), dg(n), sv(n);
   zero(ctx, A.p, A.n);
   hipLaunchKernelGGL(k_dense_scaled, grid_for(n, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p, st->t,
                      G.perm.p, G.iperm.p, (long long)n, st->coarse_eps, A.p);
-  zero(ctx, ctx->d_flag, 1);
-  hipLaunchKernelGGL(k_cholesky, 1, 1024, 0, ctx->stream, A.p, n, ctx->d_flag);
-  check_launch();
-  int fail = read_scalar(ctx, ctx->d_flag);
-  CAMFE_REQUIRE(fail == 0, CAMFE_ESINGULAR, "coarsest Cholesky failed (increase coarse_eps)");
   hipLaunchKernelGGL(k_diag_of, grid_for(n, BLK), BLK, 0, ctx->stream, S.ptr.p, S.col.p, S.M.p, S.L.p, st->t,
                      G.perm.p, (long long)n, dg.p);
   hipLaunchKernelGGL(k_inv_sqrt_diag, grid_for(n, BLK), BLK, 0, ctx->stream, n, sv.p, (const double*)dg.p);
-  if (st->Ainv64.n != (size_t)n * n) {   // kept in place on refresh: captured graphs hold these addresses
-    st->Ainv64.alloc((size_t)n * n);
-    st->Ainv32.alloc((size_t)n * n);
-  }
-  hipLaunchKernelGGL(k_chol_inverse, grid_for(n, 64), 64, 0, ctx->stream, A.p, n, sv.p, work.p, st->Ainv64.p,
-                     st->Ainv32.p);
   check_launch();
-  ctx->sync();
+  if (st->Ainv64.n != (size_t)n * n)   // kept in place on refresh: captured graphs hold its address
+    st->Ainv64.alloc((size_t)n * n);
+  // Ainv = D^-1/2 (D^-1/2 A D^-1/2 + eps I)^-1 D^-1/2
+  spd_inverse_scaled(ctx, A.p, n, sv.p, st->Ainv64.p);
 }
 
 SolverState* setup(camfe_sys s, double t, int precision, double coarse_eps) {
@@ -903,12 +854,7 @@ template <>
 const double* rw_of<double>(const GLevel& g) { return g.Rw64.p; }
 template <>
 const float* rw_of<float>(const GLevel& g) { return g.Rw32.p; }
-template <class T>
-const T* ainv_of(const SolverState* s);
-template <>
-const double* ainv_of<double>(const SolverState* s) { return s->Ainv64.p; }
-template <>
-const float* ainv_of<float>(const SolverState* s) { return s->Ainv32.p; }
+
 
 // algorithmic bytes of one matrix pass over rows with z nonzeros: matrix
 // values plus read b, read x, write x (or r)
@@ -965,19 +911,12 @@ void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward) {
                        (long long)(G.n * K), x);
 }
 
-template <class T>
-const T* cb_of(const GLevel& g);
-template <>
-const double* cb_of<double>(const GLevel& g) { return g.cb_a64.p; }
-template <>
-const float* cb_of<float>(const GLevel& g) { return g.cb_a32.p; }
-
 // batched solver: direct solves of the meshes whose coarsest depth is this level
 template <class T, int K>
 void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
   if (!G.ncb) return;
   hipLaunchKernelGGL((k_coarse_b<T, K>), grid_for((size_t)G.cb_rows * 64, BLK), BLK, 0, S->ctx->stream, G.ncb,
-                     G.cb_rowoff.p, G.cb_cum.p, G.cb_aoff.p, cb_of<T>(G), b, x);
+                     G.cb_rowoff.p, G.cb_cum.p, G.cb_aoff.p, (const double*)G.cb_a64.p, b, x);
 }
 
 // One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
@@ -994,9 +933,9 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   }
   if (d == S->d0) {
     if (S->direct) {
-      const double w = (double)S->n0 * S->n0 * sizeof(T) + 2.0 * S->n0 * K * sizeof(T);
-      CAMFE_TIMED(ctx, KT_COARSE, w, (k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st, ainv_of<T>(S),
-                  S->n0, b, x);
+      const double w = (double)S->n0 * S->n0 * sizeof(double) + 2.0 * S->n0 * K * sizeof(T);
+      CAMFE_TIMED(ctx, KT_COARSE, w, (k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st,
+                  (const double*)S->Ainv64.p, S->n0, b, x);
     } else {
       smooth<T, K>(S, G, b, x, nu1, true);
       smooth<T, K>(S, G, b, x, nu2, false);
@@ -1394,13 +1333,11 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
       copy_in(ctx, G.cb_cum.p, ccum.data(), ccum.size());
       copy_in(ctx, G.cb_aoff.p, caoff.data(), caoff.size());
       G.cb_a64.alloc(atot);
-      G.cb_a32.alloc(atot);
       int j = 0;
       for (int m = 0; m < nm; ++m)
         if (present(m, bd) && mdepth(m, bd) == ms[m]->d0 && ms[m]->direct) {
           const size_t na = (size_t)ms[m]->n0 * ms[m]->n0;
           dcopy(ctx, G.cb_a64.p + caoff[j], ms[m]->Ainv64.p, na * sizeof(double));
-          dcopy(ctx, G.cb_a32.p + caoff[j], ms[m]->Ainv32.p, na * sizeof(float));
           ++j;
         }
     }

@@ -13,6 +13,11 @@ namespace camfe {
 constexpr int SBLK = 256;     // threads per block of the vector kernels
 constexpr int SL = 64;        // SELL slice height = wavefront width
 constexpr int KMAXS = 4;      // right-hand sides per pass
+// eps of eps * Id added to the unit-diagonal-scaled coarsest matrix when a
+// call does not say (the learned-smoother calls): large enough that FP32
+// rounding of a singular system's restricted residual along its null space
+// (~1e-7) is not amplified past O(0.1), and without effect on regular systems
+constexpr double DEFAULT_COARSE_EPS = 1e-6;
 
 struct GLevel {
   int d = 0;
@@ -42,13 +47,12 @@ struct GLevel {
   DArr<float> x32, b32, r32, t32;
   // batched solver only: meshes whose coarsest depth sits at this level and is
   // solved directly: first row of each, cumulative row counts (ncb + 1) and
-  // the offset of each one's dense inverse in cb_a64 / cb_a32
+  // the offset of each one's dense FP64 inverse in cb_a64
   int ncb = 0;
   long long cb_rows = 0;
   DArr<int> cb_rowoff, cb_cum;
   DArr<long long> cb_aoff;
   DArr<double> cb_a64;
-  DArr<float> cb_a32;
 };
 
 struct SolverState {
@@ -64,8 +68,7 @@ struct SolverState {
   std::vector<GLevel> lev;   // index = depth
   bool direct = false;
   int n0 = 0;
-  DArr<double> Ainv64;
-  DArr<float> Ainv32;
+  DArr<double> Ainv64;       // coarsest inverse, FP64 in both precisions
   // outer iteration vectors (finest, internal order, n x KMAXS row-major)
   DArr<double> X, R, Z, P, Q, B;
   DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb

@@ -167,6 +167,31 @@ def test_stationary_cycles_track_oracle(cf, ctx):
         assert abs(x - xo).max() <= 1e-9 * abs(xo).max(), cyc
 
 
+def test_large_direct_coarsest_tracks_oracle(cf, ctx):
+    """Coarsest depth with ~2k functions solved through the blocked dense
+    inverse: stationary cycles match the oracle's (dense Cholesky) cycles."""
+    c = CASES["sphere_deg1"]
+    h = cf.camfe_hierarchy_build(ctx, c["V"], c["F"], depth=5, max_coarse=2048)
+    s = cf.camfe_assemble(h)
+    o = Oracle(c["V"], c["F"], 5, max_coarse=2048).check().assemble()
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    assert d0 == o.coarsest and cf.camfe_hierarchy_info(h, d0)[2] > 1024
+    b = o.load_vector(c["f"])
+    for cyc in (1, 3):
+        say(f"[gpu] large coarsest: {cyc} cycles")
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-30, max_iter=cyc, method=1)
+        xo, io = o.solve(1e-3, b, rtol=1e-30, max_iter=cyc, mode="vcycle")
+        assert st["eps_regularised"] == 1
+        assert abs(x - xo).max() <= 1e-9 * abs(xo).max(), cyc
+    for precision in (0, 1):
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-10, max_iter=200, precision=precision)
+        Mo, Lo = o.matrices(5)
+        r = np.linalg.norm(b - (Mo + 1e-3 * Lo) @ x, axis=0) / np.linalg.norm(b, axis=0)
+        assert st["converged"] and np.all(r <= 1e-9), (precision, r)
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)
+
+
 def test_reassemble_mass_with_triangle_weights(cf, ctx):
     c = CASES["knot"]
     h = cf.camfe_hierarchy_build(ctx, c["V"], c["F"], depth=6, max_coarse=256)
@@ -245,3 +270,40 @@ def test_full_size_two_sheets_properties(cf, ctx):
         assert st["converged"] and r <= 1e-6, (st, r)
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
+
+
+def test_full_size_knot_flow_system(cf, ctx):
+    """Config 3 at its full size ((3,5) knot tube, 2,097,152 triangles, depth
+    10, t = 1e-4, three right-hand sides): partition of unity and zero row
+    sums on the GPU's exports at the finest depth, and FP64, mixed-precision
+    and learned-smoother solves to 1e-8 checked with the exported FP64
+    matrices.  The mesh has rounding-sliver functions whose diagonal has no
+    FP32 inverse; the mixed solve must skip them in its FP32 sweeps."""
+    V, F = meshgen.torus_knot(nu=16384, nv=64, seed=3)
+    say("[gpu] build knot 2M depth 10")
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=10, max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    M = cf.camfe_export_matrix(s, h, fin, 0)
+    L = cf.camfe_export_matrix(s, h, fin, 1)
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    # fragments are clipped in depth-10 grid units (coordinates up to 2^10), so
+    # each clip rounds about 2^10 ulps of the fragment: 1e-9 instead of 1e-12
+    assert abs(M.sum() - area) <= 1e-9 * area
+    assert abs(L @ np.ones(L.shape[0])).max() <= 1e-9 * abs(L).max()
+    X0 = cf.camfe_linear_coeffs(s, h)
+    b = M @ X0
+    A = M + 1e-4 * L
+    model = cf.camfe_model_create(None, levels=3, bf16=True)
+    cf.camfe_smoother_attach(s, model)
+    try:
+        for precision, smoother in ((0, 0), (1, 0), (1, 2)):
+            say(f"[gpu] solve knot 2M precision={precision} smoother={smoother}")
+            x, st = cf.camfe_solve(s, b, t=1e-4, rtol=1e-8, max_iter=1500, precision=precision, smoother=smoother)
+            r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+            assert st["converged"] and not st["fell_back"] and np.all(r <= 1e-6), (precision, smoother, st, r)
+    finally:
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_model_destroy(model)
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)

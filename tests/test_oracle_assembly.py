@@ -3,7 +3,7 @@
 Closed forms (partition of unity, monomial integrals over a triangle, linear
 fields), invariants (symmetry, zero row sums of L, Galerkin identity of the
 nested spaces, Section 4.1 Claim), the planar linear dependency of the
-Section 5.3 discussion, the split's block structure and the sphere spectrum.
+the Discussion closing Section 5, the split's block structure and the sphere spectrum.
 """
 import math
 
@@ -203,7 +203,7 @@ def test_load_vector_constant_and_linear():
 
 
 def test_planar_sheet_linear_dependency():
-    """Section 5.3 discussion: a planar component gives a singular system.  The
+    """Discussion closing Section 5: a planar component gives a singular system.  The
     corner samples of the linear function vanishing on the plane are an exact
     null vector of M and L (any orientation; axis-aligned planes give more)."""
     V, F, _, _ = meshgen.two_sheets(12, gap=0.2, rotate=True)

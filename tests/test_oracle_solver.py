@@ -1,4 +1,4 @@
-"""Pins of the oracle's multigrid solver (Sections 3.2, 4.3, 5.2; 5.3 discussion).
+"""Pins of the oracle's multigrid solver (Sections 3.2, 4.3, 5.2; the Discussion closing Section 5).
 
 Against a dense direct solve, a textbook sequential Gauss-Seidel sweep, the
 colour-independence that makes the multicolour order a Gauss-Seidel order,
@@ -96,7 +96,7 @@ def test_multiple_rhs_columns_independent(small):
 
 
 def test_singular_planar_system_still_solves():
-    """Planar sheets make (M + tL) singular (Section 5.3 discussion); the
+    """Planar sheets make (M + tL) singular (Discussion closing Section 5); the
     system stays consistent and the eps-regularised coarse solve keeps the
     iteration bounded."""
     V, F, xl, sheet = meshgen.two_sheets(32, gap=1.0 / 32, rotate=False)

@@ -63,6 +63,58 @@ def cpu_baseline(sample_n=128, sample_depth=7):
             "seconds": secs, "converged": bool(info["converged"])}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_colour_two_sheets_d8_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1505_03615_amd", "csrc", "solve.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the finest-depth FP64 colour sweep from the
+    committed counter summary, or None when solve.hip has changed since the
+    counters were taken (the summary records the source's SHA-256)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline(cf, s, meas, reps=50):
+    """Algorithmic bytes of one launch of the finest-depth kernel over its
+    average duration (HIP events around a captured graph of back-to-back
+    launches on the library's stream), against the HBM peak."""
+    avg64, by64 = cf.camfe_measure_kernel(s, meas, 0, reps)
+    avg32, by32 = cf.camfe_measure_kernel(s, meas, 1, reps)
+    achieved = by64 / (avg64 / 1000.0) / 1e9
+    return {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved, "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "traffic": measured_traffic() if meas == "gs_colour" else None,
+            "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
+            "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
+                     "bytes_per_launch": by32}}
+
+
+def calibrate_copy(torch, dev):
+    """A plain device copy of 2^27 doubles (1 GiB read, 1 GiB written), three
+    times: the reference for scaling the memory counters."""
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    bb = torch.empty_like(a)
+    for _ in range(3):
+        bb.copy_(a)
+    torch.cuda.synchronize()
+
+
 def train_smoother(cf, ctx, meshgen, steps=150):
     """Learned smoother trained (untimed) on small members of the three training
     families: an icosphere, two close parallel sheets and a knot tube."""
@@ -136,6 +188,9 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--held-out", default="small", choices=["full", "small", "none"],
                     help="learned-smoother evaluation on held-out meshes (8.4M or 2.1M tris)")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
+                         "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -153,6 +208,20 @@ def main():
     fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
     stream = torch.cuda.current_stream()
     ctx = cf.camfe_ctx_create(0, stream)
+
+    if args.roofline_only:
+        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
+        s = cf.camfe_assemble(h)
+        b = cf.camfe_load_vector(s, h, fd)
+        cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=0)     # solver setup only
+        out = {"roofline": roofline(cf, s, "gs_colour")}
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+        if args.calibrate_copy:
+            calibrate_copy(torch, dev)
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
 
     keep = {}
     log("[bench] training the learned smoother")
@@ -255,25 +324,14 @@ def main():
                                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
         else:
             meas = dom if dom in ("gs_colour", "residual", "spmv_dot") else "gs_colour"
-            avg64, by64 = cf.camfe_measure_kernel(keep["s"], meas, 0, 50)
-            avg32, by32 = cf.camfe_measure_kernel(keep["s"], meas, 1, 50)
-            achieved = by64 / (avg64 / 1000.0) / 1e9
-            out["roofline"] = {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved,
-                               "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                               "traffic": None, "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
-                               "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
-                                        "bytes_per_launch": by32}}
+            out["roofline"] = roofline(cf, keep["s"], meas)
     cf.camfe_system_destroy(keep["s"])
     cf.camfe_hierarchy_destroy(keep["h"])
     if args.held_out != "none":
         out["learned_held_out"] = held_out_eval(cf, ctx, meshgen, model, args.held_out)
     cf.camfe_model_destroy(model)
     if args.calibrate_copy:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-        bb = torch.empty_like(a)
-        for _ in range(3):
-            bb.copy_(a)
-        torch.cuda.synchronize()
+        calibrate_copy(torch, dev)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline()

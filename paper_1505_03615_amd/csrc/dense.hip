@@ -1,7 +1,8 @@
 // Dense symmetric positive definite inverse for the coarsest depth: blocked
 // right-looking Cholesky A = L L^T (diagonal blocks factored in LDS, panels by
-// triangular solves, trailing updates by a tiled FP64 GEMM), then the blocked
-// inverse of L, then A^-1 = L^-T L^-1 by one more GEMM.  All matrices are n x n
+// triangular solves, trailing updates by a tiled FP64 GEMM), then the inverse
+// of L by recursive halving (two GEMMs per split), then A^-1 = L^-T L^-1 by one
+// more GEMM.  All matrices are n x n
 // row-major in device memory.
 #include <algorithm>
 #include <cmath>
@@ -174,6 +175,23 @@ void gemm(camfe_ctx ctx, int M, int N, int Kd, const double* A, long long lda, c
                      beta, lower ? 1 : 0);
 }
 
+// W[o.., o..] = inverse of the lower-triangular m x m block L[o.., o..]; the
+// two halves recurse, the off-diagonal block takes two GEMMs through T
+void trinv(camfe_ctx ctx, const double* L, double* W, double* T, long long n, int o, int m) {
+  if (m <= NB) {
+    hipLaunchKernelGGL(k_trtri_diag, 1, 64, 0, ctx->stream, L, W, n, o, m);
+    return;
+  }
+  const int h = (m / 2 + NB - 1) / NB * NB;   // a multiple of NB, 0 < h < m
+  trinv(ctx, L, W, T, n, o, h);
+  trinv(ctx, L, W, T, n, o + h, m - h);
+  // T = L21 W11 ((m-h) x h), then W21 = -W22 T
+  gemm<false, false>(ctx, m - h, h, h, L + (long long)(o + h) * n + o, n, W + (long long)o * n + o, n, T, h, 1.0,
+                     0.0, false);
+  gemm<false, false>(ctx, m - h, h, m - h, W + (long long)(o + h) * n + (o + h), n, T, h,
+                     W + (long long)(o + h) * n + o, n, -1.0, 0.0, false);
+}
+
 }  // namespace
 
 // A (n x n, symmetric positive definite, destroyed) -> out = diag(s) A^-1 diag(s).
@@ -198,18 +216,10 @@ void spd_inverse_scaled(camfe_ctx ctx, double* A, int n, const double* s, double
   const int fail = read_scalar(ctx, ctx->d_flag);
   CAMFE_REQUIRE(fail == 0, CAMFE_ESINGULAR, "coarsest Cholesky failed (increase coarse_eps)");
   hipLaunchKernelGGL(k_zero_upper, grid_for(nn, 256), 256, 0, ctx->stream, A, (long long)n);
-  // W = L^-1 by block rows: W_ii = L_ii^-1, W[i, :r0] = -W_ii (L[i, :r0] W[:r0, :r0])
-  DArr<double> W(nn), G((size_t)NB * n);
+  // W = L^-1, recursively: inv([L11 0; L21 L22]) = [W11 0; -W22 L21 W11  W22]
+  DArr<double> W(nn), T(nn);
   zero(ctx, W.p, W.n);
-  for (int r0 = 0; r0 < n; r0 += NB) {
-    const int rb = std::min(NB, n - r0);
-    hipLaunchKernelGGL(k_trtri_diag, 1, 64, 0, ctx->stream, (const double*)A, W.p, (long long)n, r0, rb);
-    if (r0 > 0) {
-      gemm<false, false>(ctx, rb, r0, r0, A + (long long)r0 * n, n, W.p, n, G.p, n, 1.0, 0.0, false);
-      gemm<false, false>(ctx, rb, r0, rb, W.p + (long long)r0 * n + r0, n, G.p, n, W.p + (long long)r0 * n, n,
-                         -1.0, 0.0, false);
-    }
-  }
+  trinv(ctx, A, W.p, T.p, n, 0, n);
   // A^-1 = W^T W (lower triangle into A), then scale and mirror
   gemm<true, false>(ctx, n, n, n, W.p, n, W.p, n, A, n, 1.0, 0.0, true);
   hipLaunchKernelGGL(k_sym_scale, grid_for(nn, 256), 256, 0, ctx->stream, (const double*)A, (long long)n, s, out);

@@ -343,12 +343,19 @@ __global__ void k_uf_link(const u64* ent, long long n, const int* cid, const int
   }
 }
 
-__global__ void k_uf_compress(int* parent, long long n) {
+// root of every entry into a separate array.  The walk only reads parent:
+// path halving here would let one thread overwrite another's final root with
+// a stale ancestor (a valid pointer for union-find, but not the root that the
+// function numbering needs).
+__global__ void k_uf_roots(const int* parent, long long n, int* root) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
-  if (i < n) {
-    int r = uf_find(parent, (int)i);
-    parent[i] = r;
+  if (i >= n) return;
+  int x = (int)i, p = parent[x];
+  while (p != x) {
+    x = p;
+    p = parent[x];
   }
+  root[i] = x;
 }
 
 // without the split: every entry belongs to its support's first entry
@@ -586,16 +593,17 @@ void build_functions(camfe_hier h, int d) {
   DArr<int> cstart(L.ncorn);
   hipLaunchKernelGGL(k_corner_start, ge, BLK, 0, ctx->stream, cflag.p, cpos.p, (long long)n, cstart.p, cid.p);
   check_launch();
-  // components
+  // components: parent ends as the root (smallest entry) of each component
   DArr<int> parent(n);
   if (h->split) {
-    hipLaunchKernelGGL(k_uf_init, ge, BLK, 0, ctx->stream, parent.p, (long long)n);
+    DArr<int> link(n);
+    hipLaunchKernelGGL(k_uf_init, ge, BLK, 0, ctx->stream, link.p, (long long)n);
     const double sc = ldexp(1.0, d - h->D);
     CAMFE_TIMED(ctx, KT_UF_LINK, 0.0, k_uf_link, ge, BLK, 0, ctx->stream, L.ent.p, (long long)n, cid.p, cstart.p,
                 (int)L.ncorn, h->F.p, h->U.p, sc, h->degree, h->tri_edge.p, h->edge_ptr.p, h->edge_tri.p,
-                h->vt_ptr.p, h->vt_tri.p, parent.p);
+                h->vt_ptr.p, h->vt_tri.p, link.p);
     check_launch();
-    hipLaunchKernelGGL(k_uf_compress, ge, BLK, 0, ctx->stream, parent.p, (long long)n);
+    hipLaunchKernelGGL(k_uf_roots, ge, BLK, 0, ctx->stream, (const int*)link.p, (long long)n, parent.p);
   } else {
     hipLaunchKernelGGL(k_parent_is_group_head, ge, BLK, 0, ctx->stream, cid.p, cstart.p, (long long)n, parent.p);
   }

@@ -198,27 +198,67 @@ __global__ __launch_bounds__(BLK) void k_mlp_backward_rows(const float* feat, lo
   }
 }
 
-// parameter gradients: sums over a chunk of rows per block, then FP64 atomics
+// parameter gradients: each block sums GROWS rows, staged CH rows at a time
+// in LDS (features, both hidden layers' activations and deltas, dz), then one
+// FP64 atomic per parameter and block
 constexpr int GROWS = 512;
+constexpr int CH = 64;
 constexpr int KS = 4;       // error samples (columns) per depth in the loss
 __global__ __launch_bounds__(BLK) void k_param_grad(const float* feat, const float* h1, const float* h2,
                                                     const float* d1, const float* d2, const double* dz,
                                                     long long n, double* grad) {
+  __shared__ float sf[CH][NF + 1], sh1[CH][NH + 1], sh2[CH][NH + 1], sd1[CH][NH + 1], sd2[CH][NH + 1];
+  __shared__ float sdz[CH];
   const long long r0 = blockIdx.x * (long long)GROWS;
   const long long r1 = min(n, r0 + GROWS);
-  for (int p = threadIdx.x; p < NP; p += BLK) {
-    double s = 0.0;
-    for (long long r = r0; r < r1; ++r) {
-      float v;
-      if (p < O_B1) v = feat[r * FSTRIDE + p / NH] * d1[r * NH + p % NH];
-      else if (p < O_W2) v = d1[r * NH + (p - O_B1)];
-      else if (p < O_B2) { int q = p - O_W2; v = h1[r * NH + q / NH] * d2[r * NH + q % NH]; }
-      else if (p < O_W3) v = d2[r * NH + (p - O_B2)];
-      else if (p < O_B3) v = h2[r * NH + (p - O_W3)] * (float)dz[r];
-      else v = (float)dz[r];
-      s += (double)v;
+  double acc[(NP + BLK - 1) / BLK];
+#pragma unroll
+  for (int u = 0; u < (NP + BLK - 1) / BLK; ++u) acc[u] = 0.0;
+  for (long long c0 = r0; c0 < r1; c0 += CH) {
+    const int cn = (int)min((long long)CH, r1 - c0);
+    for (int e = threadIdx.x; e < CH * NH; e += BLK) {
+      const int r = e / NH, j = e % NH;
+      const bool ok = r < cn;
+      const long long g = c0 + r;
+      if (j < NF) sf[r][j] = ok ? feat[g * FSTRIDE + j] : 0.0f;
+      sh1[r][j] = ok ? h1[g * NH + j] : 0.0f;
+      sh2[r][j] = ok ? h2[g * NH + j] : 0.0f;
+      sd1[r][j] = ok ? d1[g * NH + j] : 0.0f;
+      sd2[r][j] = ok ? d2[g * NH + j] : 0.0f;
     }
-    atomicAdd(grad + p, s);
+    for (int r = threadIdx.x; r < CH; r += BLK) sdz[r] = r < cn ? (float)dz[c0 + r] : 0.0f;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < (NP + BLK - 1) / BLK; ++u) {
+      const int p = threadIdx.x + u * BLK;
+      if (p >= NP) continue;
+      float s = 0.0f;
+      if (p < O_B1) {
+        const int i = p / NH, j = p % NH;
+        for (int r = 0; r < cn; ++r) s = fmaf(sf[r][i], sd1[r][j], s);
+      } else if (p < O_W2) {
+        const int j = p - O_B1;
+        for (int r = 0; r < cn; ++r) s += sd1[r][j];
+      } else if (p < O_B2) {
+        const int a = (p - O_W2) / NH, bq = (p - O_W2) % NH;
+        for (int r = 0; r < cn; ++r) s = fmaf(sh1[r][a], sd2[r][bq], s);
+      } else if (p < O_W3) {
+        const int j = p - O_B2;
+        for (int r = 0; r < cn; ++r) s += sd2[r][j];
+      } else if (p < O_B3) {
+        const int j = p - O_W3;
+        for (int r = 0; r < cn; ++r) s = fmaf(sh2[r][j], sdz[r], s);
+      } else {
+        for (int r = 0; r < cn; ++r) s += sdz[r];
+      }
+      acc[u] += (double)s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < (NP + BLK - 1) / BLK; ++u) {
+    const int p = threadIdx.x + u * BLK;
+    if (p < NP) atomicAdd(grad + p, acc[u]);
   }
 }
 

@@ -287,10 +287,10 @@ def test_full_size_knot_flow_system(cf, ctx):
     M = cf.camfe_export_matrix(s, h, fin, 0)
     L = cf.camfe_export_matrix(s, h, fin, 1)
     area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
-    # fragments are clipped in depth-10 grid units (coordinates up to 2^10), so
-    # each clip rounds about 2^10 ulps of the fragment: 1e-9 instead of 1e-12
-    assert abs(M.sum() - area) <= 1e-9 * area
-    assert abs(L @ np.ones(L.shape[0])).max() <= 1e-9 * abs(L).max()
+    # at this size a wrong (support, triangle) -> function label shows here: a
+    # race in the component labelling once lost ~3e-8 of the area
+    assert abs(M.sum() - area) <= 1e-12 * area
+    assert abs(L @ np.ones(L.shape[0])).max() <= 1e-11 * abs(L).max()
     X0 = cf.camfe_linear_coeffs(s, h)
     b = M @ X0
     A = M + 1e-4 * L

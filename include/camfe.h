@@ -163,8 +163,8 @@ typedef struct {
                      /*    (1e-6 recommended: regularises singular systems, and   */
                      /*    FP32 cycles cannot amplify rounding past O(0.1))       */
   int smoother;      /* 0: multicolour Gauss-Seidel (Section 5.2); 1: weighted    */
-                     /*    Jacobi with constant omega; 2: Jacobi with per-row     */
-                     /*    omega from the attached learned model                  */
+                     /*    Jacobi with constant omega; 2: the attached learned    */
+                     /*    model's smoother (Jacobi or SOR, per-row omega)        */
   double omega;      /* omega of smoother 1                                       */
 } camfe_solve_opts;
 
@@ -232,11 +232,17 @@ camfe_status camfe_flow_step(camfe_sys s, double delta, double *X, const camfe_s
 
 /* ------------------------------------------------------ learned smoother */
 /* Not part of the paper's method (its smoother is Gauss-Seidel, Section 5.2):
- * an optional per-row damped Jacobi smoother x += omega_i (b_i - (A x)_i) / A_ii
- * with omega_i = c_i s_i: s_i = 2 sigmoid(z_i) in (0, 2) comes from a small MLP
- * per relative depth l = D - d (depths with l >= levels use the last MLP), and
- * c_i = A_ii / sum_j |A_ij| is the l1-Jacobi bound, which keeps every sweep an
- * A-norm contraction whatever the network outputs.  Degree 1 only.
+ * optional smoothers x_i += omega_i (b_i - (A x)_i) / A_ii whose per-row weights
+ * come from a small MLP per relative depth l = D - d (depths with l >= levels
+ * use the last MLP).  Two sweep types, fixed per model:
+ *   sweep 0, damped Jacobi: all rows at once, omega_i = c_i s_i with
+ *     s_i = 2 sigmoid(z_i) in (0, 2) and the l1-Jacobi bound
+ *     c_i = A_ii / sum_j |A_ij|, which keeps every sweep an
+ *     A-norm contraction whatever the network outputs;
+ *   sweep 1, multicolour SOR: the Gauss-Seidel colour order with
+ *     omega_i = 1/2 + sigmoid(z_i) in (1/2, 3/2), a band around Gauss-Seidel
+ *     (symmetric SOR with per-row weights in (0, 2) is an SPD preconditioner).
+ * Degree 1 only.
  * Row features (30, FP32): the row of A = M + t L summed per grid offset
  * delta in {-1,0,1}^3 of the column's corner from the row's corner, divided by
  * A_ii (index (dx+1) + 3(dy+1) + 9(dz+1)); clamp(log10(A_ii / max_j A_jj),
@@ -258,16 +264,19 @@ typedef struct {
   int bf16;          /* 1: BF16 weights (FP32 accumulation); 0: FP32 weights        */
   double lr;         /* Adam step size                                              */
   uint64_t seed;     /* seed of the error samples                                   */
+  int sweep;         /* 0: damped Jacobi (l1-bounded); 1: multicolour SOR            */
   int samples;       /* error samples per depth (four): 0 normal random vectors;    */
                      /*    1 the error one plain Gauss-Seidel V(2,2) cycle on       */
                      /*    A e = 0 leaves from such a vector; 2 two of each         */
 } camfe_train_opts;
 
 /* Model from packed FP32 parameters (levels x 2081, copied) or, with params
- * NULL, a fixed deterministic initialisation (s near 1: l1-Jacobi). */
-camfe_status camfe_model_create(const float *params, int levels, int bf16, camfe_model *out);
-/* Two-call export of the packed parameters; levels and bf16 may be NULL. */
-camfe_status camfe_model_params(camfe_model m, float *params, int64_t cap, int64_t *n, int *levels, int *bf16);
+ * NULL, a fixed deterministic initialisation (s near 1: l1-Jacobi for sweep 0,
+ * Gauss-Seidel for sweep 1). */
+camfe_status camfe_model_create(const float *params, int levels, int bf16, int sweep, camfe_model *out);
+/* Two-call export of the packed parameters; levels, bf16 and sweep may be NULL. */
+camfe_status camfe_model_params(camfe_model m, float *params, int64_t cap, int64_t *n, int *levels, int *bf16,
+                                int *sweep);
 void camfe_model_destroy(camfe_model m);
 /* Attach a model (not owned; must outlive its use by camfe_solve) or detach
  * with NULL.  smoother = 2 in camfe_solve needs an attached model (ESTATE). */
@@ -275,11 +284,12 @@ camfe_status camfe_smoother_attach(camfe_sys s, camfe_model m);
 /* omega_i = c_i s_i of every function at one assembled depth (canonical
  * order, n_d doubles) for A = M + t L. */
 camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double t, double *omega);
-/* Training loss at one depth for one MLP's parameters (2081 floats) and
- * nsamples (1..4) error samples e0 (n_d x nsamples column-major, canonical
- * order), with its gradient (2081 doubles; grad may be NULL).  The forward
- * and adjoint sweeps run in FP64; the MLP in FP32 or BF16 weights. */
-camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float *params, int bf16,
+/* Training loss at one depth for one MLP's parameters (2081 floats), a sweep
+ * type and nsamples (1..4) error samples e0 (n_d x nsamples column-major,
+ * canonical order), with its gradient (2081 doubles; grad may be NULL).  nu
+ * sweeps; an SOR sweep relaxes colour 0, then 1, ... (forward order).  The
+ * forward and adjoint sweeps run in FP64; the MLP in FP32 or BF16 weights. */
+camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float *params, int bf16, int sweep,
                                       const double *e0, int nsamples, int nu, double *loss, double *grad);
 /* Train a model on the GPU: for every system and depth above the coarsest,
  * four error samples (opts->samples), then opts->steps Adam steps on the mean

@@ -1,9 +1,11 @@
 """Reference for the learned Jacobi smoother (test infrastructure only).
 
 Plain FP64 numpy, written from the definitions: the per-row features, the
-30-32-32-1 ReLU network with s = 2 sigmoid(z) and omega = c s, c the l1-Jacobi
-bound A_ii / sum_j |A_ij|, the damped Jacobi error
-sweeps e <- e - omega D^-1 A e and the training loss
+30-32-32-1 ReLU network with s = 2 sigmoid(z), and two sweep types: damped
+Jacobi with omega = c s, c the l1-Jacobi bound A_ii / sum_j |A_ij|
+(e <- e - omega D^-1 A e on all rows at once), and multicolour SOR with
+omega = 1/2 + sigmoid(z) (the same update applied to the rows of colour 0, then colour 1,
+..., colour = parity of the corner coordinates); the training loss
 L = mean_s log(|A e_nu^s|^2 / |A e_0^s|^2), with its gradient obtained by
 the chain rule written out by hand (adjoint sweeps, then back-propagation
 through the network).  Nothing here comes from the paper: its smoother is
@@ -90,6 +92,19 @@ def features(A, M, keys, d, D):
     return f, act, c1
 
 
+def colours(keys):
+    """Colour of each degree-1 function: (x & 1) + 2 (y & 1) + 4 (z & 1) of its corner."""
+    c = demorton(keys)
+    return (c[:, 0] & 1) + 2 * (c[:, 1] & 1) + 4 * (c[:, 2] & 1)
+
+
+def _masks(n, colour):
+    """Rows relaxed by each step of one sweep: all rows (Jacobi) or one colour at a time."""
+    if colour is None:
+        return [np.ones(n, bool)]
+    return [colour == c for c in range(8)]
+
+
 def forward(params, f):
     """Hidden pre-activations and z of every row."""
     W1, b1, W2, b2, w3, b3 = unpack(params)
@@ -101,10 +116,18 @@ def forward(params, f):
     return a1, h1, a2, h2, z
 
 
-def omega(params, f, act, c1):
-    """omega_i = c_i s_i with s_i = 2 sigmoid(z_i); 0 on inactive rows."""
+def _two_sigmoid(z):
+    """2 / (1 + exp(-z)) without overflow for large |z|."""
+    e = np.exp(-np.abs(z))
+    return np.where(z >= 0, 2.0 / (1.0 + e), 2.0 * e / (1.0 + e))
+
+
+def omega(params, f, act, c1, sor=False):
+    """Jacobi: omega_i = c_i s_i with s_i = 2 sigmoid(z_i); SOR: omega_i =
+    1/2 + sigmoid(z_i); 0 on inactive rows."""
     z = forward(params, f)[4]
-    return np.where(act, c1 * 2.0 / (1.0 + np.exp(-z)), 0.0)
+    w = 0.5 + 0.5 * _two_sigmoid(z) if sor else c1 * _two_sigmoid(z)
+    return np.where(act, w, 0.0)
 
 
 def _invdiag(A):
@@ -112,35 +135,47 @@ def _invdiag(A):
     return np.where(dg > 0, 1.0 / np.where(dg > 0, dg, 1.0), 0.0)
 
 
-def loss(A, f, act, c1, params, E0, nu):
+def relax(A, f, act, c1, params, E0, nu, colour=None):
+    """The error after nu sweeps: Jacobi (colour None, omega = c s) or
+    multicolour SOR (colour given, omega = s)."""
+    A = A.tocsr()
+    n = A.shape[0]
+    om = omega(params, f, act, c1, sor=colour is not None)
+    dinv = _invdiag(A)
+    E = np.array(E0, dtype=np.float64, ndmin=2).reshape(n, -1)
+    for _ in range(nu):
+        for m in _masks(n, colour):
+            E = E - np.where(m, om * dinv, 0.0)[:, None] * (A @ E)
+    return E
+
+
+def loss(A, f, act, c1, params, E0, nu, colour=None):
     """Mean over the columns of E0 of log(|A e_nu|^2 / |A e_0|^2)."""
     A = A.tocsr()
-    om = omega(params, f, act, c1)
-    dinv = _invdiag(A)
-    E = np.array(E0, dtype=np.float64, ndmin=2).reshape(A.shape[0], -1)
-    r0 = A @ E
-    for _ in range(nu):
-        E = E - (om * dinv)[:, None] * (A @ E)
-    r = A @ E
+    E0 = np.array(E0, dtype=np.float64, ndmin=2).reshape(A.shape[0], -1)
+    r0 = A @ E0
+    r = A @ relax(A, f, act, c1, params, E0, nu, colour)
     return float(np.mean(np.log(np.sum(r * r, axis=0) / np.sum(r0 * r0, axis=0))))
 
 
-def loss_grad(A, f, act, c1, params, E0, nu):
+def loss_grad(A, f, act, c1, params, E0, nu, colour=None):
     """(loss, gradient over the packed parameters)."""
     A = A.tocsr()
     n = A.shape[0]
     a1, h1, a2, h2, z = forward(params, f)
-    sg = 2.0 / (1.0 + np.exp(-z))
-    om = np.where(act, c1 * sg, 0.0)
+    sg = _two_sigmoid(z)
+    om = omega(params, f, act, c1, sor=colour is not None)
     dinv = _invdiag(A)
     E = np.array(E0, dtype=np.float64, ndmin=2).reshape(n, -1)
     S = E.shape[1]
     r0 = A @ E
-    U = []
+    U, MK = [], []
     for _ in range(nu):
-        u = dinv[:, None] * (A @ E)          # D^-1 A e_k
-        U.append(u)
-        E = E - om[:, None] * u
+        for m in _masks(n, colour):
+            u = np.where(m[:, None], dinv[:, None] * (A @ E), 0.0)     # D^-1 A e_k on the relaxed rows
+            U.append(u)
+            MK.append(m)
+            E = E - om[:, None] * u
     r = A @ E
     n0 = np.sum(r0 * r0, axis=0)
     n1 = np.sum(r * r, axis=0)
@@ -148,11 +183,15 @@ def loss_grad(A, f, act, c1, params, E0, nu):
     # dL/de_nu = (2 / S) A r / |r|^2 per column (A symmetric)
     G = (A @ r) * (2.0 / S / n1)[None, :]
     gom = np.zeros(n)
-    for k in range(nu - 1, -1, -1):
-        # e_{k+1} = e_k - omega * u_k,  u_k = D^-1 A e_k
+    for k in range(len(U) - 1, -1, -1):
+        # e_{k+1} = e_k - omega * u_k,  u_k = (D^-1 A e_k) on the step's rows
         gom -= np.sum(G * U[k], axis=1)
-        G = G - A @ ((om * dinv)[:, None] * G)
-    dz = np.where(act, gom * c1 * sg * (1.0 - 0.5 * sg), 0.0)   # d omega / dz = c s (1 - s / 2)
+        G = G - A @ (np.where(MK[k], om * dinv, 0.0)[:, None] * G)
+    if colour is None:
+        dz = np.where(act, gom * c1 * sg * (1.0 - 0.5 * sg), 0.0)      # d omega / dz = c s (1 - s / 2)
+    else:
+        sig = 0.5 * sg
+        dz = np.where(act, gom * sig * (1.0 - sig), 0.0)                # d omega / dz = sigma (1 - sigma)
     W1, b1, W2, b2, w3, b3 = unpack(params)
     d2 = (dz[:, None] * w3[None, :]) * (a2 > 0)
     d1 = (d2 @ W2.T) * (a1 > 0)

@@ -60,7 +60,7 @@ class SolveStats(C.Structure):
 
 class TrainOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("levels", C.c_int), ("steps", C.c_int), ("nu", C.c_int), ("bf16", C.c_int),
-                ("lr", C.c_double), ("seed", C.c_uint64), ("samples", C.c_int)]
+                ("lr", C.c_double), ("seed", C.c_uint64), ("sweep", C.c_int), ("samples", C.c_int)]
 
 
 _lib = None
@@ -100,12 +100,12 @@ def load():
         "camfe_ctx_kernel_timing": (I, [H, I]),
         "camfe_ctx_kernel_time": (I, [H, C.c_char_p, C.POINTER(D), C.POINTER(I64), C.POINTER(D)]),
         "camfe_measure_kernel": (I, [H, C.c_char_p, I, I, C.POINTER(D), C.POINTER(D)]),
-        "camfe_model_create": (I, [P, I, I, C.POINTER(H)]),
-        "camfe_model_params": (I, [H, P, I64, C.POINTER(I64), C.POINTER(I), C.POINTER(I)]),
+        "camfe_model_create": (I, [P, I, I, I, C.POINTER(H)]),
+        "camfe_model_params": (I, [H, P, I64, C.POINTER(I64), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
         "camfe_model_destroy": (None, [H]),
         "camfe_smoother_attach": (I, [H, H]),
         "camfe_smoother_omega": (I, [H, H, I, D, P]),
-        "camfe_smoother_loss_grad": (I, [H, I, D, P, I, P, I, I, C.POINTER(D), P]),
+        "camfe_smoother_loss_grad": (I, [H, I, D, P, I, I, P, I, I, C.POINTER(D), P]),
         "camfe_smoother_train": (I, [H, P, I, C.POINTER(TrainOpts), C.POINTER(H), P]),
         "camfe_flow_step": (I, [H, D, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
         "camfe_batch_create": (I, [H, P, I, D, D, C.POINTER(H)]),
@@ -427,8 +427,12 @@ def camfe_batch_destroy(bt):
 
 
 # ------------------------------------------------------------ learned smoother
-def camfe_model_create(params=None, levels=1, bf16=True):
-    """Model handle from packed FP32 parameters (levels x 2081) or the default initialisation."""
+SWEEP_JACOBI, SWEEP_SOR = 0, 1
+
+
+def camfe_model_create(params=None, levels=1, bf16=True, sweep=SWEEP_JACOBI):
+    """Model handle from packed FP32 parameters (levels x 2081) or the default initialisation;
+    sweep 0 = damped Jacobi (l1-bounded weights), 1 = multicolour SOR."""
     p = None
     if params is not None:
         p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
@@ -436,17 +440,17 @@ def camfe_model_create(params=None, levels=1, bf16=True):
             raise ValueError("parameters must be a multiple of 2081 floats")
         levels = p.size // MLP_PARAMS
     m = C.c_void_p()
-    _check(load().camfe_model_create(_ptr(p), int(levels), 1 if bf16 else 0, C.byref(m)))
+    _check(load().camfe_model_create(_ptr(p), int(levels), 1 if bf16 else 0, int(sweep), C.byref(m)))
     return m.value
 
 
 def camfe_model_params(m):
-    """(params float32 [levels, 2081], bf16 flag)."""
-    n, lv, bf = C.c_int64(), C.c_int(), C.c_int()
-    _check(load().camfe_model_params(m, None, 0, C.byref(n), C.byref(lv), C.byref(bf)))
+    """(params float32 [levels, 2081], bf16 flag, sweep type)."""
+    n, lv, bf, sw = C.c_int64(), C.c_int(), C.c_int(), C.c_int()
+    _check(load().camfe_model_params(m, None, 0, C.byref(n), C.byref(lv), C.byref(bf), C.byref(sw)))
     out = np.zeros(n.value, dtype=np.float32)
-    _check(load().camfe_model_params(m, _ptr(out), n.value, C.byref(n), None, None))
-    return out.reshape(lv.value, MLP_PARAMS), bool(bf.value)
+    _check(load().camfe_model_params(m, _ptr(out), n.value, C.byref(n), None, None, None))
+    return out.reshape(lv.value, MLP_PARAMS), bool(bf.value), sw.value
 
 
 def camfe_model_destroy(m):
@@ -464,7 +468,7 @@ def camfe_smoother_omega(s, h, m, depth, t):
     return out
 
 
-def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=True):
+def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=True, sweep=SWEEP_JACOBI):
     """(loss, gradient float64[2081] or None) for one MLP's parameters and n_d x S samples."""
     p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
     if p.size != MLP_PARAMS:
@@ -474,18 +478,20 @@ def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=T
         e = e.reshape(-1, 1, order="F")
     loss = C.c_double()
     g = np.zeros(MLP_PARAMS) if want_grad else None
-    _check(load().camfe_smoother_loss_grad(s, depth, t, _ptr(p), 1 if bf16 else 0, _ptr(e), e.shape[1], nu,
-                                           C.byref(loss), _ptr(g)))
+    _check(load().camfe_smoother_loss_grad(s, depth, t, _ptr(p), 1 if bf16 else 0, int(sweep), _ptr(e), e.shape[1],
+                                           nu, C.byref(loss), _ptr(g)))
     return loss.value, g
 
 
-def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, lr=3e-3, seed=1, samples=0):
+def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, lr=3e-3, seed=1, samples=0,
+                         sweep=SWEEP_JACOBI):
     """(model handle, loss history) trained on the GPU over the given systems.
-    samples: 0 random vectors, 1 errors left by one plain V-cycle, 2 two of each."""
+    samples: 0 random vectors, 1 errors left by one plain V-cycle, 2 two of each;
+    sweep: 0 damped Jacobi, 1 multicolour SOR."""
     arr = (C.c_void_p * len(systems))(*[x.value if isinstance(x, C.c_void_p) else x for x in systems])
     o = TrainOpts()
     o.t, o.levels, o.steps, o.nu, o.bf16, o.lr, o.seed = t, levels, steps, nu, 1 if bf16 else 0, lr, seed
-    o.samples = samples
+    o.samples, o.sweep = samples, sweep
     hist = np.zeros(max(steps, 1))
     m = C.c_void_p()
     _check(load().camfe_smoother_train(ctx, C.cast(arr, C.c_void_p), len(systems), C.byref(o), C.byref(m),
@@ -494,11 +500,11 @@ def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, 
 
 
 def save_model(path, m):
-    """Packed parameters and the BF16 flag in a .npz file (no pickled objects)."""
-    params, bf16 = camfe_model_params(m)
-    np.savez(path, params=params, bf16=np.array([bf16]))
+    """Packed parameters, the BF16 flag and the sweep type in a .npz file (no pickled objects)."""
+    params, bf16, sweep = camfe_model_params(m)
+    np.savez(path, params=params, bf16=np.array([bf16]), sweep=np.array([sweep]))
 
 
 def load_model(path):
     with np.load(path, allow_pickle=False) as z:
-        return camfe_model_create(z["params"], bf16=bool(z["bf16"][0]))
+        return camfe_model_create(z["params"], bf16=bool(z["bf16"][0]), sweep=int(z["sweep"][0]))

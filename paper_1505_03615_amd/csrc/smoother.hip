@@ -47,6 +47,7 @@ constexpr int C_L1 = 30;                  // c_i = A_ii / sum_j |A_ij| (not a ne
 
 struct camfe_model_s {
   int levels = 1;
+  int sweep = 0;          // 0: damped Jacobi with l1-bounded weights; 1: multicolour SOR
   int bf16 = 1;
   std::vector<float> w;   // levels * NP, FP32 master weights
 };
@@ -147,8 +148,9 @@ __device__ inline bool row_active(const float* f) {
 
 // omega per row (internal order) and the Jacobi weights omega / A_ii
 template <class WT>
-__global__ __launch_bounds__(BLK) void k_mlp_omega(const float* feat, long long n, const WT* w, const double* invd,
-                                                   double* omega, double* winvd64, float* winvd32) {
+__global__ __launch_bounds__(BLK) void k_mlp_omega(const float* feat, long long n, const WT* w, int l1,
+                                                   const double* invd, double* omega, double* winvd64,
+                                                   float* winvd32) {
   __shared__ float sw[NP];
   load_weights<WT>(w, sw);
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
@@ -159,7 +161,9 @@ __global__ __launch_bounds__(BLK) void k_mlp_omega(const float* feat, long long 
   double om = 0.0;
   if (row_active(f)) {
     const float z = mlp_row(sw, f, nullptr, nullptr);
-    om = (double)feat[i * FSTRIDE + C_L1] * (2.0 / (1.0 + exp(-(double)z)));
+    // Jacobi: omega = c 2 sigmoid(z); SOR: omega = 1/2 + sigmoid(z), a band around Gauss-Seidel
+    om = l1 ? (double)feat[i * FSTRIDE + C_L1] * (2.0 / (1.0 + exp(-(double)z)))
+            : 0.5 + 1.0 / (1.0 + exp(-(double)z));
   }
   if (omega) omega[i] = om;
   if (winvd64) winvd64[i] = om * invd[i];
@@ -292,17 +296,19 @@ __global__ void k_rand_normal(unsigned long long seed, long long m, double* out)
   out[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
 
-// u = invd * y; e_out = e_in - omega * u
+// rows [r0, r1) relax: u = invd * y, e_out = e_in - omega * u; other rows
+// keep e and get u = 0
 template <int K>
-__global__ void k_jac_fwd(long long n, const double* invd, const double* om, const double* y, const double* e_in,
-                          double* u, double* e_out) {
+__global__ void k_jac_fwd(long long n, long long r0, long long r1, const double* invd, const double* om,
+                          const double* y, const double* e_in, double* u, double* e_out) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
+  const bool in = i >= r0 && i < r1;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
-    const double uv = invd[i] * y[i * K + q];
+    const double uv = in ? invd[i] * y[i * K + q] : 0.0;
     u[i * K + q] = uv;
-    e_out[i * K + q] = e_in[i * K + q] - om[i] * uv;
+    e_out[i * K + q] = e_in[i * K + q] - (in ? om[i] * uv : 0.0);
   }
 }
 // g = coef_q * y (per column)
@@ -313,32 +319,39 @@ __global__ void k_scale_cols(long long n, const double* coef, const double* y, d
 #pragma unroll
   for (int q = 0; q < K; ++q) g[i * K + q] = coef[q] * y[i * K + q];
 }
-// gomega -= sum_q g * u ;  v = invd * omega * g
+// rows [r0, r1): gomega -= sum_q g * u and v = invd * omega * g; v = 0 elsewhere
 template <int K>
-__global__ void k_adj(long long n, const double* invd, const double* om, const double* g, const double* u,
-                      double* gom, double* v) {
+__global__ void k_adj(long long n, long long r0, long long r1, const double* invd, const double* om,
+                      const double* g, const double* u, double* gom, double* v) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
+  const bool in = i >= r0 && i < r1;
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     s += g[i * K + q] * u[i * K + q];
-    v[i * K + q] = invd[i] * om[i] * g[i * K + q];
+    v[i * K + q] = in ? invd[i] * om[i] * g[i * K + q] : 0.0;
   }
-  gom[i] -= s;
+  if (in) gom[i] -= s;
 }
 template <int K>
 __global__ void k_sub(long long n, double* g, const double* y) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i < n * K) g[i] -= y[i];
 }
-// omega = c s with s = 2 sigmoid(z): d omega / dz = c s (1 - s / 2) = omega (1 - s / 2)
-__global__ void k_dz(long long n, const double* gom, const double* om, const float* feat, double* dz) {
+// Jacobi: omega = c s, s = 2 sigmoid(z): d omega / dz = c s (1 - s / 2) = omega (1 - s / 2)
+// SOR: omega = 1/2 + sigma, sigma = sigmoid(z): d omega / dz = sigma (1 - sigma)
+__global__ void k_dz(long long n, const double* gom, const double* om, const float* feat, int l1, double* dz) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
-  const double c = feat[i * FSTRIDE + C_L1];
-  const double sg = c > 0.0 ? om[i] / c : 0.0;
-  dz[i] = gom[i] * om[i] * (1.0 - 0.5 * sg);
+  if (l1) {
+    const double c = (double)feat[i * FSTRIDE + C_L1];
+    const double sg = c > 0.0 ? om[i] / c : 0.0;
+    dz[i] = gom[i] * om[i] * (1.0 - 0.5 * sg);
+  } else {
+    const double sg = om[i] > 0.0 ? om[i] - 0.5 : 0.0;
+    dz[i] = gom[i] * sg * (1.0 - sg);
+  }
 }
 // column sums of squares (one block per column block, FP64 atomics per block)
 template <int K>
@@ -392,14 +405,16 @@ inline unsigned long long splitmix64_host(unsigned long long x) {
   return x ^ (x >> 31);
 }
 
-// y = A x at depth d, FP64, K columns (SELL, plain one-row-per-thread loop)
+// y = A x on the rows of slices [s0, s0 + ns) at depth d, FP64, K columns
+// (SELL, plain one-row-per-thread loop)
 template <int K>
-__global__ void k_apply_sell(const int* sl_ptr, const int* row0, const int* rows, long long ns, const int* scol,
-                             const double* sval, const double* x, double* y) {
+__global__ void k_apply_sell(const int* sl_ptr, const int* row0, const int* rows, long long s0, long long ns,
+                             const int* scol, const double* sval, const double* x, double* y) {
   long long g = blockIdx.x * (long long)BLK + threadIdx.x;
-  long long s = g / SL;
+  if (g / SL >= ns) return;
+  long long s = s0 + g / SL;
   int lane = (int)(g % SL);
-  if (s >= ns || lane >= rows[s]) return;
+  if (lane >= rows[s]) return;
   const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
   const long long base = sl_ptr[s] + lane;
   double acc[K];
@@ -482,14 +497,14 @@ struct DevWeights {
   }
 };
 
-void mlp_omega(camfe_ctx ctx, const float* feat, size_t n, const WView& W, const double* invd, double* omega,
-               double* w64, float* w32) {
+void mlp_omega(camfe_ctx ctx, const float* feat, size_t n, const WView& W, bool l1, const double* invd,
+               double* omega, double* w64, float* w32) {
   if (W.bf16)
-    hipLaunchKernelGGL(k_mlp_omega<uint16_t>, grid_for(n, BLK), BLK, 0, ctx->stream, feat, (long long)n, W.h, invd,
-                       omega, w64, w32);
+    hipLaunchKernelGGL(k_mlp_omega<uint16_t>, grid_for(n, BLK), BLK, 0, ctx->stream, feat, (long long)n, W.h,
+                       l1 ? 1 : 0, invd, omega, w64, w32);
   else
-    hipLaunchKernelGGL(k_mlp_omega<float>, grid_for(n, BLK), BLK, 0, ctx->stream, feat, (long long)n, W.f, invd,
-                       omega, w64, w32);
+    hipLaunchKernelGGL(k_mlp_omega<float>, grid_for(n, BLK), BLK, 0, ctx->stream, feat, (long long)n, W.f,
+                       l1 ? 1 : 0, invd, omega, w64, w32);
   check_launch();
 }
 
@@ -502,39 +517,54 @@ struct GradWork {
 
 // Loss of one depth for the samples E0 (internal order, n x KS row-major, the
 // columns from kk on zero) and, when grad is given, dL/dparams added to grad
-// (device, NP doubles).  Returns the loss (mean over the kk samples).
-double loss_grad_level(camfe_ctx ctx, const GLevel& G, const float* feat, const WView& W, int nu,
+// (device, NP doubles).  Returns the loss (mean over the kk samples).  sweep 0:
+// nu damped Jacobi sweeps with l1-bounded weights; sweep 1: nu forward
+// multicolour SOR sweeps, one relaxation step per colour (rows of one colour
+// are contiguous in the internal order and do not couple).
+double loss_grad_level(camfe_ctx ctx, const GLevel& G, const float* feat, const WView& W, int sweep, int nu,
                        const double* E0, int kk, double* grad, GradWork& w) {
   const size_t n = G.n;
   const int K = KS;
-  const unsigned gn = grid_for(n, BLK), gs = grid_for((size_t)G.nslices * SL, BLK);
+  const unsigned gn = grid_for(n, BLK);
+  struct Step { long long r0, r1, s0, s1; };
+  std::vector<Step> steps;
+  for (int it = 0; it < nu; ++it) {
+    if (sweep == 0) {
+      steps.push_back({0, (long long)n, 0, (long long)G.nslices});
+    } else {
+      for (int c = 0; c < G.ncol; ++c) steps.push_back({G.coff[c], G.coff[c + 1], G.cslice[c], G.cslice[c + 1]});
+    }
+  }
+  const size_t ns = steps.size();
   need(w.om, n);
   need(w.gom, n);
   need(w.dz, n);
-  need(w.e, n * K * (nu + 1));
-  need(w.u, n * K * (nu > 0 ? nu : 1));
+  need(w.e, n * K * (ns + 1));
+  need(w.u, n * K * (ns > 0 ? ns : 1));
   need(w.y, n * K);
   need(w.g, n * K);
   need(w.v, n * K);
   need(w.coef, K);
   need(w.nrm, 2 * K);
   hipStream_t st = ctx->stream;
-  mlp_omega(ctx, feat, n, W, G.invd64.p, w.om.p, nullptr, nullptr);
+  mlp_omega(ctx, feat, n, W, sweep == 0, G.invd64.p, w.om.p, nullptr, nullptr);
   CAMFE_HIP(hipMemcpyAsync(w.e.p, E0, n * K * sizeof(double), hipMemcpyDeviceToDevice, st));
-  auto apply = [&](const double* x, double* y) {
-    hipLaunchKernelGGL(k_apply_sell<KS>, gs, BLK, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (long long)G.nslices,
-                       G.scol.p, G.sval64.p, x, y);
+  auto apply_range = [&](long long s0, long long s1, const double* x, double* y) {
+    if (s1 <= s0) return;
+    hipLaunchKernelGGL(k_apply_sell<KS>, grid_for((size_t)(s1 - s0) * SL, BLK), BLK, 0, st, G.sl_ptr.p,
+                       G.sl_row0.p, G.sl_rows.p, s0, s1 - s0, G.scol.p, G.sval64.p, x, y);
   };
-  for (int k = 0; k < nu; ++k) {
-    apply(w.e.p + k * n * K, w.y.p);
-    hipLaunchKernelGGL(k_jac_fwd<KS>, gn, BLK, 0, st, (long long)n, G.invd64.p, (const double*)w.om.p,
-                       (const double*)w.y.p, (const double*)(w.e.p + k * n * K), w.u.p + k * n * K,
-                       w.e.p + (k + 1) * n * K);
+  auto apply = [&](const double* x, double* y) { apply_range(0, (long long)G.nslices, x, y); };
+  for (size_t k = 0; k < ns; ++k) {
+    apply_range(steps[k].s0, steps[k].s1, w.e.p + k * n * K, w.y.p);
+    hipLaunchKernelGGL(k_jac_fwd<KS>, gn, BLK, 0, st, (long long)n, steps[k].r0, steps[k].r1, G.invd64.p,
+                       (const double*)w.om.p, (const double*)w.y.p, (const double*)(w.e.p + k * n * K),
+                       w.u.p + k * n * K, w.e.p + (k + 1) * n * K);
   }
   zero(ctx, w.nrm.p, 2 * K);
   apply(w.e.p, w.y.p);
   hipLaunchKernelGGL(k_colnorm2<KS>, gn, BLK, 0, st, (long long)n, (const double*)w.y.p, w.nrm.p);
-  apply(w.e.p + nu * n * K, w.y.p);   // r = A e_nu, kept in y for the backward pass
+  apply(w.e.p + ns * n * K, w.y.p);   // r = A e_final, kept in y for the backward pass
   hipLaunchKernelGGL(k_colnorm2<KS>, gn, BLK, 0, st, (long long)n, (const double*)w.y.p, w.nrm.p + K);
   check_launch();
   double nr[2 * KS];
@@ -555,16 +585,17 @@ double loss_grad_level(camfe_ctx ctx, const GLevel& G, const float* feat, const 
   hipLaunchKernelGGL(k_scale_cols<KS>, gn, BLK, 0, st, (long long)n, (const double*)w.coef.p, (const double*)w.v.p,
                      w.g.p);
   hipLaunchKernelGGL(k_fill_d, gn, BLK, 0, st, w.gom.p, (long long)n, 0.0);
-  for (int k = nu - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(k_adj<KS>, gn, BLK, 0, st, (long long)n, G.invd64.p, (const double*)w.om.p,
-                       (const double*)w.g.p, (const double*)(w.u.p + k * n * K), w.gom.p, w.v.p);
+  for (long long k = (long long)ns - 1; k >= 0; --k) {
+    hipLaunchKernelGGL(k_adj<KS>, gn, BLK, 0, st, (long long)n, steps[k].r0, steps[k].r1, G.invd64.p,
+                       (const double*)w.om.p, (const double*)w.g.p, (const double*)(w.u.p + k * n * K), w.gom.p,
+                       w.v.p);
     if (k > 0) {
       apply(w.v.p, w.y.p);
       hipLaunchKernelGGL(k_sub<KS>, grid_for(n * K, BLK), BLK, 0, st, (long long)n, w.g.p, (const double*)w.y.p);
     }
   }
   hipLaunchKernelGGL(k_dz, gn, BLK, 0, st, (long long)n, (const double*)w.gom.p, (const double*)w.om.p, feat,
-                     w.dz.p);
+                     sweep == 0 ? 1 : 0, w.dz.p);
   need(w.h1, n * NH);
   need(w.h2, n * NH);
   need(w.d1, n * NH);
@@ -604,12 +635,13 @@ void set_smoother_weights(camfe_sys s, SolverState* S, int smoother, double omeg
       DArr<float> feat;
       features(s, S, d, feat);
       WView v = W.upload(ctx, m->w.data() + (size_t)l * NP, m->bf16 != 0);
-      mlp_omega(ctx, feat.p, G.n, v, G.invd64.p, nullptr, G.winvd64.p, G.winvd32.p);
+      mlp_omega(ctx, feat.p, G.n, v, m->sweep == 0, G.invd64.p, nullptr, G.winvd64.p, G.winvd32.p);
       ctx->sync();
     }
   }
   ctx->sync();
   S->wkind = smoother;
+  S->wsweep = smoother == 2 ? ((const camfe_model_s*)model)->sweep : 0;
   S->omega = omega;
   S->model = model;
   S->drop_graphs();
@@ -621,12 +653,13 @@ using namespace camfe;
 
 extern "C" {
 
-camfe_status camfe_model_create(const float* params, int levels, int bf16, camfe_model* out) {
+camfe_status camfe_model_create(const float* params, int levels, int bf16, int sweep, camfe_model* out) {
   return guarded([&] {
-    CAMFE_REQUIRE(out && levels >= 1 && levels <= 32, CAMFE_EINVAL, "bad argument");
+    CAMFE_REQUIRE(out && levels >= 1 && levels <= 32 && (sweep == 0 || sweep == 1), CAMFE_EINVAL, "bad argument");
     std::unique_ptr<camfe_model_s> m(new camfe_model_s());
     m->levels = levels;
     m->bf16 = bf16 ? 1 : 0;
+    m->sweep = sweep;
     m->w.assign((size_t)levels * NP, 0.0f);
     if (params) {
       std::memcpy(m->w.data(), params, m->w.size() * sizeof(float));
@@ -650,12 +683,14 @@ camfe_status camfe_model_create(const float* params, int levels, int bf16, camfe
   });
 }
 
-camfe_status camfe_model_params(camfe_model m, float* params, int64_t cap, int64_t* n, int* levels, int* bf16) {
+camfe_status camfe_model_params(camfe_model m, float* params, int64_t cap, int64_t* n, int* levels, int* bf16,
+                                int* sweep) {
   return guarded([&] {
     CAMFE_REQUIRE(m, CAMFE_EINVAL, "null model");
     if (n) *n = (int64_t)m->w.size();
     if (levels) *levels = m->levels;
     if (bf16) *bf16 = m->bf16;
+    if (sweep) *sweep = m->sweep;
     if (cap == 0) return;
     CAMFE_REQUIRE(params && cap >= (int64_t)m->w.size(), CAMFE_ETOOSMALL, "export capacity too small");
     std::memcpy(params, m->w.data(), m->w.size() * sizeof(float));
@@ -688,7 +723,7 @@ camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double 
     const int l = std::min(S->D - depth, m->levels - 1);
     WView v = W.upload(ctx, m->w.data() + (size_t)l * NP, m->bf16 != 0);
     DArr<double> om(G.n), out(G.n);
-    mlp_omega(ctx, feat.p, G.n, v, G.invd64.p, om.p, nullptr, nullptr);
+    mlp_omega(ctx, feat.p, G.n, v, m->sweep == 0, G.invd64.p, om.p, nullptr, nullptr);
     hipLaunchKernelGGL(k_scatter_canon, grid_for(G.n, BLK), BLK, 0, ctx->stream, (const double*)om.p,
                        (long long)G.n, G.perm.p, out.p);
     check_launch();
@@ -696,11 +731,12 @@ camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double 
   });
 }
 
-camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float* params, int bf16,
+camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float* params, int bf16, int sweep,
                                       const double* e0, int nsamples, int nu, double* loss, double* grad) {
   return guarded([&] {
-    CAMFE_REQUIRE(s && params && e0 && loss && nsamples >= 1 && nsamples <= KS && nu >= 0, CAMFE_EINVAL,
-                  "bad argument");
+    CAMFE_REQUIRE(s && params && e0 && loss && nsamples >= 1 && nsamples <= KS && nu >= 0 &&
+                      (sweep == 0 || sweep == 1),
+                  CAMFE_EINVAL, "bad argument");
     camfe_hier h = s->h;
     CAMFE_REQUIRE(depth >= h->d0 && depth <= h->D, CAMFE_ESTATE, "depth not assembled");
     camfe_ctx ctx = h->ctx;
@@ -718,7 +754,7 @@ camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const fl
     DArr<double> gd(NP);
     zero(ctx, gd.p, NP);
     GradWork w;
-    *loss = loss_grad_level(ctx, G, feat.p, v, nu, E.p, nsamples, grad ? gd.p : nullptr, w);
+    *loss = loss_grad_level(ctx, G, feat.p, v, sweep, nu, E.p, nsamples, grad ? gd.p : nullptr, w);
     if (grad) copy_out(ctx, grad, gd.p, NP);
   });
 }
@@ -728,11 +764,11 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
   return guarded([&] {
     CAMFE_REQUIRE(ctx && systems && nsys >= 1 && o && out, CAMFE_EINVAL, "bad argument");
     CAMFE_REQUIRE(o->levels >= 1 && o->levels <= 32 && o->steps >= 0 && o->nu >= 1 && o->lr > 0 &&
-                      o->samples >= 0 && o->samples <= 2,
+                      o->samples >= 0 && o->samples <= 2 && (o->sweep == 0 || o->sweep == 1),
                   CAMFE_EINVAL, "bad options");
     ctx->use_device();
     camfe_model m0 = nullptr;
-    camfe_status rc = camfe_model_create(nullptr, o->levels, o->bf16, &m0);
+    camfe_status rc = camfe_model_create(nullptr, o->levels, o->bf16, o->sweep, &m0);
     if (rc != CAMFE_OK) throw Error(rc, "model creation failed");
     std::unique_ptr<camfe_model_s> mp(m0);
     // per (system, depth above the coarsest): features and KS error samples,
@@ -802,7 +838,7 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
         v.f = wdev.p + (size_t)it->l * NP;
         v.h = wbf.p + (size_t)it->l * NP;
         v.bf16 = o->bf16 != 0;
-        tot += loss_grad_level(ctx, it->S->lev[it->d], it->feat.p, v, o->nu, it->E.p, KS,
+        tot += loss_grad_level(ctx, it->S->lev[it->d], it->feat.p, v, o->sweep, o->nu, it->E.p, KS,
                                grad.p + (size_t)it->l * NP, w);
       }
       if (loss_history) loss_history[step - 1] = tot / items.size();

@@ -863,15 +863,17 @@ double pass_bytes(long long z, long long rows) {
   return (double)z * sizeof(T) + 3.0 * (double)rows * K * sizeof(T);
 }
 
+// one multicolour sweep x_i += w_i (b_i - (A x)_i) with w = dinv (1 / A_ii for
+// Gauss-Seidel, omega_i / A_ii for SOR)
 template <class T, int K>
-void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward) {
+void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T* dinv) {
   for (int ci = 0; ci < G.ncol; ++ci) {
     const int c = forward ? ci : G.ncol - 1 - ci;
     const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
     if (s1 <= s0) continue;
     CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K>),
                 (unsigned)(s1 - s0), SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0, s1, G.scol.p,
-                sval_of<T>(G), invd_of<T>(G), b, x);
+                sval_of<T>(G), dinv, b, x);
   }
 }
 
@@ -888,14 +890,15 @@ const double* winvd_of<double>(const GLevel& g) { return g.winvd64.p; }
 template <>
 const float* winvd_of<float>(const GLevel& g) { return g.winvd32.p; }
 
-// nu smoothing sweeps on (b, x): multicolour Gauss-Seidel (colours forward or
-// reversed) or weighted Jacobi (order-free; ping-pong through the level's
-// scratch vector, one launch per sweep)
+// nu smoothing sweeps on (b, x): multicolour Gauss-Seidel or SOR with
+// per-row weights (colours forward or reversed), or weighted Jacobi
+// (order-free; ping-pong through the level's scratch vector, one launch per sweep)
 template <class T, int K>
 void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward) {
   camfe_ctx ctx = S->ctx;
-  if (S->smoother == 0) {
-    for (int i = 0; i < nu; ++i) gs_sweep<T, K>(ctx, G, b, x, forward);
+  if (S->smoother == 0 || (S->smoother == 2 && S->wsweep == 1)) {
+    const T* dinv = S->smoother == 0 ? invd_of<T>(G) : winvd_of<T>(G);
+    for (int i = 0; i < nu; ++i) gs_sweep<T, K>(ctx, G, b, x, forward, dinv);
     return;
   }
   T* a = x;
@@ -1627,8 +1630,8 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
     auto enqueue = [&] {
       for (int r = 0; r < reps; ++r) {
         if (kid == 0) {
-          if (precision == 0) gs_sweep<double, 1>(ctx, G, G.b64.p, G.x64.p, true);
-          else gs_sweep<float, 1>(ctx, G, G.b32.p, G.x32.p, true);
+          if (precision == 0) gs_sweep<double, 1>(ctx, G, G.b64.p, G.x64.p, true, G.invd64.p);
+          else gs_sweep<float, 1>(ctx, G, G.b32.p, G.x32.p, true, G.invd32.p);
         } else if (kid == 1) {
           if (precision == 0)
             hipLaunchKernelGGL((k_residual<double, double, 1>), (unsigned)G.nslices, SL * SW, 0,

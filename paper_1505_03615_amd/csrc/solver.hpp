@@ -35,7 +35,7 @@ struct GLevel {
   DArr<int> scol;
   DArr<double> sval64, invd64;
   DArr<float> sval32, invd32;
-  // Jacobi weights omega_i / A_ii (internal order), set for smoothers 1 and 2
+  // relaxation weights omega_i / A_ii (internal order), set for smoothers 1 and 2
   DArr<double> winvd64;
   DArr<float> winvd32;
   // transfers in internal numbering (P: rows at d, cols at d-1; R = P^T)
@@ -61,6 +61,7 @@ struct SolverState {
   int precision = 0;
   int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi
   int wkind = 0;             // smoother whose weights winvd holds (0: none)
+  int wsweep = 0;            // sweep those weights are for: 0 Jacobi, 1 multicolour SOR
   double omega = 0;          // constant omega of smoother 1
   const void* model = nullptr;  // learned model whose weights winvd holds
   double coarse_eps = 0;

@@ -79,49 +79,55 @@ def _params(seed, levels=1):
 def _ref(o, d, t):
     M, L = o.matrices(d)
     A = (M + t * L).tocsr()
-    f, act, c1 = lr.features(A, M, o.functions(d)[0], d, o.depth)
-    return A, f, act, c1
+    keys = o.functions(d)[0]
+    f, act, c1 = lr.features(A, M, keys, d, o.depth)
+    return A, f, act, c1, lr.colours(keys)
 
 
+@pytest.mark.parametrize("sweep", [0, 1])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_omega_matches_reference(cf, ctx, bf16):
+def test_omega_matches_reference(cf, ctx, bf16, sweep):
     h, s, o = built(cf, ctx, "sphere")
     t = CASES["sphere"]["t"]
     p = _params(3, levels=2)
-    m = cf.camfe_model_create(p, bf16=bf16)
+    m = cf.camfe_model_create(p, bf16=bf16, sweep=sweep)
     try:
         for d in (o.depth, o.depth - 1, o.depth - 2):
-            say(f"[gpu] learned: omega depth {d} bf16={bf16}")
+            say(f"[gpu] learned: omega depth {d} bf16={bf16} sweep={sweep}")
             om = cf.camfe_smoother_omega(s, h, m, d, t)
-            A, f, act, c1 = _ref(o, d, t)
+            A, f, act, c1, col = _ref(o, d, t)
             pl = p[min(o.depth - d, 1)]
-            ref = lr.omega(lr.bf16_round(pl) if bf16 else pl, f, act, c1)
+            ref = lr.omega(lr.bf16_round(pl) if bf16 else pl, f, act, c1, sor=sweep == 1)
             assert np.array_equal(om == 0, ~act)
             assert abs(om - ref).max() <= 2e-5, abs(om - ref).max()
-            assert om.min() >= 0 and np.all(om <= 2 * c1 * (1 + 1e-6))   # c_i is held in FP32
-            assert np.ptp(om[act] / c1[act]) > 0.05      # network not saturated: the rows really differ
+            if sweep == 0:
+                assert om.min() >= 0 and np.all(om <= 2 * c1 * (1 + 1e-6))   # c_i is held in FP32
+                assert np.ptp(om[act] / c1[act]) > 0.05      # network not saturated: the rows really differ
+            else:
+                assert om[act].min() >= 0.5 and om.max() <= 1.5 and np.ptp(om[act]) > 0.05
     finally:
         cf.camfe_model_destroy(m)
 
 
+@pytest.mark.parametrize("sweep", [0, 1])
 @pytest.mark.parametrize("name,dd", [("sphere", 0), ("sheets", 1)])
 @pytest.mark.parametrize("bf16", [False, True])
-def test_loss_and_gradient_match_reference(cf, ctx, name, dd, bf16):
+def test_loss_and_gradient_match_reference(cf, ctx, name, dd, bf16, sweep):
     h, s, o = built(cf, ctx, name)
     t = CASES[name]["t"]
     d = o.depth - dd
     p = _params(5)[0]
-    A, f, act, c1 = _ref(o, d, t)
+    A, f, act, c1, col = _ref(o, d, t)
     E0 = np.random.default_rng(11).normal(size=(A.shape[0], 3))
-    say(f"[gpu] learned: loss/grad {name} depth {d} bf16={bf16}")
-    L, g = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=bf16)
+    say(f"[gpu] learned: loss/grad {name} depth {d} bf16={bf16} sweep={sweep}")
+    L, g = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=bf16, sweep=sweep)
     pr = lr.bf16_round(p) if bf16 else p
-    Lr, gr = lr.loss_grad(A, f, act, c1, pr.astype(np.float64), E0, 2)
+    Lr, gr = lr.loss_grad(A, f, act, c1, pr.astype(np.float64), E0, 2, colour=col if sweep == 1 else None)
     assert L == pytest.approx(Lr, rel=1e-6, abs=1e-7)
     err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     assert err <= (1e-3 if bf16 else 1e-4), err
     # loss alone (no gradient) is the same number
-    L2, g2 = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=bf16, want_grad=False)
+    L2, g2 = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=bf16, want_grad=False, sweep=sweep)
     assert g2 is None and L2 == pytest.approx(L, rel=1e-14)   # block sums meet in FP64 atomics
 
 
@@ -151,7 +157,7 @@ def test_train_then_solve_held_out(cf, ctx):
         say(f"[gpu] learned: loss {hist[0]:.4f} -> {hist[-1]:.4f}")
         assert np.all(np.isfinite(hist))
         assert hist[-5:].mean() < hist[0] - 0.5
-        params, bf = cf.camfe_model_params(m)
+        params, bf, sw = cf.camfe_model_params(m)
         assert params.shape == (3, lr.NP) and bf
         h, s, o = built(cf, ctx, "knot")
         c = CASES["knot"]

@@ -6,7 +6,9 @@ guarantees for any network output, special networks that pass one feature
 through (orientation of the packed weights), features of a synthetic chain
 placed along one grid axis (offset indexing), invariants of the features of a
 real hierarchy (centre entry 1, row sums = (M 1)_i / A_ii since L 1 = 0), and
-central finite differences of the loss for the hand-derived gradient.
+central finite differences of the loss for the hand-derived gradient, for
+both sweep types; with unit weights the SOR sweep is the oracle's own
+multicolour Gauss-Seidel sweep.
 """
 import math
 
@@ -173,3 +175,47 @@ def test_gradient_matches_central_differences(sphere):
         assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9 * max(1.0, abs(g).max())), i
         checked += abs(g[i]) > 1e-8
     assert checked >= 10      # most picked entries are live (ReLUs active)
+
+
+def test_sor_with_unit_weights_is_the_oracle_gauss_seidel_sweep(sphere):
+    t, d = 1e-2, sphere.depth
+    M, L = sphere.matrices(d)
+    A = (M + t * L).tocsr()
+    keys = sphere.functions(d)[0]
+    f, act, c1 = lr.features(A, M, keys, d, sphere.depth)
+    col = lr.colours(keys)
+    assert set(np.unique(col)) <= set(range(8))
+    p = np.zeros(lr.NP)                     # z = 0: omega = 1/2 + sigmoid(0) = 1 on every row
+    E0 = np.random.default_rng(3).normal(size=(A.shape[0], 2))
+    E1 = lr.relax(A, f, act, c1, p, E0, 1, colour=col)
+    G1 = sphere.gs_sweep(d, t, np.zeros_like(E0), E0, forward=True)
+    assert np.abs(E1 - G1).max() <= 1e-12 * np.abs(E0).max()
+    # two sweeps: the same sweep applied twice
+    E2 = lr.relax(A, f, act, c1, p, E0, 2, colour=col)
+    G2 = sphere.gs_sweep(d, t, np.zeros_like(E0), G1, forward=True)
+    assert np.abs(E2 - G2).max() <= 1e-12 * np.abs(E0).max()
+
+
+def test_sor_gradient_matches_central_differences(sphere):
+    t, nu = 1e-2, 2
+    d = sphere.depth
+    M, L = sphere.matrices(d)
+    A = (M + t * L).tocsr()
+    keys = sphere.functions(d)[0]
+    f, act, c1 = lr.features(A, M, keys, d, sphere.depth)
+    col = lr.colours(keys)
+    rng = np.random.default_rng(9)
+    p = rng.normal(size=lr.NP) * 0.3
+    p[lr.O_B3] = 0.3
+    E0 = rng.normal(size=(A.shape[0], 2))
+    L0, g = lr.loss_grad(A, f, act, c1, p, E0, nu, colour=col)
+    assert L0 == pytest.approx(lr.loss(A, f, act, c1, p, E0, nu, colour=col), rel=1e-14)
+    idx = list(rng.choice(lr.O_B1, 5, replace=False)) + list(lr.O_W2 + rng.choice(lr.NH * lr.NH, 5, replace=False)) + \
+        list(lr.O_W3 + rng.choice(lr.NH, 3, replace=False)) + [lr.O_B3]
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (lr.loss(A, f, act, c1, pp, E0, nu, colour=col) - lr.loss(A, f, act, c1, pm, E0, nu, colour=col)) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9 * max(1.0, abs(g).max())), i

@@ -6,7 +6,7 @@ hierarchy (grid placement, triangle/cell pairs, octree, supports, split,
 prolongation), assembly of M and L at every depth, the load vector, and the
 solve of (M + t L) x = b to a relative residual of 1e-8 three times: with the
 FP64 Gauss-Seidel V-cycle, with the FP32 Gauss-Seidel V-cycle under FP64
-refinement, and with the FP32 V-cycle whose smoother is the learned Jacobi
+refinement, and with the FP32 V-cycle whose smoother is the learned multicolour SOR
 (conjugate gradients preconditioned by one V-cycle in all three).  The
 learned smoother is trained before timing on small meshes of other shapes.
 
@@ -115,9 +115,10 @@ def calibrate_copy(torch, dev):
     torch.cuda.synchronize()
 
 
-def train_smoother(cf, ctx, meshgen, steps=150):
+def train_smoother(cf, ctx, meshgen, steps=150, sweep=1):
     """Learned smoother trained (untimed) on small members of the three training
-    families: an icosphere, two close parallel sheets and a knot tube."""
+    families: an icosphere, two close parallel sheets and a knot tube.
+    sweep 1: multicolour SOR with learned per-row weights; 0: damped Jacobi."""
     fams = [(meshgen.icosphere(4)[:2], 6, 1e-3),
             (meshgen.two_sheets(64, 1.0 / 64)[:2], 6, 1e-3),
             (meshgen.torus_knot(nu=2048, nv=16, seed=5), 7, 1e-4)]
@@ -127,16 +128,18 @@ def train_smoother(cf, ctx, meshgen, steps=150):
         hs.append(h)
         ss.append(cf.camfe_assemble(h))
     t0 = time.perf_counter()
-    m, hist = cf.camfe_smoother_train(ctx, ss, t=1e-3, levels=3, steps=steps, nu=2, bf16=True, lr=3e-3, seed=1)
+    m, hist = cf.camfe_smoother_train(ctx, ss, t=1e-3, levels=3, steps=steps, nu=2, bf16=True, lr=3e-3, seed=1,
+                                      sweep=sweep)
     secs = time.perf_counter() - t0
     for s, h in zip(ss, hs):
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
-    return m, {"steps": steps, "seconds": secs, "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
+    return m, {"sweep": "multicolour SOR" if sweep == 1 else "damped Jacobi", "steps": steps, "seconds": secs,
+               "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
 
 
-def held_out_eval(cf, ctx, meshgen, model, size):
+def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
     """Held-out meshes (never trained on): the (3,5) knot tube and a noisy
     sphere, each about 8.4M triangles at depth 11 (size 'full'), or 2.1M at
     depth 10 ('small').  Solve (M + t L) x = b to 1e-8 with the plain FP64
@@ -159,9 +162,13 @@ def held_out_eval(cf, ctx, meshgen, model, size):
         b = cf.camfe_load_vector(s, h, fv)
         n = cf.camfe_hierarchy_info(h, depth)[2]
         res = {"tris": int(len(F)), "depth": depth, "t": t, "dof": int(n)}
-        for tag, kw in (("plain_gs_fp64", dict(precision=0, smoother=0)),
-                        ("learned_mixed", dict(precision=1, smoother=2))):
-            cf.camfe_smoother_attach(s, model if kw["smoother"] == 2 else None)
+        runs = [("plain_gs_fp64", dict(precision=0, smoother=0), None),
+                ("plain_gs_mixed", dict(precision=1, smoother=0), None),
+                ("learned_mixed", dict(precision=1, smoother=2), model)]
+        if model_jacobi is not None:
+            runs.append(("learned_jacobi_mixed", dict(precision=1, smoother=2), model_jacobi))
+        for tag, kw, mdl in runs:
+            cf.camfe_smoother_attach(s, mdl)
             for _ in range(2):
                 x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
             res[tag] = {"ms": 1000.0 * st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
@@ -224,8 +231,9 @@ def main():
         return
 
     keep = {}
-    log("[bench] training the learned smoother")
-    model, train_info = train_smoother(cf, ctx, meshgen)
+    log("[bench] training the learned smoothers")
+    model, train_info = train_smoother(cf, ctx, meshgen, sweep=1)
+    model_jac, train_info_jac = train_smoother(cf, ctx, meshgen, sweep=0)
 
     def step(record, keep_last=False):
         t0 = time.perf_counter()
@@ -313,6 +321,7 @@ def main():
                          "learned_mixed": float(max(r["stl"]["rel_residual"] for r in rec))},
         "learned_fell_back": int(max(r["stl"]["fell_back"] for r in rec)),
         "learned_training": train_info,
+        "learned_jacobi_training": train_info_jac,
     }
     if ranking:
         out["kernel_event_ms_warmup"] = {k: v[0] for k, v in ranking.items() if v[1]}
@@ -328,8 +337,9 @@ def main():
     cf.camfe_system_destroy(keep["s"])
     cf.camfe_hierarchy_destroy(keep["h"])
     if args.held_out != "none":
-        out["learned_held_out"] = held_out_eval(cf, ctx, meshgen, model, args.held_out)
+        out["learned_held_out"] = held_out_eval(cf, ctx, meshgen, model, args.held_out, model_jac)
     cf.camfe_model_destroy(model)
+    cf.camfe_model_destroy(model_jac)
     if args.calibrate_copy:
         calibrate_copy(torch, dev)
     if not args.no_cpu_baseline:

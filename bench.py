@@ -129,12 +129,13 @@ def train_smoother(cf, ctx, meshgen, steps=150, sweep=1):
         ss.append(cf.camfe_assemble(h))
     t0 = time.perf_counter()
     m, hist = cf.camfe_smoother_train(ctx, ss, t=1e-3, levels=3, steps=steps, nu=2, bf16=True, lr=3e-3, seed=1,
-                                      sweep=sweep)
+                                      sweep=sweep, cycle=1)
     secs = time.perf_counter() - t0
     for s, h in zip(ss, hs):
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
-    return m, {"sweep": "multicolour SOR" if sweep == 1 else "damped Jacobi", "steps": steps, "seconds": secs,
+    return m, {"sweep": "multicolour SOR" if sweep == 1 else "damped Jacobi", "loss": "two-grid cycle",
+               "steps": steps, "seconds": secs,
                "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
 

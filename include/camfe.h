@@ -265,6 +265,9 @@ typedef struct {
   double lr;         /* Adam step size                                              */
   uint64_t seed;     /* seed of the error samples                                   */
   int sweep;         /* 0: damped Jacobi (l1-bounded); 1: multicolour SOR            */
+  int cycle;         /* loss: 0 the nu sweeps alone; 1 a two-grid cycle (nu pre-    */
+                     /*    sweeps, coarse correction with the plain V-cycle one     */
+                     /*    depth down, nu post-sweeps in reverse colour order)      */
   int samples;       /* error samples per depth (four): 0 normal random vectors;    */
                      /*    1 the error one plain Gauss-Seidel V(2,2) cycle on       */
                      /*    A e = 0 leaves from such a vector; 2 two of each         */
@@ -286,14 +289,18 @@ camfe_status camfe_smoother_attach(camfe_sys s, camfe_model m);
 camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double t, double *omega);
 /* Training loss at one depth for one MLP's parameters (2081 floats), a sweep
  * type and nsamples (1..4) error samples e0 (n_d x nsamples column-major,
- * canonical order), with its gradient (2081 doubles; grad may be NULL).  nu
- * sweeps; an SOR sweep relaxes colour 0, then 1, ... (forward order).  The
- * forward and adjoint sweeps run in FP64; the MLP in FP32 or BF16 weights. */
+ * canonical order), with its gradient (2081 doubles; grad may be NULL).
+ * cycle 0: nu sweeps (an SOR sweep relaxes colour 0, then 1, ...); cycle 1: a
+ * two-grid cycle, nu sweeps, e - P B_c P^T A e with B_c one plain FP64
+ * Gauss-Seidel V(2,2)-cycle at depth - 1 (ESTATE at the coarsest depth), nu
+ * sweeps with the colours reversed.  Loss log(|A e_end|^2 / |A e0|^2) averaged
+ * over the samples.  Sweeps, correction and adjoints run in FP64; the MLP in
+ * FP32 or BF16 weights. */
 camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float *params, int bf16, int sweep,
-                                      const double *e0, int nsamples, int nu, double *loss, double *grad);
+                                      int cycle, const double *e0, int nsamples, int nu, double *loss, double *grad);
 /* Train a model on the GPU: for every system and depth above the coarsest,
  * four error samples (opts->samples), then opts->steps Adam steps on the mean
- * loss per MLP.
+ * loss (opts->cycle) per MLP.
  * loss_history (nullable) receives the mean loss over all depths before each
  * step.  The systems' solver state for opts->t is built when missing. */
 camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const *systems, int nsys, const camfe_train_opts *opts,

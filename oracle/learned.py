@@ -98,11 +98,52 @@ def colours(keys):
     return (c[:, 0] & 1) + 2 * (c[:, 1] & 1) + 4 * (c[:, 2] & 1)
 
 
-def _masks(n, colour):
-    """Rows relaxed by each step of one sweep: all rows (Jacobi) or one colour at a time."""
+def _masks(n, colour, forward=True):
+    """Rows relaxed by each step of one sweep: all rows (Jacobi) or one colour
+    at a time (colours 0..7, or 7..0 when not forward)."""
     if colour is None:
         return [np.ones(n, bool)]
-    return [colour == c for c in range(8)]
+    order = range(8) if forward else range(7, -1, -1)
+    return [colour == c for c in order]
+
+
+def coarse_inverse(Ac, eps):
+    """D^-1/2 (D^-1/2 Ac D^-1/2 + eps I)^-1 D^-1/2, dense; a row of zero
+    diagonal gets a unit diagonal in the scaled matrix and a zero row and
+    column in the result (the coarsest solve of the multigrid cycle)."""
+    A = Ac.toarray()
+    d = np.diag(A).copy()
+    pos = d > 0
+    s = np.where(pos, 1.0 / np.sqrt(np.where(pos, d, 1.0)), 0.0)
+    As = s[:, None] * A * s[None, :]
+    idx = np.where(~pos)[0]
+    As[idx, idx] = 1.0
+    As += eps * np.eye(len(d))
+    return s[:, None] * np.linalg.inv(As) * s[None, :]
+
+
+def coarse_correction(A, P, Bc):
+    """(e -> e - P Bc P^T A e, its transpose g -> g - A P Bc P^T g) for a
+    symmetric coarse operator Bc (a dense matrix or a function)."""
+    A = A.tocsr()
+    P = P.tocsr()
+    apply_bc = Bc if callable(Bc) else (lambda x: Bc @ x)
+    def fwd(E):
+        return E - P @ apply_bc(P.T @ (A @ E))
+    def adj(G):
+        return G - A @ (P @ apply_bc(P.T @ G))
+    return fwd, adj
+
+
+def _ops(n, nu, colour, cc):
+    """The cycle as a list of steps: ('relax', rows) or ('cc',).  Without cc:
+    nu sweeps; with cc: nu sweeps, the coarse correction, nu sweeps with the
+    colours reversed."""
+    ops = [("relax", m) for _ in range(nu) for m in _masks(n, colour, True)]
+    if cc is not None:
+        ops.append(("cc",))
+        ops += [("relax", m) for _ in range(nu) for m in _masks(n, colour, False)]
+    return ops
 
 
 def forward(params, f):
@@ -135,30 +176,33 @@ def _invdiag(A):
     return np.where(dg > 0, 1.0 / np.where(dg > 0, dg, 1.0), 0.0)
 
 
-def relax(A, f, act, c1, params, E0, nu, colour=None):
-    """The error after nu sweeps: Jacobi (colour None, omega = c s) or
-    multicolour SOR (colour given, omega = s)."""
+def relax(A, f, act, c1, params, E0, nu, colour=None, cc=None):
+    """The error after nu sweeps (Jacobi when colour is None, omega = c s;
+    multicolour SOR otherwise, omega = 1/2 + sigmoid(z)), or after a two-grid
+    cycle when cc = (forward, adjoint) of the coarse correction is given."""
     A = A.tocsr()
     n = A.shape[0]
     om = omega(params, f, act, c1, sor=colour is not None)
     dinv = _invdiag(A)
     E = np.array(E0, dtype=np.float64, ndmin=2).reshape(n, -1)
-    for _ in range(nu):
-        for m in _masks(n, colour):
-            E = E - np.where(m, om * dinv, 0.0)[:, None] * (A @ E)
+    for op in _ops(n, nu, colour, cc):
+        if op[0] == "cc":
+            E = cc[0](E)
+        else:
+            E = E - np.where(op[1], om * dinv, 0.0)[:, None] * (A @ E)
     return E
 
 
-def loss(A, f, act, c1, params, E0, nu, colour=None):
-    """Mean over the columns of E0 of log(|A e_nu|^2 / |A e_0|^2)."""
+def loss(A, f, act, c1, params, E0, nu, colour=None, cc=None):
+    """Mean over the columns of E0 of log(|A e_end|^2 / |A e_0|^2)."""
     A = A.tocsr()
     E0 = np.array(E0, dtype=np.float64, ndmin=2).reshape(A.shape[0], -1)
     r0 = A @ E0
-    r = A @ relax(A, f, act, c1, params, E0, nu, colour)
+    r = A @ relax(A, f, act, c1, params, E0, nu, colour, cc)
     return float(np.mean(np.log(np.sum(r * r, axis=0) / np.sum(r0 * r0, axis=0))))
 
 
-def loss_grad(A, f, act, c1, params, E0, nu, colour=None):
+def loss_grad(A, f, act, c1, params, E0, nu, colour=None, cc=None):
     """(loss, gradient over the packed parameters)."""
     A = A.tocsr()
     n = A.shape[0]
@@ -169,13 +213,16 @@ def loss_grad(A, f, act, c1, params, E0, nu, colour=None):
     E = np.array(E0, dtype=np.float64, ndmin=2).reshape(n, -1)
     S = E.shape[1]
     r0 = A @ E
-    U, MK = [], []
-    for _ in range(nu):
-        for m in _masks(n, colour):
-            u = np.where(m[:, None], dinv[:, None] * (A @ E), 0.0)     # D^-1 A e_k on the relaxed rows
-            U.append(u)
-            MK.append(m)
-            E = E - om[:, None] * u
+    ops = _ops(n, nu, colour, cc)
+    U = []
+    for op in ops:
+        if op[0] == "cc":
+            U.append(None)
+            E = cc[0](E)
+            continue
+        u = np.where(op[1][:, None], dinv[:, None] * (A @ E), 0.0)     # D^-1 A e_k on the relaxed rows
+        U.append(u)
+        E = E - om[:, None] * u
     r = A @ E
     n0 = np.sum(r0 * r0, axis=0)
     n1 = np.sum(r * r, axis=0)
@@ -183,10 +230,13 @@ def loss_grad(A, f, act, c1, params, E0, nu, colour=None):
     # dL/de_nu = (2 / S) A r / |r|^2 per column (A symmetric)
     G = (A @ r) * (2.0 / S / n1)[None, :]
     gom = np.zeros(n)
-    for k in range(len(U) - 1, -1, -1):
+    for k in range(len(ops) - 1, -1, -1):
+        if ops[k][0] == "cc":
+            G = cc[1](G)
+            continue
         # e_{k+1} = e_k - omega * u_k,  u_k = (D^-1 A e_k) on the step's rows
         gom -= np.sum(G * U[k], axis=1)
-        G = G - A @ (np.where(MK[k], om * dinv, 0.0)[:, None] * G)
+        G = G - A @ (np.where(ops[k][1], om * dinv, 0.0)[:, None] * G)
     if colour is None:
         dz = np.where(act, gom * c1 * sg * (1.0 - 0.5 * sg), 0.0)      # d omega / dz = c s (1 - s / 2)
     else:

@@ -60,7 +60,8 @@ class SolveStats(C.Structure):
 
 class TrainOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("levels", C.c_int), ("steps", C.c_int), ("nu", C.c_int), ("bf16", C.c_int),
-                ("lr", C.c_double), ("seed", C.c_uint64), ("sweep", C.c_int), ("samples", C.c_int)]
+                ("lr", C.c_double), ("seed", C.c_uint64), ("sweep", C.c_int), ("cycle", C.c_int),
+                ("samples", C.c_int)]
 
 
 _lib = None
@@ -105,7 +106,7 @@ def load():
         "camfe_model_destroy": (None, [H]),
         "camfe_smoother_attach": (I, [H, H]),
         "camfe_smoother_omega": (I, [H, H, I, D, P]),
-        "camfe_smoother_loss_grad": (I, [H, I, D, P, I, I, P, I, I, C.POINTER(D), P]),
+        "camfe_smoother_loss_grad": (I, [H, I, D, P, I, I, I, P, I, I, C.POINTER(D), P]),
         "camfe_smoother_train": (I, [H, P, I, C.POINTER(TrainOpts), C.POINTER(H), P]),
         "camfe_flow_step": (I, [H, D, P, C.POINTER(SolveOpts), C.POINTER(SolveStats)]),
         "camfe_batch_create": (I, [H, P, I, D, D, C.POINTER(H)]),
@@ -468,7 +469,7 @@ def camfe_smoother_omega(s, h, m, depth, t):
     return out
 
 
-def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=True, sweep=SWEEP_JACOBI):
+def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=True, sweep=SWEEP_JACOBI, cycle=0):
     """(loss, gradient float64[2081] or None) for one MLP's parameters and n_d x S samples."""
     p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
     if p.size != MLP_PARAMS:
@@ -478,20 +479,20 @@ def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=T
         e = e.reshape(-1, 1, order="F")
     loss = C.c_double()
     g = np.zeros(MLP_PARAMS) if want_grad else None
-    _check(load().camfe_smoother_loss_grad(s, depth, t, _ptr(p), 1 if bf16 else 0, int(sweep), _ptr(e), e.shape[1],
-                                           nu, C.byref(loss), _ptr(g)))
+    _check(load().camfe_smoother_loss_grad(s, depth, t, _ptr(p), 1 if bf16 else 0, int(sweep), int(cycle), _ptr(e),
+                                           e.shape[1], nu, C.byref(loss), _ptr(g)))
     return loss.value, g
 
 
 def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, lr=3e-3, seed=1, samples=0,
-                         sweep=SWEEP_JACOBI):
+                         sweep=SWEEP_JACOBI, cycle=0):
     """(model handle, loss history) trained on the GPU over the given systems.
     samples: 0 random vectors, 1 errors left by one plain V-cycle, 2 two of each;
-    sweep: 0 damped Jacobi, 1 multicolour SOR."""
+    sweep: 0 damped Jacobi, 1 multicolour SOR; cycle: 0 smoothing loss, 1 two-grid loss."""
     arr = (C.c_void_p * len(systems))(*[x.value if isinstance(x, C.c_void_p) else x for x in systems])
     o = TrainOpts()
     o.t, o.levels, o.steps, o.nu, o.bf16, o.lr, o.seed = t, levels, steps, nu, 1 if bf16 else 0, lr, seed
-    o.samples, o.sweep = samples, sweep
+    o.samples, o.sweep, o.cycle = samples, sweep, cycle
     hist = np.zeros(max(steps, 1))
     m = C.c_void_p()
     _check(load().camfe_smoother_train(ctx, C.cast(arr, C.c_void_p), len(systems), C.byref(o), C.byref(m),

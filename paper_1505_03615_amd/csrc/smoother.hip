@@ -515,25 +515,44 @@ struct GradWork {
   std::vector<double> hn;
 };
 
+}  // namespace
+void coarse_correction(SolverState* S, int d, const double* e, double* out, bool adjoint);   // solve.hip
+namespace {
+
 // Loss of one depth for the samples E0 (internal order, n x KS row-major, the
 // columns from kk on zero) and, when grad is given, dL/dparams added to grad
 // (device, NP doubles).  Returns the loss (mean over the kk samples).  sweep 0:
-// nu damped Jacobi sweeps with l1-bounded weights; sweep 1: nu forward
-// multicolour SOR sweeps, one relaxation step per colour (rows of one colour
-// are contiguous in the internal order and do not couple).
-double loss_grad_level(camfe_ctx ctx, const GLevel& G, const float* feat, const WView& W, int sweep, int nu,
-                       const double* E0, int kk, double* grad, GradWork& w) {
+// nu damped Jacobi sweeps with l1-bounded weights; sweep 1: nu multicolour SOR
+// sweeps, one relaxation step per colour (rows of one colour are contiguous in
+// the internal order and do not couple).  cycle = 0: the nu sweeps alone;
+// cycle = 1: a two-grid cycle, nu pre-sweeps (colours forward), the coarse
+// correction e - P B_c P^T A e with B_c the plain V-cycle one depth down
+// (needs d > d0), nu post-sweeps (colours reversed).
+double loss_grad_level(camfe_ctx ctx, SolverState* S, int d, const float* feat, const WView& W, int sweep, int nu,
+                       int cycle, const double* E0, int kk, double* grad, GradWork& w) {
+  const GLevel& G = S->lev[d];
   const size_t n = G.n;
   const int K = KS;
   const unsigned gn = grid_for(n, BLK);
-  struct Step { long long r0, r1, s0, s1; };
+  struct Step { int cc; long long r0, r1, s0, s1; };
   std::vector<Step> steps;
-  for (int it = 0; it < nu; ++it) {
-    if (sweep == 0) {
-      steps.push_back({0, (long long)n, 0, (long long)G.nslices});
-    } else {
-      for (int c = 0; c < G.ncol; ++c) steps.push_back({G.coff[c], G.coff[c + 1], G.cslice[c], G.cslice[c + 1]});
+  auto sweeps = [&](bool forward) {
+    for (int it = 0; it < nu; ++it) {
+      if (sweep == 0) {
+        steps.push_back({0, 0, (long long)n, 0, (long long)G.nslices});
+      } else {
+        for (int ci = 0; ci < G.ncol; ++ci) {
+          const int c = forward ? ci : G.ncol - 1 - ci;
+          steps.push_back({0, G.coff[c], G.coff[c + 1], G.cslice[c], G.cslice[c + 1]});
+        }
+      }
     }
+  };
+  sweeps(true);
+  if (cycle) {
+    CAMFE_REQUIRE(d > S->d0, CAMFE_EINVAL, "the two-grid loss needs a coarser depth");
+    steps.push_back({1, 0, 0, 0, 0});
+    sweeps(false);
   }
   const size_t ns = steps.size();
   need(w.om, n);
@@ -556,6 +575,10 @@ double loss_grad_level(camfe_ctx ctx, const GLevel& G, const float* feat, const 
   };
   auto apply = [&](const double* x, double* y) { apply_range(0, (long long)G.nslices, x, y); };
   for (size_t k = 0; k < ns; ++k) {
+    if (steps[k].cc) {
+      coarse_correction(S, d, w.e.p + k * n * K, w.e.p + (k + 1) * n * K, false);
+      continue;
+    }
     apply_range(steps[k].s0, steps[k].s1, w.e.p + k * n * K, w.y.p);
     hipLaunchKernelGGL(k_jac_fwd<KS>, gn, BLK, 0, st, (long long)n, steps[k].r0, steps[k].r1, G.invd64.p,
                        (const double*)w.om.p, (const double*)w.y.p, (const double*)(w.e.p + k * n * K),
@@ -586,6 +609,12 @@ double loss_grad_level(camfe_ctx ctx, const GLevel& G, const float* feat, const 
                      w.g.p);
   hipLaunchKernelGGL(k_fill_d, gn, BLK, 0, st, w.gom.p, (long long)n, 0.0);
   for (long long k = (long long)ns - 1; k >= 0; --k) {
+    if (steps[k].cc) {
+      // g <- (I - P B_c P^T A)^T g = g - A P B_c P^T g
+      coarse_correction(S, d, w.g.p, w.v.p, true);
+      CAMFE_HIP(hipMemcpyAsync(w.g.p, w.v.p, n * K * sizeof(double), hipMemcpyDeviceToDevice, st));
+      continue;
+    }
     hipLaunchKernelGGL(k_adj<KS>, gn, BLK, 0, st, (long long)n, steps[k].r0, steps[k].r1, G.invd64.p,
                        (const double*)w.om.p, (const double*)w.g.p, (const double*)(w.u.p + k * n * K), w.gom.p,
                        w.v.p);
@@ -732,10 +761,11 @@ camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double 
 }
 
 camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const float* params, int bf16, int sweep,
-                                      const double* e0, int nsamples, int nu, double* loss, double* grad) {
+                                      int cycle, const double* e0, int nsamples, int nu, double* loss,
+                                      double* grad) {
   return guarded([&] {
     CAMFE_REQUIRE(s && params && e0 && loss && nsamples >= 1 && nsamples <= KS && nu >= 0 &&
-                      (sweep == 0 || sweep == 1),
+                      (sweep == 0 || sweep == 1) && (cycle == 0 || cycle == 1),
                   CAMFE_EINVAL, "bad argument");
     camfe_hier h = s->h;
     CAMFE_REQUIRE(depth >= h->d0 && depth <= h->D, CAMFE_ESTATE, "depth not assembled");
@@ -754,7 +784,8 @@ camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const fl
     DArr<double> gd(NP);
     zero(ctx, gd.p, NP);
     GradWork w;
-    *loss = loss_grad_level(ctx, G, feat.p, v, sweep, nu, E.p, nsamples, grad ? gd.p : nullptr, w);
+    CAMFE_REQUIRE(!cycle || depth > S->d0, CAMFE_ESTATE, "the two-grid loss needs a depth above the coarsest");
+    *loss = loss_grad_level(ctx, S, depth, feat.p, v, sweep, nu, cycle, E.p, nsamples, grad ? gd.p : nullptr, w);
     if (grad) copy_out(ctx, grad, gd.p, NP);
   });
 }
@@ -764,7 +795,8 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
   return guarded([&] {
     CAMFE_REQUIRE(ctx && systems && nsys >= 1 && o && out, CAMFE_EINVAL, "bad argument");
     CAMFE_REQUIRE(o->levels >= 1 && o->levels <= 32 && o->steps >= 0 && o->nu >= 1 && o->lr > 0 &&
-                      o->samples >= 0 && o->samples <= 2 && (o->sweep == 0 || o->sweep == 1),
+                      o->samples >= 0 && o->samples <= 2 && (o->sweep == 0 || o->sweep == 1) &&
+                      (o->cycle == 0 || o->cycle == 1),
                   CAMFE_EINVAL, "bad options");
     ctx->use_device();
     camfe_model m0 = nullptr;
@@ -838,7 +870,7 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
         v.f = wdev.p + (size_t)it->l * NP;
         v.h = wbf.p + (size_t)it->l * NP;
         v.bf16 = o->bf16 != 0;
-        tot += loss_grad_level(ctx, it->S->lev[it->d], it->feat.p, v, o->sweep, o->nu, it->E.p, KS,
+        tot += loss_grad_level(ctx, it->S, it->d, it->feat.p, v, o->sweep, o->nu, o->cycle, it->E.p, KS,
                                grad.p + (size_t)it->l * NP, w);
       }
       if (loss_history) loss_history[step - 1] = tot / items.size();

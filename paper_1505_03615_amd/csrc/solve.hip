@@ -265,14 +265,27 @@ __global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* ro
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = s_begin + xcd_block(blockIdx.x, s_end - s_begin);
   const bool active = lane < rows[s];
+  // the writing wavefront fetches b_i, x_i and the weight first, so that these
+  // loads overlap the row's dot product instead of following it (no other row
+  // of this colour writes x_i)
+  const bool writer = sub == 0 && active;
+  long long i = 0;
+  T di = 0, bi[K], xi[K];
+  if (writer) {
+    i = row0[s] + lane;
+    di = invd[i];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      bi[q] = b[i * K + q];
+      xi[q] = x[i * K + q];
+    }
+  }
   T acc[K];
   slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
   slice_reduce<T, K>(red, lane, sub, acc);
-  if (sub == 0 && active) {
-    const int i = row0[s] + lane;
-    const T di = invd[i];
+  if (writer) {
 #pragma unroll
-    for (int q = 0; q < K; ++q) x[(long long)i * K + q] += (b[(long long)i * K + q] - acc[q]) * di;
+    for (int q = 0; q < K; ++q) x[i * K + q] = xi[q] + (bi[q] - acc[q]) * di;
   }
 }
 
@@ -285,15 +298,24 @@ __global__ __launch_bounds__(SL * SW) void k_jacobi(const int* sl_ptr, const int
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = xcd_block(blockIdx.x, ns);
   const bool active = lane < rows[s];
+  const bool writer = sub == 0 && active;
+  long long i = 0;
+  T w = 0, bi[K], xi[K];
+  if (writer) {   // fetched before the dot product (see k_gs)
+    i = row0[s] + lane;
+    w = winvd[i];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      bi[q] = b[i * K + q];
+      xi[q] = x_in[i * K + q];
+    }
+  }
   T acc[K];
   slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x_in, acc);
   slice_reduce<T, K>(red, lane, sub, acc);
-  if (sub == 0 && active) {
-    const int i = row0[s] + lane;
-    const T w = winvd[i];
+  if (writer) {
 #pragma unroll
-    for (int q = 0; q < K; ++q)
-      x_out[(long long)i * K + q] = x_in[(long long)i * K + q] + (b[(long long)i * K + q] - acc[q]) * w;
+    for (int q = 0; q < K; ++q) x_out[i * K + q] = xi[q] + (bi[q] - acc[q]) * w;
   }
 }
 
@@ -306,6 +328,13 @@ __global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const i
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = xcd_block(blockIdx.x, ns);
   const bool active = lane < rows[s];
+  long long i = 0;
+  TR bi[K];
+  if (sub == 0 && active) {   // fetched before the dot product (see k_gs)
+    i = row0[s] + lane;
+#pragma unroll
+    for (int q = 0; q < K; ++q) bi[q] = b[i * K + q];
+  }
   T acc[K];
   slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
   slice_reduce<T, K>(red, lane, sub, acc);
@@ -314,10 +343,9 @@ __global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const i
 #pragma unroll
   for (int q = 0; q < K; ++q) loc[q] = 0.0;
   if (active) {
-    const int i = row0[s] + lane;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-      TR v = b[(long long)i * K + q] - (TR)acc[q];
+      TR v = bi[q] - (TR)acc[q];
       r[(long long)i * K + q] = v;
       loc[q] = (double)v * (double)v;
     }
@@ -1585,6 +1613,51 @@ SolverState* ensure_solver(camfe_sys s, double t, double coarse_eps) {
     S = s->solver;
   }
   return S;
+}
+
+// Coarse-grid correction of the V-cycle at depth d > d0 on four columns
+// (n_d x 4 row-major, internal order), with B_c one plain FP64 Gauss-Seidel
+// V(2,2)-cycle at depth d-1 (a symmetric operator):
+//   adjoint == 0: out = e - P B_c P^T A e
+//   adjoint == 1: out = e - A P B_c P^T e   (the transpose of the first)
+void coarse_correction(SolverState* S, int d, const double* e, double* out, bool adjoint) {
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  GLevel& G = S->lev[d];
+  GLevel& C = S->lev[d - 1];
+  constexpr int K = KMAXS;
+  const long long nk = (long long)G.n * K;
+  const int sm = S->smoother;
+  S->smoother = 0;
+  double* r = G.r64.p;
+  if (!adjoint) {
+    // r = 0 - A e, b_c = P^T r = -P^T A e
+    hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.t64.p, nk, 0.0);
+    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p,
+                       G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.t64.p, e, r,
+                       (double*)nullptr);
+  } else {
+    hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, r);
+  }
+  hipLaunchKernelGGL((k_restrict<double, K>), grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, G.Rw64.p,
+                     (long long)C.n, (const double*)r, C.b64.p, C.x64.p);
+  vcycle<double, K>(S, d - 1, C.b64.p, C.x64.p, 2, 2);
+  if (!adjoint) {
+    // out = e + P x_c  (x_c = -B_c P^T A e)
+    hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, out);
+    hipLaunchKernelGGL((k_prolong<double, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, G.Pw64.p,
+                       (long long)G.n, (const double*)C.x64.p, out);
+  } else {
+    // t = P x_c (x_c = B_c P^T e), out = e - A t
+    hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.t64.p, nk, 0.0);
+    hipLaunchKernelGGL((k_prolong<double, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, G.Pw64.p,
+                       (long long)G.n, (const double*)C.x64.p, G.t64.p);
+    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p,
+                       G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, e, (const double*)G.t64.p,
+                       out, (double*)nullptr);
+  }
+  S->smoother = sm;
+  check_launch();
 }
 
 // one FP64 Gauss-Seidel V(nu1, nu2)-cycle at depth d on A e = 0 for four

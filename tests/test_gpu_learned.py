@@ -131,6 +131,28 @@ def test_loss_and_gradient_match_reference(cf, ctx, name, dd, bf16, sweep):
     assert g2 is None and L2 == pytest.approx(L, rel=1e-14)   # block sums meet in FP64 atomics
 
 
+@pytest.mark.parametrize("sweep", [0, 1])
+def test_two_grid_loss_and_gradient_match_reference(cf, ctx, sweep):
+    """One depth above the directly solved coarsest depth, where the coarse
+    operator of the cycle is the dense regularised inverse on both sides."""
+    h, s, o = built(cf, ctx, "sphere")
+    t = CASES["sphere"]["t"]
+    d = o.coarsest + 1
+    p = _params(7)[0]
+    A, f, act, c1, col = _ref(o, d, t)
+    Mc, Lc = o.matrices(d - 1)
+    cc = lr.coarse_correction(A, o.prolongation(d), lr.coarse_inverse((Mc + t * Lc).tocsr(), 1e-6))
+    E0 = np.random.default_rng(17).normal(size=(A.shape[0], 3))
+    say(f"[gpu] learned: two-grid loss/grad depth {d} sweep={sweep}")
+    L, g = cf.camfe_smoother_loss_grad(s, d, t, p, E0, nu=2, bf16=False, sweep=sweep, cycle=1)
+    Lr, gr = lr.loss_grad(A, f, act, c1, p.astype(np.float64), E0, 2, colour=col if sweep == 1 else None, cc=cc)
+    assert L == pytest.approx(Lr, rel=1e-6, abs=1e-7)
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    assert err <= 1e-4, err
+    with pytest.raises(cf.CamfeError, match="ESTATE"):
+        cf.camfe_smoother_loss_grad(s, o.coarsest, t, p, E0, nu=2, sweep=sweep, cycle=1)
+
+
 def test_constant_omega_jacobi_solves(cf, ctx):
     h, s, o = built(cf, ctx, "sphere")
     c = CASES["sphere"]

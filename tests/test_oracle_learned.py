@@ -7,8 +7,10 @@ through (orientation of the packed weights), features of a synthetic chain
 placed along one grid axis (offset indexing), invariants of the features of a
 real hierarchy (centre entry 1, row sums = (M 1)_i / A_ii since L 1 = 0), and
 central finite differences of the loss for the hand-derived gradient, for
-both sweep types; with unit weights the SOR sweep is the oracle's own
-multicolour Gauss-Seidel sweep.
+both sweep types and for the two-grid loss; with unit weights the SOR sweep is
+the oracle's own multicolour Gauss-Seidel sweep; the coarse correction with
+the exact Galerkin inverse is an A-orthogonal projection and its adjoint is
+its transpose.
 """
 import math
 
@@ -218,4 +220,62 @@ def test_sor_gradient_matches_central_differences(sphere):
         pp[i] += h
         pm[i] -= h
         fd = (lr.loss(A, f, act, c1, pp, E0, nu, colour=col) - lr.loss(A, f, act, c1, pm, E0, nu, colour=col)) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9 * max(1.0, abs(g).max())), i
+
+
+@pytest.fixture(scope="module")
+def sphere_cc():
+    """Sphere at depth 4 with a directly solved coarsest depth 3 (small enough
+    for dense algebra)."""
+    V, F = meshgen.icosphere(3)
+    o = Oracle(V, F, 4, degree=1, max_coarse=512).check().assemble()
+    assert o.coarsest == 3
+    return o
+
+
+def test_coarse_correction_is_a_projection_with_its_transpose_as_adjoint(sphere_cc):
+    o, t = sphere_cc, 1e-2
+    M, L = o.matrices(4)
+    A = (M + t * L).tocsr()
+    Mc, Lc = o.matrices(3)
+    Ac = (Mc + t * Lc).tocsr()
+    P = o.prolongation(4)
+    assert abs(P.T @ A @ P - Ac).max() <= 1e-12 * abs(Ac).max()   # Galerkin
+    B = np.linalg.pinv(Ac.toarray(), rcond=1e-13)
+    fwd, adj = lr.coarse_correction(A, P, 0.5 * (B + B.T))     # symmetric as the cycle's coarse operator is
+    rng = np.random.default_rng(2)
+    X, Y = rng.normal(size=(A.shape[0], 3)), rng.normal(size=(A.shape[0], 3))
+    C1 = fwd(X)
+    assert np.abs(fwd(C1) - C1).max() <= 1e-8 * np.abs(C1).max()
+    assert np.abs(P.T @ (A @ C1)).max() <= 1e-10 * np.abs(P.T @ (A @ X)).max()
+    assert np.sum(fwd(X) * Y) == pytest.approx(np.sum(X * adj(Y)), rel=1e-10)
+
+
+@pytest.mark.parametrize("sor", [False, True])
+def test_two_grid_gradient_matches_central_differences(sphere_cc, sor):
+    o, t, nu = sphere_cc, 1e-2, 2
+    M, L = o.matrices(4)
+    A = (M + t * L).tocsr()
+    Mc, Lc = o.matrices(3)
+    cc = lr.coarse_correction(A, o.prolongation(4), lr.coarse_inverse((Mc + t * Lc).tocsr(), 1e-6))
+    keys = o.functions(4)[0]
+    f, act, c1 = lr.features(A, M, keys, 4, 4)
+    col = lr.colours(keys) if sor else None
+    rng = np.random.default_rng(13)
+    p = rng.normal(size=lr.NP) * 0.3
+    p[lr.O_B3] = 0.2
+    E0 = rng.normal(size=(A.shape[0], 2))
+    L0, g = lr.loss_grad(A, f, act, c1, p, E0, nu, colour=col, cc=cc)
+    assert L0 == pytest.approx(lr.loss(A, f, act, c1, p, E0, nu, colour=col, cc=cc), rel=1e-13)
+    # the cycle reduces the residual much more than the sweeps alone
+    assert L0 < lr.loss(A, f, act, c1, p, E0, nu, colour=col) - 1.0
+    idx = list(rng.choice(lr.O_B1, 4, replace=False)) + list(lr.O_W2 + rng.choice(lr.NH * lr.NH, 4, replace=False)) + \
+        list(lr.O_W3 + rng.choice(lr.NH, 3, replace=False)) + [lr.O_B3]
+    h = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (lr.loss(A, f, act, c1, pp, E0, nu, colour=col, cc=cc) -
+              lr.loss(A, f, act, c1, pm, E0, nu, colour=col, cc=cc)) / (2 * h)
         assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9 * max(1.0, abs(g).max())), i

@@ -129,12 +129,12 @@ def train_smoother(cf, ctx, meshgen, steps=150, sweep=1):
         ss.append(cf.camfe_assemble(h))
     t0 = time.perf_counter()
     m, hist = cf.camfe_smoother_train(ctx, ss, t=1e-3, levels=3, steps=steps, nu=2, bf16=True, lr=3e-3, seed=1,
-                                      sweep=sweep, cycle=1)
+                                      sweep=sweep, cycle=0)
     secs = time.perf_counter() - t0
     for s, h in zip(ss, hs):
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
-    return m, {"sweep": "multicolour SOR" if sweep == 1 else "damped Jacobi", "loss": "two-grid cycle",
+    return m, {"sweep": "multicolour SOR" if sweep == 1 else "damped Jacobi", "loss": "smoothing (2 sweeps)",
                "steps": steps, "seconds": secs,
                "loss_first": float(hist[0]), "loss_last": float(hist[-1]),
                "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
@@ -183,6 +183,92 @@ def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
     return out
 
 
+def flow_eval(cf, ctx, meshgen, steps=10):
+    """Config 3: tracked cMCF steps (M_t + delta/2 L_0) X' = M_t X on the (3,5)
+    knot tube (2,097,152 triangles, depth 10), delta/2 = 1e-4, the three
+    coordinate columns, mixed precision, 1e-8 per step.  A step re-weights and
+    re-assembles M_t at every depth, refreshes the solver and solves."""
+    import torch
+    V, F = meshgen.torus_knot(nu=16384, nv=64, seed=3)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=10, degree=1,
+                                 max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    X = cf.camfe_linear_coeffs(s, h)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    Xd = torch.from_numpy(np.asfortranarray(X)).to(dev)
+    per, cyc = [], []
+    for k in range(steps):
+        t1 = time.perf_counter()
+        Xd, st = cf.camfe_flow_step(s, Xd, 2e-4, rtol=1e-8, max_iter=1000, precision=1)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t1)
+        cyc.append(st["cycles"])
+        if not st["converged"]:
+            break
+    n = cf.camfe_hierarchy_info(h, 10)[2]
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)
+    return {"mesh": "(3,5) knot tube, 2,097,152 tris, depth 10", "dof": int(n), "steps": len(per),
+            "hierarchy_and_assembly_ms": 1000.0 * setup, "ms_per_step": 1000.0 * float(np.mean(per)),
+            "first_step_ms": 1000.0 * per[0], "cycles_per_step": [int(c) for c in cyc],
+            "context": "the paper's Table 1: 1.52 s per step for its 1.27M-DoF system (CPU, its own solver)"}
+
+
+def batch_eval(cf, ctx, meshgen, count=16, seed=4000):
+    """Config 4 (scaled): `count` meshes of uneven size (icospheres, tori,
+    noise-displaced spheres), depth clamp(round(log2(side / mean edge)), 6, 10),
+    1-16 random right-hand sides each; one batched solve against the same
+    systems solved one at a time (FP64, 1e-8)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    systems, rhs = [], []
+    dev = torch.device("cuda:0")
+    for i in range(count):
+        kind = i % 3
+        if kind == 0:
+            V, F = meshgen.icosphere(int(rng.integers(3, 7)))
+        elif kind == 1:
+            R = float(rng.uniform(2.0, 6.0))
+            nu = int(rng.integers(24, 400))
+            V, F = meshgen.torus(R, 1.0, nu, max(8, int(nu / R)))
+        else:
+            V, F = meshgen.noisy_sphere(int(rng.integers(3, 7)), seed=seed + i)
+        e = np.linalg.norm(V[F[:, 1]] - V[F[:, 0]], axis=1).mean()
+        side = 1.125 * (V.max(0) - V.min(0)).max()
+        depth = int(np.clip(round(np.log2(side / e)), 6, 10))
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, degree=1, max_coarse=4096)
+        sy = cf.camfe_assemble(h)
+        k = int(rng.integers(1, 17))
+        b = cf.camfe_load_vector(sy, h, rng.normal(size=(len(V), k)))
+        systems.append((h, sy, len(F), depth, k))
+        rhs.append(b)
+    t_single = 0.0
+    for (h, sy, nt, depth, k), b in zip(systems, rhs):
+        cf.camfe_solve(sy, b, t=1e-3, rtol=1e-8, max_iter=600)      # setup and capture
+        x, st = cf.camfe_solve(sy, b, t=1e-3, rtol=1e-8, max_iter=600)
+        t_single += st["seconds"]
+    t0 = time.perf_counter()
+    bt = cf.camfe_batch_create(ctx, [x[1] for x in systems], 1e-3)
+    create = time.perf_counter() - t0
+    xs, sts = cf.camfe_batch_solve(bt, rhs, 1e-3, rtol=1e-8, max_iter=600)    # capture
+    xs, sts = cf.camfe_batch_solve(bt, rhs, 1e-3, rtol=1e-8, max_iter=600)
+    levels, rows = cf.camfe_batch_info(bt)
+    out = {"meshes": count, "tris": [int(x[2]) for x in systems], "depths": [int(x[3]) for x in systems],
+           "rhs": [int(x[4]) for x in systems], "batch_rows": int(rows), "batch_levels": int(levels),
+           "batch_create_ms": 1000.0 * create, "batch_solve_ms": 1000.0 * sts[0]["seconds"],
+           "one_at_a_time_solve_ms": 1000.0 * t_single,
+           "all_converged": bool(all(x["converged"] for x in sts)),
+           "max_rel_residual": float(max(x["rel_residual"] for x in sts))}
+    cf.camfe_batch_destroy(bt)
+    for h, sy, _, _, _ in systems:
+        cf.camfe_system_destroy(sy)
+        cf.camfe_hierarchy_destroy(h)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +282,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--held-out", default="small", choices=["full", "small", "none"],
                     help="learned-smoother evaluation on held-out meshes (8.4M or 2.1M tris)")
+    ap.add_argument("--no-flow", action="store_true", help="skip the config-3 flow steps")
+    ap.add_argument("--batch-meshes", type=int, default=16, help="meshes of the config-4 batch (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
                          "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
@@ -339,6 +427,14 @@ def main():
     cf.camfe_hierarchy_destroy(keep["h"])
     if args.held_out != "none":
         out["learned_held_out"] = held_out_eval(cf, ctx, meshgen, model, args.held_out, model_jac)
+    if not args.no_flow:
+        log("[bench] flow steps (config 3)")
+        out["flow_config3"] = flow_eval(cf, ctx, meshgen)
+        log("[bench] flow: " + json.dumps(out["flow_config3"]))
+    if args.batch_meshes > 0:
+        log(f"[bench] batch of {args.batch_meshes} meshes (config 4)")
+        out["batch_config4"] = batch_eval(cf, ctx, meshgen, args.batch_meshes)
+        log("[bench] batch: " + json.dumps(out["batch_config4"]))
     cf.camfe_model_destroy(model)
     cf.camfe_model_destroy(model_jac)
     if args.calibrate_copy:

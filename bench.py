@@ -64,13 +64,13 @@ def cpu_baseline(sample_n=128, sample_depth=7):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_colour_two_sheets_d8_traffic.md")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1505_03615_amd", "csrc", "solve.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1505_03615_amd", "csrc", "sell_kernels.hpp")
 
 
 def measured_traffic():
     """HBM bytes per launch of the finest-depth FP64 colour sweep from the
-    committed counter summary, or None when solve.hip has changed since the
-    counters were taken (the summary records the source's SHA-256)."""
+    committed counter summary, or None when the sweep kernels' source has
+    changed since the counters were taken (the summary records the source's SHA-256)."""
     import hashlib
     try:
         text = open(TRAFFIC_FILE).read()

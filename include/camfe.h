@@ -154,7 +154,8 @@ typedef struct {
   double t;          /* A = M + t L                                                */
   double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 for every column   */
   int max_iter;      /* outer iterations (CG steps or stationary cycles)          */
-  int nu_pre, nu_post; /* Gauss-Seidel sweeps before/after the coarse correction  */
+  int nu_pre, nu_post; /* sweeps before/after the coarse correction; equal for     */
+                       /*    method 0 (CG needs a symmetric V-cycle), else EINVAL   */
   int method;        /* 0: CG preconditioned by one V-cycle; 1: stationary V-cycles */
   int precision;     /* 0: FP64 throughout; 1: V-cycle in FP32, residual, CG      */
                      /*    recurrences and coarsest solve in FP64                 */

@@ -22,6 +22,7 @@
 #include <map>
 
 #include "solver.hpp"
+#include "sell_kernels.hpp"
 
 namespace camfe {
 
@@ -196,202 +197,6 @@ __global__ void k_diag_of(const int* ptr, const int* col, const double* M, const
 }
 
 // ------------------------------------------------------ V-cycle kernels
-// XCD-aware slice order: consecutive workgroups go to different XCDs, so
-// give each XCD a contiguous range of slices (neighbouring rows share x).
-__device__ inline long long xcd_block(long long b, long long nb) {
-  const long long X = 8;
-  if (nb < X) return b;
-  long long per = nb / X, rem = nb % X;
-  long long x = b % X, i = b / X;
-  long long base = x * per + min(x, rem);
-  long long lim = per + (x < rem ? 1 : 0);
-  return i < lim ? base + i : b;   // remainder blocks keep their index
-}
-
-// Each 64-row slice is processed by SW wavefronts: wavefront w takes the
-// slice's entry columns j = w, w + SW, ... (each load instruction still reads
-// one contiguous 64-entry segment), first issuing all of its value/column
-// loads, then the gathers of x; partial row sums meet in LDS.  This gives a
-// colour pass of n/8 rows enough memory-level parallelism to hide latency.
-constexpr int SW = 8;          // wavefronts per slice
-constexpr int MU = 4;          // entries per lane issued together
-
-template <class T, int K>
-__device__ inline void slice_row_dot(const int* sl_ptr, long long s, int lane, int sub, bool active, const int* scol,
-                                     const T* sval, const T* x, T acc[K]) {
-#pragma unroll
-  for (int q = 0; q < K; ++q) acc[q] = 0;
-  if (!active) return;
-  const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
-  const long long base = sl_ptr[s] + lane;
-  for (int j0 = sub; j0 < w; j0 += SW * MU) {
-    T a[MU];
-    int c[MU];
-#pragma unroll
-    for (int m = 0; m < MU; ++m) {
-      const int j = j0 + SW * m;
-      a[m] = j < w ? sval[base + (long long)j * SL] : (T)0;
-      c[m] = j < w ? scol[base + (long long)j * SL] : 0;
-    }
-#pragma unroll
-    for (int m = 0; m < MU; ++m)
-#pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fma(a[m], x[(long long)c[m] * K + q], acc[q]);
-  }
-}
-
-// sum of the SW partial sums of each row (valid in wavefront 0 after return)
-template <class T, int K>
-__device__ inline void slice_reduce(T (*red)[K][SL], int lane, int sub, T acc[K]) {
-#pragma unroll
-  for (int q = 0; q < K; ++q) red[sub][q][lane] = acc[q];
-  __syncthreads();
-  if (sub == 0) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      T s = red[0][q][lane];
-#pragma unroll
-      for (int w = 1; w < SW; ++w) s += red[w][q][lane];
-      acc[q] = s;
-    }
-  }
-}
-
-template <class T, int K>
-__global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* row0, const int* rows, int s_begin,
-                                                int s_end, const int* scol, const T* sval, const T* invd, const T* b,
-                                                T* x) {
-  __shared__ T red[SW][K][SL];
-  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
-  const long long s = s_begin + xcd_block(blockIdx.x, s_end - s_begin);
-  const bool active = lane < rows[s];
-  // the writing wavefront fetches b_i, x_i and the weight first, so that these
-  // loads overlap the row's dot product instead of following it (no other row
-  // of this colour writes x_i)
-  const bool writer = sub == 0 && active;
-  long long i = 0;
-  T di = 0, bi[K], xi[K];
-  if (writer) {
-    i = row0[s] + lane;
-    di = invd[i];
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      bi[q] = b[i * K + q];
-      xi[q] = x[i * K + q];
-    }
-  }
-  T acc[K];
-  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
-  slice_reduce<T, K>(red, lane, sub, acc);
-  if (writer) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) x[i * K + q] = xi[q] + (bi[q] - acc[q]) * di;
-  }
-}
-
-// weighted Jacobi over all slices: x_out = x_in + w_i (b - A x_in), w_i = omega_i / A_ii
-template <class T, int K>
-__global__ __launch_bounds__(SL * SW) void k_jacobi(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                    const int* scol, const T* sval, const T* winvd, const T* b,
-                                                    const T* x_in, T* x_out) {
-  __shared__ T red[SW][K][SL];
-  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
-  const long long s = xcd_block(blockIdx.x, ns);
-  const bool active = lane < rows[s];
-  const bool writer = sub == 0 && active;
-  long long i = 0;
-  T w = 0, bi[K], xi[K];
-  if (writer) {   // fetched before the dot product (see k_gs)
-    i = row0[s] + lane;
-    w = winvd[i];
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      bi[q] = b[i * K + q];
-      xi[q] = x_in[i * K + q];
-    }
-  }
-  T acc[K];
-  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x_in, acc);
-  slice_reduce<T, K>(red, lane, sub, acc);
-  if (writer) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) x_out[i * K + q] = xi[q] + (bi[q] - acc[q]) * w;
-  }
-}
-
-// r = b - A x over all slices; with nrm != null also accumulate ||r||^2 per column
-template <class T, class TR, int K>
-__global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                      const int* scol, const T* sval, const TR* b, const T* x, TR* r,
-                                                      double* nrm) {
-  __shared__ T red[SW][K][SL];
-  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
-  const long long s = xcd_block(blockIdx.x, ns);
-  const bool active = lane < rows[s];
-  long long i = 0;
-  TR bi[K];
-  if (sub == 0 && active) {   // fetched before the dot product (see k_gs)
-    i = row0[s] + lane;
-#pragma unroll
-    for (int q = 0; q < K; ++q) bi[q] = b[i * K + q];
-  }
-  T acc[K];
-  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
-  slice_reduce<T, K>(red, lane, sub, acc);
-  if (sub != 0) return;
-  double loc[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) loc[q] = 0.0;
-  if (active) {
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      TR v = bi[q] - (TR)acc[q];
-      r[(long long)i * K + q] = v;
-      loc[q] = (double)v * (double)v;
-    }
-  }
-  if (nrm) {   // per-block partial sums of ||r||^2, reduced by k_finalize
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      double v = loc[q];
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      if (lane == 0) nrm[(long long)blockIdx.x * K + q] = v;
-    }
-  }
-}
-
-// y = A p (FP64) and pq += p . y per column
-template <int K>
-__global__ __launch_bounds__(SL * SW) void k_spmv_dot(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                      const int* scol, const double* sval, const double* p, double* y,
-                                                      double* dot) {
-  __shared__ double red[SW][K][SL];
-  const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
-  const long long s = xcd_block(blockIdx.x, ns);
-  const bool active = lane < rows[s];
-  double acc[K];
-  slice_row_dot<double, K>(sl_ptr, s, lane, sub, active, scol, sval, p, acc);
-  slice_reduce<double, K>(red, lane, sub, acc);
-  if (sub != 0) return;
-  double loc[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) loc[q] = 0.0;
-  if (active) {
-    const int i = row0[s] + lane;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-      y[(long long)i * K + q] = acc[q];
-      loc[q] = acc[q] * p[(long long)i * K + q];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < K; ++q) {   // per-block partial of p . Ap
-    double v = loc[q];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0) dot[(long long)blockIdx.x * K + q] = v;
-  }
-}
-
 // b_c = R r_f (coarse rows gather their fine children, 8 lanes per row) and
 // x_c = 0 for the recursion
 constexpr int RL = 8;
@@ -1759,6 +1564,8 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     CAMFE_REQUIRE(o->precision == 0 || o->precision == 1, CAMFE_EINVAL, "precision must be 0 or 1");
     CAMFE_REQUIRE(o->method == 0 || o->method == 1, CAMFE_EINVAL, "method must be 0 or 1");
     CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0, CAMFE_EINVAL, "bad sweep counts");
+    CAMFE_REQUIRE(o->method != 0 || o->nu_pre == o->nu_post, CAMFE_EINVAL,
+                  "CG needs a symmetric V-cycle: nu_pre must equal nu_post");
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -1870,7 +1677,8 @@ camfe_status camfe_batch_solve(camfe_batch bt, const camfe_solve_opts* o, const 
     CAMFE_REQUIRE(o->method == 0 && o->smoother == 0, CAMFE_EINVAL,
                   "batched solves use CG with the Gauss-Seidel V-cycle");
     CAMFE_REQUIRE(o->precision == 0 || o->precision == 1, CAMFE_EINVAL, "precision must be 0 or 1");
-    CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0, CAMFE_EINVAL, "bad sweep counts");
+    CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0 && o->nu_pre == o->nu_post, CAMFE_EINVAL,
+                  "bad sweep counts (CG needs nu_pre == nu_post)");
     SolverState* S = bt->S.get();
     camfe_ctx ctx = bt->ctx;
     ctx->use_device();

@@ -210,6 +210,15 @@ def test_reassemble_mass_with_triangle_weights(cf, ctx):
     cf.camfe_hierarchy_destroy(h)
 
 
+def test_cg_rejects_an_unsymmetric_cycle(cf, ctx):
+    h, s, o = built(cf, ctx, "sphere_deg1")
+    b = o.load_vector(CASES["sphere_deg1"]["f"])
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_solve(s, b, t=1e-3, nu_pre=1, nu_post=2)
+    x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-30, max_iter=2, nu_pre=1, nu_post=2, method=1)
+    assert st["iterations"] == 2
+
+
 def test_invalid_inputs_and_exports(cf, ctx):
     V = np.array([[0.5, 0.5, 0.5], [1.5, 0.5, 0.5], [0.5, 1.5, 0.5]])
     F = np.array([[0, 1, 2]], np.int32)

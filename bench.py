@@ -97,12 +97,21 @@ def roofline(cf, s, meas, reps=50):
     avg64, by64 = cf.camfe_measure_kernel(s, meas, 0, reps)
     avg32, by32 = cf.camfe_measure_kernel(s, meas, 1, reps)
     achieved = by64 / (avg64 / 1000.0) / 1e9
-    return {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved, "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic() if meas == "gs_colour" else None,
-            "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
-            "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
-                     "bytes_per_launch": by32}}
+    out = {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved, "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+           "traffic": measured_traffic() if meas == "gs_colour" else None,
+           "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
+           "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
+                    "bytes_per_launch": by32}}
+    if meas == "gs_colour":
+        # what any launch of this size costs on the same graph: an empty kernel
+        # on the sweep's grid, and a plain copy of the same bytes per launch
+        e_ms, _ = cf.camfe_measure_kernel(s, "empty", 0, reps)
+        c_ms, c_by = cf.camfe_measure_kernel(s, "copy", 0, reps)
+        c_gbs = c_by / (c_ms / 1000.0) / 1e9
+        out["launch_floor"] = {"empty_us": 1000.0 * e_ms, "copy_us": 1000.0 * c_ms, "copy_bytes": c_by,
+                               "copy_GBs": c_gbs, "copy_frac": c_gbs / PEAK_HBM_GBS}
+    return out
 
 
 def calibrate_copy(torch, dev):

@@ -192,7 +192,13 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double
  * captured once into a HIP graph and replayed between two HIP events on the
  * context's stream.  avg_ms: average time of one launch; bytes_per_launch: the
  * algorithmic bytes of one launch (matrix values + three vector accesses per
- * row).  Overwrites the solver's scratch vectors only. */
+ * row).  Two reference launches put these figures in context: "empty" (a
+ * kernel that does nothing, on each colour's grid of the sweep: the launch
+ * floor; bytes 0) and "copy" (one plain device copy per colour moving the
+ * colour launch's average algorithmic bytes, half read and half written,
+ * rotating through 16 buffer pairs so that its data leaves the L2 caches
+ * between launches as the colours' matrices do; allocates and frees those
+ * buffers).  Overwrites the solver's scratch vectors only. */
 camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision, int reps, double *avg_ms,
                                   double *bytes_per_launch);
 void camfe_system_destroy(camfe_sys s);

@@ -27,30 +27,33 @@ __device__ inline long long xcd_block(long long b, long long nb) {
 // one contiguous 64-entry segment), first issuing all of its value/column
 // loads, then the gathers of x; partial row sums meet in LDS.  This gives a
 // colour pass of n/8 rows enough memory-level parallelism to hide latency.
+// Each slice's metadata is one int4 {first entry, end entry, first row, rows},
+// a single scalar load per workgroup.
 constexpr int SW = 8;          // wavefronts per slice
 constexpr int MU = 4;          // entries per lane issued together
 
 template <class T, int K>
-__device__ inline void slice_row_dot(const int* sl_ptr, long long s, int lane, int sub, bool active, const int* scol,
-                                     const T* sval, const T* x, T acc[K]) {
+__device__ inline void slice_row_dot(const int4& m, int lane, int sub, const int* scol, const T* sval, const T* x,
+                                     T acc[K]) {
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0;
-  if (!active) return;
-  const int w = (sl_ptr[s + 1] - sl_ptr[s]) / SL;
-  const long long base = sl_ptr[s] + lane;
+  // lanes past the slice's last row load its padding (value 0, a valid
+  // column) rather than wait for the row count before their first load
+  const int w = (m.y - m.x) / SL;
+  const long long base = m.x + lane;
   for (int j0 = sub; j0 < w; j0 += SW * MU) {
     T a[MU];
     int c[MU];
 #pragma unroll
-    for (int m = 0; m < MU; ++m) {
-      const int j = j0 + SW * m;
-      a[m] = j < w ? sval[base + (long long)j * SL] : (T)0;
-      c[m] = j < w ? scol[base + (long long)j * SL] : 0;
+    for (int u = 0; u < MU; ++u) {
+      const int j = j0 + SW * u;
+      a[u] = j < w ? sval[base + (long long)j * SL] : (T)0;
+      c[u] = j < w ? scol[base + (long long)j * SL] : 0;
     }
 #pragma unroll
-    for (int m = 0; m < MU; ++m)
+    for (int u = 0; u < MU; ++u)
 #pragma unroll
-      for (int q = 0; q < K; ++q) acc[q] = fma(a[m], x[(long long)c[m] * K + q], acc[q]);
+      for (int q = 0; q < K; ++q) acc[q] = fma(a[u], x[(long long)c[u] * K + q], acc[q]);
   }
 }
 
@@ -72,13 +75,13 @@ __device__ inline void slice_reduce(T (*red)[K][SL], int lane, int sub, T acc[K]
 }
 
 template <class T, int K>
-__global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* row0, const int* rows, int s_begin,
-                                                int s_end, const int* scol, const T* sval, const T* invd, const T* b,
-                                                T* x) {
+__global__ __launch_bounds__(SL * SW) void k_gs(const int4* meta, int s_begin, int s_end, const int* scol,
+                                                const T* sval, const T* invd, const T* b, T* x) {
   __shared__ T red[SW][K][SL];
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = s_begin + xcd_block(blockIdx.x, s_end - s_begin);
-  const bool active = lane < rows[s];
+  const int4 m = meta[s];
+  const bool active = lane < m.w;
   // the writing wavefront fetches b_i, x_i and the weight first, so that these
   // loads overlap the row's dot product instead of following it (no other row
   // of this colour writes x_i)
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* ro
   long long i = 0;
   T di = 0, bi[K], xi[K];
   if (writer) {
-    i = row0[s] + lane;
+    i = m.z + lane;
     di = invd[i];
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* ro
     }
   }
   T acc[K];
-  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
+  slice_row_dot<T, K>(m, lane, sub, scol, sval, x, acc);
   slice_reduce<T, K>(red, lane, sub, acc);
   if (writer) {
 #pragma unroll
@@ -105,18 +108,18 @@ __global__ __launch_bounds__(SL * SW) void k_gs(const int* sl_ptr, const int* ro
 
 // weighted Jacobi over all slices: x_out = x_in + w_i (b - A x_in), w_i = omega_i / A_ii
 template <class T, int K>
-__global__ __launch_bounds__(SL * SW) void k_jacobi(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                    const int* scol, const T* sval, const T* winvd, const T* b,
-                                                    const T* x_in, T* x_out) {
+__global__ __launch_bounds__(SL * SW) void k_jacobi(const int4* meta, int ns, const int* scol, const T* sval,
+                                                    const T* winvd, const T* b, const T* x_in, T* x_out) {
   __shared__ T red[SW][K][SL];
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = xcd_block(blockIdx.x, ns);
-  const bool active = lane < rows[s];
+  const int4 m = meta[s];
+  const bool active = lane < m.w;
   const bool writer = sub == 0 && active;
   long long i = 0;
   T w = 0, bi[K], xi[K];
   if (writer) {   // fetched before the dot product (see k_gs)
-    i = row0[s] + lane;
+    i = m.z + lane;
     w = winvd[i];
 #pragma unroll
     for (int q = 0; q < K; ++q) {
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(SL * SW) void k_jacobi(const int* sl_ptr, const int
     }
   }
   T acc[K];
-  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x_in, acc);
+  slice_row_dot<T, K>(m, lane, sub, scol, sval, x_in, acc);
   slice_reduce<T, K>(red, lane, sub, acc);
   if (writer) {
 #pragma unroll
@@ -135,22 +138,22 @@ __global__ __launch_bounds__(SL * SW) void k_jacobi(const int* sl_ptr, const int
 
 // r = b - A x over all slices; with nrm != null also accumulate ||r||^2 per column
 template <class T, class TR, int K>
-__global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                      const int* scol, const T* sval, const TR* b, const T* x, TR* r,
-                                                      double* nrm) {
+__global__ __launch_bounds__(SL * SW) void k_residual(const int4* meta, int ns, const int* scol, const T* sval,
+                                                      const TR* b, const T* x, TR* r, double* nrm) {
   __shared__ T red[SW][K][SL];
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = xcd_block(blockIdx.x, ns);
-  const bool active = lane < rows[s];
+  const int4 m = meta[s];
+  const bool active = lane < m.w;
   long long i = 0;
   TR bi[K];
   if (sub == 0 && active) {   // fetched before the dot product (see k_gs)
-    i = row0[s] + lane;
+    i = m.z + lane;
 #pragma unroll
     for (int q = 0; q < K; ++q) bi[q] = b[i * K + q];
   }
   T acc[K];
-  slice_row_dot<T, K>(sl_ptr, s, lane, sub, active, scol, sval, x, acc);
+  slice_row_dot<T, K>(m, lane, sub, scol, sval, x, acc);
   slice_reduce<T, K>(red, lane, sub, acc);
   if (sub != 0) return;
   double loc[K];
@@ -176,22 +179,22 @@ __global__ __launch_bounds__(SL * SW) void k_residual(const int* sl_ptr, const i
 
 // y = A p (FP64) and pq += p . y per column
 template <int K>
-__global__ __launch_bounds__(SL * SW) void k_spmv_dot(const int* sl_ptr, const int* row0, const int* rows, int ns,
-                                                      const int* scol, const double* sval, const double* p, double* y,
-                                                      double* dot) {
+__global__ __launch_bounds__(SL * SW) void k_spmv_dot(const int4* meta, int ns, const int* scol,
+                                                      const double* sval, const double* p, double* y, double* dot) {
   __shared__ double red[SW][K][SL];
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = xcd_block(blockIdx.x, ns);
-  const bool active = lane < rows[s];
+  const int4 m = meta[s];
+  const bool active = lane < m.w;
   double acc[K];
-  slice_row_dot<double, K>(sl_ptr, s, lane, sub, active, scol, sval, p, acc);
+  slice_row_dot<double, K>(m, lane, sub, scol, sval, p, acc);
   slice_reduce<double, K>(red, lane, sub, acc);
   if (sub != 0) return;
   double loc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) loc[q] = 0.0;
   if (active) {
-    const int i = row0[s] + lane;
+    const int i = m.z + lane;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       y[(long long)i * K + q] = acc[q];

@@ -300,6 +300,14 @@ __global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long
   }
 }
 
+// reference launches for camfe_measure_kernel: an empty kernel on the colour
+// sweep's grid, and a plain copy of 16-byte elements
+__global__ __launch_bounds__(SL * SW) void k_nop() {}
+__global__ void k_copy16(const double2* __restrict__ src, double2* __restrict__ dst, long long n) {
+  const long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 template <class T>
 __global__ void k_fill(T* p, long long n, T v) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
@@ -475,6 +483,15 @@ __global__ void k_scatter_out(const double* src, long long n, int c0, int kk, co
 }
 
 // ------------------------------------------------------------ host side
+// per-slice metadata packed for one scalar load in the sweep kernels
+void pack_meta(camfe_ctx ctx, GLevel& G, const std::vector<int>& ptr, const std::vector<int>& row0,
+               const std::vector<int>& rows) {
+  std::vector<int4> m(std::max<size_t>(G.nslices, 1), make_int4(0, 0, 0, 0));
+  for (size_t i = 0; i < G.nslices; ++i) m[i] = make_int4(ptr[i], ptr[i + 1], row0[i], rows[i]);
+  G.sl_meta.alloc(m.size());
+  copy_in(ctx, G.sl_meta.p, m.data(), m.size());
+}
+
 void setup_level(camfe_sys s, SolverState* st, int d) {
   camfe_hier h = s->h;
   camfe_ctx ctx = h->ctx;
@@ -537,6 +554,7 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
   for (size_t i = 0; i < G.nslices; ++i) hp[i + 1] = hp[i] + hw[i];
   G.snnz = (size_t)hp[G.nslices];
   copy_in(ctx, G.sl_ptr.p, hp.data(), G.nslices + 1);
+  pack_meta(ctx, G, hp, row0, rows);
   G.scol.alloc(G.snnz);
   G.sval64.alloc(G.snnz);
   G.sval32.alloc(G.snnz);
@@ -705,7 +723,7 @@ void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T*
     const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
     if (s1 <= s0) continue;
     CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K>),
-                (unsigned)(s1 - s0), SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, s0, s1, G.scol.p,
+                (unsigned)(s1 - s0), SL * SW, 0, ctx->stream, G.sl_meta.p, s0, s1, G.scol.p,
                 sval_of<T>(G), dinv, b, x);
   }
 }
@@ -738,7 +756,7 @@ void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward) {
   T* t = tmp_of<T>(G);
   for (int i = 0; i < nu; ++i) {
     CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.nnz, (long long)G.n) + (double)G.n * sizeof(T)), (k_jacobi<T, K>),
-                (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices,
+                (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p, (int)G.nslices,
                 G.scol.p, sval_of<T>(G), winvd_of<T>(G), b, (const T*)a, t);
     std::swap(a, t);
   }
@@ -781,7 +799,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   smooth<T, K>(S, G, b, x, nu1, true);
   T* r = Vec<T>::r(G);
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
-              (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+              (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
               (int)G.nslices, G.scol.p, sval_of<T>(G), b, (const T*)x, r, (double*)nullptr);
   GLevel& C = S->lev[d - 1];
   T* bc = Vec<T>::b(C);
@@ -835,7 +853,7 @@ void residual64(SolverState* S, const double* b, const double* x, double* r, dou
   GLevel& G = S->lev[S->D];
   camfe_ctx ctx = S->ctx;
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<double, K>(G.nnz, (long long)G.n)), (k_residual<double, double, K>),
-              (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p,
+              (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p,
               (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm ? S->part.p : (double*)nullptr);
   if (nrm) finalize<K>(S, (long long)G.nslices, nrm);
 }
@@ -890,7 +908,7 @@ void cg_step(SolverState* S, int nu1, int nu2) {
   const long long nb = (long long)((n + BLK - 1) / BLK);
   double* sc = S->sc.p;
   CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices, SL * SW, 0,
-              ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.sval64.p,
               (const double*)S->P.p, S->Q.p, S->part.p);
   finalize<K>(S, (long long)G.nslices, sc + K);
   CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, (unsigned)nb, BLK, 0, ctx->stream, (long long)n,
@@ -1124,6 +1142,7 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
       copy_in(ctx, G.sl_row0.p, hrow0.data(), G.nslices);
       copy_in(ctx, G.sl_rows.p, hrows.data(), G.nslices);
     }
+    pack_meta(ctx, G, hp, hrow0, hrows);
     G.scol.alloc(G.snnz);
     G.sval64.alloc(G.snnz);
     G.sval32.alloc(G.snnz);
@@ -1270,7 +1289,7 @@ void cg_step_b(SolverState* S, int nu1, int nu2) {
   const size_t n = G.n;
   const long long nb = (long long)(n / BLK);
   CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices, SL * SW, 0,
-              ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.sval64.p,
               (const double*)S->P.p, S->Q.p, S->part.p);
   dot_seg<K>(S, S->P.p, S->Q.p, K);
   CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update_b<K>, (unsigned)nb, BLK, 0, ctx->stream, (long long)n,
@@ -1311,9 +1330,9 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
   }
   hipLaunchKernelGGL((k_fill<double>), grid_for(S->sc.n, BLK), BLK, 0, st, S->sc.p, (long long)S->sc.n, 0.0);
   dot_seg<K>(S, S->B.p, S->B.p, 4 * K);
-  hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p, G.sl_row0.p,
-                     G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p,
-                     (const double*)S->X.p, S->R.p, (double*)nullptr);
+  hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
+                     (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
+                     (double*)nullptr);
   dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
   check_launch();
   std::vector<double> hs((size_t)nm * SCS);
@@ -1361,9 +1380,9 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
       copy_in(ctx, S->sc.p, hs.data(), hs.size());
     }
     // true residuals of the final iterates
-    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p,
-                       G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p,
-                       (const double*)S->X.p, S->R.p, (double*)nullptr);
+    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
+                       (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
+                       (double*)nullptr);
     dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
     copy_out(ctx, hs.data(), S->sc.p, hs.size());
     update(false);
@@ -1438,9 +1457,8 @@ void coarse_correction(SolverState* S, int d, const double* e, double* out, bool
   if (!adjoint) {
     // r = 0 - A e, b_c = P^T r = -P^T A e
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.t64.p, nk, 0.0);
-    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p,
-                       G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.t64.p, e, r,
-                       (double*)nullptr);
+    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
+                       (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.t64.p, e, r, (double*)nullptr);
   } else {
     hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, r);
   }
@@ -1457,9 +1475,8 @@ void coarse_correction(SolverState* S, int d, const double* e, double* out, bool
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.t64.p, nk, 0.0);
     hipLaunchKernelGGL((k_prolong<double, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, G.Pw64.p,
                        (long long)G.n, (const double*)C.x64.p, G.t64.p);
-    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_ptr.p,
-                       G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, e, (const double*)G.t64.p,
-                       out, (double*)nullptr);
+    hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
+                       (int)G.nslices, G.scol.p, G.sval64.p, e, (const double*)G.t64.p, out, (double*)nullptr);
   }
   S->smoother = sm;
   check_launch();
@@ -1497,15 +1514,45 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
     if (name == "gs_colour") kid = 0;
     else if (name == "residual") kid = 1;
     else if (name == "spmv_dot") kid = 2;
-    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL, "measurable kernels: gs_colour, residual, spmv_dot");
+    else if (name == "empty") kid = 3;
+    else if (name == "copy") kid = 4;
+    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL, "measurable kernels: gs_colour, residual, spmv_dot, empty, copy");
     const long long nk = (long long)G.n;
     hipStream_t st = ctx->stream;
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.b64.p, nk, 1.0);
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.x64.p, nk, 0.0);
     hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.b32.p, nk, 1.0f);
     hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
-    double launches = 0, bytes = 0;
+    // launches per repetition and algorithmic bytes of a colour sweep
+    double launches = 0, sweep_bytes = 0;
+    for (int c = 0; c < G.ncol; ++c)
+      if (G.cslice[c + 1] > G.cslice[c]) {
+        launches += 1;
+        sweep_bytes += precision == 0 ? pass_bytes<double, 1>(G.cnnz[c], G.coff[c + 1] - G.coff[c])
+                                      : pass_bytes<float, 1>(G.cnnz[c], G.coff[c + 1] - G.coff[c]);
+      }
+    double bytes = sweep_bytes;
+    if (kid == 1) {
+      launches = 1;
+      bytes = precision == 0 ? pass_bytes<double, 1>(G.nnz, nk) : pass_bytes<float, 1>(G.nnz, nk);
+    }
+    if (kid == 2) { launches = 1; bytes = (double)G.nnz * 8 + 2.0 * nk * 8; }
+    if (kid == 3) bytes = 0;
+    // the copy moves a colour launch's average bytes (half read, half written)
+    // per launch, rotating through NCP buffer pairs so that, like the colours'
+    // matrices, its data does not stay in the L2 caches between launches
+    constexpr int NCP = 16;
+    const long long m16 = std::max(1LL, (long long)(sweep_bytes / std::max(launches, 1.0) / 32.0 + 0.5));
+    DArr<double2> csrc, cdst;
+    if (kid == 4) {
+      csrc.alloc((size_t)m16 * NCP);
+      cdst.alloc((size_t)m16 * NCP);
+      hipLaunchKernelGGL((k_fill<double>), grid_for(2 * m16 * NCP, BLK), BLK, 0, st, (double*)csrc.p,
+                         2 * m16 * NCP, 1.0);
+      bytes = 32.0 * m16 * launches;
+    }
     auto enqueue = [&] {
+      int cp = 0;
       for (int r = 0; r < reps; ++r) {
         if (kid == 0) {
           if (precision == 0) gs_sweep<double, 1>(ctx, G, G.b64.p, G.x64.p, true, G.invd64.p);
@@ -1513,31 +1560,44 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
         } else if (kid == 1) {
           if (precision == 0)
             hipLaunchKernelGGL((k_residual<double, double, 1>), (unsigned)G.nslices, SL * SW, 0,
-                               ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p,
+                               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p,
                                G.sval64.p, (const double*)G.b64.p, (const double*)G.x64.p, G.r64.p, (double*)nullptr);
           else
             hipLaunchKernelGGL((k_residual<float, float, 1>), (unsigned)G.nslices, SL * SW, 0,
-                               ctx->stream, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p,
+                               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p,
                                G.sval32.p, (const float*)G.b32.p, (const float*)G.x32.p, G.r32.p, (double*)nullptr);
+        } else if (kid == 2) {
+          hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p,
+                             (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p, G.r64.p, S->part.p);
         } else {
-          hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_ptr.p,
-                             G.sl_row0.p, G.sl_rows.p, (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p,
-                             G.r64.p, S->part.p);
+          for (int c = 0; c < G.ncol; ++c) {
+            const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
+            if (s1 == s0) continue;
+            if (kid == 3) {
+              hipLaunchKernelGGL(k_nop, (unsigned)(s1 - s0), SL * SW, 0, ctx->stream);
+            } else {
+              const long long o = (long long)(cp++ % NCP) * m16;
+              hipLaunchKernelGGL(k_copy16, grid_for(m16, BLK), BLK, 0, ctx->stream, (const double2*)csrc.p + o,
+                                 cdst.p + o, m16);
+            }
+          }
         }
       }
     };
-    for (int c = 0; c < G.ncol; ++c) {
-      if (kid == 0) {
-        if (G.cslice[c + 1] > G.cslice[c]) {
-          launches += 1;
-          bytes += precision == 0 ? pass_bytes<double, 1>(G.cnnz[c], G.coff[c + 1] - G.coff[c])
-                                  : pass_bytes<float, 1>(G.cnnz[c], G.coff[c + 1] - G.coff[c]);
-        }
-      }
-    }
-    if (kid == 1) { launches = 1; bytes = precision == 0 ? pass_bytes<double, 1>(G.nnz, nk) : pass_bytes<float, 1>(G.nnz, nk); }
-    if (kid == 2) { launches = 1; bytes = (double)G.nnz * 8 + 2.0 * nk * 8; }
     const long long key = -1 - (((long long)kid * 2 + precision) << 20) - reps;
+    // reference graphs are not kept: the copy's buffers end with this call
+    struct DropGraph {
+      SolverState* S;
+      long long key;
+      bool on;
+      ~DropGraph() {
+        auto it = on ? S->graphs.find(key) : S->graphs.end();
+        if (it == S->graphs.end()) return;
+        (void)hipStreamSynchronize(S->ctx->stream);
+        (void)hipGraphExecDestroy(it->second);
+        S->graphs.erase(it);
+      }
+    } drop{S, key, kid >= 3};
     run_graph(S, key, enqueue);   // instantiate and warm
     ctx->sync();
     hipEvent_t e0, e1;

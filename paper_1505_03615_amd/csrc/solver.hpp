@@ -32,6 +32,7 @@ struct GLevel {
   DArr<int> sl_ptr;           // slice offsets into the value arrays (nslices + 1)
   DArr<int> sl_row0;          // first internal row of each slice
   DArr<int> sl_rows;          // rows in each slice (<= 64)
+  DArr<int4> sl_meta;         // {sl_ptr[s], sl_ptr[s + 1], sl_row0[s], sl_rows[s]} per slice
   DArr<int> scol;
   DArr<double> sval64, invd64;
   DArr<float> sval32, invd32;

@@ -219,6 +219,30 @@ def test_cg_rejects_an_unsymmetric_cycle(cf, ctx):
     assert st["iterations"] == 2
 
 
+def test_kernel_measurement_and_references(cf, ctx):
+    h, s, o = built(cf, ctx, "sheets_split")
+    b = o.load_vector(CASES["sheets_split"]["f"])
+    x1, st1 = cf.camfe_solve(s, b, t=1e-3, max_iter=600)
+    say("measure: gs_colour, residual, spmv_dot, empty, copy")
+    gs_ms, gs_by = cf.camfe_measure_kernel(s, "gs_colour", 0, 5)
+    gs32_ms, gs32_by = cf.camfe_measure_kernel(s, "gs_colour", 1, 5)
+    assert gs_ms > 0 and gs32_ms > 0 and 0 < gs32_by < gs_by
+    for name in ("residual", "spmv_dot"):
+        ms, by = cf.camfe_measure_kernel(s, name, 0, 5)
+        assert ms > 0 and by > gs_by
+    e_ms, e_by = cf.camfe_measure_kernel(s, "empty", 0, 5)
+    assert e_ms > 0 and e_by == 0
+    for _ in range(2):   # the copy's graph is rebuilt on new buffers each call
+        c_ms, c_by = cf.camfe_measure_kernel(s, "copy", 0, 5)
+        assert c_ms > 0 and abs(c_by - gs_by) <= 32
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_measure_kernel(s, "no_such_kernel")
+    # the measurements leave the solver as it was: the same solve again
+    x2, st2 = cf.camfe_solve(s, b, t=1e-3, max_iter=600)
+    assert st1["converged"] and st2["iterations"] == st1["iterations"]
+    assert np.array_equal(x1, x2)
+
+
 def test_invalid_inputs_and_exports(cf, ctx):
     V = np.array([[0.5, 0.5, 0.5], [1.5, 0.5, 0.5], [0.5, 1.5, 0.5]])
     F = np.array([[0, 1, 2]], np.int32)

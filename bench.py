@@ -192,6 +192,42 @@ def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
     return out
 
 
+def assembly_eval(cf, ctx, meshgen, reps=2):
+    """Assembly of M and L at every depth (the FP64 matrix-core kernel) on the
+    bench workload, the config-3 knot (degree 1) and two degree-2 cases: event
+    time of the assembly launches, the useful flops of their dense
+    contractions (2 NB^2 per quadrature point for M and for each of the three
+    gradient products), and that rate against the FP64 matrix peak.  Best of
+    `reps` assemblies of one hierarchy."""
+    import torch
+    dev = torch.device("cuda:0")
+    cases = [("two sheets 2 x 256 x 256 quads, depth 8, degree 1", meshgen.config_mesh("two_sheets_256")[:2], 8, 1),
+             ("(3,5) knot tube 2,097,152 tris, depth 10, degree 1", meshgen.torus_knot(nu=16384, nv=64, seed=3), 10, 1),
+             ("icosphere level 3 (1280 tris), depth 5, degree 2", meshgen.icosphere(3), 5, 2),
+             ("noisy sphere 327,680 tris, depth 8, degree 2", meshgen.noisy_sphere(7, seed=5), 8, 2)]
+    out = []
+    for name, (V, F), depth, degree in cases:
+        h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=depth,
+                                     degree=degree, max_coarse=4096)
+        best = None
+        for _ in range(reps):
+            cf.camfe_ctx_kernel_timing(ctx, True)
+            s = cf.camfe_assemble(h)
+            cf.camfe_ctx_kernel_timing(ctx, False)
+            ms, launches, flops = cf.camfe_ctx_kernel_time(ctx, "assemble")
+            cf.camfe_system_destroy(s)
+            if best is None or ms < best[0]:
+                best = (ms, launches, flops)
+        cf.camfe_hierarchy_destroy(h)
+        ms, launches, flops = best
+        tf = flops / (ms / 1000.0) / 1e12
+        out.append({"case": name, "tris": int(len(F)), "assemble_kernel_ms": ms, "launches": int(launches),
+                    "useful_mfma_flops": flops, "achieved_tflops": tf, "peak_tflops": PEAK_FP64_TFLOPS,
+                    "frac": tf / PEAK_FP64_TFLOPS})
+        log("[bench] assembly: " + json.dumps(out[-1]))
+    return out
+
+
 def flow_eval(cf, ctx, meshgen, steps=10):
     """Config 3: tracked cMCF steps (M_t + delta/2 L_0) X' = M_t X on the (3,5)
     knot tube (2,097,152 triangles, depth 10), delta/2 = 1e-4, the three
@@ -296,6 +332,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
                          "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
+    ap.add_argument("--assembly-only", action="store_true",
+                    help="only the assembly measurement (four meshes, both degrees); for matrix-core counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -313,6 +351,12 @@ def main():
     fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
     stream = torch.cuda.current_stream()
     ctx = cf.camfe_ctx_create(0, stream)
+
+    if args.assembly_only:
+        out = {"assembly": assembly_eval(cf, ctx, meshgen)}
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
 
     if args.roofline_only:
         h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
@@ -423,6 +467,12 @@ def main():
     }
     if ranking:
         out["kernel_event_ms_warmup"] = {k: v[0] for k, v in ranking.items() if v[1]}
+        a_ms, a_n, a_flops = ranking["assemble"]
+        if a_ms > 0:
+            tf = a_flops / (a_ms / 1000.0) / 1e12
+            out["assembly_mfma"] = {"kernel": "assemble (all depths, FP64 matrix cores)", "ms": a_ms,
+                                    "useful_flops": a_flops, "achieved_tflops": tf, "peak_tflops": PEAK_FP64_TFLOPS,
+                                    "frac": tf / PEAK_FP64_TFLOPS}
         dom = max(ranking, key=lambda k: ranking[k][0])
         if dom == "assemble":
             tot_ms, launches, work = ranking[dom]

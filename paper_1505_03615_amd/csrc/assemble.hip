@@ -6,12 +6,14 @@
 // cell.  Per pair the triangle is clipped against the six cell planes with
 // one polygon vertex per lane (ballots give each lane its output slot), the
 // polygon is fanned from its first vertex and every sub-triangle gets a
-// collapsed Gauss-Legendre rule.  Four quadrature points at a time, the 64
-// lanes evaluate (function slot, point) pairs and the FP64 matrix cores
-// contract them: M_e += Phi W Phi^T and L_e += sum_axes G W G^T with
-// v_mfma_f64_16x16x4 (operands: lane l holds row/column l % 16 at k = l / 16;
-// result: lane l, register r holds row l / 16 + 4 r, column l % 16).  Consecutive pairs whose eight (27) rows coincide share
-// one element block, which is scattered with atomics when the rows change.
+// collapsed Gauss-Legendre rule.  Eight (degree 1) or four (degree 2)
+// quadrature points at a time, the 64 lanes evaluate (function slot, point)
+// pairs and the FP64 matrix cores contract them: M_e += Phi W Phi^T and
+// L_e += sum_axes G W G^T with v_mfma_f64_16x16x4 (operands: lane l holds
+// row/column l % 16 at k = l / 16; result: lane l, register r holds row
+// l / 16 + 4 r, column l % 16).  Consecutive pairs whose eight (27) rows
+// coincide share one element block, which is scattered with atomics when the
+// rows change.
 #include <algorithm>
 #include <cmath>
 
@@ -179,6 +181,11 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
   constexpr int NQ = DEG == 1 ? 4 : 7;
   constexpr int Q = NQ * NQ;
   constexpr int RI = DEG == 1 ? 0 : 1;
+  // quadrature points per matrix-core step: degree 1 fills the 16 rows with
+  // its 8 functions at two sets of 4 points (rows and columns f + 8 h hold
+  // function f at point set h; the element block is the sum of the two
+  // diagonal 8x8 blocks of the product), degree 2 its 27 functions at 4 points
+  constexpr int PG = DEG == 1 ? 8 : 4;
   constexpr int PMAX = 16;   // clipped polygon vertices (9 in exact arithmetic)
   __shared__ double poly[PMAX][6];
   const int lane = threadIdx.x;
@@ -187,6 +194,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
   const u64 lt_mask = (1ULL << lane) - 1ULL;
   const bool want_mat = a.M != nullptr;
   const bool want_rhs = a.rhs != nullptr;
+  unsigned long long wave_pts = 0;   // quadrature points of this wavefront (measurement)
 
   for (int ch = blockIdx.x; ch < a.nchunk; ch += gridDim.x) {
     const int2 cd = a.chunks[ch];
@@ -208,7 +216,27 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
       const bool changed = __any(lane < NB && new_row != cur_row);
       if (have && (changed || pi == cd.y)) {
         // ---- scatter the element block
-        if (want_mat) {
+        if (want_mat && DEG == 1) {
+          // lane (pt, slot < 8) holds rows pt and pt + 4 of column slot of the
+          // first diagonal block; the lane 8 above it, the same entries of the second
+          const double m0 = accM[0][0] + __shfl(accM[0][2], lane + 8);
+          const double m1 = accM[0][1] + __shfl(accM[0][3], lane + 8);
+          const double l0 = accL[0][0] + __shfl(accL[0][2], lane + 8);
+          const double l1 = accL[0][1] + __shfl(accL[0][3], lane + 8);
+          const int colrow = __shfl(cur_row, slot & 7);
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            const int rowrow = __shfl(cur_row, pt + 4 * r);
+            if (slot < 8) {
+              const int e1 = a.ptr[rowrow + 1];
+              const int p = find_col(a.col, a.ptr[rowrow], e1, colrow);
+              if (p < e1 && a.col[p] == colrow) {
+                atomicAdd(a.M + p, r == 0 ? m0 : m1);
+                if (a.L) atomicAdd(a.L + p, r == 0 ? l0 : l1);
+              }
+            }
+          }
+        } else if (want_mat) {
           int ti = 0;
 #pragma unroll
           for (int I = 0; I < T; ++I)
@@ -246,13 +274,14 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
 #pragma unroll
             for (int c = 0; c < KMAX; ++c) {
               double v = accB[i][c];
+              if (DEG == 1) v += __shfl_xor(v, 8);
               v += __shfl_xor(v, 16);
               v += __shfl_xor(v, 32);
               accB[i][c] = v;
             }
 #pragma unroll
           for (int i = 0; i < T; ++i) {
-            const int j = 16 * i + slot;
+            const int j = 16 * i + slot;   // (degree 1: slots 8-15 repeat functions 0-7)
             const int rr = __shfl(cur_row, j < NB ? j : 0);
             if (pt == 0 && j < NB)
               for (int c = 0; c < a.k; ++c) atomicAdd(a.rhs + (long long)c * a.ldr + rr, accB[i][c]);
@@ -332,9 +361,9 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
         }
       }
       const int npts = (n - 2) * Q;
-      if (a.npts && lane == 0) atomicAdd(a.npts, (unsigned long long)npts);
-      for (int p0 = 0; p0 < npts; p0 += 4) {
-        const int p = p0 + pt;
+      wave_pts += (unsigned long long)npts;
+      for (int p0 = 0; p0 < npts; p0 += PG) {
+        const int p = p0 + pt + (DEG == 1 ? 4 * (slot >> 3) : 0);
         double val[T], gx[T], gy[T], gz[T];
         double wl = 0.0, wm = 0.0, bar[3] = {0, 0, 0};
 #pragma unroll
@@ -364,7 +393,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           for (int q = 0; q < 3; ++q) bar[q] = A0[3 + q] + xi * (A1[3 + q] - A0[3 + q]) + eta * (A2[3 + q] - A0[3 + q]);
 #pragma unroll
           for (int i = 0; i < T; ++i) {
-            const int j = 16 * i + slot;
+            const int j = DEG == 1 ? (slot & 7) : 16 * i + slot;
             if (j < NB) {
               const int jx = j % W, jy = (j / W) % W, jz = j / (W * W);
               double bx, dbx, by, dby, bz, dbz;
@@ -403,6 +432,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
       }
     }
   }
+  if (a.npts && lane == 0 && wave_pts) atomicAdd(a.npts, wave_pts);
 }
 
 // ---------------------------------------------------------- compaction

@@ -254,9 +254,14 @@ def flow_eval(cf, ctx, meshgen, steps=10):
         if not st["converged"]:
             break
     n = cf.camfe_hierarchy_info(h, 10)[2]
+    # the same colour-sweep measurement as the bench's roofline, on this
+    # 2.2M-function finest depth (launches about twelve times larger)
+    big = roofline(cf, s, "gs_colour", reps=10)
+    big.pop("traffic", None)
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
     return {"mesh": "(3,5) knot tube, 2,097,152 tris, depth 10", "dof": int(n), "steps": len(per),
+            "gs_colour_roofline_depth10": big,
             "hierarchy_and_assembly_ms": 1000.0 * setup, "ms_per_step": 1000.0 * float(np.mean(per)),
             "first_step_ms": 1000.0 * per[0], "cycles_per_step": [int(c) for c in cyc],
             "context": "the paper's Table 1: 1.52 s per step for its 1.27M-DoF system (CPU, its own solver)"}
@@ -332,6 +337,7 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
                          "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
+    ap.add_argument("--flow-only", action="store_true", help="only the config-3 flow steps (for profiler runs)")
     ap.add_argument("--assembly-only", action="store_true",
                     help="only the assembly measurement (four meshes, both degrees); for matrix-core counter runs")
     args = ap.parse_args()
@@ -351,6 +357,12 @@ def main():
     fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
     stream = torch.cuda.current_stream()
     ctx = cf.camfe_ctx_create(0, stream)
+
+    if args.flow_only:
+        out = {"flow_config3": flow_eval(cf, ctx, meshgen)}
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
 
     if args.assembly_only:
         out = {"assembly": assembly_eval(cf, ctx, meshgen)}

@@ -134,7 +134,12 @@ void camfe_hierarchy_destroy(camfe_hier h);
  * (nullable, nt doubles) scales each triangle's contribution to M only (the
  * mass of an evolved surface, Section 5.3); L always uses weight 1. */
 camfe_status camfe_assemble(camfe_hier h, const double *tri_weight, camfe_sys *out);
-/* Re-assemble M alone with new triangle weights (L and the structure kept). */
+/* Re-assemble M alone with new triangle weights (L and the structure kept).
+ * Degree 1: the first call also keeps every (cell, triangle) pair's
+ * unweighted element block on the device (36 doubles per pair, held by the
+ * system until it is destroyed; skipped when that would take more than a
+ * quarter of the free device memory), and later calls only weight and scatter
+ * those blocks.  tri_weight: host or device pointer, nt doubles (null = 1). */
 camfe_status camfe_reassemble_mass(camfe_sys s, const double *tri_weight);
 /* which: 0 = M, 1 = L.  CSR with ascending columns, canonical order. */
 camfe_status camfe_export_matrix(camfe_sys s, int depth, int which, int64_t *rowptr,

@@ -171,9 +171,15 @@ struct AsmArgs {
   double* rhs;        // n x ldr column-major (column offset applied by caller)
   long long ldr;
   unsigned long long* npts;   // nullable: quadrature points processed (measurement)
+  double* pcache;     // degree 1, mass only: each pair's unweighted 8 x 8 block (36 packed entries)
 };
 
-template <int DEG>
+// position of (r, c), r <= c, in a packed upper triangle of 8 x 8
+__host__ __device__ constexpr int upk8(int r, int c) { return r * (17 - r) / 2 + c - r; }
+
+// CACHE (degree 1, mass only): every pair's unweighted element block also
+// goes to a.pcache, so that later re-weightings skip clipping and quadrature
+template <int DEG, bool CACHE = false>
 __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
   constexpr int W = DEG == 1 ? 2 : 3;
   constexpr int NB = W * W * W;
@@ -195,6 +201,8 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
   const bool want_mat = a.M != nullptr;
   const bool want_rhs = a.rhs != nullptr;
   unsigned long long wave_pts = 0;   // quadrature points of this wavefront (measurement)
+  static_assert(!CACHE || DEG == 1, "the block cache holds degree-1 blocks");
+  d4 accP = (d4){0, 0, 0, 0};        // CACHE: this pair's block
 
   for (int ch = blockIdx.x; ch < a.nchunk; ch += gridDim.x) {
     const int2 cd = a.chunks[ch];
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
       for (int p0 = 0; p0 < npts; p0 += PG) {
         const int p = p0 + pt + (DEG == 1 ? 4 * (slot >> 3) : 0);
         double val[T], gx[T], gy[T], gz[T];
-        double wl = 0.0, wm = 0.0, bar[3] = {0, 0, 0};
+        double wl = 0.0, wm = 0.0, wmu = 0.0, bar[3] = {0, 0, 0};
 #pragma unroll
         for (int i = 0; i < T; ++i) { val[i] = gx[i] = gy[i] = gz[i] = 0.0; }
         if (p < npts) {
@@ -385,7 +393,8 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           const double u = c_glx[RI][iu], wu = c_glw[RI][iu];
           const double xi = u, eta = (1.0 - u) * c_glx[RI][iv];
           wl = 2.0 * area * wu * c_glw[RI][iv] * (1.0 - u);
-          wm = wl * a.hd2 * tw;
+          wmu = wl * a.hd2;
+          wm = wmu * tw;
           double lc[3];
 #pragma unroll
           for (int q = 0; q < 3; ++q) lc[q] = A0[q] + xi * e1[q] + eta * e2[q] - (double)cc[q];
@@ -409,7 +418,9 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
             }
           }
         }
-        if (want_mat) {
+        if (CACHE) {
+          accP = __builtin_amdgcn_mfma_f64_16x16x4f64(val[0], wmu * val[0], accP, 0, 0, 0);
+        } else if (want_mat) {
           int ti = 0;
 #pragma unroll
           for (int I = 0; I < T; ++I)
@@ -430,9 +441,58 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           }
         }
       }
+      if (CACHE) {
+        // the pair's block (sum of the two diagonal 8 x 8 blocks, as in the
+        // scatter), stored as its upper triangle; then weighted into the run's block
+        const double e0 = accP[0] + __shfl(accP[2], lane + 8);
+        const double e1 = accP[1] + __shfl(accP[3], lane + 8);
+        const long long base = (long long)(cd.x + pi) * 36;
+        if (slot < 8 && pt <= slot) a.pcache[base + upk8(pt, slot)] = e0;
+        if (slot < 8 && pt + 4 <= slot) a.pcache[base + upk8(pt + 4, slot)] = e1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) accM[0][q] += tw * accP[q];
+        accP = (d4){0, 0, 0, 0};
+      }
     }
   }
   if (a.npts && lane == 0 && wave_pts) atomicAdd(a.npts, wave_pts);
+}
+
+// M from the cached unweighted blocks of every pair: one wavefront per chunk
+// of pairs, lane (r, c) = entry (r, c) of the element block; blocks of
+// consecutive pairs with the same eight rows are summed, each weighted by its
+// triangle's weight, and scattered when the rows change
+__global__ __launch_bounds__(64) void k_mass_cached(const int2* chunks, int nchunk, const u64* pairs,
+                                                    const int* pair_rows, const double* pcache, const double* tri_w,
+                                                    const int* ptr, const int* col, double* M) {
+  const int lane = threadIdx.x;
+  const int r = lane >> 3, c = lane & 7;
+  const int e = upk8(min(r, c), max(r, c));
+  for (int ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+    const int2 cd = chunks[ch];
+    int cur_row = -1;
+    bool have = false;
+    double acc = 0.0;
+    for (int pi = 0; pi <= cd.y; ++pi) {
+      int new_row = -2;
+      if (pi < cd.y && lane < 8) new_row = pair_rows[(long long)(cd.x + pi) * 8 + lane];
+      const bool changed = __any(lane < 8 && new_row != cur_row);
+      if (have && (changed || pi == cd.y)) {
+        const int rowrow = __shfl(cur_row, r), colrow = __shfl(cur_row, c);
+        const int e1 = ptr[rowrow + 1];
+        const int p = find_col(col, ptr[rowrow], e1, colrow);
+        if (p < e1 && col[p] == colrow) atomicAdd(M + p, acc);
+        acc = 0.0;
+        have = false;
+      }
+      if (pi == cd.y) break;
+      cur_row = new_row;
+      have = true;
+      const long long q = cd.x + pi;
+      const double w = tri_w ? tri_w[(int)(pairs[q] & TRI_MASK)] : 1.0;
+      acc += w * pcache[q * 36 + e];
+    }
+  }
 }
 
 // ---------------------------------------------------------- compaction
@@ -679,6 +739,59 @@ void assemble_level(camfe_sys s, int d, bool want_L, bool want_M) {
   ctx->sync();
 }
 
+// M at depth d for new triangle weights.  Degree 1: the first call runs the
+// quadrature once more and keeps every pair's unweighted element block (36
+// doubles per pair, when that fits in a quarter of the free device memory);
+// later calls only weight and scatter the kept blocks.  Degree 2, or no room:
+// the full mass assembly.
+void reassemble_mass_level(camfe_sys s, int d) {
+  camfe_hier h = s->h;
+  camfe_ctx ctx = h->ctx;
+  if (h->degree != 1) {
+    assemble_level(s, d, false, true);
+    return;
+  }
+  if (s->mcache.size() <= (size_t)d) s->mcache.resize(d + 1);
+  DArr<double>& C = s->mcache[d];
+  const HLevel& L = h->lev[d];
+  SLevel& S = s->lev[d];
+  const size_t need = L.npairs * 36;
+  if (C.n != need) {
+    size_t free_b = 0, total_b = 0;
+    CAMFE_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (need * sizeof(double) > free_b / 4) {
+      assemble_level(s, d, false, true);
+      return;
+    }
+    upload_rules();
+    Chunks ch = make_chunks(ctx, L);
+    C.alloc(need);
+    zero(ctx, C.p, need);
+    zero(ctx, S.M.p, S.nnz);
+    AsmArgs a = base_args(h, d, ch);
+    a.tri_w = s->tri_w.n ? s->tri_w.p : nullptr;
+    a.ptr = S.ptr.p;
+    a.col = S.col.p;
+    a.M = S.M.p;
+    a.pcache = C.p;
+    if (ch.n) {
+      CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, (k_assemble<1, true>), (unsigned)std::min(ch.n, 1 << 20), 64, 0,
+                  ctx->stream, a);
+    }
+    check_launch();
+    ctx->sync();
+    return;
+  }
+  Chunks ch = make_chunks(ctx, L);
+  zero(ctx, S.M.p, S.nnz);
+  if (ch.n)
+    hipLaunchKernelGGL(k_mass_cached, (unsigned)std::min(ch.n, 1 << 20), 64, 0, ctx->stream, ch.c.p, ch.n,
+                       L.pairs.p, L.pair_rows.p, (const double*)C.p,
+                       (const double*)(s->tri_w.n ? s->tri_w.p : nullptr), S.ptr.p, S.col.p, S.M.p);
+  check_launch();
+  ctx->sync();
+}
+
 void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b) {
   camfe_hier h = s->h;
   camfe_ctx ctx = h->ctx;
@@ -748,7 +861,7 @@ camfe_status camfe_reassemble_mass(camfe_sys s, const double* tri_weight) {
     } else {
       s->tri_w.release();
     }
-    for (int d = s->h->d0; d <= s->h->D; ++d) assemble_level(s, d, false, true);
+    for (int d = s->h->d0; d <= s->h->D; ++d) reassemble_mass_level(s, d);
     refresh_solver(s);
   });
 }

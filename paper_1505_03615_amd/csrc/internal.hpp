@@ -76,6 +76,7 @@ struct camfe_sys_s {
   camfe::SolverState* solver = nullptr;
   const void* model = nullptr;      // attached learned smoother (not owned)
   camfe::DArr<double> area0;        // triangle areas of the original surface (flow)
+  std::vector<camfe::DArr<double>> mcache;   // per depth: unweighted degree-1 mass blocks of every pair
   ~camfe_sys_s() { camfe::destroy_solver(solver); }
 };
 

@@ -193,19 +193,24 @@ def test_large_direct_coarsest_tracks_oracle(cf, ctx):
 
 
 def test_reassemble_mass_with_triangle_weights(cf, ctx):
+    # the first re-weighting runs the quadrature (and keeps each pair's degree-1
+    # block); the later ones weight the kept blocks: all must match the oracle
     c = CASES["knot"]
     h = cf.camfe_hierarchy_build(ctx, c["V"], c["F"], depth=6, max_coarse=256)
     s = cf.camfe_assemble(h)
-    w = np.random.default_rng(7).uniform(0.5, 1.5, len(c["F"]))
-    cf.camfe_reassemble_mass(s, w)
-    o = Oracle(c["V"], c["F"], 6, max_coarse=256).check().assemble(tri_weight=w)
+    rng = np.random.default_rng(7)
     fin, d0 = cf.camfe_hierarchy_levels(h)
-    for d in range(d0, fin + 1):
-        Mo, Lo = o.matrices(d)
-        M = cf.camfe_export_matrix(s, h, d, 0)
-        L = cf.camfe_export_matrix(s, h, d, 1)
-        assert abs(M - Mo).max() <= 1e-12 * abs(Mo).max()
-        assert abs(L - Lo).max() <= 1e-12 * abs(Lo).max()
+    for w in (rng.uniform(0.5, 1.5, len(c["F"])), rng.uniform(0.1, 3.0, len(c["F"])), None):
+        say(f"[gpu] reassemble mass, weights {'none' if w is None else 'random'}")
+        cf.camfe_reassemble_mass(s, w)
+        o = Oracle(c["V"], c["F"], 6, max_coarse=256).check().assemble(tri_weight=w)
+        for d in range(d0, fin + 1):
+            Mo, Lo = o.matrices(d)
+            M = cf.camfe_export_matrix(s, h, d, 0)
+            L = cf.camfe_export_matrix(s, h, d, 1)
+            assert abs(M - Mo).max() <= 1e-12 * abs(Mo).max()
+            assert abs(L - Lo).max() <= 1e-12 * abs(Lo).max()
+            assert abs(M - M.T).max() <= 1e-14 * abs(Mo).max()
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
 

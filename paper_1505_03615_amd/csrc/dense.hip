@@ -1,8 +1,8 @@
 // Dense symmetric positive definite inverse for the coarsest depth: blocked
 // right-looking Cholesky A = L L^T (diagonal blocks factored in LDS, panels by
 // triangular solves, trailing updates by a tiled FP64 GEMM), then the inverse
-// of L by recursive halving (two GEMMs per split), then A^-1 = L^-T L^-1 by one
-// more GEMM.  All matrices are n x n
+// of L bottom up (all diagonal blocks at once, then doubling block sizes, two
+// batched GEMMs per level), then A^-1 = L^-T L^-1 by one more GEMM.  All matrices are n x n
 // row-major in device memory.
 #include <algorithm>
 #include <cmath>
@@ -16,18 +16,19 @@ constexpr int NB = 32;      // block size of the factorisation and of the triang
 constexpr int TM = 64;      // GEMM tile
 constexpr int TK = 16;      // GEMM k-chunk staged in LDS
 
-// C = beta C + alpha op(A) op(B) on an M x N output; op(A)(i, p) = TA ? A[p][i] : A[i][p],
-// op(B)(p, j) = TB ? B[j][p] : B[p][j].  lower != 0: only entries with j <= i are written.
+// One TM x TM tile (ti, tj) of C = beta C + alpha op(A) op(B) on an M x N
+// output; op(A)(i, p) = TA ? A[p][i] : A[i][p], op(B)(p, j) = TB ? B[j][p] :
+// B[p][j].  lower != 0: only entries with j <= i are written.
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int Kd, const double* A, long long lda, const double* B,
-                                               long long ldb, double* C, long long ldc, double alpha, double beta,
-                                               int lower) {
-  const int ti = blockIdx.y, tj = blockIdx.x;
+__device__ inline void dgemm_tile(int ti, int tj, int M, int N, int Kd, const double* A, long long lda,
+                                  const double* B, long long ldb, double* C, long long ldc, double alpha, double beta,
+                                  int lower) {
   if (lower && tj > ti) return;
+  const int i0 = ti * TM, j0 = tj * TM;
+  if (i0 >= M || j0 >= N) return;
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TM + 1];
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int i0 = ti * TM, j0 = tj * TM;
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -69,6 +70,30 @@ __global__ __launch_bounds__(256) void k_dgemm(int M, int N, int Kd, const doubl
         *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[u][v];
       }
     }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_dgemm(int M, int N, int Kd, const double* A, long long lda, const double* B,
+                                               long long ldb, double* C, long long ldc, double alpha, double beta,
+                                               int lower) {
+  dgemm_tile<TA, TB>(blockIdx.y, blockIdx.x, M, N, Kd, A, lda, B, ldb, C, ldc, alpha, beta, lower);
+}
+
+// One level of the bottom-up triangular inverse: for every pair z of
+// neighbouring diagonal blocks of size h (rows o = 2 h z .. o + h and
+// o + h .. min(o + 2h, n)), whose inverses W11 and W22 are in place,
+// STEP 1: T_z = L21 W11, STEP 2: W21 = -W22 T_z (T_z at T + z h^2, leading dimension h)
+template <int STEP>
+__global__ __launch_bounds__(256) void k_trinv_level(const double* L, double* W, double* T, long long n, int h) {
+  const long long o = 2LL * h * blockIdx.z;
+  const int mz = (int)(std::min((long long)2 * h, n - o) - h);   // rows of the second block (> 0)
+  double* Tz = T + (long long)blockIdx.z * h * h;
+  if (STEP == 1)
+    dgemm_tile<false, false>(blockIdx.y, blockIdx.x, mz, h, h, L + (o + h) * n + o, n, W + o * n + o, n, Tz, h,
+                             1.0, 0.0, 0);
+  else
+    dgemm_tile<false, false>(blockIdx.y, blockIdx.x, mz, h, mz, W + (o + h) * n + (o + h), n, Tz, h,
+                             W + (o + h) * n + o, n, -1.0, 0.0, 0);
 }
 
 // Cholesky of the kb x kb diagonal block at (k0, k0) in LDS; writes L_kk with
@@ -127,8 +152,11 @@ __global__ __launch_bounds__(64) void k_trsm_panel(double* A, long long n, int k
     if (j < kb) row[j] = x[j];
 }
 
-// inverse of the lower-triangular rb x rb block L[r0.., r0..] into W[r0.., r0..]
-__global__ __launch_bounds__(64) void k_trtri_diag(const double* L, double* W, long long n, int r0, int rb) {
+// inverse of the lower-triangular diagonal block number blockIdx.x (rows
+// r0 = NB blockIdx.x .. r0 + rb) of L into the same block of W
+__global__ __launch_bounds__(64) void k_trtri_diag(const double* L, double* W, long long n) {
+  const int r0 = blockIdx.x * NB;
+  const int rb = (int)std::min((long long)NB, n - r0);
   __shared__ double T[NB][NB + 1];
   for (int e = threadIdx.x; e < NB * NB; e += 64) {
     const int i = e / NB, j = e % NB;
@@ -175,21 +203,19 @@ void gemm(camfe_ctx ctx, int M, int N, int Kd, const double* A, long long lda, c
                      beta, lower ? 1 : 0);
 }
 
-// W[o.., o..] = inverse of the lower-triangular m x m block L[o.., o..]; the
-// two halves recurse, the off-diagonal block takes two GEMMs through T
-void trinv(camfe_ctx ctx, const double* L, double* W, double* T, long long n, int o, int m) {
-  if (m <= NB) {
-    hipLaunchKernelGGL(k_trtri_diag, 1, 64, 0, ctx->stream, L, W, n, o, m);
-    return;
+// W = inverse of the lower-triangular L (n x n), bottom up: every NB x NB
+// diagonal block in one launch, then levels of doubling block size, each
+// pairing neighbouring inverted blocks with two batched GEMMs
+void trinv(camfe_ctx ctx, const double* L, double* W, double* T, long long n) {
+  const int nb = (int)((n + NB - 1) / NB);
+  hipLaunchKernelGGL(k_trtri_diag, nb, 64, 0, ctx->stream, L, W, n);
+  for (long long h = NB; h < n; h *= 2) {
+    const unsigned pairs = (unsigned)((n - h + 2 * h - 1) / (2 * h));   // pairs with a second block
+    const unsigned tiles = (unsigned)((h + TM - 1) / TM);
+    dim3 grid(tiles, tiles, pairs);
+    hipLaunchKernelGGL(k_trinv_level<1>, grid, 256, 0, ctx->stream, L, W, T, n, (int)h);
+    hipLaunchKernelGGL(k_trinv_level<2>, grid, 256, 0, ctx->stream, L, W, T, n, (int)h);
   }
-  const int h = (m / 2 + NB - 1) / NB * NB;   // a multiple of NB, 0 < h < m
-  trinv(ctx, L, W, T, n, o, h);
-  trinv(ctx, L, W, T, n, o + h, m - h);
-  // T = L21 W11 ((m-h) x h), then W21 = -W22 T
-  gemm<false, false>(ctx, m - h, h, h, L + (long long)(o + h) * n + o, n, W + (long long)o * n + o, n, T, h, 1.0,
-                     0.0, false);
-  gemm<false, false>(ctx, m - h, h, m - h, W + (long long)(o + h) * n + (o + h), n, T, h,
-                     W + (long long)(o + h) * n + o, n, -1.0, 0.0, false);
 }
 
 }  // namespace
@@ -219,7 +245,7 @@ void spd_inverse_scaled(camfe_ctx ctx, double* A, int n, const double* s, double
   // W = L^-1, recursively: inv([L11 0; L21 L22]) = [W11 0; -W22 L21 W11  W22]
   DArr<double> W(nn), T(nn);
   zero(ctx, W.p, W.n);
-  trinv(ctx, A, W.p, T.p, n, 0, n);
+  trinv(ctx, A, W.p, T.p, n);
   // A^-1 = W^T W (lower triangle into A), then scale and mirror
   gemm<true, false>(ctx, n, n, n, W.p, n, W.p, n, A, n, 1.0, 0.0, true);
   hipLaunchKernelGGL(k_sym_scale, grid_for(nn, 256), 256, 0, ctx->stream, (const double*)A, (long long)n, s, out);

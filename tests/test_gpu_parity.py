@@ -215,6 +215,22 @@ def test_reassemble_mass_with_triangle_weights(cf, ctx):
     cf.camfe_hierarchy_destroy(h)
 
 
+@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "knot"])
+def test_apply_matches_oracle_matrices(cf, ctx, name):
+    h, s, o = built(cf, ctx, name)
+    c = CASES[name]
+    Mo, Lo = o.matrices(c["depth"])
+    rng = np.random.default_rng(11)
+    t = 1e-3
+    for k in (1, 3, 6):
+        say(f"[gpu] apply {name} k={k}")
+        x = rng.standard_normal((Mo.shape[0], k))
+        for which, A in ((0, Mo), (1, Lo), (2, Mo + t * Lo)):
+            y = cf.camfe_apply(s, which, t, x)
+            ref = A @ x
+            assert np.abs(y - ref).max() <= 1e-12 * np.abs(ref).max(), (which, k)
+
+
 def test_cg_rejects_an_unsymmetric_cycle(cf, ctx):
     h, s, o = built(cf, ctx, "sphere_deg1")
     b = o.load_vector(CASES["sphere_deg1"]["f"])

@@ -56,28 +56,50 @@ camfe_status guarded(Fn&& f) {
   }
 }
 
+// ------------------------------------------------------ device memory cache
+// Device memory of the library comes from a cache of blocks keyed by device,
+// stream and size class (pool.hip).  A freed block goes back to the list of
+// the stream it was allocated for and is handed out again only for that
+// stream, so stream order puts every earlier use of the block ahead of the
+// next one.  The stream is the one of the context whose entry point is
+// running (set by camfe_ctx_s::use_device); streams are attached by
+// camfe_ctx_create and detached (their blocks freed) by camfe_ctx_destroy.
+// Blocks of a detached stream, and blocks beyond a quarter of the device's
+// memory, are freed at once.
+struct PoolBlock {
+  size_t cls = 0;           // size class in bytes
+  int dev = 0;
+  hipStream_t st = nullptr;
+};
+void* pool_alloc(size_t bytes, PoolBlock* b);
+void pool_free(void* p, const PoolBlock& b);
+void pool_attach_stream(int dev, hipStream_t st);
+void pool_detach_stream(int dev, hipStream_t st);   // the stream must be idle
+void set_current_stream(hipStream_t st);             // of the calling thread
+
 // ----------------------------------------------------------- device arrays
 template <class T>
 struct DArr {
   T* p = nullptr;
   size_t n = 0;
+  PoolBlock blk;
   DArr() = default;
   explicit DArr(size_t count) { alloc(count); }
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
-  DArr(DArr&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n), blk(o.blk) { o.p = nullptr; o.n = 0; }
   DArr& operator=(DArr&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; blk = o.blk; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DArr() { release(); }
   void alloc(size_t count) {
     release();
-    if (count) CAMFE_HIP(hipMalloc((void**)&p, count * sizeof(T)));
+    if (count) p = (T*)pool_alloc(count * sizeof(T), &blk);
     n = count;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) pool_free(p, blk);
     p = nullptr;
     n = 0;
   }
@@ -163,7 +185,10 @@ struct camfe_ctx_s {
     return scratch2.p;
   }
   void sync() { CAMFE_HIP(hipStreamSynchronize(stream)); }
-  void use_device() { CAMFE_HIP(hipSetDevice(device)); }
+  void use_device() {
+    CAMFE_HIP(hipSetDevice(device));
+    camfe::set_current_stream(stream);
+  }
 };
 
 namespace camfe {

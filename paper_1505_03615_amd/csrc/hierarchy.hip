@@ -814,6 +814,7 @@ camfe_status camfe_ctx_create(int device, void* hip_stream, camfe_ctx* out) {
       c->own_stream = true;
     }
     CAMFE_HIP(hipMalloc((void**)&c->d_flag, sizeof(int)));
+    pool_attach_stream(device, c->stream);
     *out = c.release();
   });
 }
@@ -824,6 +825,7 @@ void camfe_ctx_destroy(camfe_ctx ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   ctx->scratch.release();
   ctx->scratch2.release();
+  pool_detach_stream(ctx->device, ctx->stream);
   if (ctx->d_flag) (void)hipFree(ctx->d_flag);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;

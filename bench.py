@@ -183,6 +183,7 @@ def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
                 x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
             res[tag] = {"ms": 1000.0 * st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
                         "converged": bool(st["converged"]), "fell_back": int(st["fell_back"])}
+            log(f"[bench] held-out {name} {tag}: {res[tag]['cycles']} cycles, {res[tag]['ms']:.0f} ms")
         res["speedup_learned_vs_plain"] = res["plain_gs_fp64"]["ms"] / res["learned_mixed"]["ms"]
         cf.camfe_smoother_attach(s, None)
         cf.camfe_system_destroy(s)

@@ -283,6 +283,8 @@ typedef struct {
   int samples;       /* error samples per depth (four): 0 normal random vectors;    */
                      /*    1 the error one plain Gauss-Seidel V(2,2) cycle on       */
                      /*    A e = 0 leaves from such a vector; 2 two of each         */
+  const double *t_each; /* nullable host array of nsys values: t of each system    */
+                     /*    (replaces t; each system may then appear only once)      */
 } camfe_train_opts;
 
 /* Model from packed FP32 parameters (levels x 2081, copied) or, with params

@@ -61,7 +61,7 @@ class SolveStats(C.Structure):
 class TrainOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("levels", C.c_int), ("steps", C.c_int), ("nu", C.c_int), ("bf16", C.c_int),
                 ("lr", C.c_double), ("seed", C.c_uint64), ("sweep", C.c_int), ("cycle", C.c_int),
-                ("samples", C.c_int)]
+                ("samples", C.c_int), ("t_each", C.c_void_p)]
 
 
 _lib = None
@@ -487,12 +487,20 @@ def camfe_smoother_loss_grad(s, depth, t, params, e0, nu, bf16=True, want_grad=T
 def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, lr=3e-3, seed=1, samples=0,
                          sweep=SWEEP_JACOBI, cycle=0):
     """(model handle, loss history) trained on the GPU over the given systems.
+    t: one value, or one per system (each system then listed once);
     samples: 0 random vectors, 1 errors left by one plain V-cycle, 2 two of each;
     sweep: 0 damped Jacobi, 1 multicolour SOR; cycle: 0 smoothing loss, 1 two-grid loss."""
     arr = (C.c_void_p * len(systems))(*[x.value if isinstance(x, C.c_void_p) else x for x in systems])
     o = TrainOpts()
+    t_each = None
+    if np.ndim(t):
+        t_each = np.ascontiguousarray(t, dtype=np.float64)
+        if t_each.shape != (len(systems),):
+            raise ValueError("t: one value per system")
+        t = 0.0
     o.t, o.levels, o.steps, o.nu, o.bf16, o.lr, o.seed = t, levels, steps, nu, 1 if bf16 else 0, lr, seed
     o.samples, o.sweep, o.cycle = samples, sweep, cycle
+    o.t_each = None if t_each is None else t_each.ctypes.data
     hist = np.zeros(max(steps, 1))
     m = C.c_void_p()
     _check(load().camfe_smoother_train(ctx, C.cast(arr, C.c_void_p), len(systems), C.byref(o), C.byref(m),

@@ -798,6 +798,12 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
                       o->samples >= 0 && o->samples <= 2 && (o->sweep == 0 || o->sweep == 1) &&
                       (o->cycle == 0 || o->cycle == 1),
                   CAMFE_EINVAL, "bad options");
+    for (int i = 0; i < nsys; ++i) {
+      const double ti = o->t_each ? o->t_each[i] : o->t;
+      CAMFE_REQUIRE(ti >= 0.0 && std::isfinite(ti), CAMFE_EINVAL, "t must be finite and >= 0");
+      if (o->t_each)   // one solver state per system: a repeated system cannot take two t
+        for (int j = 0; j < i; ++j) CAMFE_REQUIRE(systems[j] != systems[i], CAMFE_EINVAL, "repeated system");
+    }
     ctx->use_device();
     camfe_model m0 = nullptr;
     camfe_status rc = camfe_model_create(nullptr, o->levels, o->bf16, o->sweep, &m0);
@@ -817,7 +823,7 @@ camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int n
       camfe_sys s = systems[i];
       CAMFE_REQUIRE(s && s->h->ctx == ctx, CAMFE_EINVAL, "systems must belong to the context");
       CAMFE_REQUIRE(s->h->degree == 1, CAMFE_EINVAL, "the learned smoother is defined for degree 1");
-      SolverState* S = ensure_solver(s, o->t, DEFAULT_COARSE_EPS);
+      SolverState* S = ensure_solver(s, o->t_each ? o->t_each[i] : o->t, DEFAULT_COARSE_EPS);
       const int saved = S->smoother;
       S->smoother = 0;
       for (int d = S->d0 + 1; d <= S->D; ++d) {

@@ -235,3 +235,27 @@ def test_learned_smoother_errors(cf, ctx):
         cf.camfe_smoother_loss_grad(s, o.depth, 1e-3, _params(1)[0], np.ones((len(b), 5)), nu=2)
     with pytest.raises(cf.CamfeError, match="ESTATE"):
         cf.camfe_smoother_loss_grad(s, o.depth + 1, 1e-3, _params(1)[0], np.ones((len(b), 1)), nu=2)
+
+
+def test_training_with_a_t_per_system(cf, ctx):
+    """Per-system t: each system trains at its own t (a system listed twice is
+    rejected, since it keeps one solver state), and the result matches a run
+    whose systems all share that t when the values coincide."""
+    h, s, o = built(cf, ctx, "sphere")
+    h2, s2, o2 = built(cf, ctx, "sheets")
+    say("[gpu] learned: per-system t")
+    m1, hist1 = cf.camfe_smoother_train(ctx, [s, s2], t=[1e-3, 1e-3], levels=2, steps=3, sweep=1)
+    m2, hist2 = cf.camfe_smoother_train(ctx, [s, s2], t=1e-3, levels=2, steps=3, sweep=1)
+    assert np.allclose(hist1, hist2, rtol=1e-12, atol=0)
+    assert np.allclose(cf.camfe_model_params(m1)[0], cf.camfe_model_params(m2)[0], rtol=1e-5, atol=1e-7)
+    m3, hist3 = cf.camfe_smoother_train(ctx, [s, s2], t=[1e-4, 1e-1], levels=2, steps=3, sweep=1)
+    assert np.all(np.isfinite(hist3)) and not np.array_equal(hist3, hist1)
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_smoother_train(ctx, [s, s], t=[1e-3, 1e-2], levels=2, steps=1, sweep=1)
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_smoother_train(ctx, [s], t=[-1.0], levels=2, steps=1, sweep=1)
+    for m in (m1, m2, m3):
+        cf.camfe_model_destroy(m)
+    # the systems' solver states go back to the t the other tests use
+    cf.camfe_solve(s, np.ones((o.count(o.depth, "functions"), 1)), t=1e-3, max_iter=1)
+    cf.camfe_solve(s2, np.ones((o2.count(o2.depth, "functions"), 1)), t=1e-3, max_iter=1)

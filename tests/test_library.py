@@ -52,3 +52,31 @@ def test_product_path_never_touches_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "liboracle" not in txt, f
+
+
+def _header_struct_fields(name):
+    """Field names of `typedef struct { ... } name;` in the header, in order
+    (array fields by name, pointer fields without their stars)."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + ";", src)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = re.sub(r"\[.*?\]", "", decl).replace("*", " ").strip()
+        if decl:
+            first, *rest = decl.split(",")
+            fields.append(first.split()[-1])
+            fields.extend(r.strip() for r in rest)
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("camfe_hier_opts", "HierOpts"), ("camfe_solve_opts", "SolveOpts"),
+                                          ("camfe_solve_stats", "SolveStats"), ("camfe_train_opts", "TrainOpts")])
+def test_binding_structs_follow_the_header(cname, pyname):
+    py = [f[0] for f in getattr(camfe, pyname)._fields_]
+    assert py == _header_struct_fields(cname)
+
+
+def test_training_t_per_system_is_checked_before_any_call():
+    with pytest.raises(ValueError):
+        camfe.camfe_smoother_train(None, [1, 2], t=[1e-3])

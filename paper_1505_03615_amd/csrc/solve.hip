@@ -28,6 +28,8 @@ namespace camfe {
 
 namespace {
 constexpr int BLK = SBLK;
+constexpr int SORT_MIN_ROWS = 65536;   // rows of a colour from which its rows are sorted by length
+constexpr int SORT_WINDOW = 1024;      // rows per sorted window (16 slices)
 }  // namespace
 
 void destroy_solver(SolverState* s) { delete s; }
@@ -50,6 +52,20 @@ __global__ void k_iperm(const uint32_t* perm, long long n, int* iperm, int* perm
   if (i >= n) return;
   iperm[perm[i]] = (int)i;
   permi[i] = (int)perm[i];
+}
+// sort keys that order the rows of each colour window by decreasing row length
+// (colours outside mask keep their order): window index << 8 | (255 - length)
+__global__ void k_window_keys(const int* perm, const int* ptr, long long n, const int* coff, const int* wbase,
+                              int ncol, int mask, uint32_t* key, uint32_t* val) {
+  const long long r = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (r >= n) return;
+  int c = 0;
+  while (c + 1 < ncol && r >= coff[c + 1]) ++c;
+  const int f = perm[r];
+  const int len = ptr[f + 1] - ptr[f];
+  const uint32_t lk = ((mask >> c) & 1) ? 255u - (uint32_t)min(len, 255) : 0u;
+  key[r] = ((uint32_t)(wbase[c] + (int)((r - coff[c]) / SORT_WINDOW)) << 8) | lk;
+  val[r] = (uint32_t)f;
 }
 __global__ void k_slice_width(const int* ptr, const int* perm, const int* row0, const int* rows, long long ns,
                               int* width) {
@@ -518,6 +534,35 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
   G.coff.assign(G.ncol + 1, 0);
   for (size_t i = 0; i < n; ++i) G.coff[hcol[i] + 1]++;
   for (int c = 0; c < G.ncol; ++c) G.coff[c + 1] += G.coff[c];
+  // Large colours: rows sorted by decreasing length inside windows of
+  // SORT_WINDOW rows, so that a slice's rows have similar lengths and the
+  // SELL padding shrinks (about 1.45x -> 1.03x of the nonzeros).  Rows of
+  // one colour are independent, so the order changes no row's arithmetic;
+  // small colours keep the canonical order, whose neighbouring rows share
+  // more of the cache lines their x gathers touch (latency dominates there).
+  {
+    std::vector<int> wbase(G.ncol + 1, 0);
+    int mask = 0;
+    for (int c = 0; c < G.ncol; ++c) {
+      const int nc = G.coff[c + 1] - G.coff[c];
+      wbase[c + 1] = wbase[c] + (nc + SORT_WINDOW - 1) / SORT_WINDOW;
+      if (nc >= SORT_MIN_ROWS) mask |= 1 << c;
+    }
+    if (mask) {
+      DArr<int> dco(G.ncol + 1), dwb(G.ncol + 1);
+      copy_in(ctx, dco.p, G.coff.data(), G.ncol + 1);
+      copy_in(ctx, dwb.p, wbase.data(), G.ncol + 1);
+      DArr<uint32_t> key(n), val(n);
+      hipLaunchKernelGGL(k_window_keys, g, BLK, 0, ctx->stream, (const int*)G.perm.p, S.ptr.p, (long long)n, dco.p,
+                         dwb.p, G.ncol, mask, key.p, val.p);
+      check_launch();
+      int bits = 8;
+      while ((1LL << (bits - 8)) <= wbase[G.ncol]) ++bits;
+      sort_pairs_u32(ctx, key.p, val.p, n, bits);
+      hipLaunchKernelGGL(k_iperm, g, BLK, 0, ctx->stream, (const uint32_t*)val.p, (long long)n, G.iperm.p, G.perm.p);
+      check_launch();
+    }
+  }
   // slices: per colour, runs of 64 rows
   G.cslice.assign(G.ncol + 1, 0);
   std::vector<int> row0, rows;

@@ -32,8 +32,8 @@ size_t size_class(size_t b) {
 size_t limit_of(int dev) {   // g_mu held
   auto it = g_limit.find(dev);
   if (it != g_limit.end()) return it->second;
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = 0;
+  size_t total_b = 0;
+  if (hipDeviceTotalMem(&total_b, dev) != hipSuccess) total_b = 0;
   return g_limit[dev] = total_b / 4;
 }
 

@@ -349,27 +349,6 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
-// alpha = rz / pq per column; x += alpha p; r -= alpha q; per-block partials of r.r
-template <int K>
-__global__ __launch_bounds__(BLK) void k_cg_update(long long n, const double* sc, double* x, double* r,
-                                                   const double* p, const double* q, double* part) {
-  __shared__ double sh[BLK / 64];
-  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
-#pragma unroll
-  for (int c = 0; c < K; ++c) {
-    const double rz = sc[c], pq = sc[K + c];
-    const double al = (pq != 0.0 && rz != 0.0) ? rz / pq : 0.0;
-    double loc = 0.0;
-    if (i < n) {
-      x[i * K + c] += al * p[i * K + c];
-      double v = r[i * K + c] - al * q[i * K + c];
-      r[i * K + c] = v;
-      loc = v * v;
-    }
-    const double s = block_sum(loc, sh);
-    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
-  }
-}
 // per-block partials of a . b per column
 template <int K>
 __global__ __launch_bounds__(BLK) void k_dot(long long n, const double* a, const double* b, double* part) {
@@ -399,20 +378,98 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* part, int nb, d
     __syncthreads();
   }
 }
-// beta = rz_new / rz; p = z + beta p
+// p = z + beta p per column
 template <int K>
-__global__ void k_cg_direction(long long n, const double* rz_old, const double* rz_new, const double* z, double* p) {
+__global__ void k_cg_direction(long long n, const double* beta, const double* z, double* p) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
 #pragma unroll
+  for (int c = 0; c < K; ++c) p[i * K + c] = z[i * K + c] + beta[c] * p[i * K + c];
+}
+
+// The CG step's vector work around the V-cycle, fused with the V-cycle's
+// start and end.  MODE 0 (FP64 cycle): the update also zeroes z, the cycle's
+// initial guess.  MODE 1 (FP32 cycle): the update also writes b32 = r and
+// zeroes x32, and the dot product converts the cycle's x32 into z.
+// alpha = rz / pq; x += alpha p; r -= alpha q; per-block partials of r.r
+template <int K, int MODE>
+__global__ __launch_bounds__(BLK) void k_cg_update_v(long long n, const double* sc, double* x, double* r,
+                                                     const double* p, const double* q, double* part, double* z,
+                                                     float* b32, float* x32) {
+  __shared__ double sh[BLK / 64];
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+#pragma unroll
   for (int c = 0; c < K; ++c) {
-    const double be = rz_old[c] != 0.0 ? rz_new[c] / rz_old[c] : 0.0;
-    p[i * K + c] = z[i * K + c] + be * p[i * K + c];
+    const double rz = sc[c], pq = sc[K + c];
+    const double al = (pq != 0.0 && rz != 0.0) ? rz / pq : 0.0;
+    double loc = 0.0;
+    if (i < n) {
+      x[i * K + c] += al * p[i * K + c];
+      double v = r[i * K + c] - al * q[i * K + c];
+      r[i * K + c] = v;
+      loc = v * v;
+      if (MODE == 0) {
+        z[i * K + c] = 0.0;
+      } else {
+        b32[i * K + c] = (float)v;
+        x32[i * K + c] = 0.0f;
+      }
+    }
+    const double s = block_sum(loc, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
   }
 }
-__global__ void k_copy_scalars(const double* src, double* dst, int n) {
-  int i = threadIdx.x;
-  if (i < n) dst[i] = src[i];
+// per-block partials of r . z (MODE 1: z = x32 converted first)
+template <int K, int MODE>
+__global__ __launch_bounds__(BLK) void k_dot_rz(long long n, const double* r, double* z, const float* x32,
+                                                double* part) {
+  __shared__ double sh[BLK / 64];
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    double v = 0.0;
+    if (i < n) {
+      double zz;
+      if (MODE == 0) {
+        zz = z[i * K + c];
+      } else {
+        zz = (double)x32[i * K + c];
+        z[i * K + c] = zz;
+      }
+      v = r[i * K + c] * zz;
+    }
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
+  }
+}
+// one block: rr = sum of part_rr, rz_new = sum of part_rz; beta = rz_new / rz;
+// sc: rz[K] pq[K] rr[K] rz_new[K] bb[K] beta[K]; rz <- rz_new
+template <int K>
+__global__ __launch_bounds__(1024) void k_finalize_cg(const double* part_rz, const double* part_rr, int nb,
+                                                      double* sc) {
+  __shared__ double sh[16];
+  for (int c = 0; c < 2 * K; ++c) {
+    const double* part = c < K ? part_rr : part_rz;
+    const int q = c % K;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 1024) v += part[(long long)b * K + q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int w = 0; w < 16; ++w) s += sh[w];
+      if (c < K) {
+        sc[2 * K + q] = s;
+      } else {
+        const double old = sc[q];
+        sc[3 * K + q] = s;
+        sc[5 * K + q] = old != 0.0 ? s / old : 0.0;
+        sc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
 }
 template <int K>
 __global__ void k_axpy_inplace(long long n, double* x, const double* y) {
@@ -701,6 +758,7 @@ SolverState* setup(camfe_sys s, double t, int precision, double coarse_eps) {
     const GLevel& F = st->lev[h->D];
     const size_t nb = std::max(F.nslices, (F.n + BLK - 1) / BLK) + 1;
     st->part.alloc(nb * KMAXS);
+    st->part2.alloc(nb * KMAXS);
   }
   ctx->sync();
   st->setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -956,15 +1014,26 @@ void cg_step(SolverState* S, int nu1, int nu2) {
               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.sval64.p,
               (const double*)S->P.p, S->Q.p, S->part.p);
   finalize<K>(S, (long long)G.nslices, sc + K);
-  CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update<K>, (unsigned)nb, BLK, 0, ctx->stream, (long long)n,
-              (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, S->part.p);
-  finalize<K>(S, nb, sc + 2 * K);
-  precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
-  dot<K>(S, S->R.p, S->Z.p, sc + 3 * K);
   hipStream_t st = ctx->stream;
-  hipLaunchKernelGGL(k_cg_direction<K>, (unsigned)nb, BLK, 0, st, (long long)n, (const double*)sc,
-                     (const double*)(sc + 3 * K), (const double*)S->Z.p, S->P.p);
-  hipLaunchKernelGGL(k_copy_scalars, 1, 64, 0, st, (const double*)(sc + 3 * K), sc, K);
+  if (S->precision == 0) {
+    CAMFE_TIMED(ctx, KT_CG_VEC, (7.0 * n * K * 8), (k_cg_update_v<K, 0>), (unsigned)nb, BLK, 0, st, (long long)n,
+                (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, S->part2.p, S->Z.p,
+                (float*)nullptr, (float*)nullptr);
+    vcycle<double, K>(S, S->D, S->R.p, S->Z.p, nu1, nu2);
+    hipLaunchKernelGGL((k_dot_rz<K, 0>), (unsigned)nb, BLK, 0, st, (long long)n, (const double*)S->R.p, S->Z.p,
+                       (const float*)nullptr, S->part.p);
+  } else {
+    CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8 + 8.0 * n * K), (k_cg_update_v<K, 1>), (unsigned)nb, BLK, 0, st,
+                (long long)n, (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p,
+                S->part2.p, (double*)nullptr, G.b32.p, G.x32.p);
+    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2);
+    hipLaunchKernelGGL((k_dot_rz<K, 1>), (unsigned)nb, BLK, 0, st, (long long)n, (const double*)S->R.p, S->Z.p,
+                       (const float*)G.x32.p, S->part.p);
+  }
+  hipLaunchKernelGGL(k_finalize_cg<K>, 1, 1024, 0, st, (const double*)S->part.p, (const double*)S->part2.p, (int)nb,
+                     sc);
+  hipLaunchKernelGGL(k_cg_direction<K>, (unsigned)nb, BLK, 0, st, (long long)n, (const double*)(sc + 5 * K),
+                     (const double*)S->Z.p, S->P.p);
 }
 
 // One stationary step: x += V(b - A x); r = b - A x (||r||^2 into rr)
@@ -989,7 +1058,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   const size_t n = G.n;
   const long long nk = (long long)n * K;
   unsigned gn = grid_for(n, BLK), gnk = grid_for(nk, BLK);
-  double* sc = S->sc.p;   // rz[K] pq[K] rr[K] rzn[K] bb[K]
+  double* sc = S->sc.p;   // rz[K] pq[K] rr[K] rzn[K] bb[K] beta[K]
   hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, db, (long long)n, c0, kk, G.iperm.p, S->B.p);
   if (o.x0_given)
     hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, (const double*)dx, (long long)n, c0, kk, G.iperm.p, S->X.p);

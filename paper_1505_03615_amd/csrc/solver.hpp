@@ -73,8 +73,9 @@ struct SolverState {
   DArr<double> Ainv64;       // coarsest inverse, FP64 in both precisions
   // outer iteration vectors (finest, internal order, n x KMAXS row-major)
   DArr<double> X, R, Z, P, Q, B;
-  DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb
-  DArr<double> part;         // per-block partial sums of the reductions
+  DArr<double> sc;           // device scalars: [0..K) rz, [K..2K) pq, [2K..3K) rr, [3K..4K) rz_new, [4K..5K) bb,
+                             // [5K..6K) beta
+  DArr<double> part, part2;  // per-block partial sums of the reductions (two live at once in a CG step)
   double setup_seconds = 0;
   // batched solver: nmesh meshes side by side at every level (rows mesh-major,
   // each mesh's rows padded to whole SBLK-row blocks); bmesh: mesh of each

@@ -28,7 +28,7 @@ namespace camfe {
 
 namespace {
 constexpr int BLK = SBLK;
-constexpr int SORT_MIN_ROWS = 65536;   // rows of a colour from which its rows are sorted by length
+constexpr int SORT_MIN_ROWS = 1 << 19;  // rows of a colour from which its rows are sorted by length
 constexpr int SORT_WINDOW = 1024;      // rows per sorted window (16 slices)
 }  // namespace
 

@@ -361,3 +361,34 @@ def test_full_size_knot_flow_system(cf, ctx):
         cf.camfe_model_destroy(model)
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
+
+
+def test_length_sorted_layout_on_a_7m_function_system(cf, ctx):
+    """A noise-displaced sphere of 2,097,152 triangles at depth 10 (7.4M
+    functions, about 930k rows per colour), whose finest colours take the
+    length-sorted SELL order (colours of 2^19 rows or more).  Properties that
+    hold at any size: partition of unity and zero row sums of the exports,
+    and FP64 and mixed solves to 1e-8 checked with the exported FP64 matrices
+    (the row order inside a colour changes no row's arithmetic)."""
+    V, F = meshgen.noisy_sphere(9, seed=7, base="octa")
+    say("[gpu] build noisy sphere 2M depth 10")
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=10, max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    M = cf.camfe_export_matrix(s, h, fin, 0)
+    L = cf.camfe_export_matrix(s, h, fin, 1)
+    assert M.shape[0] >= 8 * (1 << 19)
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    assert abs(M.sum() - area) <= 1e-12 * area
+    assert abs(L @ np.ones(L.shape[0])).max() <= 1e-11 * abs(L).max()
+    b = cf.camfe_load_vector(s, h, V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
+    A = M + 1e-3 * L
+    try:
+        for precision in (0, 1):
+            say(f"[gpu] solve noisy sphere 2M precision={precision}")
+            x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-8, max_iter=1500, precision=precision)
+            r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+            assert st["converged"] and np.all(r <= 1e-6), (precision, st, r)
+    finally:
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)

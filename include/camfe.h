@@ -172,17 +172,26 @@ typedef struct {
                      /*    Jacobi with constant omega; 2: the attached learned    */
                      /*    model's smoother (Jacobi or SOR, per-row omega)        */
   double omega;      /* omega of smoother 1                                       */
+  int judge;         /* smoother 1 or 2 with method 0: Gauss-Seidel as judge.     */
+                     /*    The requested smoother and plain Gauss-Seidel each run */
+                     /*    `judge` CG iterations from the start; the one with the */
+                     /*    smaller residual continues.  All of them count in       */
+                     /*    iterations and cycles.  0: off.  The batched solve     */
+                     /*    ignores it                                             */
 } camfe_solve_opts;
 
 typedef struct {
   int iterations;    /* outer iterations done                                     */
-  int fell_back;     /* 1 when the learned smoother failed and Gauss-Seidel redid */
-                     /*    the solve                                               */
+  int fell_back;     /* 1 when the smoother (1 or 2) failed and Gauss-Seidel redid */
+                     /*    the solve; 2 when the judge continued with Gauss-Seidel */
   int cycles;        /* V-cycles applied                                          */
   int eps_regularised;
   double rel_residual; /* max over columns of ||b - A x|| / ||b|| (FP64)          */
   double seconds;      /* wall time of the iteration (setup excluded)             */
   double setup_seconds;/* forming A at every depth, packing, coarsest factor      */
+  double judge_rel[2]; /* judged solves: largest relative CG residual over the    */
+                       /*    columns after the judge's iterations, [0] requested  */
+                       /*    smoother, [1] Gauss-Seidel (0 when not judged)       */
 } camfe_solve_stats;
 
 /* Solve (M + t L) x = b at the finest depth (Sections 3.2, 4.3, 5.2).

@@ -50,12 +50,17 @@ class HierOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("method", C.c_int), ("precision", C.c_int), ("x0_given", C.c_int),
-                ("coarse_eps", C.c_double), ("smoother", C.c_int), ("omega", C.c_double)]
+                ("coarse_eps", C.c_double), ("smoother", C.c_int), ("omega", C.c_double), ("judge", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("fell_back", C.c_int), ("cycles", C.c_int), ("eps_regularised", C.c_int),
-                ("rel_residual", C.c_double), ("seconds", C.c_double), ("setup_seconds", C.c_double)]
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("setup_seconds", C.c_double),
+                ("judge_rel", C.c_double * 2)]
+
+
+def _stats_dict(st):
+    return {f: (list(getattr(st, f)) if f == "judge_rel" else getattr(st, f)) for f, _ in SolveStats._fields_}
 
 
 class TrainOpts(C.Structure):
@@ -328,9 +333,10 @@ def camfe_eval_vertices(s, nv, x):
 
 
 def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0, precision=0, x0=None,
-                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0):
+                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0, judge=0):
     """Returns (x, stats dict).  method 0 = V-cycle-preconditioned CG, 1 = stationary;
-    smoother 0 = multicolour Gauss-Seidel, 1 = Jacobi(omega), 2 = attached learned model."""
+    smoother 0 = multicolour Gauss-Seidel, 1 = Jacobi(omega), 2 = attached learned model;
+    judge > 0: smoother 1/2 and Gauss-Seidel each run `judge` CG iterations, the better continues."""
     bc, n, k = _colmajor(b)
     if x0 is None:
         x = _empty_like_kind(bc, n, k)
@@ -339,12 +345,12 @@ def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0,
     o = SolveOpts()
     o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
     o.method, o.precision, o.x0_given, o.coarse_eps = method, precision, 0 if x0 is None else 1, coarse_eps
-    o.smoother, o.omega = smoother, omega
+    o.smoother, o.omega, o.judge = smoother, omega, judge
     st = SolveStats()
     code = load().camfe_solve(s, C.byref(o), _ptr(bc), k, _ptr(x), C.byref(st))
     if code != 0 and (code != -4 or raise_on_noconv):
         _check(code)
-    stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+    stats = _stats_dict(st)
     stats["converged"] = code == 0
     return x, stats
 
@@ -375,7 +381,7 @@ def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, p
         _check(code)
     if Xc is not X:
         X[...] = Xc
-    stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+    stats = _stats_dict(st)
     stats["converged"] = code == 0
     return X, stats
 

@@ -961,9 +961,15 @@ void residual64(SolverState* S, const double* b, const double* x, double* r, dou
   if (nrm) finalize<K>(S, (long long)G.nslices, nrm);
 }
 
+void dcopy(camfe_ctx ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes) CAMFE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+}
+
 struct SolveResult {
   int it = 0, cycles = 0;
   double rel = 0;
+  bool judged_gs = false;   // the judge continued with plain Gauss-Seidel
+  double judge_rel[2] = {0.0, 0.0};   // residuals after the judge's iterations (smoother, GS)
 };
 
 // Record `enqueue` into a graph once (keyed), replay it on the context stream.
@@ -1086,11 +1092,13 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   // captured steps are replayed `check_every` times between convergence checks
   const bool use_graph = !ctx->timer.on;
   const int check_every = 4;
-  const long long gkey = (((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother;
+  auto gkey = [&] {   // the smoother may change during a judged solve
+    return (((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother;
+  };
   auto run_steps = [&](int m, bool cg) {
     for (int i = 0; i < m; ++i) {
       if (use_graph)
-        run_graph(S, gkey, [&] { if (cg) cg_step<K>(S, nu1, nu2); else stationary_step<K>(S, nu1, nu2); });
+        run_graph(S, gkey(), [&] { if (cg) cg_step<K>(S, nu1, nu2); else stationary_step<K>(S, nu1, nu2); });
       else if (cg)
         cg_step<K>(S, nu1, nu2);
       else
@@ -1115,11 +1123,55 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     }
   } else if (res.rel > o.rtol && o.max_iter > 0) {
     // conjugate gradients preconditioned by one V-cycle
-    precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
-    ++res.cycles;
-    hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)S->Z.p, nk, S->P.p);
-    dot<K>(S, S->R.p, S->Z.p, sc);
-    while (res.it < o.max_iter) {
+    auto cg_start = [&] {
+      precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
+      ++res.cycles;
+      hipLaunchKernelGGL((k_convert<double, double>), gnk, BLK, 0, st, (const double*)S->Z.p, nk, S->P.p);
+      dot<K>(S, S->R.p, S->Z.p, sc);
+    };
+    cg_start();
+    const int nj = std::min(o.judge, o.max_iter);
+    if (S->smoother != 0 && nj > 0) {
+      // Gauss-Seidel judges the replacement smoother: each runs nj CG
+      // iterations from the start, and the one with the smaller residual
+      // continues (its state kept, the other's iterations counted)
+      const int smoother = S->smoother;
+      res.rel = run_steps(nj, true);
+      res.it += nj;
+      res.cycles += nj;
+      res.judge_rel[0] = res.rel;
+      if (!(res.rel <= o.rtol)) {
+        DArr<double> xs(nk), rs(nk), ps(nk), scs(8 * KMAXS);
+        dcopy(ctx, xs.p, S->X.p, nk * sizeof(double));
+        dcopy(ctx, rs.p, S->R.p, nk * sizeof(double));
+        dcopy(ctx, ps.p, S->P.p, nk * sizeof(double));
+        dcopy(ctx, scs.p, sc, 8 * KMAXS * sizeof(double));
+        const double rel_a = res.rel;
+        S->smoother = 0;
+        if (o.x0_given)
+          hipLaunchKernelGGL(k_gather_in<K>, gn, BLK, 0, st, (const double*)dx, (long long)n, c0, kk, G.iperm.p,
+                             S->X.p);
+        else
+          hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->X.p, nk, 0.0);
+        residual64<K>(S, S->B.p, S->X.p, S->R.p, nullptr);
+        cg_start();
+        const double rel_b = run_steps(nj, true);
+        res.it += nj;
+        res.cycles += nj;
+        res.judge_rel[1] = rel_b;
+        if (rel_b < rel_a || !std::isfinite(rel_a)) {
+          res.rel = rel_b;
+          res.judged_gs = true;
+        } else {
+          S->smoother = smoother;
+          dcopy(ctx, S->X.p, xs.p, nk * sizeof(double));
+          dcopy(ctx, S->R.p, rs.p, nk * sizeof(double));
+          dcopy(ctx, S->P.p, ps.p, nk * sizeof(double));
+          dcopy(ctx, sc, scs.p, 8 * KMAXS * sizeof(double));
+        }
+      }
+    }
+    while (res.it < o.max_iter && !(res.rel <= o.rtol)) {
       const int m = std::min(check_every, o.max_iter - res.it);
       res.rel = run_steps(m, true);
       res.it += m;
@@ -1164,9 +1216,6 @@ __global__ void k_copy_add(const int* src, long long n, int add, int* dst) {
 
 inline long long pad_rows(long long n) { return (n + BLK - 1) / BLK * BLK; }
 
-void dcopy(camfe_ctx ctx, void* dst, const void* src, size_t bytes) {
-  if (bytes) CAMFE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-}
 
 }  // namespace
 }  // namespace camfe
@@ -1740,6 +1789,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0, CAMFE_EINVAL, "bad sweep counts");
     CAMFE_REQUIRE(o->method != 0 || o->nu_pre == o->nu_post, CAMFE_EINVAL,
                   "CG needs a symmetric V-cycle: nu_pre must equal nu_post");
+    CAMFE_REQUIRE(o->judge >= 0, CAMFE_EINVAL, "judge must be >= 0");
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -1772,13 +1822,15 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
         }
         tot.it = std::max(tot.it, r.it);
         tot.cycles += r.cycles;
+        tot.judged_gs = tot.judged_gs || r.judged_gs;
+        for (int j = 0; j < 2; ++j) tot.judge_rel[j] = std::max(tot.judge_rel[j], r.judge_rel[j]);
         if (!(r.rel <= tot.rel)) tot.rel = r.rel;
       }
       return tot;
     };
     SolveResult tot = run_all(*o);
-    int fell_back = 0;
-    if (o->smoother != 0 && !(tot.rel <= o->rtol)) {
+    int fell_back = tot.judged_gs ? 2 : 0;
+    if (o->smoother != 0 && !tot.judged_gs && !(tot.rel <= o->rtol)) {
       // the Jacobi smoother failed (diverged or stalled): Gauss-Seidel redoes the solve
       camfe_solve_opts go = *o;
       go.smoother = 0;
@@ -1787,6 +1839,8 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
       SolveResult t2 = run_all(go);
       t2.it += tot.it;
       t2.cycles += tot.cycles;
+      t2.judge_rel[0] = tot.judge_rel[0];
+      t2.judge_rel[1] = tot.judge_rel[1];
       tot = t2;
       fell_back = 1;
     }
@@ -1802,6 +1856,8 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
       stats->rel_residual = tot.rel;
       stats->seconds = secs;
       stats->setup_seconds = S->setup_seconds;
+      stats->judge_rel[0] = tot.judge_rel[0];
+      stats->judge_rel[1] = tot.judge_rel[1];
     }
     if (!(tot.rel <= o->rtol)) rc = CAMFE_ENOCONV;
   });
@@ -1894,6 +1950,7 @@ camfe_status camfe_batch_solve(camfe_batch bt, const camfe_solve_opts* o, const 
         stats[m].rel_residual = res[m].rel;
         stats[m].seconds = secs;
         stats[m].setup_seconds = S->setup_seconds;
+        stats[m].judge_rel[0] = stats[m].judge_rel[1] = 0.0;
       }
       if (!(res[m].rel <= o->rtol)) rc = CAMFE_ENOCONV;
     }

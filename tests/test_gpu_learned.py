@@ -259,3 +259,50 @@ def test_training_with_a_t_per_system(cf, ctx):
     # the systems' solver states go back to the t the other tests use
     cf.camfe_solve(s, np.ones((o.count(o.depth, "functions"), 1)), t=1e-3, max_iter=1)
     cf.camfe_solve(s2, np.ones((o2.count(o2.depth, "functions"), 1)), t=1e-3, max_iter=1)
+
+
+def _const_sor(cf, omega, levels=3):
+    """An SOR model whose network outputs one weight everywhere (zero weights,
+    b3 = logit(omega - 1/2))."""
+    p = np.zeros(levels * lr.NP, np.float32)
+    for l in range(levels):
+        p[l * lr.NP + lr.O_B3] = np.log((omega - 0.5) / (1.5 - omega))
+    return cf.camfe_model_create(p, levels=levels, bf16=False, sweep=1)
+
+
+@pytest.mark.parametrize("omega", [0.55, 0.8, 1.3])
+def test_judge_continues_with_the_smaller_residual(cf, ctx, omega):
+    """With judge = nj, the requested smoother and Gauss-Seidel each run nj CG
+    iterations from the start and the one with the smaller residual continues
+    (fell_back 2 for Gauss-Seidel).  The Gauss-Seidel contender must match a
+    plain nj-iteration solve, and the continuation must take the iterations of
+    a plain solve with the chosen smoother, plus the loser's nj."""
+    h, s, o = built(cf, ctx, "knot")
+    c = CASES["knot"]
+    t, nj = c["t"], 6
+    b = o.load_vector(c["f"])
+    m = _const_sor(cf, omega)
+    cf.camfe_smoother_attach(s, m)
+    try:
+        say(f"[gpu] learned: judge omega={omega}")
+        x, sj = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=600, precision=1, smoother=2, judge=nj)
+        assert sj["converged"], sj
+        rl, rg = sj["judge_rel"]
+        assert rl > 0 and rg > 0, sj
+        assert sj["fell_back"] == (2 if rg < rl else 0), sj
+        _, sg = cf.camfe_solve(s, b, t=t, rtol=1e-30, max_iter=nj, precision=1, smoother=0)
+        assert abs(sg["rel_residual"] - rg) <= 1e-3 * rg, (sg, sj)
+        want_gs = sj["fell_back"] == 2
+        _, sw = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=600, precision=1, smoother=0 if want_gs else 2)
+        assert sw["fell_back"] == 0
+        assert abs(sj["iterations"] - (sw["iterations"] + nj)) <= 4, (sj, sw)   # checks every four iterations
+        Mo, Lo = o.matrices(c["depth"])
+        r = np.linalg.norm(b - (Mo + t * Lo) @ x, axis=0) / np.linalg.norm(b, axis=0)
+        assert np.all(r <= 1e-6), r
+        # Gauss-Seidel itself is never judged
+        _, s0 = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=600, precision=1, smoother=0, judge=nj)
+        _, s1 = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=600, precision=1, smoother=0)
+        assert s0["iterations"] == s1["iterations"] and s0["fell_back"] == 0 and s0["judge_rel"] == [0.0, 0.0]
+    finally:
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_model_destroy(m)

@@ -226,7 +226,10 @@ void camfe_system_destroy(camfe_sys s);
 typedef struct camfe_batch_s *camfe_batch;
 /* Copies the systems' solver data for A = M + t L (building it where missing);
  * later changes to the systems do not reach the batch.  All systems share the
- * context and the degree. */
+ * context and the degree.  A system may be listed more than once.  A batch
+ * solve takes one pass over all members per four right-hand-side columns of
+ * its widest member, so a system with many columns is best listed once per
+ * chunk of up to four (each entry then gets its chunk's columns). */
 camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const *systems, int nsys, double t, double coarse_eps,
                                 camfe_batch *out);
 /* levels of the batched hierarchy; rows of its finest level (padded) */

@@ -119,3 +119,20 @@ def test_batch_warm_start_and_errors(cf, setup):
     _check(items, xs2, stats2)
     with pytest.raises(cf.CamfeError, match="EINVAL"):
         cf.camfe_batch_solve(bt, [it[3] for it in items], 2 * T)
+
+
+def test_batch_with_a_system_listed_per_column_chunk(cf, setup):
+    """A system may appear several times in one batch (here once per chunk of
+    at most four right-hand sides), so one pass of the batch covers all its
+    columns; each chunk must satisfy the oracle's system."""
+    ctx, items, bt = setup
+    h, s, o, b = items[2]                       # five right-hand sides, one of them zero
+    chunks = [b[:, :4], b[:, 4:]]
+    say("[gpu] batch: one system per column chunk")
+    bt2 = cf.camfe_batch_create(ctx, [s, s, items[0][1]], T)
+    try:
+        xs, stats = cf.camfe_batch_solve(bt2, chunks + [items[0][3]], T, rtol=1e-8, max_iter=800)
+        assert all(st["converged"] for st in stats), stats
+        _check([(h, s, o, chunks[0]), (h, s, o, chunks[1]), items[0]], xs, stats)
+    finally:
+        cf.camfe_batch_destroy(bt2)

@@ -1,6 +1,6 @@
 // Dense symmetric positive definite inverse for the coarsest depth: blocked
 // right-looking Cholesky A = L L^T (diagonal blocks factored in LDS, panels by
-// triangular solves, trailing updates by a tiled FP64 GEMM), then the inverse
+// triangular solves, trailing updates by a tiled FP64 MFMA GEMM), then the inverse
 // of L bottom up (all diagonal blocks at once, then doubling block sizes, two
 // batched GEMMs per level), then A^-1 = L^-T L^-1 by one more GEMM.  All matrices are n x n
 // row-major in device memory.
@@ -12,8 +12,9 @@
 namespace camfe {
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int NB = 32;      // block size of the factorisation and of the triangular inverse
-constexpr int TM = 64;      // GEMM tile
+constexpr int TM = 64;      // GEMM tile (four wavefronts of 32 x 32 on the FP64 matrix cores)
 constexpr int TK = 16;      // GEMM k-chunk staged in LDS
 
 // One TM x TM tile (ti, tj) of C = beta C + alpha op(A) op(B) on an M x N
@@ -28,12 +29,17 @@ __device__ inline void dgemm_tile(int ti, int tj, int M, int N, int Kd, const do
   if (i0 >= M || j0 >= N) return;
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TM + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
+  // four wavefronts, each a 32 x 32 quadrant of the tile as 2 x 2 blocks of
+  // v_mfma_f64_16x16x4 (operand lane l: row/column l % 16 at k = l / 16;
+  // result lane l, register r: row l / 16 + 4 r, column l % 16)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int qr = 32 * (w >> 1), qc = 32 * (w & 1);
+  const int sl = lane & 15, kq = lane >> 4;
+  d4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+    for (int v = 0; v < 2; ++v) acc[u][v] = (d4){0.0, 0.0, 0.0, 0.0};
   for (int p0 = 0; p0 < Kd; p0 += TK) {
     for (int e = threadIdx.x; e < TM * TK; e += 256) {
       int r, p;
@@ -47,29 +53,28 @@ __device__ inline void dgemm_tile(int ti, int tj, int M, int N, int Kd, const do
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < TK; ++p) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = As[p][ty * 4 + u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Bs[p][tx * 4 + v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    for (int k0 = 0; k0 < TK; k0 += 4) {
+      const double a0 = As[k0 + kq][qr + sl], a1 = As[k0 + kq][qr + 16 + sl];
+      const double b0 = Bs[k0 + kq][qc + sl], b1 = Bs[k0 + kq][qc + 16 + sl];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gi = i0 + ty * 4 + u, gj = j0 + tx * 4 + v;
-      if (gi < M && gj < N && (!lower || gj <= gi)) {
-        double* c = C + (long long)gi * ldc + gj;
-        *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[u][v];
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = i0 + qr + 16 * u + kq + 4 * r, gj = j0 + qc + 16 * v + sl;
+        if (gi < M && gj < N && (!lower || gj <= gi)) {
+          double* c = C + (long long)gi * ldc + gj;
+          *c = (beta == 0.0 ? 0.0 : beta * *c) + alpha * acc[u][v][r];
+        }
       }
-    }
 }
 
 template <bool TA, bool TB>

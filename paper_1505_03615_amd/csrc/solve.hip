@@ -1131,6 +1131,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     };
     cg_start();
     const int nj = std::min(o.judge, o.max_iter);
+    const int requested = S->smoother;   // restored below for the next column block
     if (S->smoother != 0 && nj > 0) {
       // Gauss-Seidel judges the replacement smoother: each runs nj CG
       // iterations from the start, and the one with the smaller residual
@@ -1183,6 +1184,7 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
     double rr[KMAXS];
     copy_out(ctx, rr, sc + 2 * K, K);
     res.rel = relmax(rr);
+    S->smoother = requested;
   }
   hipLaunchKernelGGL(k_scatter_out<K>, gn, BLK, 0, st, (const double*)S->X.p, (long long)n, c0, kk, G.iperm.p, dx);
   check_launch();

@@ -429,7 +429,8 @@ def main():
         n = cf.camfe_hierarchy_info(h, fin)[2]
         if record is not None:
             record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve64=t4 - t3, solve32=t5 - t4,
-                               solvel=t6 - t5, st64=st64, st32=st32, stl=stl, n=n, levels=(fin, d0)))
+                               solvel=t6 - t5, st64=st64, st32=st32, stl=stl, n=n, levels=(fin, d0),
+                               xs=(x64, x32, xl)))
         if keep_last:
             keep["h"], keep["s"] = h, s
         else:
@@ -494,6 +495,12 @@ def main():
                          "mixed_fp32_fp64": float(max(r["st32"]["rel_residual"] for r in rec)),
                          "learned_mixed": float(max(r["stl"]["rel_residual"] for r in rec))},
         "learned_fell_back": int(max(r["stl"]["fell_back"] for r in rec)),
+        # difference of each solution from the FP64 one (all three reach 1e-8 residuals)
+        "rel_diff_from_fp64_solution": {
+            "mixed_fp32_fp64": max(float(torch.linalg.norm(r["xs"][1] - r["xs"][0]) / torch.linalg.norm(r["xs"][0]))
+                                   for r in rec),
+            "learned_mixed": max(float(torch.linalg.norm(r["xs"][2] - r["xs"][0]) / torch.linalg.norm(r["xs"][0]))
+                                 for r in rec)},
         "learned_training": train_info,
         "learned_jacobi_training": train_info_jac,
     }

@@ -149,6 +149,38 @@ def train_smoother(cf, ctx, meshgen, steps=150, sweep=1):
                "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
 
 
+def vcycle_bytes(cf, s, h, k, sv, sx, nu=4):
+    """Algorithmic bytes of one V-cycle: per depth d above the coarsest,
+    (nu + 1) passes over the matrix values and three vector accesses per row
+    (nu sweeps and the residual), the parent map read twice (restriction and
+    prolongation, 4 B per entry) and the transfer vectors; at the coarsest
+    depth the dense inverse (8 n0^2) and its vectors.  Counts come from the
+    library's two-call exports with zero capacity."""
+    import ctypes
+    lib = cf.load()
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    nz = ctypes.c_int64()
+    total = 0.0
+    for d in range(d0, fin + 1):
+        n = cf.camfe_hierarchy_info(h, d)[2]
+        if d == d0:
+            total += 8.0 * n * n + 2.0 * n * k * sx
+            continue
+        cf._check(lib.camfe_export_matrix(s, d, 0, None, None, None, 0, ctypes.byref(nz)))
+        z = nz.value
+        cf._check(lib.camfe_export_prolongation(h, d, None, None, None, 0, ctypes.byref(nz)))
+        pn = nz.value
+        nc = cf.camfe_hierarchy_info(h, d - 1)[2]
+        total += (nu + 1) * (z * sv + 3.0 * n * k * sx) + 2.0 * 4.0 * pn + (3.0 * n + 2.0 * nc) * k * sx
+    return total
+
+
+def cycle_roofline(bytes_per_cycle, ms, cycles):
+    t = ms / 1000.0 / max(cycles, 1)
+    gbs = bytes_per_cycle / t / 1e9
+    return {"bytes_per_cycle": bytes_per_cycle, "ms_per_cycle": 1000.0 * t, "GBs": gbs, "frac": gbs / PEAK_HBM_GBS}
+
+
 def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
     """Held-out meshes (never trained on): the (3,5) knot tube and a noisy
     sphere, each about 8.4M triangles at depth 11 (size 'full'), or 2.1M at
@@ -185,6 +217,12 @@ def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
                         "converged": bool(st["converged"]), "fell_back": int(st["fell_back"])}
             log(f"[bench] held-out {name} {tag}: {res[tag]['cycles']} cycles, {res[tag]['ms']:.0f} ms")
         res["speedup_learned_vs_plain"] = res["plain_gs_fp64"]["ms"] / res["learned_mixed"]["ms"]
+        # whole V-cycle (inside CG, whose vector work is not counted) against the HBM peak
+        b64 = vcycle_bytes(cf, s, h, 1, 8, 8)
+        b32 = vcycle_bytes(cf, s, h, 1, 4, 4)
+        res["vcycle_roofline"] = {
+            "plain_gs_fp64": cycle_roofline(b64, res["plain_gs_fp64"]["ms"], res["plain_gs_fp64"]["cycles"]),
+            "plain_gs_mixed": cycle_roofline(b32, res["plain_gs_mixed"]["ms"], res["plain_gs_mixed"]["cycles"])}
         cf.camfe_smoother_attach(s, None)
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
@@ -245,16 +283,18 @@ def flow_eval(cf, ctx, meshgen, steps=10):
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     Xd = torch.from_numpy(np.asfortranarray(X)).to(dev)
-    per, cyc = [], []
+    per, cyc, solve_s = [], [], []
     for k in range(steps):
         t1 = time.perf_counter()
         Xd, st = cf.camfe_flow_step(s, Xd, 2e-4, rtol=1e-8, max_iter=1000, precision=1)
         torch.cuda.synchronize()
         per.append(time.perf_counter() - t1)
         cyc.append(st["cycles"])
+        solve_s.append(st["seconds"])
         if not st["converged"]:
             break
     n = cf.camfe_hierarchy_info(h, 10)[2]
+    vb = vcycle_bytes(cf, s, h, 3, 4, 4)   # FP32 cycles, three columns
     # the same colour-sweep measurement as the bench's roofline, on this
     # 2.2M-function finest depth (launches about twelve times larger)
     big = roofline(cf, s, "gs_colour", reps=10)
@@ -263,6 +303,8 @@ def flow_eval(cf, ctx, meshgen, steps=10):
     cf.camfe_hierarchy_destroy(h)
     return {"mesh": "(3,5) knot tube, 2,097,152 tris, depth 10", "dof": int(n), "steps": len(per),
             "gs_colour_roofline_depth10": big,
+            # solve iterations of steps 2.. (the first also builds the mass-block cache)
+            "vcycle_roofline": cycle_roofline(vb, 1000.0 * float(np.sum(solve_s[1:])), int(np.sum(cyc[1:]))),
             "hierarchy_and_assembly_ms": 1000.0 * setup, "ms_per_step": 1000.0 * float(np.mean(per)),
             "first_step_ms": 1000.0 * per[0], "cycles_per_step": [int(c) for c in cyc],
             "context": "the paper's Table 1: 1.52 s per step for its 1.27M-DoF system (CPU, its own solver)"}

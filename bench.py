@@ -531,6 +531,11 @@ def main():
         "solve_to_1e-8_ms": {"plain_fp64": 1000.0 * solve64, "mixed_fp32_fp64": 1000.0 * solve32,
                              "learned_mixed": 1000.0 * solvel},
         "solve_cycles": {"plain_fp64": float(cyc64), "mixed_fp32_fp64": float(cyc32), "learned_mixed": float(cycl)},
+        # the iterations alone (solver setup excluded), and the setup the first solve of a system pays
+        "solve_iterations_ms": {k: 1000.0 * float(np.mean([r[st]["seconds"] for r in rec]))
+                                for k, st in (("plain_fp64", "st64"), ("mixed_fp32_fp64", "st32"),
+                                              ("learned_mixed", "stl"))},
+        "solver_setup_ms": 1000.0 * float(np.mean([r["st64"]["setup_seconds"] for r in rec])),
         "solve_dof_cycles_per_s": {"plain_fp64": n * cyc64 / solve64, "mixed_fp32_fp64": n * cyc32 / solve32,
                                    "learned_mixed": n * cycl / solvel},
         "rel_residual": {"plain_fp64": float(max(r["st64"]["rel_residual"] for r in rec)),

@@ -267,7 +267,7 @@ def assembly_eval(cf, ctx, meshgen, reps=2):
     return out
 
 
-def flow_eval(cf, ctx, meshgen, steps=10):
+def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     """Config 3: tracked cMCF steps (M_t + delta/2 L_0) X' = M_t X on the (3,5)
     knot tube (2,097,152 triangles, depth 10), delta/2 = 1e-4, the three
     coordinate columns, mixed precision, 1e-8 per step.  A step re-weights and
@@ -277,7 +277,7 @@ def flow_eval(cf, ctx, meshgen, steps=10):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=10, degree=1,
-                                 max_coarse=4096)
+                                 max_coarse=max_coarse)
     s = cf.camfe_assemble(h)
     X = cf.camfe_linear_coeffs(s, h)
     torch.cuda.synchronize()

@@ -217,7 +217,8 @@ __global__ void k_diag_of(const int* ptr, const int* col, const double* M, const
 // x_c = 0 for the recursion
 constexpr int RL = 8;
 template <class T, int K>
-__global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long long nc, const T* rf, T* bc, T* xc) {
+__global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long long nc, const T* rf, T* bc, T* xc,
+                           const T* dinv, long long n0c) {
   const long long g = blockIdx.x * (long long)BLK + threadIdx.x;
   const long long i = g / RL;
   const int sub = (int)(g % RL);
@@ -240,7 +241,9 @@ __global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long l
 #pragma unroll
     for (int q = 1; q < K; ++q) if (sub == q) v = acc[q];
     bc[i * K + sub] = v;
-    xc[i * K + sub] = 0;
+    // x_c starts at zero; with dinv, the first sweep's colour-0 rows (the
+    // first n0c) are relaxed here: from x = 0, Gauss-Seidel gives b_i * dinv_i
+    xc[i * K + sub] = (dinv && i < n0c) ? v * dinv[i] : (T)0;
   }
 }
 
@@ -390,12 +393,15 @@ __global__ void k_cg_direction(long long n, const double* beta, const double* z,
 // The CG step's vector work around the V-cycle, fused with the V-cycle's
 // start and end.  MODE 0 (FP64 cycle): the update also zeroes z, the cycle's
 // initial guess.  MODE 1 (FP32 cycle): the update also writes b32 = r and
-// zeroes x32, and the dot product converts the cycle's x32 into z.
+// zeroes x32, and the dot product converts the cycle's x32 into z.  With row
+// weights (dinv64 / dinv32), the first n0c rows (colour 0) also take the first
+// pre-sweep's relaxation from the zero guess, b_i * dinv_i.
 // alpha = rz / pq; x += alpha p; r -= alpha q; per-block partials of r.r
 template <int K, int MODE>
 __global__ __launch_bounds__(BLK) void k_cg_update_v(long long n, const double* sc, double* x, double* r,
                                                      const double* p, const double* q, double* part, double* z,
-                                                     float* b32, float* x32) {
+                                                     float* b32, float* x32, const double* dinv64,
+                                                     const float* dinv32, long long n0c) {
   __shared__ double sh[BLK / 64];
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
 #pragma unroll
@@ -409,10 +415,11 @@ __global__ __launch_bounds__(BLK) void k_cg_update_v(long long n, const double* 
       r[i * K + c] = v;
       loc = v * v;
       if (MODE == 0) {
-        z[i * K + c] = 0.0;
+        z[i * K + c] = (dinv64 && i < n0c) ? v * dinv64[i] : 0.0;
       } else {
-        b32[i * K + c] = (float)v;
-        x32[i * K + c] = 0.0f;
+        const float v32 = (float)v;
+        b32[i * K + c] = v32;
+        x32[i * K + c] = (dinv32 && i < n0c) ? v32 * dinv32[i] : 0.0f;
       }
     }
     const double s = block_sum(loc, sh);
@@ -820,8 +827,8 @@ double pass_bytes(long long z, long long rows) {
 // one multicolour sweep x_i += w_i (b_i - (A x)_i) with w = dinv (1 / A_ii for
 // Gauss-Seidel, omega_i / A_ii for SOR)
 template <class T, int K>
-void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T* dinv) {
-  for (int ci = 0; ci < G.ncol; ++ci) {
+void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T* dinv, int first = 0) {
+  for (int ci = first; ci < G.ncol; ++ci) {
     const int c = forward ? ci : G.ncol - 1 - ci;
     const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
     if (s1 <= s0) continue;
@@ -847,12 +854,22 @@ const float* winvd_of<float>(const GLevel& g) { return g.winvd32.p; }
 // nu smoothing sweeps on (b, x): multicolour Gauss-Seidel or SOR with
 // per-row weights (colours forward or reversed), or weighted Jacobi
 // (order-free; ping-pong through the level's scratch vector, one launch per sweep)
+// Row weights of a colour-ordered sweep (Gauss-Seidel: 1 / A_ii; SOR: omega_i /
+// A_ii), or null for the Jacobi smoothers
+template <class T>
+const T* sweep_dinv(const SolverState* S, const GLevel& G) {
+  if (S->smoother == 0) return invd_of<T>(G);
+  if (S->smoother == 2 && S->wsweep == 1) return winvd_of<T>(G);
+  return nullptr;
+}
+
+// first0: x was zero and the first sweep's colour-0 rows are already relaxed
+// (by the kernel that zeroed x), so that sweep starts at colour 1
 template <class T, int K>
-void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward) {
+void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward, bool first0 = false) {
   camfe_ctx ctx = S->ctx;
-  if (S->smoother == 0 || (S->smoother == 2 && S->wsweep == 1)) {
-    const T* dinv = S->smoother == 0 ? invd_of<T>(G) : winvd_of<T>(G);
-    for (int i = 0; i < nu; ++i) gs_sweep<T, K>(ctx, G, b, x, forward, dinv);
+  if (const T* dinv = sweep_dinv<T>(S, G)) {
+    for (int i = 0; i < nu; ++i) gs_sweep<T, K>(ctx, G, b, x, forward, dinv, i == 0 && first0 && forward ? 1 : 0);
     return;
   }
   T* a = x;
@@ -877,8 +894,9 @@ void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
 }
 
 // One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
+// first0: as for smooth() (x zero, colour 0 of the first pre-sweep done)
 template <class T, int K>
-void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
+void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool first0 = false) {
   camfe_ctx ctx = S->ctx;
   hipStream_t st = ctx->stream;
   GLevel& G = S->lev[d];
@@ -899,7 +917,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
     }
     return;
   }
-  smooth<T, K>(S, G, b, x, nu1, true);
+  smooth<T, K>(S, G, b, x, nu1, true, first0);
   T* r = Vec<T>::r(G);
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
               (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
@@ -907,11 +925,14 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2) {
   GLevel& C = S->lev[d - 1];
   T* bc = Vec<T>::b(C);
   T* xc = Vec<T>::x(C);
-  // transfers: parent map (4 B per entry) plus the vectors read and written
+  // transfers: parent map (4 B per entry) plus the vectors read and written;
+  // above the coarsest depth of a single system (colour-major rows) the
+  // restriction also takes the coarse depth's first colour-0 relaxation
+  const T* cdinv = (!S->batch && nu1 > 0 && d - 1 > S->d0) ? sweep_dinv<T>(S, C) : nullptr;
   CAMFE_TIMED(ctx, KT_RESTRICT, (4.0 * G.pnnz + ((double)G.n + C.n) * K * sizeof(T)), (k_restrict<T, K>),
               grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc,
-              xc);
-  vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2);
+              xc, cdinv, cdinv ? (long long)C.coff[1] : 0LL);
+  vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2, cdinv != nullptr);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
   if (G.ncb) coarse_batched<T, K>(S, G, b, x);   // meshes that bottom out here
@@ -1021,18 +1042,24 @@ void cg_step(SolverState* S, int nu1, int nu2) {
               (const double*)S->P.p, S->Q.p, S->part.p);
   finalize<K>(S, (long long)G.nslices, sc + K);
   hipStream_t st = ctx->stream;
+  // the top depth's first colour-0 relaxation goes into the update (a
+  // colour-ordered smoother above the coarsest depth)
+  const bool first0 = nu1 > 0 && S->D > S->d0 && sweep_dinv<double>(S, G) != nullptr;
+  const long long n0c = first0 ? (long long)G.coff[1] : 0LL;
   if (S->precision == 0) {
     CAMFE_TIMED(ctx, KT_CG_VEC, (7.0 * n * K * 8), (k_cg_update_v<K, 0>), (unsigned)nb, BLK, 0, st, (long long)n,
                 (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, S->part2.p, S->Z.p,
-                (float*)nullptr, (float*)nullptr);
-    vcycle<double, K>(S, S->D, S->R.p, S->Z.p, nu1, nu2);
+                (float*)nullptr, (float*)nullptr, first0 ? sweep_dinv<double>(S, G) : (const double*)nullptr,
+                (const float*)nullptr, n0c);
+    vcycle<double, K>(S, S->D, S->R.p, S->Z.p, nu1, nu2, first0);
     hipLaunchKernelGGL((k_dot_rz<K, 0>), (unsigned)nb, BLK, 0, st, (long long)n, (const double*)S->R.p, S->Z.p,
                        (const float*)nullptr, S->part.p);
   } else {
     CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8 + 8.0 * n * K), (k_cg_update_v<K, 1>), (unsigned)nb, BLK, 0, st,
                 (long long)n, (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p,
-                S->part2.p, (double*)nullptr, G.b32.p, G.x32.p);
-    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2);
+                S->part2.p, (double*)nullptr, G.b32.p, G.x32.p, (const double*)nullptr,
+                first0 ? sweep_dinv<float>(S, G) : (const float*)nullptr, n0c);
+    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2, first0);
     hipLaunchKernelGGL((k_dot_rz<K, 1>), (unsigned)nb, BLK, 0, st, (long long)n, (const double*)S->R.p, S->Z.p,
                        (const float*)G.x32.p, S->part.p);
   }
@@ -1628,7 +1655,7 @@ void coarse_correction(SolverState* S, int d, const double* e, double* out, bool
     hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, r);
   }
   hipLaunchKernelGGL((k_restrict<double, K>), grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, G.Rw64.p,
-                     (long long)C.n, (const double*)r, C.b64.p, C.x64.p);
+                     (long long)C.n, (const double*)r, C.b64.p, C.x64.p, (const double*)nullptr, 0LL);
   vcycle<double, K>(S, d - 1, C.b64.p, C.x64.p, 2, 2);
   if (!adjoint) {
     // out = e + P x_c  (x_c = -B_c P^T A e)

@@ -28,6 +28,8 @@
 //                                    Section 5.2 (Gauss-Seidel smoothing), the
 //                                    Discussion closing Section 5 (eps * Id for
 //                                    singular systems)
+//   gradient constraint, W-cycle .... Section 6.2 (colour fitting: int <grad f,
+//                                    grad b_i>, one W-cycle, minimum depth)
 //
 // Parity pins for every function here live in tests/test_oracle_*.py.
 #include <algorithm>
@@ -159,6 +161,7 @@ struct Hier {
   double o[3] = {0, 0, 0}, s = 1.0;
   long nv = 0, nt = 0;
   std::vector<double> U;  // grid coordinates at depth D, nv x 3
+  std::vector<double> V;  // world positions, nv x 3
   std::vector<int> F;     // nt x 3
   std::vector<Level> lev; // index = depth
   // mesh adjacency: edge (sorted vertex pair) -> incident triangles; vertex -> triangles
@@ -540,8 +543,11 @@ int func_of(const Level& L, uint64_t key, int t) {
 // tri_w (nullable) scales each triangle's contribution to M only (area ratio
 // of an evolved surface; the stiffness stays that of the original surface).  fv (nullable, nv x k col-major) gives per-vertex values of
 // f, interpolated linearly inside each triangle; rhs is n x k col-major.
+// rhs (nullable) receives b_i = int f b_i, or with grad_rhs the gradient
+// constraint b_i = int <grad f, grad b_i> of the colour-fitting problem
+// (Section 6.2), for f linear on each triangle from per-vertex values fv.
 bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k, double* rhs,
-                    bool want_matrix) {
+                    bool want_matrix, bool grad_rhs = false) {
   Level& L = h.lev[d];
   const int W = width(h.degree);
   const int NB = W * W * W;
@@ -585,6 +591,33 @@ bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k
     }
     if (poly.size() < 3) continue;
     const double tw = tri_w ? tri_w[t] : 1.0;
+    // gradient of f on the triangle in world units: sum over corners m of
+    // f_m grad(lambda_m), where grad(lambda_1) = (e2 x n)/|n|^2 and
+    // grad(lambda_2) = (n x e1)/|n|^2 with e1, e2 the edges from corner 0 and
+    // n = e1 x e2 (each is orthogonal to the opposite edge and to n, and rises
+    // by 1 along its own edge); zero on a triangle of zero area
+    std::vector<double> gf(grad_rhs ? 3 * (size_t)k : 0, 0.0);
+    if (grad_rhs) {
+      double w1[3], w2[3];
+      for (int a = 0; a < 3; ++a) {
+        w1[a] = h.V[3 * (size_t)f[1] + a] - h.V[3 * (size_t)f[0] + a];
+        w2[a] = h.V[3 * (size_t)f[2] + a] - h.V[3 * (size_t)f[0] + a];
+      }
+      const double nw[3] = {w1[1] * w2[2] - w1[2] * w2[1], w1[2] * w2[0] - w1[0] * w2[2],
+                            w1[0] * w2[1] - w1[1] * w2[0]};
+      const double n2 = nw[0] * nw[0] + nw[1] * nw[1] + nw[2] * nw[2];
+      if (n2 > 0.0) {
+        const double gl1[3] = {(w2[1] * nw[2] - w2[2] * nw[1]) / n2, (w2[2] * nw[0] - w2[0] * nw[2]) / n2,
+                               (w2[0] * nw[1] - w2[1] * nw[0]) / n2};
+        const double gl2[3] = {(nw[1] * w1[2] - nw[2] * w1[1]) / n2, (nw[2] * w1[0] - nw[0] * w1[2]) / n2,
+                               (nw[0] * w1[1] - nw[1] * w1[0]) / n2};
+        for (int col = 0; col < k; ++col) {
+          const double* fc = fv + (size_t)col * h.nv;
+          const double d1 = fc[f[1]] - fc[f[0]], d2 = fc[f[2]] - fc[f[0]];
+          for (int a = 0; a < 3; ++a) gf[3 * (size_t)col + a] = d1 * gl1[a] + d2 * gl2[a];
+        }
+      }
+    }
     std::vector<double> Me(NB * NB, 0.0), Le(NB * NB, 0.0);
     std::vector<double> be((size_t)NB * (k > 0 ? k : 1), 0.0);
     // fan from vertex 0; collapsed Gauss-Legendre on each sub-triangle
@@ -629,7 +662,13 @@ bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k
                 Me[i * NB + j] += wqm * phi[i] * phi[j];
                 Le[i * NB + j] += wq * (g[i][0] * g[j][0] + g[i][1] * g[j][1] + g[i][2] * g[j][2]);
               }
-          if (rhs)
+          if (rhs && grad_rhs)
+            for (int col = 0; col < k; ++col) {
+              const double* gc = &gf[3 * (size_t)col];
+              for (int i = 0; i < NB; ++i)
+                be[(size_t)col * NB + i] += wq * (gc[0] * g[i][0] + gc[1] * g[i][1] + gc[2] * g[i][2]);
+            }
+          else if (rhs)
             for (int col = 0; col < k; ++col) {
               const double* fc = fv + (size_t)col * h.nv;
               double fx = lam[0] * fc[f[0]] + lam[1] * fc[f[1]] + lam[2] * fc[f[2]];
@@ -718,6 +757,7 @@ struct Solver {
   Hier* h = nullptr;
   std::vector<SysLevel> sl;   // index = depth
   int nu1 = 2, nu2 = 2;
+  int gamma = 1;              // coarse corrections per level: 1 V-cycle, 2 W-cycle
   int eps_used = 0;
 };
 
@@ -755,6 +795,9 @@ void matvec(const SysLevel& S, const double* x, int k, double* y) {
     }
 }
 
+// One multigrid cycle at depth d on (b, x), x given: nu1 forward sweeps, the
+// coarse correction (gamma cycles at depth d - 1 from zero), nu2 reverse
+// sweeps; the coarsest depth is solved directly or relaxed.
 void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
   SysLevel& S = sv.sl[d];
   if (d == sv.h->d0) {
@@ -783,7 +826,8 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
     for (long i = 0; i < S.n; ++i)
       for (long e = Lf.Pptr[i]; e < Lf.Pptr[i + 1]; ++e)
         bc[(size_t)q * C.n + Lf.Pcol[e]] += Lf.Pw[e] * r[(size_t)q * S.n + i];
-  vcycle(sv, d - 1, bc.data(), xc.data(), k);
+  // the coarse problem gets gamma cycles from zero (one: V-cycle, two: W-cycle)
+  for (int g = 0; g < sv.gamma; ++g) vcycle(sv, d - 1, bc.data(), xc.data(), k);
   for (int q = 0; q < k; ++q)
     for (long i = 0; i < S.n; ++i)
       for (long e = Lf.Pptr[i]; e < Lf.Pptr[i + 1]; ++e)
@@ -817,8 +861,9 @@ void* oracle_build(const double* V, long nv, const int* F, long nt, int depth, i
   if (depth < 1 || depth > 12 || (degree != 1 && degree != 2) || nt <= 0 || nv <= 0 ||
       nt >= (1L << 24)) {
     h.err = "invalid arguments";
-  } else if (!build(h, V, F, box)) {
-    if (h.err.empty()) h.err = "build failed";
+  } else {
+    h.V.assign(V, V + 3 * nv);
+    if (!build(h, V, F, box) && h.err.empty()) h.err = "build failed";
   }
   h.timing[0] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return H;
@@ -902,8 +947,17 @@ int oracle_load_vector(void* hp, int d, const double* fv, int k, double* b) {
   return assemble_level(h, d, nullptr, fv, k, b, false) ? 0 : -1;
 }
 
+// b_i = int <grad f, grad b_i> at depth d (the gradient constraint of the
+// screened Poisson colour fit, Section 6.2), f per-vertex (nv x k col-major)
+int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
+  Hier& h = ((OracleHandle*)hp)->h;
+  if (!h.err.empty() || d < h.d0 || d > h.D) return -1;
+  return assemble_level(h, d, nullptr, fv, k, b, false, true) ? 0 : -1;
+}
+
 // Solve (M + t L) x = b at the finest depth.
-// mode 0: stationary multigrid, x <- x + V(b - A x) with V a V(nu1, nu2) cycle.
+// mode 0: stationary multigrid, x <- x + V(b - A x) with V a (nu1, nu2) cycle,
+//         a V-cycle (gamma 1) or a W-cycle (gamma 2, Section 6.2).
 // mode 1: conjugate gradients preconditioned by one V-cycle (V is symmetric:
 //         forward colour order before the coarse correction, reverse after,
 //         nu1 == nu2, exact coarse solve), one independent CG per column.
@@ -919,12 +973,13 @@ int oracle_load_vector(void* hp, int d, const double* fv, int k, double* b) {
 // before the first and after every iteration (true residual).
 int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2,
                  const double* b, int k, double* x, int x0_given, double* stats,
-                 double* history, int mode, double coarse_eps) {
+                 double* history, int mode, double coarse_eps, int gamma) {
   Hier& h = ((OracleHandle*)hp)->h;
   if (!h.err.empty()) return -1;
+  if (gamma < 1 || gamma > 2) { h.err = "gamma must be 1 or 2"; return -1; }
   auto t0 = std::chrono::steady_clock::now();
   Solver sv;
-  sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2;
+  sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2; sv.gamma = gamma;
   sv.sl.assign(h.D + 1, SysLevel());
   for (int d = h.d0; d <= h.D; ++d) {
     Level& L = h.lev[d];

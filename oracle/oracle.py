@@ -54,7 +54,8 @@ def _load():
         lib.oracle_assemble.argtypes = [vp, P]
         lib.oracle_matrix.argtypes = [vp, I, P, P, P, P]
         lib.oracle_load_vector.argtypes = [vp, I, P, I, P]
-        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D]
+        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I]
+        lib.oracle_gradient_load.argtypes = [vp, I, P, I, P]
         lib.oracle_apply.argtypes = [vp, I, D, P, I, P]
         lib.oracle_gs_sweep.argtypes = [vp, I, D, P, I, P, I]
         lib.oracle_eval_vertices.argtypes = [vp, P, I, P]
@@ -169,16 +170,26 @@ class Oracle:
             raise RuntimeError("oracle load vector failed")
         return b
 
+    def gradient_load(self, fv, d=None):
+        """b_i = int <grad f, grad b_i> for f linear on each triangle (Section 6.2)."""
+        d = self.depth if d is None else d
+        fv, k = _colmajor(fv, len(self.V))
+        b = np.zeros((self.count(d, "functions"), k), order="F")
+        if self.lib.oracle_gradient_load(self.h, d, _p(fv), k, _p(b)) != 0:
+            raise RuntimeError("oracle gradient load failed")
+        return b
+
     def solve(self, t, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, x0=None, mode="pcg",
-              coarse_eps=1e-6):
-        """mode 'pcg' (CG preconditioned by one V-cycle) or 'vcycle' (stationary)."""
+              coarse_eps=1e-6, gamma=1):
+        """mode 'pcg' (CG preconditioned by one cycle) or 'vcycle' (stationary
+        cycles); gamma 1 for V-cycles, 2 for W-cycles."""
         n = self.count(self.depth, "functions")
         b, k = _colmajor(b, n)
         x = np.zeros((n, k), order="F") if x0 is None else np.array(_colmajor(x0, n)[0], order="F")
         stats = np.zeros(5); hist = np.zeros(max_iter + 1)
         rc = self.lib.oracle_solve(self.h, t, rtol, max_iter, nu1, nu2, _p(b), k, _p(x),
                                    0 if x0 is None else 1, _p(stats), _p(hist),
-                                   {"vcycle": 0, "pcg": 1}[mode], coarse_eps)
+                                   {"vcycle": 0, "pcg": 1}[mode], coarse_eps, gamma)
         if rc < 0:
             raise RuntimeError("oracle solve: " + self.lib.oracle_error(self.h).decode())
         it = int(stats[4])

@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "icosphere", "octasphere", "two_sheets", "torus", "torus_knot",
-    "noisy_sphere", "unit_cubes", "single_triangle", "config_mesh",
+    "noisy_sphere", "unit_cubes", "cubes_checker", "single_triangle", "config_mesh",
 ]
 
 
@@ -191,6 +191,50 @@ def unit_cubes(n: int = 6, pitch: float = 2.0, rotate: bool = True):
     if rotate:
         V = V @ rodrigues((1.0, 2.0, 3.0), 0.3).T
     return V, F.astype(np.int32)
+
+
+def _cube_lattice(s: int):
+    """Surface of [0, s]^3 as split unit quads on the integer lattice, one
+    vertex per lattice point (faces share the vertices of the cube's edges)."""
+    quads = []
+    for ax in range(3):
+        u, v = (ax + 1) % 3, (ax + 2) % 3
+        for side in (0, s):
+            a, b = np.meshgrid(np.arange(s), np.arange(s), indexing="ij")
+            a, b = a.ravel(), b.ravel()
+            corners = []
+            for da, db in ((0, 0), (1, 0), (1, 1), (0, 1)):
+                p = np.zeros((a.size, 3), np.int64)
+                p[:, ax] = side; p[:, u] = a + da; p[:, v] = b + db
+                corners.append(p)
+            quads.append(np.stack(corners, 1))
+    q = np.concatenate(quads)                                  # (6 s^2, 4, 3)
+    pts, inv = np.unique(q.reshape(-1, 3), axis=0, return_inverse=True)
+    qi = inv.reshape(-1, 4)
+    F = np.concatenate([qi[:, [0, 1, 2]], qi[:, [0, 2, 3]]])
+    return pts.astype(np.float64) / s, F
+
+
+def cubes_checker(n: int = 6, pitch: float = 2.0, subdiv: int = 4, size: float = 0.5,
+                  offset: float = 0.1234):
+    """n x n x n equidistant unit cubes (centre pitch `pitch`), each face an
+    subdiv x subdiv grid of split quads, shifted by `offset` along every axis
+    (faces parallel to the grid planes but off them), with a solid 3D checker
+    of cell `size` as a per-vertex colour: (0.9, 0.2, 0.2) where
+    floor(x/size) + floor(y/size) + floor(z/size) is even, else
+    (0.2, 0.3, 0.9), taken in the cubes' unshifted frame.  Returns V, F and
+    the colours (nv x 3)."""
+    cv, cf = _cube_lattice(subdiv)
+    Vs, Fs = [], []
+    for i in range(n):
+        for j in range(n):
+            for k in range(n):
+                Fs.append(cf + len(cv) * len(Vs))
+                Vs.append(cv + pitch * np.array([i, j, k], dtype=np.float64))
+    V = np.concatenate(Vs)
+    par = np.floor(V / size).astype(np.int64).sum(1) % 2
+    col = np.where(par[:, None] == 0, np.array([0.9, 0.2, 0.2]), np.array([0.2, 0.3, 0.9]))
+    return V + offset, np.concatenate(Fs).astype(np.int32), col
 
 
 def single_triangle():

@@ -147,6 +147,15 @@ camfe_status camfe_export_matrix(camfe_sys s, int depth, int which, int64_t *row
 /* b_i = int f b_i at the finest depth (Eq. 2) for f linear on each triangle
  * from per-vertex values vertex_f (nv x k column-major); b is n x k. */
 camfe_status camfe_load_vector(camfe_sys s, const double *vertex_f, int k, double *b);
+/* b_i = int <grad f, grad b_i> at the finest depth: the gradient constraint of
+ * the screened Poisson colour fit (L + alpha M) u = b + alpha s (Section 6.2),
+ * with s from camfe_load_vector and grad f the surface gradient of f, linear
+ * on each triangle from per-vertex values vertex_f (nv x k column-major; zero
+ * on triangles without area, which the hierarchy build rejects; on a sliver
+ * whose corners' values differ the gradient grows like the inverse of its
+ * width, so such inputs are ill-conditioned); b is n x k.  Host or device
+ * pointers. */
+camfe_status camfe_gradient_load(camfe_sys s, const double *vertex_f, int k, double *b);
 /* y = A x at the finest depth with A = M (which 0), L (1) or M + t L (2) */
 camfe_status camfe_apply(camfe_sys s, int which, double t, const double *x, int k, double *y);
 /* coefficients that reproduce the embedding: n x 3 column-major (x, y, z) */
@@ -178,6 +187,10 @@ typedef struct {
                      /*    smaller residual continues.  All of them count in       */
                      /*    iterations and cycles.  0: off.  The batched solve     */
                      /*    ignores it                                             */
+  int cycle;         /* 0 or 1: V-cycle; 2: W-cycle (Section 6.2): at every depth */
+                     /*    above the coarsest the coarse problem gets two cycles, */
+                     /*    the second starting from the first's result.  The      */
+                     /*    batched solve takes 0 or 1 only (else EINVAL)          */
 } camfe_solve_opts;
 
 typedef struct {
@@ -194,7 +207,7 @@ typedef struct {
                        /*    smoother, [1] Gauss-Seidel (0 when not judged)       */
 } camfe_solve_stats;
 
-/* Solve (M + t L) x = b at the finest depth (Sections 3.2, 4.3, 5.2).
+/* Solve (M + t L) x = b at the finest depth (Sections 3.2, 4.3, 5.2, 6.2).
  * b, x: n x k column-major (x is read when x0_given).  Returns CAMFE_ENOCONV
  * with stats filled when max_iter is reached above rtol. */
 camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double *b, int k,

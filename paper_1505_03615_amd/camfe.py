@@ -24,7 +24,7 @@ EXPORTS = [
     "camfe_hierarchy_levels", "camfe_hierarchy_cube", "camfe_hierarchy_info", "camfe_export_pairs",
     "camfe_export_functions", "camfe_export_support_entries", "camfe_export_prolongation",
     "camfe_hierarchy_destroy", "camfe_assemble", "camfe_reassemble_mass", "camfe_export_matrix",
-    "camfe_load_vector", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
+    "camfe_load_vector", "camfe_gradient_load", "camfe_apply", "camfe_linear_coeffs", "camfe_eval_vertices", "camfe_solve",
     "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time", "camfe_measure_kernel",
     "camfe_model_create", "camfe_model_params", "camfe_model_destroy", "camfe_smoother_attach",
     "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
@@ -50,7 +50,8 @@ class HierOpts(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("method", C.c_int), ("precision", C.c_int), ("x0_given", C.c_int),
-                ("coarse_eps", C.c_double), ("smoother", C.c_int), ("omega", C.c_double), ("judge", C.c_int)]
+                ("coarse_eps", C.c_double), ("smoother", C.c_int), ("omega", C.c_double), ("judge", C.c_int),
+                ("cycle", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -98,6 +99,7 @@ def load():
         "camfe_reassemble_mass": (I, [H, P]),
         "camfe_export_matrix": (I, [H, I, I, P, P, P, I64, C.POINTER(I64)]),
         "camfe_load_vector": (I, [H, P, I, P]),
+        "camfe_gradient_load": (I, [H, P, I, P]),
         "camfe_apply": (I, [H, I, D, P, I, P]),
         "camfe_linear_coeffs": (I, [H, P]),
         "camfe_eval_vertices": (I, [H, P, I, P]),
@@ -311,6 +313,15 @@ def camfe_load_vector(s, h, vertex_f):
     return b
 
 
+def camfe_gradient_load(s, h, vertex_f):
+    """b_i = int <grad f, grad b_i> (the colour fit's gradient constraint)."""
+    fv, nv, k = _colmajor(vertex_f)
+    n = camfe_hierarchy_info(h, camfe_hierarchy_levels(h)[0])[2]
+    b = _empty_like_kind(fv, n, k)
+    _check(load().camfe_gradient_load(s, _ptr(fv), k, _ptr(b)))
+    return b
+
+
 def camfe_apply(s, which, t, x):
     xc, n, k = _colmajor(x)
     y = _empty_like_kind(xc, n, k)
@@ -333,10 +344,11 @@ def camfe_eval_vertices(s, nv, x):
 
 
 def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0, precision=0, x0=None,
-                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0, judge=0):
-    """Returns (x, stats dict).  method 0 = V-cycle-preconditioned CG, 1 = stationary;
+                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0, judge=0, cycle=1):
+    """Returns (x, stats dict).  method 0 = cycle-preconditioned CG, 1 = stationary cycles;
     smoother 0 = multicolour Gauss-Seidel, 1 = Jacobi(omega), 2 = attached learned model;
-    judge > 0: smoother 1/2 and Gauss-Seidel each run `judge` CG iterations, the better continues."""
+    judge > 0: smoother 1/2 and Gauss-Seidel each run `judge` CG iterations, the better continues;
+    cycle 1 = V-cycle, 2 = W-cycle."""
     bc, n, k = _colmajor(b)
     if x0 is None:
         x = _empty_like_kind(bc, n, k)
@@ -345,7 +357,7 @@ def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0,
     o = SolveOpts()
     o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
     o.method, o.precision, o.x0_given, o.coarse_eps = method, precision, 0 if x0 is None else 1, coarse_eps
-    o.smoother, o.omega, o.judge = smoother, omega, judge
+    o.smoother, o.omega, o.judge, o.cycle = smoother, omega, judge, cycle
     st = SolveStats()
     code = load().camfe_solve(s, C.byref(o), _ptr(bc), k, _ptr(x), C.byref(st))
     if code != 0 and (code != -4 or raise_on_noconv):
@@ -404,8 +416,9 @@ def camfe_batch_info(bt):
 
 
 def camfe_batch_solve(bt, bs, t, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, x0s=None,
-                      coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False):
-    """bs: list of n_m x k_m right-hand sides.  Returns (list of solutions, list of stats dicts)."""
+                      coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, cycle=1):
+    """bs: list of n_m x k_m right-hand sides.  Returns (list of solutions, list of stats dicts).
+    The batch takes V-cycles only (cycle 1); other values are passed on and rejected."""
     cols = [_colmajor(b) for b in bs]
     if x0s is None:
         xs = [_empty_like_kind(bc, n, k) for bc, n, k in cols]
@@ -418,6 +431,7 @@ def camfe_batch_solve(bt, bs, t, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, p
     o = SolveOpts()
     o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
     o.method, o.precision, o.x0_given, o.coarse_eps = 0, precision, 0 if x0s is None else 1, coarse_eps
+    o.cycle = cycle
     st = (SolveStats * m)()
     code = load().camfe_batch_solve(bt, C.byref(o), C.cast(bp, C.c_void_p), C.cast(kk, C.c_void_p),
                                     C.cast(xp, C.c_void_p), C.cast(st, C.c_void_p))

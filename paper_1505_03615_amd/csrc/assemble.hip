@@ -170,6 +170,7 @@ struct AsmArgs {
   int k;              // columns in this pass (<= KMAX)
   double* rhs;        // n x ldr column-major (column offset applied by caller)
   long long ldr;
+  int grad_rhs;       // rhs receives int <grad f, grad b_i> instead of int f b_i
   unsigned long long* npts;   // nullable: quadrature points processed (measurement)
   double* pcache;     // degree 1, mass only: each pair's unweighted 8 x 8 block (36 packed entries)
 };
@@ -367,6 +368,34 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           const int v = a.F[3 * t + m];
           for (int c = 0; c < KMAX; ++c) fvv[m][c] = c < a.k ? a.fv[(long long)c * a.nv + v] : 0.0;
         }
+        if (a.grad_rhs) {
+          // fvv becomes the gradient of f on the triangle, in depth-d cell
+          // units: (f1 - f0) (e2 x n) / |n|^2 + (f2 - f0) (n x e1) / |n|^2
+          // with e1, e2 the edges from corner 0 and n = e1 x e2 (zero on a
+          // triangle without area)
+          double q0[3], e1[3], e2[3];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            q0[q] = a.U[3 * (long long)a.F[3 * t] + q] * a.sc;
+            e1[q] = a.U[3 * (long long)a.F[3 * t + 1] + q] * a.sc - q0[q];
+            e2[q] = a.U[3 * (long long)a.F[3 * t + 2] + q] * a.sc - q0[q];
+          }
+          const double n0 = e1[1] * e2[2] - e1[2] * e2[1];
+          const double n1 = e1[2] * e2[0] - e1[0] * e2[2];
+          const double n2 = e1[0] * e2[1] - e1[1] * e2[0];
+          const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+          const double inv = nn > 0.0 ? 1.0 / nn : 0.0;
+          const double g1[3] = {(e2[1] * n2 - e2[2] * n1) * inv, (e2[2] * n0 - e2[0] * n2) * inv,
+                                (e2[0] * n1 - e2[1] * n0) * inv};
+          const double g2[3] = {(n1 * e1[2] - n2 * e1[1]) * inv, (n2 * e1[0] - n0 * e1[2]) * inv,
+                                (n0 * e1[1] - n1 * e1[0]) * inv};
+#pragma unroll
+          for (int c = 0; c < KMAX; ++c) {
+            const double d1 = fvv[1][c] - fvv[0][c], d2 = fvv[2][c] - fvv[0][c];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) fvv[q][c] = d1 * g1[q] + d2 * g2[q];
+          }
+        }
       }
       const int npts = (n - 2) * Q;
       wave_pts += (unsigned long long)npts;
@@ -432,7 +461,15 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
               accL[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(gz[I], wl * gz[J], accL[ti], 0, 0, 0);
             }
         }
-        if (want_rhs) {
+        if (want_rhs && a.grad_rhs) {
+          // surface gradients in cell units with the cell-unit weight: the
+          // Dirichlet form is invariant under the scaling
+#pragma unroll
+          for (int c = 0; c < KMAX; ++c)
+#pragma unroll
+            for (int i = 0; i < T; ++i)
+              accB[i][c] += wl * (gx[i] * fvv[0][c] + gy[i] * fvv[1][c] + gz[i] * fvv[2][c]);
+        } else if (want_rhs) {
 #pragma unroll
           for (int c = 0; c < KMAX; ++c) {
             const double fx = bar[0] * fvv[0][c] + bar[1] * fvv[1][c] + bar[2] * fvv[2][c];
@@ -807,7 +844,7 @@ void reassemble_mass_level(camfe_sys s, int d) {
   ctx->sync();
 }
 
-void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b) {
+void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b, bool grad) {
   camfe_hier h = s->h;
   camfe_ctx ctx = h->ctx;
   upload_rules();
@@ -822,6 +859,7 @@ void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b) {
     a.k = std::min(KMAX, k - c0);
     a.rhs = d_b + (size_t)c0 * L.nfun;
     a.ldr = (long long)L.nfun;
+    a.grad_rhs = grad ? 1 : 0;
     launch_assemble(h, d, ch, a);
   }
   ctx->sync();
@@ -846,6 +884,22 @@ void to_colmajor(camfe_ctx ctx, const double* in, size_t n, int k, double* out) 
 }  // namespace camfe
 
 using namespace camfe;
+
+// host or device vertex values in, host or device b out
+static camfe_status load_common(camfe_sys s, const double* vertex_f, int k, double* b, bool grad) {
+  return guarded([&] {
+    CAMFE_REQUIRE(s && vertex_f && b && k > 0, CAMFE_EINVAL, "bad argument");
+    camfe_hier h = s->h;
+    camfe_ctx ctx = h->ctx;
+    ctx->use_device();
+    const size_t n = h->lev[h->D].nfun;
+    DArr<double> fv(h->nv * (size_t)k), bd(n * (size_t)k);
+    copy_in(ctx, fv.p, vertex_f, fv.n);
+    load_vector_dev(s, fv.p, k, bd.p, grad);
+    copy_out(ctx, b, bd.p, bd.n);
+    ctx->sync();
+  });
+}
 
 extern "C" {
 
@@ -908,19 +962,13 @@ camfe_status camfe_export_matrix(camfe_sys s, int depth, int which, int64_t* row
   });
 }
 
+
 camfe_status camfe_load_vector(camfe_sys s, const double* vertex_f, int k, double* b) {
-  return guarded([&] {
-    CAMFE_REQUIRE(s && vertex_f && b && k > 0, CAMFE_EINVAL, "bad argument");
-    camfe_hier h = s->h;
-    camfe_ctx ctx = h->ctx;
-    ctx->use_device();
-    const size_t n = h->lev[h->D].nfun;
-    DArr<double> fv(h->nv * (size_t)k), bd(n * (size_t)k);
-    copy_in(ctx, fv.p, vertex_f, fv.n);
-    load_vector_dev(s, fv.p, k, bd.p);
-    copy_out(ctx, b, bd.p, bd.n);
-    ctx->sync();
-  });
+  return load_common(s, vertex_f, k, b, false);
+}
+
+camfe_status camfe_gradient_load(camfe_sys s, const double* vertex_f, int k, double* b) {
+  return load_common(s, vertex_f, k, b, true);
 }
 
 camfe_status camfe_apply(camfe_sys s, int which, double t, const double* x, int k, double* y) {

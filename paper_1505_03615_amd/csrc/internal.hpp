@@ -83,7 +83,9 @@ struct camfe_sys_s {
 namespace camfe {
 // assemble.hip
 void assemble_level(camfe_sys s, int d, bool want_L, bool want_M);
-void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b);   // b n x k row-major (device)
+// b = int f b_i (grad: int <grad f, grad b_i>) at the finest depth; fv nv x k,
+// b n x k, both column-major on the device
+void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b, bool grad = false);
 // dense.hip: out = diag(s) A^-1 diag(s) for SPD A (n x n row-major, destroyed)
 void spd_inverse_scaled(camfe_ctx ctx, double* A, int n, const double* s, double* out);
 // solve.hip helpers used by the C ABI in assemble.hip

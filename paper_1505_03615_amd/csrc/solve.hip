@@ -893,7 +893,9 @@ void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
                      G.cb_rowoff.p, G.cb_cum.p, G.cb_aoff.p, (const double*)G.cb_a64.p, b, x);
 }
 
-// One V-cycle at depth d on (b, x) of that depth, x given (zero on entry below the top)
+// One cycle at depth d on (b, x) of that depth, x given (zero on entry below
+// the top): the coarse problem gets S->gamma cycles, the first from zero (one:
+// V-cycle, two: W-cycle, Section 6.2).
 // first0: as for smooth() (x zero, colour 0 of the first pre-sweep done)
 template <class T, int K>
 void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool first0 = false) {
@@ -932,7 +934,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool firs
   CAMFE_TIMED(ctx, KT_RESTRICT, (4.0 * G.pnnz + ((double)G.n + C.n) * K * sizeof(T)), (k_restrict<T, K>),
               grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc,
               xc, cdinv, cdinv ? (long long)C.coff[1] : 0LL);
-  vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2, cdinv != nullptr);
+  for (int g = 0; g < S->gamma; ++g) vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2, g == 0 && cdinv != nullptr);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
   if (G.ncb) coarse_batched<T, K>(S, G, b, x);   // meshes that bottom out here
@@ -1120,7 +1122,8 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   const bool use_graph = !ctx->timer.on;
   const int check_every = 4;
   auto gkey = [&] {   // the smoother may change during a judged solve
-    return (((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother;
+    return ((((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother) * 4 +
+           S->gamma;
   };
   auto run_steps = [&](int m, bool cg) {
     for (int i = 0; i < m; ++i) {
@@ -1819,6 +1822,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     CAMFE_REQUIRE(o->method != 0 || o->nu_pre == o->nu_post, CAMFE_EINVAL,
                   "CG needs a symmetric V-cycle: nu_pre must equal nu_post");
     CAMFE_REQUIRE(o->judge >= 0, CAMFE_EINVAL, "judge must be >= 0");
+    CAMFE_REQUIRE(o->cycle >= 0 && o->cycle <= 2, CAMFE_EINVAL, "cycle must be 0, 1 (V) or 2 (W)");
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -1827,6 +1831,13 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     CAMFE_REQUIRE(o->smoother != 2 || s->model, CAMFE_ESTATE, "learned smoother requested but no model attached");
     SolverState* S = ensure_solver(s, o->t, o->coarse_eps);
     S->precision = o->precision;   // both precisions share one setup
+    // the cycle shape holds for this call only (other users of the state,
+    // such as smoother training, take V-cycles)
+    struct GammaScope {
+      SolverState* S;
+      ~GammaScope() { S->gamma = 1; }
+    } gamma_scope{S};
+    S->gamma = o->cycle == 2 ? 2 : 1;
     const bool stale = o->smoother != S->wkind || (o->smoother == 1 && o->omega != S->omega) ||
                        (o->smoother == 2 && s->model != S->model);
     if (o->smoother != 0 && stale) {
@@ -1936,6 +1947,7 @@ camfe_status camfe_batch_solve(camfe_batch bt, const camfe_solve_opts* o, const 
     CAMFE_REQUIRE(o->method == 0 && o->smoother == 0, CAMFE_EINVAL,
                   "batched solves use CG with the Gauss-Seidel V-cycle");
     CAMFE_REQUIRE(o->precision == 0 || o->precision == 1, CAMFE_EINVAL, "precision must be 0 or 1");
+    CAMFE_REQUIRE(o->cycle == 0 || o->cycle == 1, CAMFE_EINVAL, "the batched solve takes V-cycles (cycle 0 or 1)");
     CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0 && o->nu_pre == o->nu_post, CAMFE_EINVAL,
                   "bad sweep counts (CG needs nu_pre == nu_post)");
     SolverState* S = bt->S.get();

@@ -60,6 +60,7 @@ struct SolverState {
   camfe_ctx ctx = nullptr;
   double t = 0;
   int precision = 0;
+  int gamma = 1;             // coarse cycles per depth: 1 V-cycle, 2 W-cycle (set per solve)
   int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi
   int wkind = 0;             // smoother whose weights winvd holds (0: none)
   int wsweep = 0;            // sweep those weights are for: 0 Jacobi, 1 multicolour SOR

@@ -149,29 +149,32 @@ def train_smoother(cf, ctx, meshgen, steps=150, sweep=1):
                "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
 
 
-def vcycle_bytes(cf, s, h, k, sv, sx, nu=4):
-    """Algorithmic bytes of one V-cycle: per depth d above the coarsest,
-    (nu + 1) passes over the matrix values and three vector accesses per row
-    (nu sweeps and the residual), the parent map read twice (restriction and
-    prolongation, 4 B per entry) and the transfer vectors; at the coarsest
-    depth the dense inverse (8 n0^2) and its vectors.  Counts come from the
-    library's two-call exports with zero capacity."""
+def vcycle_bytes(cf, s, h, k, sv, sx, nu=4, gamma=1, direct=True):
+    """Algorithmic bytes of one V-cycle (gamma 1) or W-cycle (gamma 2): per
+    depth d above the coarsest, (nu + 1) passes over the matrix values and
+    three vector accesses per row (nu sweeps and the residual), the parent
+    map read twice (restriction and prolongation, 4 B per entry) and the
+    transfer vectors; at the coarsest depth the dense inverse (8 n0^2) and its
+    vectors, or nu sweeps when it is only relaxed.  A W-cycle visits depth d
+    gamma^(D - d) times.  Counts come from the library's two-call exports
+    with zero capacity."""
     import ctypes
     lib = cf.load()
     fin, d0 = cf.camfe_hierarchy_levels(h)
     nz = ctypes.c_int64()
     total = 0.0
     for d in range(d0, fin + 1):
+        visits = float(gamma) ** (fin - d)
         n = cf.camfe_hierarchy_info(h, d)[2]
-        if d == d0:
-            total += 8.0 * n * n + 2.0 * n * k * sx
-            continue
         cf._check(lib.camfe_export_matrix(s, d, 0, None, None, None, 0, ctypes.byref(nz)))
         z = nz.value
+        if d == d0:
+            total += visits * ((8.0 * n * n + 2.0 * n * k * sx) if direct else nu * (z * sv + 3.0 * n * k * sx))
+            continue
         cf._check(lib.camfe_export_prolongation(h, d, None, None, None, 0, ctypes.byref(nz)))
         pn = nz.value
         nc = cf.camfe_hierarchy_info(h, d - 1)[2]
-        total += (nu + 1) * (z * sv + 3.0 * n * k * sx) + 2.0 * 4.0 * pn + (3.0 * n + 2.0 * nc) * k * sx
+        total += visits * ((nu + 1) * (z * sv + 3.0 * n * k * sx) + 2.0 * 4.0 * pn + (3.0 * n + 2.0 * nc) * k * sx)
     return total
 
 
@@ -310,6 +313,62 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
             "context": "the paper's Table 1: 1.52 s per step for its 1.27M-DoF system (CPU, its own solver)"}
 
 
+CUBES_ALPHA = 0.01
+
+
+def cubes_eval(cf, ctx, meshgen, depth=5):
+    """Figure cubes (Section 6.2): the 6x6x6 unit cubes (each face 4 x 4 split
+    quads, 41,472 triangles) with a solid 3D checker as the colour f, the
+    screened Poisson fit (L + alpha M) u = g + alpha s with alpha = 0.01 and
+    g the gradient constraint, depth 5, one W-cycle with ten Gauss-Seidel
+    sweeps before and after each coarse correction, from a seeded guess
+    uniform in [0, 1], for every minimum depth, split and unsplit.  The
+    coarsest depth is relaxed (ten sweeps each way).  Residual after the
+    cycle over the norm of the guess (max over the three colour columns),
+    the warm W-cycle time (a second identical solve replays the captured
+    graph) and the gradient-load time."""
+    import torch
+    V, F, col = meshgen.cubes_checker()
+    dev = torch.device("cuda:0")
+    Vd, Fd = torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)
+    cold = torch.from_numpy(np.asfortranarray(col)).to(dev)
+    rows = []
+    for split in (1, 0):
+        for m in range(depth + 1):
+            h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=depth, split=split, min_depth=m, max_coarse=0)
+            s = cf.camfe_assemble(h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = cf.camfe_gradient_load(s, h, cold)
+            torch.cuda.synchronize()
+            grad_ms = 1000.0 * (time.perf_counter() - t0)
+            b = (g + CUBES_ALPHA * cf.camfe_load_vector(s, h, cold)) / CUBES_ALPHA
+            n = b.shape[0]
+            x0 = torch.from_numpy(np.asfortranarray(np.random.default_rng(6200).uniform(0.0, 1.0, size=(n, 3))))
+            x0 = x0.to(dev)
+            secs = []
+            for _ in range(2):
+                x, st = cf.camfe_solve(s, b, t=1.0 / CUBES_ALPHA, rtol=0.0, max_iter=1, nu_pre=10, nu_post=10,
+                                       method=1, x0=x0, cycle=2)
+                secs.append(st["seconds"])
+            r = CUBES_ALPHA * (b - cf.camfe_apply(s, 2, 1.0 / CUBES_ALPHA, x))
+            res = float((torch.linalg.norm(r, dim=0).max() / torch.linalg.norm(x0, dim=0).min()).item())
+            wb = vcycle_bytes(cf, s, h, 3, 8, 8, nu=20, gamma=2, direct=False)
+            rows.append({"split": split, "min_depth": m, "finest_functions": int(n),
+                         "coarsest_functions": int(cf.camfe_hierarchy_info(h, m)[2]),
+                         "residual_over_guess": res, "w_cycle_ms": 1000.0 * secs[1],
+                         "w_cycle_bytes": wb, "w_cycle_GBs": wb / secs[1] / 1e9, "gradient_load_ms": grad_ms})
+            log("[bench] cubes: " + json.dumps(rows[-1]))
+            cf.camfe_system_destroy(s)
+            cf.camfe_hierarchy_destroy(h)
+    rs = {r["min_depth"]: r["residual_over_guess"] for r in rows if r["split"] == 1}
+    rp = {r["min_depth"]: r["residual_over_guess"] for r in rows if r["split"] == 0}
+    return {"mesh": "6x6x6 unit cubes, pitch 2, 41,472 tris, 3D checker colour", "depth": depth,
+            "alpha": CUBES_ALPHA, "cycle": "W(10,10), relaxed coarsest", "rows": rows,
+            "split_gain_full_vs_finest_only": rs[depth] / rs[0],
+            "unsplit_gain_full_vs_finest_only": rp[depth] / rp[0]}
+
+
 def batch_eval(cf, ctx, meshgen, count=16, seed=4000):
     """Config 4 (scaled): `count` meshes of uneven size (icospheres, tori,
     noise-displaced spheres), depth clamp(round(log2(side / mean edge)), 6, 10),
@@ -400,6 +459,9 @@ def main():
                     help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
                          "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
     ap.add_argument("--flow-only", action="store_true", help="only the config-3 flow steps (for profiler runs)")
+    ap.add_argument("--cubes-only", action="store_true",
+                    help="only the minimum-depth experiment of Figure cubes (W-cycles, gradient constraint)")
+    ap.add_argument("--no-cubes", action="store_true", help="skip the Figure cubes experiment")
     ap.add_argument("--assembly-only", action="store_true",
                     help="only the assembly measurement (four meshes, both degrees); for matrix-core counter runs")
     args = ap.parse_args()
@@ -422,6 +484,12 @@ def main():
 
     if args.flow_only:
         out = {"flow_config3": flow_eval(cf, ctx, meshgen)}
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.cubes_only:
+        out = {"colour_fit_cubes": cubes_eval(cf, ctx, meshgen)}
         cf.camfe_ctx_destroy(ctx)
         print(json.dumps(out), flush=True)
         return
@@ -580,6 +648,9 @@ def main():
         log(f"[bench] batch of {args.batch_meshes} meshes (config 4)")
         out["batch_config4"] = batch_eval(cf, ctx, meshgen, args.batch_meshes)
         log("[bench] batch: " + json.dumps(out["batch_config4"]))
+    if not args.no_cubes:
+        log("[bench] Figure cubes: one W-cycle per minimum depth, split and unsplit")
+        out["colour_fit_cubes"] = cubes_eval(cf, ctx, meshgen)
     cf.camfe_model_destroy(model)
     cf.camfe_model_destroy(model_jac)
     if args.calibrate_copy:

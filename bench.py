@@ -324,7 +324,8 @@ def cubes_eval(cf, ctx, meshgen, depth=5):
     sweeps before and after each coarse correction, from a seeded guess
     uniform in [0, 1], for every minimum depth, split and unsplit.  The
     coarsest depth is relaxed (ten sweeps each way).  Residual after the
-    cycle over the norm of the guess (max over the three colour columns),
+    cycle over the norm of the guess, column by column (max over the three
+    colour columns),
     the warm W-cycle time (a second identical solve replays the captured
     graph) and the gradient-load time."""
     import torch
@@ -352,7 +353,7 @@ def cubes_eval(cf, ctx, meshgen, depth=5):
                                        method=1, x0=x0, cycle=2)
                 secs.append(st["seconds"])
             r = CUBES_ALPHA * (b - cf.camfe_apply(s, 2, 1.0 / CUBES_ALPHA, x))
-            res = float((torch.linalg.norm(r, dim=0).max() / torch.linalg.norm(x0, dim=0).min()).item())
+            res = float((torch.linalg.norm(r, dim=0) / torch.linalg.norm(x0, dim=0)).max().item())
             wb = vcycle_bytes(cf, s, h, 3, 8, 8, nu=20, gamma=2, direct=False)
             rows.append({"split": split, "min_depth": m, "finest_functions": int(n),
                          "coarsest_functions": int(cf.camfe_hierarchy_info(h, m)[2]),

@@ -116,17 +116,22 @@ __global__ void k_chunk_fill(const int* start, const int* coff, int ncell, long 
 }
 
 // ------------------------------------------------- superset row structure
-// Row (k, i) may couple with every function at the supports k + delta.
+// Row (k, i) may couple with every function at the supports k + delta.  The
+// functions of support g are cfirst[g] .. cfirst[g + 1] - 1, ascending in g,
+// so emitting the neighbouring supports in ascending order writes a sorted row
+// (the supports, at most 27 or 125, are sorted instead of the row's entries:
+// coarse split depths have rows of thousands).
 template <int DEG, bool FILL>
 __global__ void k_struct(const u64* fkey, long long nf, const u64* ckey, long long ncorn, const int* cfirst,
                          int* cnt, const int* ptr, int* col) {
   long long f = blockIdx.x * (long long)BLK + threadIdx.x;
   if (f >= nf) return;
-  const int R = DEG == 1 ? 1 : 2;
+  constexpr int R = DEG == 1 ? 1 : 2;
+  constexpr int NS = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
   long long c[3];
   demorton(fkey[f], c);
-  int m = 0;
-  int o = FILL ? ptr[f] : 0;
+  int gs[FILL ? NS : 1];
+  int ng = 0, m = 0;
   for (int dz = -R; dz <= R; ++dz)
     for (int dy = -R; dy <= R; ++dy)
       for (int dx = -R; dx <= R; ++dx) {
@@ -135,18 +140,22 @@ __global__ void k_struct(const u64* fkey, long long nf, const u64* ckey, long lo
         u64 k = morton((u64)x, (u64)y, (u64)z);
         long long g = lower_bound_u64(ckey, 0, ncorn, k);
         if (g < ncorn && ckey[g] == k) {
-          for (int q = cfirst[g]; q < cfirst[g + 1]; ++q) {
-            if (FILL) {
-              // insertion keeps the row sorted
-              int p = o + m;
-              while (p > o && col[p - 1] > q) { col[p] = col[p - 1]; --p; }
-              col[p] = q;
-            }
-            ++m;
+          if (FILL) {
+            int p = ng++;
+            while (p > 0 && gs[p - 1] > (int)g) { gs[p] = gs[p - 1]; --p; }
+            gs[p] = (int)g;
+          } else {
+            m += cfirst[g + 1] - cfirst[g];
           }
         }
       }
-  if (!FILL) cnt[f] = m;
+  if (!FILL) {
+    cnt[f] = m;
+    return;
+  }
+  const int o = ptr[f];
+  for (int i = 0; i < ng; ++i)
+    for (int q = cfirst[gs[i]]; q < cfirst[gs[i] + 1]; ++q) col[o + m++] = q;
 }
 
 // ------------------------------------------------------------ assembly

@@ -162,7 +162,7 @@ def test_figure_cubes_minimum_depth_full_model(cf, ctx):
             x, _ = cf.camfe_solve(s, b, t=1.0 / ALPHA, rtol=0.0, max_iter=1, nu_pre=10, nu_post=10, method=1,
                                   x0=x0, cycle=2)
             r = ALPHA * (b - cf.camfe_apply(s, 2, 1.0 / ALPHA, x))
-            res[split, m] = np.linalg.norm(r, axis=0).max() / np.linalg.norm(x0, axis=0).min()
+            res[split, m] = (np.linalg.norm(r, axis=0) / np.linalg.norm(x0, axis=0)).max()
             say(f"[gpu] cubes split={split} min_depth={m} n={n} residual={res[split, m]:.3e}")
             if split == 1 and m == 0:
                 o = Oracle(V, F, D, split=1, min_depth=0, max_coarse=0).check().assemble()

@@ -122,7 +122,7 @@ def _one_w_cycle_residual(V, F, col, depth, split, min_depth):
     x0 = np.random.default_rng(6200).uniform(0.0, 1.0, size=(n, 3))
     x, _ = o.solve(1.0 / ALPHA, b, rtol=0.0, max_iter=1, nu1=10, nu2=10, x0=x0, mode="vcycle", gamma=2)
     r = ALPHA * (b - o.apply(depth, 1.0 / ALPHA, x))
-    return np.linalg.norm(r, axis=0).max() / np.linalg.norm(x0, axis=0).min(), n
+    return (np.linalg.norm(r, axis=0) / np.linalg.norm(x0, axis=0)).max(), n
 
 
 def test_minimum_depth_experiment_reproduces_figure_cubes():

@@ -313,6 +313,68 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
             "context": "the paper's Table 1: 1.52 s per step for its 1.27M-DoF system (CPU, its own solver)"}
 
 
+def flow_study_eval(cf, ctx, meshgen, T=0.01, steps=(4, 8, 16), ref_steps=64, depth=8):
+    """The cMCF study (Section 5.3) on a genus-0 two-lobe surface: a U-shaped
+    capsule (tube radius 0.2, arms 1.0 long and 0.004 apart, 128 vertices
+    per ring), depth 8 (finest cells about 0.007 wide, wider than the gap).
+    Flow time T is reached in n tracked steps of T/n, split and unsplit,
+    mixed precision, 1e-10 per step.  Every surface is compared with the
+    split FP64 flow in ref_steps steps: RMS and largest vertex distance over
+    all vertices and over the facing walls (vertices of the arms within 0.05
+    of the plane between them, where the unsplit functions straddle the
+    gap), and the wall time of the n steps."""
+    import torch
+    V, F = meshgen.u_tube(nv=128, ncap=16)
+    dev = torch.device("cuda:0")
+    Vd, Fd = torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev)
+    wall_mask = torch.from_numpy((np.abs(V[:, 0]) < 0.05) & (V[:, 1] > 0.0)).to(dev)
+    systems = {}
+    for split in (1, 0):
+        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=depth, split=split, max_coarse=4096)
+        systems[split] = (h, cf.camfe_assemble(h))
+
+    def run(split, n, precision):
+        h, s = systems[split]
+        X = cf.camfe_linear_coeffs(s, h)
+        Xd = torch.from_numpy(np.asfortranarray(X)).to(dev)
+        cycles = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            Xd, st = cf.camfe_flow_step(s, Xd, T / n, rtol=1e-10, max_iter=2000, precision=precision)
+            cycles += st["cycles"]
+            if not st["converged"]:
+                raise RuntimeError("flow step did not converge")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return cf.camfe_eval_vertices(s, len(V), Xd), wall, cycles
+
+    ref, ref_wall, _ = run(1, ref_steps, 0)
+    rows = []
+    for split in (1, 0):
+        for n in steps:
+            P, wall, cyc = run(split, n, 1)
+            d = torch.linalg.norm(P - ref, dim=1)
+            dw = d[wall_mask]
+            rows.append({"split": split, "steps": n, "delta": T / n, "wall_ms": 1000.0 * wall,
+                         "ms_per_step": 1000.0 * wall / n, "cycles": int(cyc),
+                         "rms_vertex_error": float(torch.sqrt((d * d).mean()).item()),
+                         "max_vertex_error": float(d.max().item()),
+                         "rms_facing_wall_error": float(torch.sqrt((dw * dw).mean()).item()),
+                         "max_facing_wall_error": float(dw.max().item())})
+            log("[bench] flow study: " + json.dumps(rows[-1]))
+    out = {"mesh": f"U-shaped capsule, {len(F)} tris, arms 0.004 apart, depth {depth}", "flow_time": T,
+           "facing_wall_vertices": int(wall_mask.sum().item()), "vertices": int(len(V)),
+           "functions": {"split": int(cf.camfe_hierarchy_info(systems[1][0], depth)[2]),
+                         "unsplit": int(cf.camfe_hierarchy_info(systems[0][0], depth)[2])},
+           "reference": f"split, FP64, {ref_steps} steps, {1000.0 * ref_wall:.0f} ms", "rows": rows}
+    for split in (1, 0):
+        h, s = systems[split]
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+    return out
+
+
 CUBES_ALPHA = 0.01
 
 
@@ -463,6 +525,9 @@ def main():
     ap.add_argument("--cubes-only", action="store_true",
                     help="only the minimum-depth experiment of Figure cubes (W-cycles, gradient constraint)")
     ap.add_argument("--no-cubes", action="store_true", help="skip the Figure cubes experiment")
+    ap.add_argument("--flow-study-only", action="store_true",
+                    help="only the cMCF study on the two-lobe surface (split against unsplit)")
+    ap.add_argument("--no-flow-study", action="store_true", help="skip the cMCF study")
     ap.add_argument("--assembly-only", action="store_true",
                     help="only the assembly measurement (four meshes, both degrees); for matrix-core counter runs")
     args = ap.parse_args()
@@ -485,6 +550,12 @@ def main():
 
     if args.flow_only:
         out = {"flow_config3": flow_eval(cf, ctx, meshgen)}
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.flow_study_only:
+        out = {"flow_study": flow_study_eval(cf, ctx, meshgen)}
         cf.camfe_ctx_destroy(ctx)
         print(json.dumps(out), flush=True)
         return
@@ -652,6 +723,9 @@ def main():
     if not args.no_cubes:
         log("[bench] Figure cubes: one W-cycle per minimum depth, split and unsplit")
         out["colour_fit_cubes"] = cubes_eval(cf, ctx, meshgen)
+    if not args.no_flow_study:
+        log("[bench] cMCF study: two-lobe surface, split against unsplit")
+        out["flow_study"] = flow_study_eval(cf, ctx, meshgen)
     cf.camfe_model_destroy(model)
     cf.camfe_model_destroy(model_jac)
     if args.calibrate_copy:

@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "icosphere", "octasphere", "two_sheets", "torus", "torus_knot",
-    "noisy_sphere", "unit_cubes", "cubes_checker", "single_triangle", "config_mesh",
+    "noisy_sphere", "unit_cubes", "cubes_checker", "u_tube", "single_triangle", "config_mesh",
 ]
 
 
@@ -191,6 +191,60 @@ def unit_cubes(n: int = 6, pitch: float = 2.0, rotate: bool = True):
     if rotate:
         V = V @ rodrigues((1.0, 2.0, 3.0), 0.3).T
     return V, F.astype(np.int32)
+
+
+def u_tube(radius: float = 0.2, gap: float = 0.004, arm: float = 1.0, nv: int = 64, ncap: int = 12):
+    """A genus-0 two-lobe surface: a tube of `radius` swept along a U (two
+    parallel arms of length `arm` along y joined by a half circle of radius
+    radius + gap/2, so the arms' facing walls are `gap` apart), closed by
+    hemispherical caps.  nv vertices per ring; body rings about a quad's
+    width apart; ncap rings per cap plus a pole; split quads and pole fans."""
+    rb = radius + 0.5 * gap
+    ltot = 2.0 * arm + np.pi * rb
+    nb = max(2, int(round(ltot / (2.0 * np.pi * radius / nv)))) + 1
+    s = np.linspace(0.0, ltot, nb)
+
+    def centre(s):
+        c = np.zeros((len(s), 3)); t = np.zeros((len(s), 3))
+        a = s < arm                                   # arm A, down along -y at x = -rb
+        c[a] = np.stack([np.full(a.sum(), -rb), arm - s[a], np.zeros(a.sum())], 1)
+        t[a] = [0.0, -1.0, 0.0]
+        b = (s >= arm) & (s <= arm + np.pi * rb)      # half circle under the origin
+        ph = np.pi + (s[b] - arm) / rb
+        c[b] = np.stack([rb * np.cos(ph), rb * np.sin(ph), np.zeros(b.sum())], 1)
+        t[b] = np.stack([-np.sin(ph), np.cos(ph), np.zeros(b.sum())], 1)
+        e = s > arm + np.pi * rb                      # arm B, up along +y at x = +rb
+        c[e] = np.stack([np.full(e.sum(), rb), s[e] - arm - np.pi * rb, np.zeros(e.sum())], 1)
+        t[e] = [0.0, 1.0, 0.0]
+        return c, t
+
+    c, t = centre(s)
+    # cap rings beyond each end: angle psi from the pole, distance r cos psi past the end
+    psi = np.pi / 2 * np.arange(1, ncap) / ncap
+    caps_a = [(c[0] - t[0] * radius * np.cos(p), t[0], radius * np.sin(p)) for p in psi]
+    caps_b = [(c[-1] + t[-1] * radius * np.cos(p), t[-1], radius * np.sin(p)) for p in psi[::-1]]
+    rings = caps_a + [(c[i], t[i], radius) for i in range(nb)] + caps_b
+    th = 2.0 * np.pi * np.arange(nv) / nv
+    z = np.array([0.0, 0.0, 1.0])
+    Vr = []
+    for cc, tt, rr in rings:
+        n = np.cross(z, tt)                           # in-plane normal
+        Vr.append(cc[None, :] + rr * (np.cos(th)[:, None] * n[None, :] + np.sin(th)[:, None] * z[None, :]))
+    Vr = np.concatenate(Vr)
+    nr = len(rings)
+    pole_a = c[0] - t[0] * radius
+    pole_b = c[-1] + t[-1] * radius
+    V = np.concatenate([Vr, pole_a[None, :], pole_b[None, :]])
+    ia, ib = nr * nv, nr * nv + 1
+    i = np.arange(nr - 1)[:, None]; j = np.arange(nv)[None, :]
+    a = i * nv + j; b = (i + 1) * nv + j; cq = (i + 1) * nv + (j + 1) % nv; d = i * nv + (j + 1) % nv
+    a, b, cq, d = (x.ravel() for x in (a, b, cq, d))
+    F = [np.stack([a, b, cq], 1), np.stack([a, cq, d], 1)]
+    jj = np.arange(nv)
+    F.append(np.stack([np.full(nv, ia), jj, (jj + 1) % nv], 1))
+    last = (nr - 1) * nv
+    F.append(np.stack([np.full(nv, ib), last + (jj + 1) % nv, last + jj], 1))
+    return V, np.concatenate(F).astype(np.int32)
 
 
 def _cube_lattice(s: int):

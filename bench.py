@@ -379,7 +379,7 @@ CUBES_ALPHA = 0.01
 
 
 def cubes_eval(cf, ctx, meshgen, depth=5):
-    """Figure cubes (Section 6.2): the 6x6x6 unit cubes (each face 4 x 4 split
+    """Figure cubes (Section 5.2): the 6x6x6 unit cubes (each face 4 x 4 split
     quads, 41,472 triangles) with a solid 3D checker as the colour f, the
     screened Poisson fit (L + alpha M) u = g + alpha s with alpha = 0.01 and
     g the gradient constraint, depth 5, one W-cycle with ten Gauss-Seidel

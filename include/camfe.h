@@ -148,7 +148,7 @@ camfe_status camfe_export_matrix(camfe_sys s, int depth, int which, int64_t *row
  * from per-vertex values vertex_f (nv x k column-major); b is n x k. */
 camfe_status camfe_load_vector(camfe_sys s, const double *vertex_f, int k, double *b);
 /* b_i = int <grad f, grad b_i> at the finest depth: the gradient constraint of
- * the screened Poisson colour fit (L + alpha M) u = b + alpha s (Section 6.2),
+ * the screened Poisson colour fit (L + alpha M) u = b + alpha s (Section 5.2),
  * with s from camfe_load_vector and grad f the surface gradient of f, linear
  * on each triangle from per-vertex values vertex_f (nv x k column-major; zero
  * on triangles without area, which the hierarchy build rejects; on a sliver
@@ -187,7 +187,7 @@ typedef struct {
                      /*    smaller residual continues.  All of them count in       */
                      /*    iterations and cycles.  0: off.  The batched solve     */
                      /*    ignores it                                             */
-  int cycle;         /* 0 or 1: V-cycle; 2: W-cycle (Section 6.2): at every depth */
+  int cycle;         /* 0 or 1: V-cycle; 2: W-cycle (Section 5.2): at every depth */
                      /*    above the coarsest the coarse problem gets two cycles, */
                      /*    the second starting from the first's result.  The      */
                      /*    batched solve takes 0 or 1 only (else EINVAL)          */
@@ -207,7 +207,7 @@ typedef struct {
                        /*    smoother, [1] Gauss-Seidel (0 when not judged)       */
 } camfe_solve_stats;
 
-/* Solve (M + t L) x = b at the finest depth (Sections 3.2, 4.3, 5.2, 6.2).
+/* Solve (M + t L) x = b at the finest depth (Sections 3.2, 4.3, 5.2).
  * b, x: n x k column-major (x is read when x0_given).  Returns CAMFE_ENOCONV
  * with stats filled when max_iter is reached above rtol. */
 camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double *b, int k,
@@ -229,6 +229,43 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double
 camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision, int reps, double *avg_ms,
                                   double *bytes_per_launch);
 void camfe_system_destroy(camfe_sys s);
+
+/* ------------------------------------------------------------ spectrum */
+/* The smallest generalised eigenpairs L x = lambda M x at the finest depth
+ * (Section 5.1: the spectrum of the estimated Laplace-Beltrami operator).
+ * Shift-invert subspace iteration: each step solves (L + sigma M) Y = M X
+ * for the block with the system's multigrid-preconditioned CG (as
+ * camfe_solve with t = 1/sigma), then a Rayleigh-Ritz step on the GPU
+ * (k x k Gram matrices of L and M, Cholesky of the M Gram matrix, Jacobi
+ * rotations) makes the block M-orthonormal with ascending Ritz values.
+ * The start block is pseudo-random from seed. */
+typedef struct {
+  int nev;            /* eigenpairs wanted, 1 <= nev <= block                    */
+  int block;          /* subspace width, nev <= block <= 32 (0: min(32, nev + 8)) */
+  double sigma;       /* shift > 0; convergence per step is (l_j + s)/(l_b + s)  */
+  int max_iter;       /* subspace iterations                                     */
+  double tol;         /* stop when every wanted pair has                         */
+                      /*   ||L x - l M x|| <= tol (|l| + sigma) ||M x||          */
+  double solve_rtol;  /* relative residual of each inner solve (e.g. 1e-10)      */
+  int precision;      /* inner cycles: 0 FP64, 1 FP32 (residuals in FP64)        */
+  uint64_t seed;      /* start block                                             */
+} camfe_eig_opts;
+
+typedef struct {
+  int iterations;      /* subspace iterations done                               */
+  int solve_cycles;    /* V-cycles over all inner solves                         */
+  double max_residual; /* largest scaled residual of the wanted pairs (above)    */
+  double seconds;      /* wall time                                              */
+} camfe_eig_stats;
+
+/* evals: nev doubles, ascending; evecs (nullable): n x nev column-major,
+ * M-orthonormal, canonical order.  Host or device pointers.  Sets up the
+ * system's solver for t = 1/sigma (the next camfe_solve with another t
+ * rebuilds it).  Returns CAMFE_ENOCONV (outputs written) when max_iter is
+ * reached above tol, CAMFE_ESINGULAR when the block's M Gram matrix is not
+ * positive definite (a start block in the null space of M). */
+camfe_status camfe_eigs(camfe_sys s, const camfe_eig_opts *opts, double *evals, double *evecs,
+                        camfe_eig_stats *stats);
 
 /* ------------------------------------------------------------- batching */
 /* Many systems solved together (not in the paper): the hierarchies are lined

@@ -28,7 +28,7 @@
 //                                    Section 5.2 (Gauss-Seidel smoothing), the
 //                                    Discussion closing Section 5 (eps * Id for
 //                                    singular systems)
-//   gradient constraint, W-cycle .... Section 6.2 (colour fitting: int <grad f,
+//   gradient constraint, W-cycle .... Section 5.2 (colour fitting: int <grad f,
 //                                    grad b_i>, one W-cycle, minimum depth)
 //
 // Parity pins for every function here live in tests/test_oracle_*.py.
@@ -545,7 +545,7 @@ int func_of(const Level& L, uint64_t key, int t) {
 // f, interpolated linearly inside each triangle; rhs is n x k col-major.
 // rhs (nullable) receives b_i = int f b_i, or with grad_rhs the gradient
 // constraint b_i = int <grad f, grad b_i> of the colour-fitting problem
-// (Section 6.2), for f linear on each triangle from per-vertex values fv.
+// (Section 5.2), for f linear on each triangle from per-vertex values fv.
 bool assemble_level(Hier& h, int d, const double* tri_w, const double* fv, int k, double* rhs,
                     bool want_matrix, bool grad_rhs = false) {
   Level& L = h.lev[d];
@@ -948,7 +948,7 @@ int oracle_load_vector(void* hp, int d, const double* fv, int k, double* b) {
 }
 
 // b_i = int <grad f, grad b_i> at depth d (the gradient constraint of the
-// screened Poisson colour fit, Section 6.2), f per-vertex (nv x k col-major)
+// screened Poisson colour fit, Section 5.2), f per-vertex (nv x k col-major)
 int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
   Hier& h = ((OracleHandle*)hp)->h;
   if (!h.err.empty() || d < h.d0 || d > h.D) return -1;
@@ -957,7 +957,7 @@ int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
 
 // Solve (M + t L) x = b at the finest depth.
 // mode 0: stationary multigrid, x <- x + V(b - A x) with V a (nu1, nu2) cycle,
-//         a V-cycle (gamma 1) or a W-cycle (gamma 2, Section 6.2).
+//         a V-cycle (gamma 1) or a W-cycle (gamma 2, Section 5.2).
 // mode 1: conjugate gradients preconditioned by one V-cycle (V is symmetric:
 //         forward colour order before the coarse correction, reverse after,
 //         nu1 == nu2, exact coarse solve), one independent CG per column.

@@ -171,13 +171,28 @@ class Oracle:
         return b
 
     def gradient_load(self, fv, d=None):
-        """b_i = int <grad f, grad b_i> for f linear on each triangle (Section 6.2)."""
+        """b_i = int <grad f, grad b_i> for f linear on each triangle (Section 5.2)."""
         d = self.depth if d is None else d
         fv, k = _colmajor(fv, len(self.V))
         b = np.zeros((self.count(d, "functions"), k), order="F")
         if self.lib.oracle_gradient_load(self.h, d, _p(fv), k, _p(b)) != 0:
             raise RuntimeError("oracle gradient load failed")
         return b
+
+    def eigenvalues(self, k, d=None):
+        """The k smallest generalised eigenvalues L x = lambda M x at depth d
+        (Section 5.1), by a dense symmetric solve of the unit-diagonal-scaled
+        pair (the scaling keeps the eigenvalues).  Functions of zero computed
+        mass have all-zero rows and columns in both matrices and are left out."""
+        import scipy.linalg as la
+        d = self.depth if d is None else d
+        M, L = self.matrices(d)
+        m = M.diagonal()
+        keep = m > 0.0
+        s = 1.0 / np.sqrt(m[keep])
+        Ms = M[keep][:, keep].toarray() * np.outer(s, s)
+        Ls = L[keep][:, keep].toarray() * np.outer(s, s)
+        return la.eigh(Ls, Ms, eigvals_only=True, subset_by_index=[0, k - 1])
 
     def solve(self, t, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, x0=None, mode="pcg",
               coarse_eps=1e-6, gamma=1):

@@ -28,7 +28,7 @@ EXPORTS = [
     "camfe_system_destroy", "camfe_ctx_kernel_timing", "camfe_ctx_kernel_time", "camfe_measure_kernel",
     "camfe_model_create", "camfe_model_params", "camfe_model_destroy", "camfe_smoother_attach",
     "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
-    "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy",
+    "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy", "camfe_eigs",
 ]
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 DEFAULT_COARSE_EPS = 1e-6   # eps * Id on the unit-diagonal-scaled coarsest matrix (the library's own default)
@@ -62,6 +62,16 @@ class SolveStats(C.Structure):
 
 def _stats_dict(st):
     return {f: (list(getattr(st, f)) if f == "judge_rel" else getattr(st, f)) for f, _ in SolveStats._fields_}
+
+
+class EigOpts(C.Structure):
+    _fields_ = [("nev", C.c_int), ("block", C.c_int), ("sigma", C.c_double), ("max_iter", C.c_int),
+                ("tol", C.c_double), ("solve_rtol", C.c_double), ("precision", C.c_int), ("seed", C.c_uint64)]
+
+
+class EigStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("solve_cycles", C.c_int), ("max_residual", C.c_double),
+                ("seconds", C.c_double)]
 
 
 class TrainOpts(C.Structure):
@@ -100,6 +110,7 @@ def load():
         "camfe_export_matrix": (I, [H, I, I, P, P, P, I64, C.POINTER(I64)]),
         "camfe_load_vector": (I, [H, P, I, P]),
         "camfe_gradient_load": (I, [H, P, I, P]),
+        "camfe_eigs": (I, [H, P, P, P, P]),
         "camfe_apply": (I, [H, I, D, P, I, P]),
         "camfe_linear_coeffs": (I, [H, P]),
         "camfe_eval_vertices": (I, [H, P, I, P]),
@@ -365,6 +376,30 @@ def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0,
     stats = _stats_dict(st)
     stats["converged"] = code == 0
     return x, stats
+
+
+def camfe_eigs(s, h, nev, sigma, block=0, max_iter=200, tol=1e-8, solve_rtol=1e-10, precision=0, seed=1,
+               vectors=True, raise_on_noconv=False, device=None):
+    """Smallest eigenpairs of L x = lambda M x: (evals, evecs n x nev or None, stats dict).
+    device: a torch device for the outputs (default: numpy on the host)."""
+    n = camfe_hierarchy_info(h, camfe_hierarchy_levels(h)[0])[2]
+    if device is not None:
+        import torch
+        ev = torch.empty(nev, dtype=torch.float64, device=device)
+        X = torch.empty((nev, n), dtype=torch.float64, device=device).t() if vectors else None
+    else:
+        ev = np.zeros(nev)
+        X = np.zeros((n, nev), order="F") if vectors else None
+    o = EigOpts()
+    o.nev, o.block, o.sigma, o.max_iter, o.tol = nev, block, sigma, max_iter, tol
+    o.solve_rtol, o.precision, o.seed = solve_rtol, precision, seed
+    st = EigStats()
+    code = load().camfe_eigs(s, C.byref(o), _ptr(ev), None if X is None else _ptr(X), C.byref(st))
+    if code != 0 and (code != -4 or raise_on_noconv):
+        _check(code)
+    stats = {f: getattr(st, f) for f, _ in EigStats._fields_}
+    stats["converged"] = code == 0
+    return ev, X, stats
 
 
 def camfe_measure_kernel(s, kernel: str, precision: int = 0, reps: int = 50):

@@ -88,6 +88,15 @@ void assemble_level(camfe_sys s, int d, bool want_L, bool want_M);
 void load_vector_dev(camfe_sys s, const double* d_fv, int k, double* d_b, bool grad = false);
 // dense.hip: out = diag(s) A^-1 diag(s) for SPD A (n x n row-major, destroyed)
 void spd_inverse_scaled(camfe_ctx ctx, double* A, int n, const double* s, double* out);
-// solve.hip helpers used by the C ABI in assemble.hip
+// assemble.hip helpers: y = (a M + b L) x at the finest depth, x and y n x k
+// row-major; layout changes of n x k blocks
 void csr_apply(camfe_ctx ctx, const SLevel& L, double a, double b, const double* x, int k, double* y);
+void to_rowmajor(camfe_ctx ctx, const double* in, size_t n, int k, double* out);
+void to_colmajor(camfe_ctx ctx, const double* in, size_t n, int k, double* out);
+// solve.hip: (M + t L) X = B for k device columns (canonical, column-major)
+struct SolveSummary {
+  int iterations = 0, cycles = 0;
+  double rel = 0.0;   // largest relative residual over the columns
+};
+SolveSummary solve_device(camfe_sys s, const camfe_solve_opts& o, const double* db, double* dx, int k);
 }  // namespace camfe

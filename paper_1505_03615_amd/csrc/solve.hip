@@ -895,7 +895,7 @@ void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
 
 // One cycle at depth d on (b, x) of that depth, x given (zero on entry below
 // the top): the coarse problem gets S->gamma cycles, the first from zero (one:
-// V-cycle, two: W-cycle, Section 6.2).
+// V-cycle, two: W-cycle, Section 5.2).
 // first0: as for smooth() (x zero, colour 0 of the first pre-sweep done)
 template <class T, int K>
 void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool first0 = false) {
@@ -1692,6 +1692,37 @@ void plain_vcycle_at(SolverState* S, int d, double* x, int nu1, int nu2) {
 }  // namespace camfe
 
 using namespace camfe;
+
+namespace camfe {
+// Solve (M + t L) X = B for k device columns (canonical order, n x k
+// column-major) with the multicolour Gauss-Seidel cycles of o (smoother 0);
+// X is the start when o.x0_given.  For callers inside the library.
+SolveSummary solve_device(camfe_sys s, const camfe_solve_opts& o, const double* db, double* dx, int k) {
+  SolverState* S = ensure_solver(s, o.t, o.coarse_eps);
+  S->precision = o.precision;
+  S->smoother = 0;
+  struct GammaScope {
+    SolverState* S;
+    ~GammaScope() { S->gamma = 1; }
+  } gamma_scope{S};
+  S->gamma = o.cycle == 2 ? 2 : 1;
+  SolveSummary tot;
+  for (int c0 = 0; c0 < k; c0 += KMAXS) {
+    const int kb = std::min(KMAXS, k - c0);
+    SolveResult r;
+    switch (kb) {
+      case 1: r = solve_block<1>(s, S, o, db, dx, k, c0); break;
+      case 2: r = solve_block<2>(s, S, o, db, dx, k, c0); break;
+      case 3: r = solve_block<3>(s, S, o, db, dx, k, c0); break;
+      default: r = solve_block<4>(s, S, o, db, dx, k, c0); break;
+    }
+    tot.iterations = std::max(tot.iterations, r.it);
+    tot.cycles += r.cycles;
+    if (!(r.rel <= tot.rel)) tot.rel = r.rel;
+  }
+  return tot;
+}
+}  // namespace camfe
 
 extern "C" {
 

@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "icosphere", "octasphere", "two_sheets", "torus", "torus_knot",
-    "noisy_sphere", "unit_cubes", "cubes_checker", "u_tube", "single_triangle", "config_mesh",
+    "noisy_sphere", "unit_cubes", "cubes_checker", "u_tube", "nested_spheres", "single_triangle", "config_mesh",
 ]
 
 
@@ -245,6 +245,18 @@ def u_tube(radius: float = 0.2, gap: float = 0.004, arm: float = 1.0, nv: int = 
     last = (nr - 1) * nv
     F.append(np.stack([np.full(nv, ib), last + (jj + 1) % nv, last + jj], 1))
     return V, np.concatenate(F).astype(np.int32)
+
+
+def nested_spheres(level: int = 4, gap: float = 0.02, rotation=None):
+    """Two concentric icospheres (radii 1 and 1 + gap), optionally turned by
+    a rotation matrix: a closed surface pair closer than a cell, whose exact
+    Laplace-Beltrami spectrum is l(l + 1) and l(l + 1) / (1 + gap)^2, each
+    with multiplicity 2l + 1."""
+    V1, F1 = icosphere(level)
+    V = np.concatenate([V1, V1 * (1.0 + gap)])
+    if rotation is not None:
+        V = V @ np.asarray(rotation, dtype=np.float64).T
+    return V, np.concatenate([F1, F1 + len(V1)]).astype(np.int32)
 
 
 def _cube_lattice(s: int):

@@ -1,4 +1,4 @@
-"""Colour fitting on the GPU (Section 6.2, Figure cubes), through the C ABI.
+"""Colour fitting on the GPU (Section 5.2, Figure cubes), through the C ABI.
 
 The gradient constraint b_i = int <grad f, grad b_i> matches the oracle's
 within 1e-12 relative (max-norm), at both degrees, over several assembly

@@ -1,4 +1,4 @@
-"""Pins of the oracle's colour-fitting pieces (Section 6.2, Figure cubes).
+"""Pins of the oracle's colour-fitting pieces (Section 5.2, Figure cubes).
 
 The gradient constraint b_i = int <grad f, grad b_i> is pinned by linear
 reproduction (a linear f is sum_i (a . node_i) b_i exactly, at both degrees

@@ -375,6 +375,70 @@ def flow_study_eval(cf, ctx, meshgen, T=0.01, steps=(4, 8, 16), ref_steps=64, de
     return out
 
 
+SPEC_GAP = 0.02
+
+
+def spectrum_eval(cf, ctx, meshgen, depths=(4, 5, 6, 7), rot_depth=5, rotations=6, nev=16):
+    """The spectral study (Section 5.1) on two concentric icospheres (level 6,
+    2 x 81,920 triangles) 0.02 apart, closer than a cell at every depth used:
+    the nev smallest eigenvalues of L x = lambda M x by camfe_eigs (block
+    nev + 8, sigma 1, 1e-9), split and unsplit, against the exact spectrum
+    l(l+1) and l(l+1)/1.02^2 (multiplicity 2l + 1 each).  Resolution sweep
+    over depths; rotation sweep at one depth (rotations about seeded random
+    axes): the spread of each eigenvalue over the rotations."""
+    import torch
+    dev = torch.device("cuda:0")
+    exact = []
+    for l in range(8):
+        exact += [l * (l + 1.0)] * (2 * l + 1) + [l * (l + 1.0) / (1 + SPEC_GAP) ** 2] * (2 * l + 1)
+    exact = np.sort(exact)[:nev]
+    nz = exact > 0
+
+    def spectrum(V, F, depth, split):
+        h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=depth,
+                                     split=split, max_coarse=4096)
+        s = cf.camfe_assemble(h)
+        n = cf.camfe_hierarchy_info(h, depth)[2]
+        ev, _, st = cf.camfe_eigs(s, h, nev, sigma=1.0, max_iter=400, tol=1e-9, solve_rtol=1e-10, precision=1,
+                                  vectors=False)
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+        return np.asarray(ev), int(n), st
+
+    V, F = meshgen.nested_spheres(6, SPEC_GAP)
+    res = []
+    for depth in depths:
+        for split in (1, 0):
+            ev, n, st = spectrum(V, F, depth, split)
+            err = np.abs(ev[nz] - exact[nz]) / exact[nz]
+            res.append({"depth": depth, "split": split, "functions": n, "zero_eigenvalues": int((np.abs(ev) < 1e-6).sum()),
+                        "max_rel_error": float(err.max()), "mean_rel_error": float(err.mean()),
+                        "eigs_ms": 1000.0 * st["seconds"], "iterations": st["iterations"],
+                        "solve_cycles": st["solve_cycles"], "converged": st["converged"],
+                        "eigenvalues": [round(float(x), 5) for x in ev]})
+            log("[bench] spectrum: " + json.dumps({k: v for k, v in res[-1].items() if k != "eigenvalues"}))
+    rng = np.random.default_rng(5100)
+    rot = {1: [], 0: []}
+    for r in range(rotations):
+        axis = rng.normal(size=3)
+        R = meshgen.rodrigues(axis, rng.uniform(0.1, 3.0))
+        Vr, Fr = meshgen.nested_spheres(6, SPEC_GAP, rotation=R)
+        for split in (1, 0):
+            ev, _, _ = spectrum(Vr, Fr, rot_depth, split)
+            rot[split].append(ev)
+    spread = {}
+    for split in (1, 0):
+        E = np.array(rot[split])[:, nz]
+        spread["split" if split else "unsplit"] = {
+            "max_rel_spread": float(((E.max(0) - E.min(0)) / E.mean(0)).max()),
+            "mean_rel_spread": float(((E.max(0) - E.min(0)) / E.mean(0)).mean()),
+            "max_rel_error": float((np.abs(E - exact[nz]) / exact[nz]).max())}
+        log("[bench] spectrum rotations: " + json.dumps(spread))
+    return {"mesh": "two concentric icospheres, level 6, radii 1 and 1.02 (163,840 tris)", "nev": nev,
+            "exact": [round(float(x), 5) for x in exact], "resolution": res,
+            "rotations": {"depth": rot_depth, "count": rotations, **spread}}
+
+
 CUBES_ALPHA = 0.01
 
 
@@ -525,6 +589,9 @@ def main():
     ap.add_argument("--cubes-only", action="store_true",
                     help="only the minimum-depth experiment of Figure cubes (W-cycles, gradient constraint)")
     ap.add_argument("--no-cubes", action="store_true", help="skip the Figure cubes experiment")
+    ap.add_argument("--spectrum-only", action="store_true",
+                    help="only the spectral study (nested spheres, resolution and rotation sweeps)")
+    ap.add_argument("--no-spectrum", action="store_true", help="skip the spectral study")
     ap.add_argument("--flow-study-only", action="store_true",
                     help="only the cMCF study on the two-lobe surface (split against unsplit)")
     ap.add_argument("--no-flow-study", action="store_true", help="skip the cMCF study")
@@ -550,6 +617,12 @@ def main():
 
     if args.flow_only:
         out = {"flow_config3": flow_eval(cf, ctx, meshgen)}
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.spectrum_only:
+        out = {"spectrum": spectrum_eval(cf, ctx, meshgen)}
         cf.camfe_ctx_destroy(ctx)
         print(json.dumps(out), flush=True)
         return
@@ -726,6 +799,9 @@ def main():
     if not args.no_flow_study:
         log("[bench] cMCF study: two-lobe surface, split against unsplit")
         out["flow_study"] = flow_study_eval(cf, ctx, meshgen)
+    if not args.no_spectrum:
+        log("[bench] spectral study: nested spheres, split against unsplit")
+        out["spectrum"] = spectrum_eval(cf, ctx, meshgen)
     cf.camfe_model_destroy(model)
     cf.camfe_model_destroy(model_jac)
     if args.calibrate_copy:

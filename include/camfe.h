@@ -246,7 +246,8 @@ typedef struct {
   int max_iter;       /* subspace iterations                                     */
   double tol;         /* stop when every wanted pair has                         */
                       /*   ||L x - l M x|| <= tol (|l| + sigma) ||M x||          */
-  double solve_rtol;  /* relative residual of each inner solve (e.g. 1e-10)      */
+  double solve_rtol;  /* inner solves stop at max(solve_rtol, 0.01 x the wanted */
+                      /*   pairs' largest scaled residual of the previous step)  */
   int precision;      /* inner cycles: 0 FP64, 1 FP32 (residuals in FP64)        */
   uint64_t seed;      /* start block                                             */
 } camfe_eig_opts;

@@ -101,94 +101,161 @@ __global__ void k_sum_parts(const double* part, int nb, int len, double* out) {
   out[e] = s;
 }
 
-// G_L c = theta G_M c for k <= KE in one thread (the matrices are tiny):
-// G_M = R R^T (lower R), A = R^-1 G_L R^-T, cyclic Jacobi rotations on A
-// until its off-diagonal mass is below 1e-30 of its total (at most 64
-// sweeps), C = R^-T Q with the columns in ascending order of theta.
+// G_L c = theta G_M c for k <= KE in one workgroup of SG threads: G_M = R R^T
+// (lower R, column by column), A = R^-1 G_L R^-T (one column, then one row,
+// per thread), cyclic Jacobi on A in the round-robin order of Brent and Luk
+// (each round rotates k/2 disjoint index pairs at once; rotations of disjoint
+// pairs commute, so a round equals the same rotations done one by one) until
+// the off-diagonal mass is below 1e-30 of the total (at most 64 sweeps), then
+// C = R^-T Q with the columns in ascending order of theta.
 // flag: 1 when G_M is not positive definite.
-__global__ void k_small_geig(int k, const double* GL, const double* GM, double* theta, double* C, int* flag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+constexpr int SG = 64;
+__global__ __launch_bounds__(SG) void k_small_geig(int k, const double* GL, const double* GM, double* theta,
+                                                   double* C, int* flag) {
   __shared__ double R[KE * KE], A[KE * KE], Q[KE * KE];
-  *flag = 0;
-  for (int e = 0; e < k * k; ++e) { R[e] = 0.5 * (GM[e] + GM[(e % k) * k + e / k]); A[e] = 0.5 * (GL[e] + GL[(e % k) * k + e / k]); }
-  // Cholesky in place (lower triangle of R)
+  __shared__ double rc[KE / 2], rs[KE / 2];
+  __shared__ int rp[KE / 2], rq[KE / 2];
+  __shared__ double red[2 * SG];
+  __shared__ int bad, done, ord[KE];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < k * k; e += SG) {
+    const int tr = (e % k) * k + e / k;
+    R[e] = 0.5 * (GM[e] + GM[tr]);
+    A[e] = 0.5 * (GL[e] + GL[tr]);
+  }
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // Cholesky, one column at a time
   for (int j = 0; j < k; ++j) {
-    double d = R[j * k + j];
-    for (int p = 0; p < j; ++p) d -= R[j * k + p] * R[j * k + p];
-    if (!(d > 0.0)) { *flag = 1; return; }
-    d = sqrt(d);
-    R[j * k + j] = d;
-    for (int i = j + 1; i < k; ++i) {
+    if (tid == 0) {
+      double d = R[j * k + j];
+      for (int p = 0; p < j; ++p) d -= R[j * k + p] * R[j * k + p];
+      if (!(d > 0.0)) bad = 1;
+      R[j * k + j] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < k; i += SG) {
       double v = R[i * k + j];
       for (int p = 0; p < j; ++p) v -= R[i * k + p] * R[j * k + p];
-      R[i * k + j] = v / d;
+      R[i * k + j] = v / R[j * k + j];
     }
-    for (int i = 0; i < j; ++i) R[i * k + j] = 0.0;
+    __syncthreads();
   }
-  // A <- R^-1 A (forward substitution on each column), then A <- A R^-T
-  for (int c = 0; c < k; ++c)
+  if (bad) {
+    if (tid == 0) *flag = 1;
+    return;   // uniform: every thread read the same shared flag
+  }
+  for (int e = tid; e < k * k; e += SG)
+    if (e % k > e / k) R[e] = 0.0;   // upper part
+  __syncthreads();
+  // A <- R^-1 A: thread c solves column c
+  for (int c = tid; c < k; c += SG)
     for (int i = 0; i < k; ++i) {
       double v = A[i * k + c];
       for (int p = 0; p < i; ++p) v -= R[i * k + p] * A[p * k + c];
       A[i * k + c] = v / R[i * k + i];
     }
-  for (int r = 0; r < k; ++r)
+  __syncthreads();
+  // A <- A R^-T: thread r solves row r
+  for (int r = tid; r < k; r += SG)
     for (int i = 0; i < k; ++i) {
       double v = A[r * k + i];
       for (int p = 0; p < i; ++p) v -= A[r * k + p] * R[i * k + p];
       A[r * k + i] = v / R[i * k + i];
     }
-  for (int i = 0; i < k; ++i)
-    for (int j = 0; j < k; ++j) {
-      const double s = 0.5 * (A[i * k + j] + A[j * k + i]);
-      A[i * k + j] = s;
-      A[j * k + i] = s;
-      Q[i * k + j] = i == j ? 1.0 : 0.0;
+  __syncthreads();
+  for (int e = tid; e < k * k; e += SG) {
+    const int i = e / k, j = e % k;
+    if (i < j) {
+      const double v = 0.5 * (A[i * k + j] + A[j * k + i]);
+      A[i * k + j] = v;
+      A[j * k + i] = v;
     }
-  // cyclic Jacobi: each rotation zeroes A[p][q] (Golub and Van Loan, Alg. 8.5.2)
+    Q[e] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int m = (k + 1) & ~1;   // even number of slots; slot k (odd k) idles
   for (int sweep = 0; sweep < 64; ++sweep) {
+    // off-diagonal and total mass, one row per thread
     double off = 0.0, tot = 0.0;
-    for (int i = 0; i < k; ++i)
+    for (int r = tid; r < k; r += SG)
       for (int j = 0; j < k; ++j) {
-        const double v = A[i * k + j] * A[i * k + j];
+        const double v = A[r * k + j] * A[r * k + j];
         tot += v;
-        if (i != j) off += v;
+        if (j != r) off += v;
       }
-    if (off <= 1e-30 * tot) break;
-    for (int p = 0; p < k - 1; ++p)
-      for (int q = p + 1; q < k; ++q) {
-        const double apq = A[p * k + q];
-        if (apq == 0.0) continue;
-        const double tau = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
-        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int r = 0; r < k; ++r) {   // columns p, q of A
+    red[tid] = off;
+    red[SG + tid] = tot;
+    __syncthreads();
+    if (tid == 0) {
+      double so = 0.0, st = 0.0;
+      for (int t = 0; t < SG; ++t) { so += red[t]; st += red[SG + t]; }
+      done = so <= 1e-30 * st;
+    }
+    __syncthreads();
+    if (done) break;
+    for (int round = 0; round < m - 1; ++round) {
+      // pair i: slots i and m - 1 - i of [0, 1 + (round + 0) % (m - 1), ...]
+      if (tid < m / 2) {
+        const int a = tid == 0 ? 0 : 1 + (tid - 1 + round) % (m - 1);
+        const int b = 1 + (m - 2 - tid + round) % (m - 1);
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, sn = 0.0;
+        if (q < k) {
+          const double apq = A[p * k + q];
+          if (apq != 0.0) {
+            const double tau = (A[q * k + q] - A[p * k + p]) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+          }
+        }
+        rp[tid] = p;
+        rq[tid] = q < k ? q : p;   // an idle pair rotates nothing
+        rc[tid] = c;
+        rs[tid] = sn;
+      }
+      __syncthreads();
+      // columns p, q of A and Q: thread r owns row r
+      for (int r = tid; r < k; r += SG)
+        for (int i = 0; i < m / 2; ++i) {
+          const int p = rp[i], q = rq[i];
+          if (p == q) continue;
+          const double c = rc[i], sn = rs[i];
           const double ap = A[r * k + p], aq = A[r * k + q];
-          A[r * k + p] = c * ap - s * aq;
-          A[r * k + q] = s * ap + c * aq;
-        }
-        for (int r = 0; r < k; ++r) {   // rows p, q of A
-          const double ap = A[p * k + r], aq = A[q * k + r];
-          A[p * k + r] = c * ap - s * aq;
-          A[q * k + r] = s * ap + c * aq;
-        }
-        for (int r = 0; r < k; ++r) {   // columns p, q of Q
+          A[r * k + p] = c * ap - sn * aq;
+          A[r * k + q] = sn * ap + c * aq;
           const double qp = Q[r * k + p], qq = Q[r * k + q];
-          Q[r * k + p] = c * qp - s * qq;
-          Q[r * k + q] = s * qp + c * qq;
+          Q[r * k + p] = c * qp - sn * qq;
+          Q[r * k + q] = sn * qp + c * qq;
         }
-      }
+      __syncthreads();
+      // rows p, q of A: thread r owns column r
+      for (int r = tid; r < k; r += SG)
+        for (int i = 0; i < m / 2; ++i) {
+          const int p = rp[i], q = rq[i];
+          if (p == q) continue;
+          const double c = rc[i], sn = rs[i];
+          const double ap = A[p * k + r], aq = A[q * k + r];
+          A[p * k + r] = c * ap - sn * aq;
+          A[q * k + r] = sn * ap + c * aq;
+        }
+      __syncthreads();
+    }
   }
-  // ascending order (selection), then C = R^-T Q (back substitution per column)
-  int ord[KE];
-  for (int i = 0; i < k; ++i) ord[i] = i;
-  for (int i = 0; i < k; ++i) {
-    int m = i;
-    for (int j = i + 1; j < k; ++j)
-      if (A[ord[j] * k + ord[j]] < A[ord[m] * k + ord[m]]) m = j;
-    const int tmp = ord[i]; ord[i] = ord[m]; ord[m] = tmp;
+  if (tid == 0) {
+    for (int i = 0; i < k; ++i) ord[i] = i;
+    for (int i = 0; i < k; ++i) {
+      int mi = i;
+      for (int j = i + 1; j < k; ++j)
+        if (A[ord[j] * k + ord[j]] < A[ord[mi] * k + ord[mi]]) mi = j;
+      const int tmp = ord[i]; ord[i] = ord[mi]; ord[mi] = tmp;
+    }
+    *flag = 0;
   }
-  for (int j = 0; j < k; ++j) {
+  __syncthreads();
+  // C = R^-T Q: thread j back-substitutes column j
+  for (int j = tid; j < k; j += SG) {
     const int src = ord[j];
     theta[j] = A[src * k + src];
     for (int i = k - 1; i >= 0; --i) {
@@ -322,7 +389,7 @@ camfe_status camfe_eigs(camfe_sys s, const camfe_eig_opts* o, double* evals, dou
       hipLaunchKernelGGL(k_gram2, nbg, BLK, 0, st, n, k, (const double*)Y.p, (const double*)LY.p,
                          (const double*)MY.p, part.p);
       hipLaunchKernelGGL(k_sum_parts, grid_for(2 * kk, BLK), BLK, 0, st, (const double*)part.p, nbg, 2 * kk, G.p);
-      hipLaunchKernelGGL(k_small_geig, 1, 64, 0, st, k, (const double*)G.p, (const double*)(G.p + kk), theta.p, C.p,
+      hipLaunchKernelGGL(k_small_geig, 1, SG, 0, st, k, (const double*)G.p, (const double*)(G.p + kk), theta.p, C.p,
                          flag.p);
       check_launch();
       CAMFE_REQUIRE(read_scalar(ctx, flag.p) == 0, CAMFE_ESINGULAR, "the block's M Gram matrix is not positive definite");

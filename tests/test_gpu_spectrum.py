@@ -96,3 +96,25 @@ def test_eigs_block_and_argument_checks(cf, ctx):
             cf.camfe_eigs(s, h, kw.pop("nev"), **kw)
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
+
+
+def test_eigs_odd_block_and_solve_afterwards(cf, ctx):
+    """An odd block (the round-robin Jacobi then idles one slot per round),
+    and a solve with another t after the eigensolver set the solver up for
+    t = 1/sigma."""
+    V, F = meshgen.icosphere(3)
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=4, max_coarse=512)
+    s = cf.camfe_assemble(h)
+    o = Oracle(V, F, 4, max_coarse=512).check().assemble()
+    ev, X, st = cf.camfe_eigs(s, h, 5, sigma=0.5, block=9, tol=1e-9, solve_rtol=1e-11)
+    assert st["converged"], st
+    evo = o.eigenvalues(5)
+    assert np.all(np.abs(ev - evo) <= 1e-8 * np.maximum(1.0, evo)), (ev, evo)
+    M, L = o.matrices(4)
+    assert np.abs(X.T @ (M @ X) - np.eye(5)).max() <= 1e-10
+    b = o.load_vector(V[:, 2])
+    x, sst = cf.camfe_solve(s, b, t=1e-3, rtol=1e-10, max_iter=400)
+    r = np.linalg.norm(b - (M + 1e-3 * L) @ x) / np.linalg.norm(b)
+    assert sst["converged"] and r <= 1e-9
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)

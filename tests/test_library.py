@@ -71,7 +71,8 @@ def _header_struct_fields(name):
 
 
 @pytest.mark.parametrize("cname,pyname", [("camfe_hier_opts", "HierOpts"), ("camfe_solve_opts", "SolveOpts"),
-                                          ("camfe_solve_stats", "SolveStats"), ("camfe_train_opts", "TrainOpts")])
+                                          ("camfe_solve_stats", "SolveStats"), ("camfe_train_opts", "TrainOpts"),
+                                          ("camfe_eig_opts", "EigOpts"), ("camfe_eig_stats", "EigStats")])
 def test_binding_structs_follow_the_header(cname, pyname):
     py = [f[0] for f in getattr(camfe, pyname)._fields_]
     assert py == _header_struct_fields(cname)

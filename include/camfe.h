@@ -191,6 +191,9 @@ typedef struct {
                      /*    above the coarsest the coarse problem gets two cycles, */
                      /*    the second starting from the first's result.  The      */
                      /*    batched solve takes 0 or 1 only (else EINVAL)          */
+  int nu_coarse;     /* sweeps each way at the depths below the finest; 0: the    */
+                     /*    finest depth's nu_pre / nu_post.  The batched solve    */
+                     /*    ignores it                                             */
 } camfe_solve_opts;
 
 typedef struct {

@@ -758,6 +758,7 @@ struct Solver {
   std::vector<SysLevel> sl;   // index = depth
   int nu1 = 2, nu2 = 2;
   int gamma = 1;              // coarse corrections per level: 1 V-cycle, 2 W-cycle
+  int nu_coarse = 0;          // sweeps each way below the finest depth (0: nu1, nu2)
   int eps_used = 0;
 };
 
@@ -800,6 +801,8 @@ void matvec(const SysLevel& S, const double* x, int k, double* y) {
 // sweeps; the coarsest depth is solved directly or relaxed.
 void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
   SysLevel& S = sv.sl[d];
+  const bool coarse = d < sv.h->D && sv.nu_coarse > 0;
+  const int nu1 = coarse ? sv.nu_coarse : sv.nu1, nu2 = coarse ? sv.nu_coarse : sv.nu2;
   if (d == sv.h->d0) {
     if (S.direct) {
       // x = D^-1/2 (D^-1/2 A D^-1/2 + eps I)^-1 D^-1/2 b
@@ -811,12 +814,12 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
         for (long i = 0; i < S.n; ++i) xq[i] = S.diag[i] > 0.0 ? xq[i] / std::sqrt(S.diag[i]) : 0.0;
       }
     } else {
-      for (int s = 0; s < sv.nu1; ++s) gs_sweep(S, b, x, k, true);
-      for (int s = 0; s < sv.nu2; ++s) gs_sweep(S, b, x, k, false);
+      for (int s = 0; s < nu1; ++s) gs_sweep(S, b, x, k, true);
+      for (int s = 0; s < nu2; ++s) gs_sweep(S, b, x, k, false);
     }
     return;
   }
-  for (int s = 0; s < sv.nu1; ++s) gs_sweep(S, b, x, k, true);
+  for (int s = 0; s < nu1; ++s) gs_sweep(S, b, x, k, true);
   std::vector<double> r((size_t)S.n * k);
   residual(S, b, x, k, r.data());
   const Level& Lf = sv.h->lev[d];
@@ -832,7 +835,7 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
     for (long i = 0; i < S.n; ++i)
       for (long e = Lf.Pptr[i]; e < Lf.Pptr[i + 1]; ++e)
         x[(size_t)q * S.n + i] += Lf.Pw[e] * xc[(size_t)q * C.n + Lf.Pcol[e]];
-  for (int s = 0; s < sv.nu2; ++s) gs_sweep(S, b, x, k, false);
+  for (int s = 0; s < nu2; ++s) gs_sweep(S, b, x, k, false);
 }
 
 double col_norm(const double* v, long n) {
@@ -957,7 +960,8 @@ int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
 
 // Solve (M + t L) x = b at the finest depth.
 // mode 0: stationary multigrid, x <- x + V(b - A x) with V a (nu1, nu2) cycle,
-//         a V-cycle (gamma 1) or a W-cycle (gamma 2, Section 5.2).
+//         a V-cycle (gamma 1) or a W-cycle (gamma 2, Section 5.2); below the
+//         finest depth nu_coarse sweeps each way when it is positive.
 // mode 1: conjugate gradients preconditioned by one V-cycle (V is symmetric:
 //         forward colour order before the coarse correction, reverse after,
 //         nu1 == nu2, exact coarse solve), one independent CG per column.
@@ -973,13 +977,14 @@ int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
 // before the first and after every iteration (true residual).
 int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2,
                  const double* b, int k, double* x, int x0_given, double* stats,
-                 double* history, int mode, double coarse_eps, int gamma) {
+                 double* history, int mode, double coarse_eps, int gamma, int nu_coarse) {
   Hier& h = ((OracleHandle*)hp)->h;
   if (!h.err.empty()) return -1;
   if (gamma < 1 || gamma > 2) { h.err = "gamma must be 1 or 2"; return -1; }
+  if (nu_coarse < 0) { h.err = "nu_coarse must be >= 0"; return -1; }
   auto t0 = std::chrono::steady_clock::now();
   Solver sv;
-  sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2; sv.gamma = gamma;
+  sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2; sv.gamma = gamma; sv.nu_coarse = nu_coarse;
   sv.sl.assign(h.D + 1, SysLevel());
   for (int d = h.d0; d <= h.D; ++d) {
     Level& L = h.lev[d];

@@ -54,7 +54,7 @@ def _load():
         lib.oracle_assemble.argtypes = [vp, P]
         lib.oracle_matrix.argtypes = [vp, I, P, P, P, P]
         lib.oracle_load_vector.argtypes = [vp, I, P, I, P]
-        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I]
+        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I, I]
         lib.oracle_gradient_load.argtypes = [vp, I, P, I, P]
         lib.oracle_apply.argtypes = [vp, I, D, P, I, P]
         lib.oracle_gs_sweep.argtypes = [vp, I, D, P, I, P, I]
@@ -195,16 +195,17 @@ class Oracle:
         return la.eigh(Ls, Ms, eigvals_only=True, subset_by_index=[0, k - 1])
 
     def solve(self, t, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, x0=None, mode="pcg",
-              coarse_eps=1e-6, gamma=1):
+              coarse_eps=1e-6, gamma=1, nu_coarse=0):
         """mode 'pcg' (CG preconditioned by one cycle) or 'vcycle' (stationary
-        cycles); gamma 1 for V-cycles, 2 for W-cycles."""
+        cycles); gamma 1 for V-cycles, 2 for W-cycles; nu_coarse > 0 sweeps
+        each way below the finest depth."""
         n = self.count(self.depth, "functions")
         b, k = _colmajor(b, n)
         x = np.zeros((n, k), order="F") if x0 is None else np.array(_colmajor(x0, n)[0], order="F")
         stats = np.zeros(5); hist = np.zeros(max_iter + 1)
         rc = self.lib.oracle_solve(self.h, t, rtol, max_iter, nu1, nu2, _p(b), k, _p(x),
                                    0 if x0 is None else 1, _p(stats), _p(hist),
-                                   {"vcycle": 0, "pcg": 1}[mode], coarse_eps, gamma)
+                                   {"vcycle": 0, "pcg": 1}[mode], coarse_eps, gamma, nu_coarse)
         if rc < 0:
             raise RuntimeError("oracle solve: " + self.lib.oracle_error(self.h).decode())
         it = int(stats[4])

@@ -51,7 +51,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("t", C.c_double), ("rtol", C.c_double), ("max_iter", C.c_int), ("nu_pre", C.c_int),
                 ("nu_post", C.c_int), ("method", C.c_int), ("precision", C.c_int), ("x0_given", C.c_int),
                 ("coarse_eps", C.c_double), ("smoother", C.c_int), ("omega", C.c_double), ("judge", C.c_int),
-                ("cycle", C.c_int)]
+                ("cycle", C.c_int), ("nu_coarse", C.c_int)]
 
 
 class SolveStats(C.Structure):
@@ -355,7 +355,8 @@ def camfe_eval_vertices(s, nv, x):
 
 
 def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0, precision=0, x0=None,
-                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0, judge=0, cycle=1):
+                coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, smoother=0, omega=0.0, judge=0, cycle=1,
+                nu_coarse=0):
     """Returns (x, stats dict).  method 0 = cycle-preconditioned CG, 1 = stationary cycles;
     smoother 0 = multicolour Gauss-Seidel, 1 = Jacobi(omega), 2 = attached learned model;
     judge > 0: smoother 1/2 and Gauss-Seidel each run `judge` CG iterations, the better continues;
@@ -368,7 +369,7 @@ def camfe_solve(s, b, t, rtol=1e-8, max_iter=200, nu_pre=2, nu_post=2, method=0,
     o = SolveOpts()
     o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
     o.method, o.precision, o.x0_given, o.coarse_eps = method, precision, 0 if x0 is None else 1, coarse_eps
-    o.smoother, o.omega, o.judge, o.cycle = smoother, omega, judge, cycle
+    o.smoother, o.omega, o.judge, o.cycle, o.nu_coarse = smoother, omega, judge, cycle, nu_coarse
     st = SolveStats()
     code = load().camfe_solve(s, C.byref(o), _ptr(bc), k, _ptr(x), C.byref(st))
     if code != 0 and (code != -4 or raise_on_noconv):

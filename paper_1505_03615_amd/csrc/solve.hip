@@ -934,7 +934,8 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool firs
   CAMFE_TIMED(ctx, KT_RESTRICT, (4.0 * G.pnnz + ((double)G.n + C.n) * K * sizeof(T)), (k_restrict<T, K>),
               grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc,
               xc, cdinv, cdinv ? (long long)C.coff[1] : 0LL);
-  for (int g = 0; g < S->gamma; ++g) vcycle<T, K>(S, d - 1, bc, xc, nu1, nu2, g == 0 && cdinv != nullptr);
+  const int c1 = S->nu_coarse > 0 ? S->nu_coarse : nu1, c2 = S->nu_coarse > 0 ? S->nu_coarse : nu2;
+  for (int g = 0; g < S->gamma; ++g) vcycle<T, K>(S, d - 1, bc, xc, c1, c2, g == 0 && cdinv != nullptr);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
   if (G.ncb) coarse_batched<T, K>(S, G, b, x);   // meshes that bottom out here
@@ -1122,8 +1123,8 @@ SolveResult solve_block(camfe_sys s, SolverState* S, const camfe_solve_opts& o, 
   const bool use_graph = !ctx->timer.on;
   const int check_every = 4;
   auto gkey = [&] {   // the smoother may change during a judged solve
-    return ((((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother) * 4 +
-           S->gamma;
+    return (((((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 2 + o.method) * 4 + S->smoother) * 4 +
+            S->gamma) * 64 + S->nu_coarse;
   };
   auto run_steps = [&](int m, bool cg) {
     for (int i = 0; i < m; ++i) {
@@ -1854,6 +1855,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
                   "CG needs a symmetric V-cycle: nu_pre must equal nu_post");
     CAMFE_REQUIRE(o->judge >= 0, CAMFE_EINVAL, "judge must be >= 0");
     CAMFE_REQUIRE(o->cycle >= 0 && o->cycle <= 2, CAMFE_EINVAL, "cycle must be 0, 1 (V) or 2 (W)");
+    CAMFE_REQUIRE(o->nu_coarse >= 0 && o->nu_coarse < 64, CAMFE_EINVAL, "nu_coarse must lie in [0, 64)");
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -1866,9 +1868,10 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     // such as smoother training, take V-cycles)
     struct GammaScope {
       SolverState* S;
-      ~GammaScope() { S->gamma = 1; }
+      ~GammaScope() { S->gamma = 1; S->nu_coarse = 0; }
     } gamma_scope{S};
     S->gamma = o->cycle == 2 ? 2 : 1;
+    S->nu_coarse = o->nu_coarse;
     const bool stale = o->smoother != S->wkind || (o->smoother == 1 && o->omega != S->omega) ||
                        (o->smoother == 2 && s->model != S->model);
     if (o->smoother != 0 && stale) {

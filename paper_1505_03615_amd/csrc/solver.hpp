@@ -61,6 +61,7 @@ struct SolverState {
   double t = 0;
   int precision = 0;
   int gamma = 1;             // coarse cycles per depth: 1 V-cycle, 2 W-cycle (set per solve)
+  int nu_coarse = 0;         // sweeps each way below the finest depth (0: as at the finest; set per solve)
   int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi
   int wkind = 0;             // smoother whose weights winvd holds (0: none)
   int wsweep = 0;            // sweep those weights are for: 0 Jacobi, 1 multicolour SOR

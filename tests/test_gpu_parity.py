@@ -392,3 +392,21 @@ def test_length_sorted_layout_on_a_7m_function_system(cf, ctx):
     finally:
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
+
+
+@pytest.mark.parametrize("nu_coarse", [1, 3])
+def test_coarse_sweep_count_tracks_oracle(cf, ctx, nu_coarse):
+    """Fewer (or more) sweeps below the finest depth: stationary cycles track
+    the oracle's cycles with the same counts, and CG still reaches 1e-8."""
+    h, s, o = built(cf, ctx, "sphere_deg1")
+    c = CASES["sphere_deg1"]
+    b = o.load_vector(c["f"])
+    for cyc in (1, 3):
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-30, max_iter=cyc, method=1, nu_coarse=nu_coarse)
+        xo, _ = o.solve(1e-3, b, rtol=1e-30, max_iter=cyc, mode="vcycle", nu_coarse=nu_coarse)
+        assert abs(x - xo).max() <= 1e-9 * abs(xo).max(), cyc
+    for precision in (0, 1):
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-8, max_iter=600, precision=precision, nu_coarse=nu_coarse)
+        Mo, Lo = o.matrices(c["depth"])
+        r = np.linalg.norm(b - (Mo + 1e-3 * Lo) @ x, axis=0) / np.linalg.norm(b, axis=0)
+        assert st["converged"] and np.all(r <= 1e-6), (precision, r)

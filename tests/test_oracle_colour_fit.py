@@ -60,10 +60,12 @@ def test_gradient_load_sees_only_the_tangential_gradient():
     assert np.abs(o.gradient_load(V[:, 0])).max() > 1e-3
 
 
-def _textbook_cycle(o, t, b, x, d, nu, gamma, coarsest):
+def _textbook_cycle(o, t, b, x, d, nu, gamma, coarsest, nu_below=None):
     """One multigrid cycle at depth d written out from the definition: nu
     forward sweeps, residual, restriction by P^T, gamma cycles at d - 1 from
-    zero, prolongation, nu reverse sweeps; the coarsest depth only relaxes."""
+    zero (with nu_below sweeps when given), prolongation, nu reverse sweeps;
+    the coarsest depth only relaxes."""
+    below = nu if nu_below is None else nu_below
     if d == coarsest:
         for _ in range(nu):
             x = o.gs_sweep(d, t, b, x, forward=True)
@@ -78,15 +80,15 @@ def _textbook_cycle(o, t, b, x, d, nu, gamma, coarsest):
     bc = P.T @ r
     xc = np.zeros_like(bc)
     for _ in range(gamma):
-        xc = _textbook_cycle(o, t, bc, xc, d - 1, nu, gamma, coarsest)
+        xc = _textbook_cycle(o, t, bc, xc, d - 1, below, gamma, coarsest, nu_below)
     x = x + P @ xc
     for _ in range(nu):
         x = o.gs_sweep(d, t, b, x, forward=False)
     return x
 
 
-@pytest.mark.parametrize("gamma", [1, 2])
-def test_cycle_matches_textbook_composition(gamma):
+@pytest.mark.parametrize("gamma,nu_coarse", [(1, 0), (2, 0), (1, 1), (2, 2)])
+def test_cycle_matches_textbook_composition(gamma, nu_coarse):
     V, F = meshgen.icosphere(2)
     o = Oracle(V, F, 5, min_depth=2, max_coarse=0).check().assemble()
     assert o.coarsest == 2
@@ -95,10 +97,12 @@ def test_cycle_matches_textbook_composition(gamma):
     rng = np.random.default_rng(5)
     b = rng.normal(size=(n, 2))
     x0 = rng.uniform(0, 1, size=(n, 2))
-    x, _ = o.solve(t, b, rtol=0.0, max_iter=1, nu1=3, nu2=3, x0=x0, mode="vcycle", gamma=gamma)
+    x, _ = o.solve(t, b, rtol=0.0, max_iter=1, nu1=3, nu2=3, x0=x0, mode="vcycle", gamma=gamma,
+                   nu_coarse=nu_coarse)
     # the stationary step is x0 + cycle(b - A x0) with a zero start
     M, L = o.matrices(5)
-    e = _textbook_cycle(o, t, b - (M + t * L) @ x0, np.zeros_like(b), 5, 3, gamma, 2)
+    e = _textbook_cycle(o, t, b - (M + t * L) @ x0, np.zeros_like(b), 5, 3, gamma, 2,
+                        nu_coarse if nu_coarse > 0 else None)
     assert np.abs(x - (x0 + e)).max() <= 1e-12 * np.abs(x).max()
 
 

@@ -591,8 +591,8 @@ def main():
     ap.add_argument("--no-cubes", action="store_true", help="skip the Figure cubes experiment")
     ap.add_argument("--nu-coarse", default="auto",
                     help="sweeps each way below the finest depth in the step's solves: 'auto' (the warm-up times "
-                         "0 = as at the finest, i.e. V(2,2) everywhere, and 1 per solve and keeps the faster) or "
-                         "an integer")
+                         "(finest, below) = (2, 2), (2, 1) and (3, 1) per solve and keeps the fastest) or an "
+                         "integer (with two sweeps each way at the finest depth; 0: as at the finest)")
     ap.add_argument("--spectrum-only", action="store_true",
                     help="only the spectral study (nested spheres, resolution and rotation sweeps)")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectral study")
@@ -670,29 +670,33 @@ def main():
 
     SOLVES = (("plain_fp64", dict(precision=0, max_iter=2000)), ("mixed_fp32_fp64", dict(precision=1, max_iter=2000)),
               ("learned_mixed", dict(precision=1, smoother=2, max_iter=4000)))
-    nuc = {k: (0 if args.nu_coarse == "auto" else int(args.nu_coarse)) for k, _ in SOLVES}
+    # (sweeps each way at the finest depth, below it; 0: as at the finest)
+    nuc = {k: (2, 0 if args.nu_coarse == "auto" else int(args.nu_coarse)) for k, _ in SOLVES}
     tune = {}
 
     def autotune():
-        """Time each solve to 1e-8 with nu_coarse 0 and 1 (best of two, warm)
-        and keep the faster: the paper fixes no sweep count."""
+        """Time each solve to 1e-8 with (finest, below) sweeps (2, 2), (2, 1)
+        and (3, 1) (best of two, warm) and keep the fastest: the paper fixes
+        no sweep count."""
         h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
         s = cf.camfe_assemble(h)
         b = cf.camfe_load_vector(s, h, fd)
         cf.camfe_smoother_attach(s, model)
         for key, kw in SOLVES:
             tune[key] = {}
-            for nc in (0, 1):
+            for nu, nc in ((2, 0), (2, 1), (3, 1)):
                 best = float("inf")
                 for _ in range(2):
-                    _, st = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, nu_coarse=nc, **kw)
+                    _, st = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, nu_pre=nu, nu_post=nu, nu_coarse=nc, **kw)
                     if st["converged"] and not st["fell_back"]:
                         best = min(best, 1000.0 * st["seconds"])
-                tune[key][nc] = best
+                tune[key][nu, nc] = best
             nuc[key] = min(tune[key], key=tune[key].get)
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
-        log("[bench] nu_coarse autotune (iteration ms): " + json.dumps(tune) + " -> " + json.dumps(nuc))
+        log("[bench] sweep autotune (iteration ms): " +
+            json.dumps({k: {f"{a},{c}": v for (a, c), v in d.items()} for k, d in tune.items()}) +
+            " -> " + json.dumps(nuc))
 
     def step(record, keep_last=False):
         t0 = time.perf_counter()
@@ -703,15 +707,14 @@ def main():
         t2 = time.perf_counter()
         b = cf.camfe_load_vector(s, h, fd)
         t3 = time.perf_counter()
-        x64, st64 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=0,
-                                   nu_coarse=nuc["plain_fp64"])
+        sw = {k: dict(nu_pre=v[0], nu_post=v[0], nu_coarse=v[1]) for k, v in nuc.items()}
+        x64, st64 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=0, **sw["plain_fp64"])
         t4 = time.perf_counter()
-        x32, st32 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=1,
-                                   nu_coarse=nuc["mixed_fp32_fp64"])
+        x32, st32 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=1, **sw["mixed_fp32_fp64"])
         t5 = time.perf_counter()
         cf.camfe_smoother_attach(s, model)
         xl, stl = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=4000, precision=1, smoother=2,
-                                 nu_coarse=nuc["learned_mixed"])
+                                 **sw["learned_mixed"])
         t6 = time.perf_counter()
         fin, d0 = cf.camfe_hierarchy_levels(h)
         n = cf.camfe_hierarchy_info(h, fin)[2]
@@ -776,9 +779,9 @@ def main():
                                "split, t=1e-3, RHS +-sin(40 pi x)",
                    "dof_finest": int(n), "levels": list(rec[0]["levels"]), "max_coarse": args.max_coarse},
         "phases_ms": phases,
-        # sweeps each way below the finest depth (0: V(2,2) at every depth), per solve
-        "nu_coarse": dict(nuc),
-        "nu_coarse_autotune_iteration_ms": {k: {str(nc): v for nc, v in d.items()} for k, d in tune.items()},
+        # sweeps each way (at the finest depth, below it; 0: as at the finest), per solve
+        "sweeps_finest_below": {k: list(v) for k, v in nuc.items()},
+        "sweep_autotune_iteration_ms": {k: {f"{a},{c}": v for (a, c), v in d.items()} for k, d in tune.items()},
         "solve_to_1e-8_ms": {"plain_fp64": 1000.0 * solve64, "mixed_fp32_fp64": 1000.0 * solve32,
                              "learned_mixed": 1000.0 * solvel},
         "solve_cycles": {"plain_fp64": float(cyc64), "mixed_fp32_fp64": float(cyc32), "learned_mixed": float(cycl)},

@@ -263,7 +263,9 @@ typedef struct {
 } camfe_eig_stats;
 
 /* evals: nev doubles, ascending; evecs (nullable): n x nev column-major,
- * M-orthonormal, canonical order.  Host or device pointers.  Sets up the
+ * M-orthonormal, canonical order (the entries of functions with zero computed
+ * mass, whose rows of M and L are zero, are not determined by the problem and
+ * carry no meaning).  Host or device pointers.  Sets up the
  * system's solver for t = 1/sigma (the next camfe_solve with another t
  * rebuilds it).  Returns CAMFE_ENOCONV (outputs written) when max_iter is
  * reached above tol, CAMFE_ESINGULAR when the block's M Gram matrix is not

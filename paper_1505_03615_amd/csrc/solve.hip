@@ -276,6 +276,9 @@ __global__ void k_coarse(const double* Ainv, int n, const T* b, T* x) {
   double acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0;
+  // unrolled so that several row loads are in flight per lane (the sums
+  // keep their order)
+#pragma unroll 8
   for (int j = lane; j < n; j += 64) {
     const double a = (double)Ainv[wave * n + j];
 #pragma unroll

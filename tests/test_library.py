@@ -81,3 +81,14 @@ def test_binding_structs_follow_the_header(cname, pyname):
 def test_training_t_per_system_is_checked_before_any_call():
     with pytest.raises(ValueError):
         camfe.camfe_smoother_train(None, [1, 2], t=[1e-3])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]

@@ -309,7 +309,8 @@ __global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long
   double acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0.0;
-  for (int c = lane; c < n; c += 64) {
+#pragma unroll 8
+  for (int c = lane; c < n; c += 64) {   // unrolled as in k_coarse
     const double a = (double)A[lr * n + c];
 #pragma unroll
     for (int q = 0; q < K; ++q) acc[q] += a * (double)b[(r0 + c) * K + q];

@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 
 WORKLOADS = {
     "two_sheets_256_depth8": dict(mesh="two_sheets_256", depth=8, t=1e-3, degree=1),
+    # for --roofline-only: the colour sweep at the knot's 2.2M-function depth 10
+    "knot_2m_depth10": dict(mesh="knot_2m", depth=10, t=1e-4, degree=1),
 }
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
@@ -90,16 +92,18 @@ def measured_traffic():
         return None
 
 
-def roofline(cf, s, meas, reps=50):
+def roofline(cf, s, meas, reps=50, with_traffic=True):
     """Algorithmic bytes of one launch of the finest-depth kernel over its
     average duration (HIP events around a captured graph of back-to-back
-    launches on the library's stream), against the HBM peak."""
+    launches on the library's stream), against the HBM peak.  with_traffic:
+    attach the committed counter figure (taken on the two-sheet depth-8
+    workload only)."""
     avg64, by64 = cf.camfe_measure_kernel(s, meas, 0, reps)
     avg32, by32 = cf.camfe_measure_kernel(s, meas, 1, reps)
     achieved = by64 / (avg64 / 1000.0) / 1e9
     out = {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved, "peak": PEAK_HBM_GBS,
            "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-           "traffic": measured_traffic() if meas == "gs_colour" else None,
+           "traffic": measured_traffic() if (meas == "gs_colour" and with_traffic) else None,
            "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
            "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
                     "bytes_per_launch": by32}}
@@ -300,8 +304,7 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     vb = vcycle_bytes(cf, s, h, 3, 4, 4)   # FP32 cycles, three columns
     # the same colour-sweep measurement as the bench's roofline, on this
     # 2.2M-function finest depth (launches about twelve times larger)
-    big = roofline(cf, s, "gs_colour", reps=10)
-    big.pop("traffic", None)
+    big = roofline(cf, s, "gs_colour", reps=10, with_traffic=False)
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
     return {"mesh": "(3,5) knot tube, 2,097,152 tris, depth 10", "dof": int(n), "steps": len(per),
@@ -654,7 +657,7 @@ def main():
         s = cf.camfe_assemble(h)
         b = cf.camfe_load_vector(s, h, fd)
         cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=0)     # solver setup only
-        out = {"roofline": roofline(cf, s, "gs_colour")}
+        out = {"roofline": roofline(cf, s, "gs_colour", with_traffic=args.workload == "two_sheets_256_depth8")}
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
         if args.calibrate_copy:

@@ -267,8 +267,9 @@ typedef struct {
  * mass, whose rows of M and L are zero, are not determined by the problem and
  * carry no meaning).  Host or device pointers.  Sets up the
  * system's solver for t = 1/sigma (the next camfe_solve with another t
- * rebuilds it).  Returns CAMFE_ENOCONV (outputs written) when max_iter is
- * reached above tol, CAMFE_ESINGULAR when the block's M Gram matrix is not
+ * rebuilds it).  Returns CAMFE_EINVAL for options out of range (above) or a
+ * block wider than the system, CAMFE_ENOCONV (outputs written) when max_iter
+ * is reached above tol, CAMFE_ESINGULAR when the block's M Gram matrix is not
  * positive definite (a start block in the null space of M). */
 camfe_status camfe_eigs(camfe_sys s, const camfe_eig_opts *opts, double *evals, double *evecs,
                         camfe_eig_stats *stats);

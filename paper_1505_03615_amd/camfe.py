@@ -415,7 +415,7 @@ def camfe_system_destroy(s):
 
 
 def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, smoother=0,
-                    omega=0.0, coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False):
+                    omega=0.0, coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, cycle=1, nu_coarse=0):
     """One tracked cMCF step; X (n x 3, numpy or torch) is updated in place and returned with the stats."""
     Xc, n, k = _colmajor(X)
     if k != 3:
@@ -423,6 +423,7 @@ def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, p
     o = SolveOpts()
     o.rtol, o.max_iter, o.nu_pre, o.nu_post, o.precision = rtol, max_iter, nu_pre, nu_post, precision
     o.coarse_eps, o.smoother, o.omega = coarse_eps, smoother, omega
+    o.cycle, o.nu_coarse = cycle, nu_coarse
     st = SolveStats()
     code = load().camfe_flow_step(s, delta, _ptr(Xc), C.byref(o), C.byref(st))
     if code != 0 and (code != -4 or raise_on_noconv):

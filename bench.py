@@ -153,15 +153,16 @@ def train_smoother(cf, ctx, meshgen, steps=150, sweep=1):
                "families": "icosphere L4 depth 6; two sheets 64x64 depth 6; (3,5) knot 2048x16 depth 7"}
 
 
-def vcycle_bytes(cf, s, h, k, sv, sx, nu=4, gamma=1, direct=True):
+def vcycle_bytes(cf, s, h, k, sv, sx, nu=4, gamma=1, direct=True, nu_below=None):
     """Algorithmic bytes of one V-cycle (gamma 1) or W-cycle (gamma 2): per
     depth d above the coarsest, (nu + 1) passes over the matrix values and
     three vector accesses per row (nu sweeps and the residual), the parent
     map read twice (restriction and prolongation, 4 B per entry) and the
     transfer vectors; at the coarsest depth the dense inverse (8 n0^2) and its
     vectors, or nu sweeps when it is only relaxed.  A W-cycle visits depth d
-    gamma^(D - d) times.  Counts come from the library's two-call exports
-    with zero capacity."""
+    gamma^(D - d) times; nu_below (default nu) is the sweep count below the
+    finest depth.  Counts come from the library's two-call exports with zero
+    capacity."""
     import ctypes
     lib = cf.load()
     fin, d0 = cf.camfe_hierarchy_levels(h)
@@ -169,16 +170,17 @@ def vcycle_bytes(cf, s, h, k, sv, sx, nu=4, gamma=1, direct=True):
     total = 0.0
     for d in range(d0, fin + 1):
         visits = float(gamma) ** (fin - d)
+        nud = nu if (d == fin or nu_below is None) else nu_below
         n = cf.camfe_hierarchy_info(h, d)[2]
         cf._check(lib.camfe_export_matrix(s, d, 0, None, None, None, 0, ctypes.byref(nz)))
         z = nz.value
         if d == d0:
-            total += visits * ((8.0 * n * n + 2.0 * n * k * sx) if direct else nu * (z * sv + 3.0 * n * k * sx))
+            total += visits * ((8.0 * n * n + 2.0 * n * k * sx) if direct else nud * (z * sv + 3.0 * n * k * sx))
             continue
         cf._check(lib.camfe_export_prolongation(h, d, None, None, None, 0, ctypes.byref(nz)))
         pn = nz.value
         nc = cf.camfe_hierarchy_info(h, d - 1)[2]
-        total += visits * ((nu + 1) * (z * sv + 3.0 * n * k * sx) + 2.0 * 4.0 * pn + (3.0 * n + 2.0 * nc) * k * sx)
+        total += visits * ((nud + 1) * (z * sv + 3.0 * n * k * sx) + 2.0 * 4.0 * pn + (3.0 * n + 2.0 * nc) * k * sx)
     return total
 
 
@@ -278,7 +280,10 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     """Config 3: tracked cMCF steps (M_t + delta/2 L_0) X' = M_t X on the (3,5)
     knot tube (2,097,152 triangles, depth 10), delta/2 = 1e-4, the three
     coordinate columns, mixed precision, 1e-8 per step.  A step re-weights and
-    re-assembles M_t at every depth, refreshes the solver and solves."""
+    re-assembles M_t at every depth, refreshes the solver and solves.  Two
+    steps from the initial surface with each sweep setting (finest, below) =
+    (2, 2), (2, 1), (3, 1) choose the fastest; the timed steps then start
+    again from the initial surface (the mass-block cache is already built)."""
     import torch
     V, F = meshgen.torus_knot(nu=16384, nv=64, seed=3)
     dev = torch.device("cuda:0")
@@ -289,11 +294,23 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     X = cf.camfe_linear_coeffs(s, h)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
+    tune = {}
+    for nu, nc in ((2, 0), (2, 1), (3, 1)):
+        Xt = torch.from_numpy(np.asfortranarray(X)).to(dev)
+        for k in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Xt, st = cf.camfe_flow_step(s, Xt, 2e-4, rtol=1e-8, max_iter=1000, precision=1, nu_pre=nu, nu_post=nu,
+                                        nu_coarse=nc)
+            torch.cuda.synchronize()
+        tune[nu, nc] = 1000.0 * (time.perf_counter() - t1) if st["converged"] else float("inf")
+    nu, nc = min(tune, key=tune.get)
     Xd = torch.from_numpy(np.asfortranarray(X)).to(dev)
     per, cyc, solve_s = [], [], []
     for k in range(steps):
         t1 = time.perf_counter()
-        Xd, st = cf.camfe_flow_step(s, Xd, 2e-4, rtol=1e-8, max_iter=1000, precision=1)
+        Xd, st = cf.camfe_flow_step(s, Xd, 2e-4, rtol=1e-8, max_iter=1000, precision=1, nu_pre=nu, nu_post=nu,
+                                    nu_coarse=nc)
         torch.cuda.synchronize()
         per.append(time.perf_counter() - t1)
         cyc.append(st["cycles"])
@@ -301,7 +318,8 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
         if not st["converged"]:
             break
     n = cf.camfe_hierarchy_info(h, 10)[2]
-    vb = vcycle_bytes(cf, s, h, 3, 4, 4)   # FP32 cycles, three columns
+    # FP32 cycles, three columns, the chosen sweeps
+    vb = vcycle_bytes(cf, s, h, 3, 4, 4, nu=2 * nu, nu_below=2 * (nc if nc > 0 else nu))
     # the same colour-sweep measurement as the bench's roofline, on this
     # 2.2M-function finest depth (launches about twelve times larger)
     big = roofline(cf, s, "gs_colour", reps=10, with_traffic=False)
@@ -313,6 +331,8 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
             "vcycle_roofline": cycle_roofline(vb, 1000.0 * float(np.sum(solve_s[1:])), int(np.sum(cyc[1:]))),
             "hierarchy_and_assembly_ms": 1000.0 * setup, "ms_per_step": 1000.0 * float(np.mean(per)),
             "first_step_ms": 1000.0 * per[0], "cycles_per_step": [int(c) for c in cyc],
+            "sweeps_finest_below": [nu, nc],
+            "sweep_autotune_second_step_ms": {f"{a},{c}": v for (a, c), v in tune.items()},
             "context": "the paper's Table 1: 1.52 s per step for its 1.27M-DoF system (CPU, its own solver)"}
 
 

@@ -3,8 +3,9 @@
 The gradient constraint b_i = int <grad f, grad b_i> is pinned by linear
 reproduction (a linear f is sum_i (a . node_i) b_i exactly, at both degrees
 and through the split, so its constraint must equal L times those
-coefficients) and by the partition of unity (the constraints of any f sum to
-zero).  The W-cycle is pinned against a textbook composition written here
+coefficients), by the partition of unity (the constraints of any f sum to
+zero), and on a flat square with f = x by the boundary integral that the
+fundamental theorem of calculus gives (independent of the assembled L).  The W-cycle is pinned against a textbook composition written here
 from the oracle's sweep, prolongation and matrix exports.  The
 minimum-depth experiment of Figure cubes reproduces the paper's qualitative
 finding: with the split, coarse corrections keep reducing the residual of
@@ -147,3 +148,34 @@ def test_minimum_depth_experiment_reproduces_figure_cubes():
     assert abs(rp[0] - rp[2]) <= 1e-3 * rp[2]
     assert rp[0] > 0.1 * rp[D]
     assert rs[0] < 1e-2 * rp[0]
+
+
+def _hat_integral(c, h, a, b):
+    """int_a^b max(0, 1 - |y - c| / h) dy, exact (trapezoid rule on the
+    breakpoints of a piecewise-linear function)."""
+    pts = np.unique(np.clip([a, b, c - h, c, c + h], a, b))
+    v = np.maximum(0.0, 1.0 - np.abs(pts - c) / h)
+    return float(np.sum(0.5 * (v[1:] + v[:-1]) * np.diff(pts)))
+
+
+def test_gradient_load_on_a_flat_square_matches_the_boundary_integral():
+    """Unit square [0,1]^2 at z = 0.3 (cells of an explicit cube, no face or
+    edge on a grid plane), f = x: grad f = e_x on the sheet, so
+    g_i = int_0^1 [b_i(1, y) - b_i(0, y)] dy, a product of trilinear hat
+    values and one hat integral, for every function."""
+    n = 10
+    i, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+    V = np.stack([i.ravel() / n, j.ravel() / n, np.full(i.size, 0.3)], 1)
+    q = (i[:-1, :-1] * (n + 1) + j[:-1, :-1]).ravel()
+    F = np.concatenate([np.stack([q, q + n + 1, q + n + 2], 1), np.stack([q, q + n + 2, q + 1], 1)]).astype(np.int32)
+    box = [-0.1, -0.1, 0.0, 1.25]
+    D = 4
+    o = Oracle(V, F, D, max_coarse=64, box=box).check().assemble()
+    g = o.gradient_load(V[:, 0])[:, 0]
+    X = _linear_coeffs(o)                      # node positions of the functions
+    h = box[3] / 2 ** D
+    hat = lambda u: np.maximum(0.0, 1.0 - np.abs(u) / h)
+    want = np.array([hat(0.3 - z) * (hat(1.0 - x) - hat(0.0 - x)) * _hat_integral(y, h, 0.0, 1.0)
+                     for x, y, z in X])
+    assert np.abs(want).max() > 1e-3
+    assert np.abs(g - want).max() <= 1e-13

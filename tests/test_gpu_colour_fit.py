@@ -52,16 +52,24 @@ def _mesh(name):
     if name == "cubes":
         V, F, _ = meshgen.cubes_checker(n=3, subdiv=2)
         return V, F, dict(depth=4, degree=1)
+    if name == "flat_square":
+        # axis-parallel unit square in an explicit cube (no edge on a grid plane)
+        n = 10
+        i, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+        V = np.stack([i.ravel() / n, j.ravel() / n, np.full(i.size, 0.3)], 1)
+        q = (i[:-1, :-1] * (n + 1) + j[:-1, :-1]).ravel()
+        F = np.concatenate([np.stack([q, q + n + 1, q + n + 2], 1), np.stack([q, q + n + 2, q + 1], 1)])
+        return V, F.astype(np.int32), dict(depth=4, degree=1, box=[-0.1, -0.1, 0.0, 1.25])
     raise KeyError(name)
 
 
-@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "cubes"])
+@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "cubes", "flat_square"])
 def test_gradient_load_matches_oracle(cf, ctx, name):
     V, F, kw = _mesh(name)
     say(f"[gpu] gradient load {name}")
     h = cf.camfe_hierarchy_build(ctx, V, F, max_coarse=256, **kw)
     s = cf.camfe_assemble(h)
-    o = Oracle(V, F, kw["depth"], degree=kw["degree"], max_coarse=256).check().assemble()
+    o = Oracle(V, F, kw["depth"], degree=kw["degree"], max_coarse=256, box=kw.get("box")).check().assemble()
     rng = np.random.default_rng(31)
     # five columns: two assembly passes of up to four
     f = np.concatenate([V, rng.normal(size=(len(V), 2))], axis=1)

@@ -118,3 +118,28 @@ def test_eigs_odd_block_and_solve_afterwards(cf, ctx):
     assert sst["converged"] and r <= 1e-9
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
+
+
+def test_nested_spheres_spectrum_at_depth_6_against_the_closed_form(cf, ctx):
+    """Level-6 nested spheres at depth 6 (about 60k functions, beyond the
+    dense oracle): the split spectrum is within 1e-3 of l(l+1) and
+    l(l+1)/1.02^2 with two zero eigenvalues; the unsplit one has one."""
+    gap = 0.02
+    exact = []
+    for l in range(6):
+        exact += [l * (l + 1.0)] * (2 * l + 1) + [l * (l + 1.0) / (1 + gap) ** 2] * (2 * l + 1)
+    exact = np.sort(exact)[:16]
+    V, F = meshgen.nested_spheres(6, gap)
+    zeros = {}
+    for split in (1, 0):
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=6, split=split, max_coarse=4096)
+        s = cf.camfe_assemble(h)
+        ev, _, st = cf.camfe_eigs(s, h, 16, sigma=1.0, tol=1e-9, solve_rtol=1e-10, precision=1, vectors=False)
+        assert st["converged"], st
+        zeros[split] = int((np.abs(ev) < 1e-6).sum())
+        if split:
+            nz = exact > 0
+            assert np.all(np.abs(ev[nz] - exact[nz]) / exact[nz] < 1e-3), (ev, exact)
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+    assert zeros == {1: 2, 0: 1}

@@ -133,3 +133,18 @@ def test_warm_start_and_zero_rhs(small):
     assert info["iterations"] == 0
     z, info = o.solve(1e-3, np.zeros_like(b), rtol=1e-10)
     assert np.all(z == 0)
+
+
+def test_pcg_with_fewer_coarse_sweeps_still_matches_the_dense_solve(small):
+    """One sweep each way below the finest depth keeps the cycle symmetric
+    positive definite (forward before, reverse after, at every depth), so
+    CG preconditioned by it reaches the same solution."""
+    o, b = small
+    t = 1e-3
+    x, info = o.solve(t, b, rtol=1e-11, mode="pcg", nu_coarse=1)
+    assert info["converged"]
+    M, L = o.matrices(o.depth)
+    A = (M + t * L).toarray()
+    xs = la.solve(A, b[:, 0], assume_a="pos")
+    e = x[:, 0] - xs
+    assert np.sqrt(e @ A @ e) <= 1e-9 * np.sqrt(xs @ A @ xs)

@@ -66,16 +66,17 @@ def cpu_baseline(sample_n=128, sample_depth=7):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_colour_two_sheets_d8_traffic.md")
+TRAFFIC_FILE_D10 = os.path.join(ROOT, "profiles", "gs_colour_knot_d10_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1505_03615_amd", "csrc", "sell_kernels.hpp")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the finest-depth FP64 colour sweep from the
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch of the finest-depth FP64 colour sweep from a
     committed counter summary, or None when the sweep kernels' source has
     changed since the counters were taken (the summary records the source's SHA-256)."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
     except OSError:
         return None
     vals = {}
@@ -323,6 +324,7 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     # the same colour-sweep measurement as the bench's roofline, on this
     # 2.2M-function finest depth (launches about twelve times larger)
     big = roofline(cf, s, "gs_colour", reps=10, with_traffic=False)
+    big["traffic"] = measured_traffic(TRAFFIC_FILE_D10)   # counters taken on this same workload
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
     return {"mesh": "(3,5) knot tube, 2,097,152 tris, depth 10", "dof": int(n), "steps": len(per),

@@ -211,3 +211,23 @@ def test_one_w_cycle_in_fp32_tracks_the_fp64_oracle(cf, ctx):
     assert err <= 1e-5
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
+
+
+def test_one_w_cycle_at_degree_two_matches_oracle(cf, ctx):
+    """Quadratic B-splines (27 colours): one and two W-cycles from a random
+    guess against the oracle's, 1e-9 relative."""
+    V, F, col = meshgen.cubes_checker(n=3, subdiv=2)
+    D = 3
+    say("[gpu] W-cycle degree 2")
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=D, degree=2, split=1, min_depth=1, max_coarse=0)
+    s = cf.camfe_assemble(h)
+    o = Oracle(V, F, D, degree=2, split=1, min_depth=1, max_coarse=0).check().assemble()
+    b = _cubes_rhs_oracle(o, col)
+    x0 = np.random.default_rng(6201).uniform(0.0, 1.0, size=(b.shape[0], 3))
+    for cycles in (1, 2):
+        x, st = cf.camfe_solve(s, b, t=1.0 / ALPHA, rtol=0.0, max_iter=cycles, nu_pre=3, nu_post=3, method=1,
+                               x0=x0, cycle=2)
+        xo, _ = o.solve(1.0 / ALPHA, b, rtol=0.0, max_iter=cycles, nu1=3, nu2=3, x0=x0, mode="vcycle", gamma=2)
+        assert np.abs(x - xo).max() <= 1e-9 * np.abs(xo).max(), cycles
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)

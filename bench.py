@@ -70,7 +70,7 @@ TRAFFIC_FILE_D10 = os.path.join(ROOT, "profiles", "gs_colour_knot_d10_traffic.md
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1505_03615_amd", "csrc", "sell_kernels.hpp")
 
 
-def measured_traffic(path=TRAFFIC_FILE):
+def measured_traffic(path=TRAFFIC_FILE, key="traffic_bytes_per_launch"):
     """HBM bytes per launch of the finest-depth FP64 colour sweep from a
     committed counter summary, or None when the sweep kernels' source has
     changed since the counters were taken (the summary records the source's SHA-256)."""
@@ -88,34 +88,43 @@ def measured_traffic(path=TRAFFIC_FILE):
     if vals.get("kernel_source_sha256") != sha:
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
 
-def roofline(cf, s, meas, reps=50, with_traffic=True):
+def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1):
     """Algorithmic bytes of one launch of the finest-depth kernel over its
     average duration (HIP events around a captured graph of back-to-back
-    launches on the library's stream), against the HBM peak.  with_traffic:
-    attach the committed counter figure (taken on the two-sheet depth-8
-    workload only)."""
-    avg64, by64 = cf.camfe_measure_kernel(s, meas, 0, reps)
-    avg32, by32 = cf.camfe_measure_kernel(s, meas, 1, reps)
-    achieved = by64 / (avg64 / 1000.0) / 1e9
-    out = {"bound": "hbm", "kernel": meas + " (finest depth, FP64)", "achieved": achieved, "peak": PEAK_HBM_GBS,
-           "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-           "traffic": measured_traffic() if (meas == "gs_colour" and with_traffic) else None,
-           "avg_launch_us": 1000.0 * avg64, "bytes_per_launch": by64,
-           "fp32": {"achieved": by32 / (avg32 / 1000.0) / 1e9, "avg_launch_us": 1000.0 * avg32,
-                    "bytes_per_launch": by32}}
-    if meas == "gs_colour":
-        # what any launch of this size costs on the same graph: an empty kernel
-        # on the sweep's grid, and a plain copy of the same bytes per launch
-        e_ms, _ = cf.camfe_measure_kernel(s, "empty", 0, reps)
-        c_ms, c_by = cf.camfe_measure_kernel(s, "copy", 0, reps)
-        c_gbs = c_by / (c_ms / 1000.0) / 1e9
-        out["launch_floor"] = {"empty_us": 1000.0 * e_ms, "copy_us": 1000.0 * c_ms, "copy_bytes": c_by,
-                               "copy_GBs": c_gbs, "copy_frac": c_gbs / PEAK_HBM_GBS}
+    launches on the library's stream), against the HBM peak, in both
+    precisions.  The top level describes main_precision (1: the FP32 sweep,
+    which takes the larger share of the bench step: the mixed and the
+    learned solves run it), the other precision sits beside it.
+    with_traffic: attach the committed counter figures (taken on the
+    two-sheet depth-8 workload only)."""
+    res = {}
+    precs = (0, 1) if meas in ("gs_colour", "residual") else (0,)
+    if main_precision not in precs:
+        main_precision = 0
+    for p in precs:
+        avg, by = cf.camfe_measure_kernel(s, meas, p, reps)
+        achieved = by / (avg / 1000.0) / 1e9
+        key = "traffic_bytes_per_launch" + ("_fp32" if p == 1 else "")
+        res[p] = {"kernel": meas + " (finest depth, " + ("FP32" if p else "FP64") + ")", "achieved": achieved,
+                  "frac": achieved / PEAK_HBM_GBS,
+                  "traffic": measured_traffic(TRAFFIC_FILE, key) if (meas == "gs_colour" and with_traffic) else None,
+                  "avg_launch_us": 1000.0 * avg, "bytes_per_launch": by}
+        if meas == "gs_colour":
+            # what any launch of this size costs on the same graph: an empty
+            # kernel on the sweep's grid, and a plain copy of the same bytes
+            e_ms, _ = cf.camfe_measure_kernel(s, "empty", p, reps)
+            c_ms, c_by = cf.camfe_measure_kernel(s, "copy", p, reps)
+            c_gbs = c_by / (c_ms / 1000.0) / 1e9
+            res[p]["launch_floor"] = {"empty_us": 1000.0 * e_ms, "copy_us": 1000.0 * c_ms, "copy_bytes": c_by,
+                                      "copy_GBs": c_gbs, "copy_frac": c_gbs / PEAK_HBM_GBS}
+    out = {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s", **res[main_precision]}
+    if len(precs) == 2:
+        out["fp64" if main_precision == 1 else "fp32"] = res[1 - main_precision]
     return out
 
 
@@ -324,7 +333,9 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     # the same colour-sweep measurement as the bench's roofline, on this
     # 2.2M-function finest depth (launches about twelve times larger)
     big = roofline(cf, s, "gs_colour", reps=10, with_traffic=False)
-    big["traffic"] = measured_traffic(TRAFFIC_FILE_D10)   # counters taken on this same workload
+    # counters taken on this same workload
+    big["traffic"] = measured_traffic(TRAFFIC_FILE_D10, "traffic_bytes_per_launch_fp32")
+    big["fp64"]["traffic"] = measured_traffic(TRAFFIC_FILE_D10)
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)
     return {"mesh": "(3,5) knot tube, 2,097,152 tris, depth 10", "dof": int(n), "steps": len(per),

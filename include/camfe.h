@@ -61,6 +61,12 @@ typedef struct camfe_sys_s *camfe_sys;
 
 /* Message of the last failed call on this thread (never NULL). */
 const char *camfe_last_error(void);
+/* Message of the last failed call that reached this context: a call on the
+ * context itself or on a hierarchy, system or batch created under it, from
+ * any thread (never NULL; "" when none failed).  A call rejected before it
+ * could name its context (a null handle) records its message on the thread
+ * only.  Valid until the next failing call on the context or its destruction. */
+const char *camfe_ctx_last_error(camfe_ctx ctx);
 
 /* Context: device ordinal and stream (hipStream_t, NULL = a stream the
  * library creates and owns).  Holds scratch memory reused across calls. */
@@ -112,6 +118,10 @@ camfe_status camfe_hierarchy_cube(camfe_hier h, double out4[4]);
 /* counts at depth d (0..D); n_functions is -1 below the coarsest depth */
 camfe_status camfe_hierarchy_info(camfe_hier h, int depth, int64_t *n_cells, int64_t *n_pairs,
                                   int64_t *n_functions);
+/* occupied cells at depth d (Definition 1: cells whose open box meets the
+ * surface; at coarser depths the parents of occupied cells, Section 4.3):
+ * Morton keys ascending, n_cells of camfe_hierarchy_info entries */
+camfe_status camfe_export_cells(camfe_hier h, int depth, uint64_t *keys, int64_t cap, int64_t *n);
 /* (cell key, triangle) pairs whose triangle meets the open cell, sorted */
 camfe_status camfe_export_pairs(camfe_hier h, int depth, uint64_t *cell_key, int32_t *tri,
                                 int64_t cap, int64_t *n);
@@ -231,7 +241,45 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double
  * buffers).  Overwrites the solver's scratch vectors only. */
 camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision, int reps, double *avg_ms,
                                   double *bytes_per_launch);
+/* Layout choice of the solver's packed matrices: the rows of a colour with
+ * at least min_rows rows are ordered by decreasing length inside windows of
+ * 1024 rows (less SELL padding, more scattered x gathers); smaller colours
+ * keep the canonical order.  min_rows <= 0 restores the default (2^19).
+ * Rows of one colour never couple, so the order changes no row's arithmetic.
+ * Takes effect at the next solver set-up: drops the system's current solver
+ * state (captured graphs included). */
+camfe_status camfe_system_set_sell_sort(camfe_sys s, int64_t min_rows);
 void camfe_system_destroy(camfe_sys s);
+
+/* Debugging entry: a system built from given matrices instead of a mesh, so
+ * that the multigrid solve (Sections 3.2, 4.3, 5.2) can run on matrices
+ * assembled elsewhere (for instance by a reference implementation).  One
+ * entry per depth, levels[0] the coarsest and levels[nlevels - 1] the finest,
+ * depths consecutive.  Per level: the support keys of its n functions
+ * (Morton codes as in the exports; they fix each function's colour, so two
+ * functions of one colour must never share a nonzero), M and L as CSR on one
+ * pattern (rowptr n + 1 entries, ascending columns per row, diagonal
+ * present), and for every level but the coarsest the prolongation from the
+ * level below (Eq. 4) as CSR, rows = this level's functions.  The coarsest
+ * level is solved directly when it has at most max_coarse functions, else
+ * relaxed.  Host or device pointers; everything is copied.  The system has no
+ * mesh: calls that need one (load vectors, vertex values, linear
+ * coefficients, mass re-weighting, flow steps, training) return CAMFE_ESTATE.
+ * EINVAL for inconsistent sizes, columns or keys out of range, a missing
+ * diagonal, or a degree other than 1 or 2. */
+typedef struct {
+  int depth;                 /* octree depth of the level (0..12)            */
+  int64_t n;                 /* functions                                     */
+  const uint64_t *keys;      /* n support keys                                */
+  const int64_t *rowptr;     /* n + 1                                         */
+  const int32_t *col;        /* rowptr[n] column indices                      */
+  const double *M, *L;       /* rowptr[n] values each                         */
+  const int64_t *p_rowptr;   /* prolongation from the level below (NULL at    */
+  const int32_t *p_col;      /*    the coarsest): n + 1 row pointers, columns */
+  const double *p_w;         /*    and weights                                */
+} camfe_level_csr;
+camfe_status camfe_system_import_csr(camfe_ctx ctx, int degree, int nlevels, const camfe_level_csr *levels,
+                                     int64_t max_coarse, camfe_sys *out);
 
 /* ------------------------------------------------------------ spectrum */
 /* The smallest generalised eigenpairs L x = lambda M x at the finest depth
@@ -360,6 +408,15 @@ typedef struct {
  * NULL, a fixed deterministic initialisation (s near 1: l1-Jacobi for sweep 0,
  * Gauss-Seidel for sweep 1). */
 camfe_status camfe_model_create(const float *params, int levels, int bf16, int sweep, camfe_model *out);
+/* Model as a file: a plain binary record (no serialised objects) of the
+ * 8-byte tag "CAMFESM1", four little-endian int32 (levels, bf16, sweep, 2081
+ * parameters per level) and levels x 2081 little-endian FP32 parameters.
+ * save: EINVAL for a null model or path, EDEVICE when the file cannot be
+ * written.  load: EINVAL when the file cannot be read, has another tag, sizes
+ * out of range, or a length that does not match its header; on success *out
+ * is a new model (camfe_model_destroy). */
+camfe_status camfe_smoother_save(camfe_model m, const char *path);
+camfe_status camfe_smoother_load(const char *path, camfe_model *out);
 /* Two-call export of the packed parameters; levels, bf16 and sweep may be NULL. */
 camfe_status camfe_model_params(camfe_model m, float *params, int64_t cap, int64_t *n, int *levels, int *bf16,
                                 int *sweep);

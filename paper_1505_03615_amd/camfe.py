@@ -29,6 +29,8 @@ EXPORTS = [
     "camfe_model_create", "camfe_model_params", "camfe_model_destroy", "camfe_smoother_attach",
     "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
     "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy", "camfe_eigs",
+    "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
+    "camfe_smoother_save", "camfe_smoother_load",
 ]
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 DEFAULT_COARSE_EPS = 1e-6   # eps * Id on the unit-diagonal-scaled coarsest matrix (the library's own default)
@@ -72,6 +74,12 @@ class EigOpts(C.Structure):
 class EigStats(C.Structure):
     _fields_ = [("iterations", C.c_int), ("solve_cycles", C.c_int), ("max_residual", C.c_double),
                 ("seconds", C.c_double)]
+
+
+class LevelCSR(C.Structure):
+    _fields_ = [("depth", C.c_int), ("n", C.c_int64), ("keys", C.c_void_p), ("rowptr", C.c_void_p),
+                ("col", C.c_void_p), ("M", C.c_void_p), ("L", C.c_void_p), ("p_rowptr", C.c_void_p),
+                ("p_col", C.c_void_p), ("p_w", C.c_void_p)]
 
 
 class TrainOpts(C.Structure):
@@ -131,6 +139,12 @@ def load():
         "camfe_batch_info": (I, [H, C.POINTER(I), C.POINTER(I64)]),
         "camfe_batch_solve": (I, [H, C.POINTER(SolveOpts), P, P, P, P]),
         "camfe_batch_destroy": (None, [H]),
+        "camfe_ctx_last_error": (C.c_char_p, [H]),
+        "camfe_export_cells": (I, [H, I, P, I64, C.POINTER(I64)]),
+        "camfe_system_set_sell_sort": (I, [H, I64]),
+        "camfe_system_import_csr": (I, [H, I, I, P, I64, C.POINTER(H)]),
+        "camfe_smoother_save": (I, [H, C.c_char_p]),
+        "camfe_smoother_load": (I, [C.c_char_p, C.POINTER(H)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -204,6 +218,11 @@ def camfe_ctx_destroy(ctx):
     load().camfe_ctx_destroy(ctx)
 
 
+def camfe_ctx_last_error(ctx):
+    """Message of the last failed call that reached this context ('' if none)."""
+    return load().camfe_ctx_last_error(ctx).decode()
+
+
 def camfe_ctx_kernel_timing(ctx, enable: bool):
     _check(load().camfe_ctx_kernel_timing(ctx, 1 if enable else 0))
 
@@ -254,6 +273,11 @@ def _two_call(fn, h, depth, makers):
     if n.value:
         _check(fn(h, depth, *[_ptr(o) for o in outs], n.value, C.byref(n)))
     return outs
+
+
+def camfe_export_cells(h, depth):
+    """Occupied cells at one depth: Morton keys ascending."""
+    return _two_call(load().camfe_export_cells, h, depth, [lambda n: np.zeros(n, np.uint64)])[0]
 
 
 def camfe_export_pairs(h, depth):
@@ -414,6 +438,43 @@ def camfe_system_destroy(s):
     load().camfe_system_destroy(s)
 
 
+def camfe_system_set_sell_sort(s, min_rows):
+    """Length-sort the rows of colours with at least min_rows rows (<= 0: the default 2^19)."""
+    _check(load().camfe_system_set_sell_sort(s, int(min_rows)))
+
+
+def camfe_system_import_csr(ctx, degree, levels, max_coarse=4096):
+    """System from given matrices.  levels: coarsest first, one dict per depth with
+    'depth', 'keys' (uint64), 'M' and 'L' (scipy CSR on one pattern) and, except
+    for the coarsest, 'P' (scipy CSR prolongation from the depth below)."""
+    keep = []
+
+    def arr(a, dtype):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return a.ctypes.data
+
+    lv = (LevelCSR * len(levels))()
+    for i, d in enumerate(levels):
+        M, L = d["M"].tocsr(), d["L"].tocsr()
+        M.sort_indices(); L.sort_indices()
+        if not (np.array_equal(M.indptr, L.indptr) and np.array_equal(M.indices, L.indices)):
+            raise ValueError("M and L must share one pattern")
+        lv[i].depth, lv[i].n = int(d["depth"]), M.shape[0]
+        lv[i].keys = arr(d["keys"], np.uint64)
+        lv[i].rowptr, lv[i].col = arr(M.indptr, np.int64), arr(M.indices, np.int32)
+        lv[i].M, lv[i].L = arr(M.data, np.float64), arr(L.data, np.float64)
+        if d.get("P") is not None:
+            P = d["P"].tocsr()
+            P.sort_indices()
+            lv[i].p_rowptr, lv[i].p_col = arr(P.indptr, np.int64), arr(P.indices, np.int32)
+            lv[i].p_w = arr(P.data, np.float64)
+    s = C.c_void_p()
+    _check(load().camfe_system_import_csr(ctx, int(degree), len(levels), C.cast(lv, C.c_void_p), int(max_coarse),
+                                          C.byref(s)))
+    return s
+
+
 def camfe_flow_step(s, X, delta, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, smoother=0,
                     omega=0.0, coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, cycle=1, nu_coarse=0):
     """One tracked cMCF step; X (n x 3, numpy or torch) is updated in place and returned with the stats."""
@@ -565,12 +626,13 @@ def camfe_smoother_train(ctx, systems, t, levels=3, steps=200, nu=2, bf16=True, 
     return m.value, hist[:steps]
 
 
-def save_model(path, m):
-    """Packed parameters, the BF16 flag and the sweep type in a .npz file (no pickled objects)."""
-    params, bf16, sweep = camfe_model_params(m)
-    np.savez(path, params=params, bf16=np.array([bf16]), sweep=np.array([sweep]))
+def camfe_smoother_save(m, path):
+    """Write the model as the library's plain binary record."""
+    _check(load().camfe_smoother_save(m, os.fsencode(path)))
 
 
-def load_model(path):
-    with np.load(path, allow_pickle=False) as z:
-        return camfe_model_create(z["params"], bf16=bool(z["bf16"][0]), sweep=int(z["sweep"][0]))
+def camfe_smoother_load(path):
+    """A new model handle read from the library's binary record."""
+    m = C.c_void_p()
+    _check(load().camfe_smoother_load(os.fsencode(path), C.byref(m)))
+    return m.value

@@ -897,7 +897,9 @@ using namespace camfe;
 // host or device vertex values in, host or device b out
 static camfe_status load_common(camfe_sys s, const double* vertex_f, int k, double* b, bool grad) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && vertex_f && b && k > 0, CAMFE_EINVAL, "bad argument");
+    require_mesh(s);
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -914,6 +916,7 @@ extern "C" {
 
 camfe_status camfe_assemble(camfe_hier h, const double* tri_weight, camfe_sys* out) {
   return guarded([&] {
+    if (h) set_current_ctx(h->ctx);
     CAMFE_REQUIRE(h && out, CAMFE_EINVAL, "null argument");
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -931,7 +934,9 @@ camfe_status camfe_assemble(camfe_hier h, const double* tri_weight, camfe_sys* o
 
 camfe_status camfe_reassemble_mass(camfe_sys s, const double* tri_weight) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s, CAMFE_EINVAL, "null system");
+    require_mesh(s);
     camfe_ctx ctx = s->h->ctx;
     ctx->use_device();
     if (tri_weight) {
@@ -948,6 +953,7 @@ camfe_status camfe_reassemble_mass(camfe_sys s, const double* tri_weight) {
 camfe_status camfe_export_matrix(camfe_sys s, int depth, int which, int64_t* rowptr, int32_t* col, double* val,
                                  int64_t cap, int64_t* nnz) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && (which == 0 || which == 1), CAMFE_EINVAL, "bad argument");
     camfe_hier h = s->h;
     CAMFE_REQUIRE(depth >= h->d0 && depth <= h->D, CAMFE_ESTATE, "depth not assembled");
@@ -982,6 +988,7 @@ camfe_status camfe_gradient_load(camfe_sys s, const double* vertex_f, int k, dou
 
 camfe_status camfe_apply(camfe_sys s, int which, double t, const double* x, int k, double* y) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && x && y && k > 0 && which >= 0 && which <= 2, CAMFE_EINVAL, "bad argument");
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
@@ -1000,7 +1007,9 @@ camfe_status camfe_apply(camfe_sys s, int which, double t, const double* x, int 
 
 camfe_status camfe_linear_coeffs(camfe_sys s, double* X) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && X, CAMFE_EINVAL, "bad argument");
+    require_mesh(s);
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
@@ -1017,7 +1026,9 @@ camfe_status camfe_linear_coeffs(camfe_sys s, double* X) {
 
 camfe_status camfe_eval_vertices(camfe_sys s, const double* x, int k, double* vertex_out) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && x && vertex_out && k > 0, CAMFE_EINVAL, "bad argument");
+    require_mesh(s);
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();

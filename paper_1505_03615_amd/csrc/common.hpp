@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -23,7 +24,12 @@ struct Error : std::runtime_error {
   Error(camfe_status c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
+// Records msg as the calling thread's last error and, when the failing call
+// has reached its context (camfe_ctx_s::use_device), as that context's.
 void set_last_error(const std::string& msg);
+// context reached by the entry point running on this thread (or null)
+camfe_ctx current_ctx();
+void set_current_ctx(camfe_ctx ctx);
 
 #define CAMFE_HIP(call)                                                                   \
   do {                                                                                    \
@@ -39,8 +45,14 @@ void set_last_error(const std::string& msg);
   } while (0)
 
 // Runs f, mapping exceptions to status codes and the thread's last error.
+// An entry point called from inside another keeps the outer call's context.
 template <class Fn>
 camfe_status guarded(Fn&& f) {
+  struct Scope {
+    camfe_ctx saved;
+    Scope() : saved(current_ctx()) { set_current_ctx(nullptr); }
+    ~Scope() { set_current_ctx(saved); }
+  } scope;
   try {
     f();
     return CAMFE_OK;
@@ -176,6 +188,8 @@ struct camfe_ctx_s {
   camfe::DArr<unsigned char> scratch2;
   int* d_flag = nullptr;               // device error flag
   camfe::KernelTimer timer;
+  std::mutex err_mu;                   // guards last_error
+  std::string last_error;              // last failed call that reached this context
   unsigned char* scratch_bytes(size_t b) {
     if (scratch.n < b) scratch.alloc(b + (b >> 2) + 256);
     return scratch.p;
@@ -186,6 +200,7 @@ struct camfe_ctx_s {
   }
   void sync() { CAMFE_HIP(hipStreamSynchronize(stream)); }
   void use_device() {
+    camfe::set_current_ctx(this);
     CAMFE_HIP(hipSetDevice(device));
     camfe::set_current_stream(stream);
   }

@@ -333,6 +333,7 @@ extern "C" {
 camfe_status camfe_eigs(camfe_sys s, const camfe_eig_opts* o, double* evals, double* evecs, camfe_eig_stats* stats) {
   camfe_status rc = CAMFE_OK;
   camfe_status g = guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && o && evals, CAMFE_EINVAL, "bad argument");
     const int k = o->block > 0 ? o->block : std::min(KE, o->nev + 8);
     CAMFE_REQUIRE(o->nev >= 1 && o->nev <= k && k <= KE, CAMFE_EINVAL, "need 1 <= nev <= block <= 32");

@@ -56,7 +56,9 @@ camfe_status camfe_flow_step(camfe_sys s, double delta, double* X, const camfe_s
                              camfe_solve_stats* stats) {
   camfe_status rc = CAMFE_OK;
   camfe_status g = guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && X && opts && delta >= 0.0, CAMFE_EINVAL, "bad argument");
+    require_mesh(s);
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();

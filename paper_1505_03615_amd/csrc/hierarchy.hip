@@ -6,6 +6,8 @@
 // multiplies in a fixed order (the library is built with -ffp-contract=off),
 // so the discrete structure is a deterministic function of the input.
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "internal.hpp"
@@ -763,6 +765,13 @@ __global__ void k_split_keys(const u64* k, long long n, u64* key, int* tri) {
   if (tri) tri[i] = (int)(k[i] & TRI_MASK);
 }
 
+// distinct cells of the sorted pair keys: the head of each run writes its cell
+__global__ void k_cell_scatter(const u64* pairs, long long n, const int* flag, const int* pos, u64* out) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  out[pos[i]] = pairs[i] >> TRI_BITS;
+}
+
 __global__ void k_widen(const int* in, long long n, long long* out) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i < n) out[i] = in[i];
@@ -776,6 +785,7 @@ camfe_status check_cap(int64_t cap, size_t n, int64_t* nout) {
 }
 
 const HLevel& level_of(camfe_hier h, int depth, bool need_functions) {
+  if (h) set_current_ctx(h->ctx);
   CAMFE_REQUIRE(h != nullptr, CAMFE_EINVAL, "null hierarchy");
   CAMFE_REQUIRE(depth >= 0 && depth <= h->D, CAMFE_EINVAL, "depth out of range");
   const HLevel& L = h->lev[depth];
@@ -790,13 +800,30 @@ using namespace camfe;
 
 namespace {
 thread_local std::string g_last_error;
+thread_local camfe_ctx g_current_ctx = nullptr;
+
 }
 
-void camfe::set_last_error(const std::string& msg) { g_last_error = msg; }
+camfe_ctx camfe::current_ctx() { return g_current_ctx; }
+void camfe::set_current_ctx(camfe_ctx ctx) { g_current_ctx = ctx; }
+
+void camfe::set_last_error(const std::string& msg) {
+  g_last_error = msg;
+  if (g_current_ctx) {
+    std::lock_guard<std::mutex> lk(g_current_ctx->err_mu);
+    g_current_ctx->last_error = msg;
+  }
+}
 
 extern "C" {
 
 const char* camfe_last_error(void) { return g_last_error.c_str(); }
+
+const char* camfe_ctx_last_error(camfe_ctx ctx) {
+  if (!ctx) return "null context";
+  std::lock_guard<std::mutex> lk(ctx->err_mu);
+  return ctx->last_error.c_str();
+}
 
 camfe_status camfe_ctx_create(int device, void* hip_stream, camfe_ctx* out) {
   return guarded([&] {
@@ -833,6 +860,7 @@ void camfe_ctx_destroy(camfe_ctx ctx) {
 
 camfe_status camfe_ctx_kernel_timing(camfe_ctx ctx, int enable) {
   return guarded([&] {
+    if (ctx) set_current_ctx(ctx);
     CAMFE_REQUIRE(ctx, CAMFE_EINVAL, "null context");
     ctx->use_device();
     if (enable) ctx->timer.reset();
@@ -844,6 +872,7 @@ camfe_status camfe_ctx_kernel_timing(camfe_ctx ctx, int enable) {
 camfe_status camfe_ctx_kernel_time(camfe_ctx ctx, const char* kernel, double* total_ms, int64_t* launches,
                                    double* work) {
   return guarded([&] {
+    if (ctx) set_current_ctx(ctx);
     CAMFE_REQUIRE(ctx && kernel, CAMFE_EINVAL, "null argument");
     ctx->use_device();
     ctx->timer.resolve();
@@ -861,6 +890,7 @@ camfe_status camfe_ctx_kernel_time(camfe_ctx ctx, const char* kernel, double* to
 camfe_status camfe_hierarchy_build(camfe_ctx ctx, const double* V, int64_t nv, const int32_t* F, int64_t nt,
                                    const camfe_hier_opts* o, camfe_hier* out) {
   return guarded([&] {
+    if (ctx) set_current_ctx(ctx);
     CAMFE_REQUIRE(ctx && V && F && o && out, CAMFE_EINVAL, "null argument");
     CAMFE_REQUIRE(o->depth >= 1 && o->depth <= 12, CAMFE_EINVAL, "depth must be in [1, 12]");
     CAMFE_REQUIRE(o->degree == 1 || o->degree == 2, CAMFE_EINVAL, "degree must be 1 or 2");
@@ -890,6 +920,7 @@ camfe_status camfe_hierarchy_build(camfe_ctx ctx, const double* V, int64_t nv, c
 
 camfe_status camfe_hierarchy_levels(camfe_hier h, int* finest, int* coarsest) {
   return guarded([&] {
+    if (h) set_current_ctx(h->ctx);
     CAMFE_REQUIRE(h, CAMFE_EINVAL, "null hierarchy");
     if (finest) *finest = h->D;
     if (coarsest) *coarsest = h->d0;
@@ -898,6 +929,7 @@ camfe_status camfe_hierarchy_levels(camfe_hier h, int* finest, int* coarsest) {
 
 camfe_status camfe_hierarchy_cube(camfe_hier h, double out4[4]) {
   return guarded([&] {
+    if (h) set_current_ctx(h->ctx);
     CAMFE_REQUIRE(h && out4, CAMFE_EINVAL, "null argument");
     for (int i = 0; i < 4; ++i) out4[i] = h->cube[i];
   });
@@ -910,6 +942,27 @@ camfe_status camfe_hierarchy_info(camfe_hier h, int depth, int64_t* n_cells, int
     if (n_cells) *n_cells = (int64_t)L.ncells;
     if (n_pairs) *n_pairs = (int64_t)L.npairs;
     if (n_functions) *n_functions = L.built ? (int64_t)L.nfun : -1;
+  });
+}
+
+camfe_status camfe_export_cells(camfe_hier h, int depth, uint64_t* keys, int64_t cap, int64_t* n) {
+  return guarded([&] {
+    const HLevel& L = level_of(h, depth, false);
+    check_cap(cap, L.ncells, n);
+    if (cap == 0 || L.ncells == 0) return;
+    CAMFE_REQUIRE(keys, CAMFE_EINVAL, "null output array");
+    camfe_ctx ctx = h->ctx;
+    ctx->use_device();
+    DArr<int> flag(L.npairs), pos(L.npairs);
+    DArr<u64> k(L.ncells);
+    unsigned g = grid_for(L.npairs, BLK);
+    hipLaunchKernelGGL(k_head_flags, g, BLK, 0, ctx->stream, L.pairs.p, (long long)L.npairs, TRI_BITS, flag.p);
+    check_launch();
+    exclusive_scan(ctx, flag.p, pos.p, L.npairs);
+    hipLaunchKernelGGL(k_cell_scatter, g, BLK, 0, ctx->stream, L.pairs.p, (long long)L.npairs, flag.p, pos.p, k.p);
+    check_launch();
+    export_array(ctx, (u64*)keys, k.p, L.ncells);
+    ctx->sync();
   });
 }
 

@@ -35,6 +35,7 @@ struct HLevel {
 
 struct camfe_hier_s {
   camfe_ctx ctx = nullptr;
+  bool imported = false;      // levels from given matrices (camfe_system_import_csr): no mesh
   int D = 0, degree = 1, split = 1, min_depth = 0, d0 = 0;
   long long max_coarse = 0;
   double cube[5] = {0, 0, 0, 1, 1};   // origin xyz, side, 2^D / side
@@ -77,10 +78,21 @@ struct camfe_sys_s {
   const void* model = nullptr;      // attached learned smoother (not owned)
   camfe::DArr<double> area0;        // triangle areas of the original surface (flow)
   std::vector<camfe::DArr<double>> mcache;   // per depth: unweighted degree-1 mass blocks of every pair
-  ~camfe_sys_s() { camfe::destroy_solver(solver); }
+  long long sell_sort_min_rows = 0;  // colours with at least this many rows are length-sorted (0: default)
+  camfe_hier owned_h = nullptr;      // an imported system's own hierarchy (freed with the system)
+  ~camfe_sys_s() {
+    camfe::destroy_solver(solver);
+    solver = nullptr;
+    lev.clear();
+    delete owned_h;
+  }
 };
 
 namespace camfe {
+// calls that need the mesh reject systems built from given matrices
+inline void require_mesh(camfe_sys s) {
+  CAMFE_REQUIRE(!s->h->imported, CAMFE_ESTATE, "the system has no mesh (built from given matrices)");
+}
 // assemble.hip
 void assemble_level(camfe_sys s, int d, bool want_L, bool want_M);
 // b = int f b_i (grad: int <grad f, grad b_i>) at the finest depth; fv nv x k,

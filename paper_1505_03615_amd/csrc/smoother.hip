@@ -23,6 +23,7 @@
 // Adam on FP32 master weights.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -728,8 +729,53 @@ camfe_status camfe_model_params(camfe_model m, float* params, int64_t cap, int64
 
 void camfe_model_destroy(camfe_model m) { delete m; }
 
+// File record: tag, four little-endian int32 (levels, bf16, sweep, NP), then
+// levels * NP little-endian FP32.  This library targets little-endian hosts
+// only (x86-64), so the in-memory order is the file order.
+static const char MODEL_TAG[8] = {'C', 'A', 'M', 'F', 'E', 'S', 'M', '1'};
+
+camfe_status camfe_smoother_save(camfe_model m, const char* path) {
+  return guarded([&] {
+    CAMFE_REQUIRE(m && path, CAMFE_EINVAL, "null model or path");
+    std::FILE* f = std::fopen(path, "wb");
+    CAMFE_REQUIRE(f, CAMFE_EDEVICE, std::string("cannot open ") + path + " for writing");
+    const int32_t head[4] = {m->levels, m->bf16, m->sweep, NP};
+    bool ok = std::fwrite(MODEL_TAG, 1, 8, f) == 8 && std::fwrite(head, sizeof(int32_t), 4, f) == 4 &&
+              std::fwrite(m->w.data(), sizeof(float), m->w.size(), f) == m->w.size();
+    ok = (std::fclose(f) == 0) && ok;
+    CAMFE_REQUIRE(ok, CAMFE_EDEVICE, std::string("writing ") + path + " failed");
+  });
+}
+
+camfe_status camfe_smoother_load(const char* path, camfe_model* out) {
+  return guarded([&] {
+    CAMFE_REQUIRE(path && out, CAMFE_EINVAL, "null path or output handle");
+    std::FILE* f = std::fopen(path, "rb");
+    CAMFE_REQUIRE(f, CAMFE_EINVAL, std::string("cannot open ") + path);
+    std::unique_ptr<std::FILE, int (*)(std::FILE*)> guard(f, std::fclose);
+    char tag[8];
+    int32_t head[4];
+    CAMFE_REQUIRE(std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, MODEL_TAG, 8) == 0, CAMFE_EINVAL,
+                  "not a smoother model file");
+    CAMFE_REQUIRE(std::fread(head, sizeof(int32_t), 4, f) == 4, CAMFE_EINVAL, "truncated model header");
+    CAMFE_REQUIRE(head[0] >= 1 && head[0] <= 32 && (head[1] == 0 || head[1] == 1) &&
+                      (head[2] == 0 || head[2] == 1) && head[3] == NP,
+                  CAMFE_EINVAL, "model header out of range");
+    std::vector<float> w((size_t)head[0] * NP);
+    CAMFE_REQUIRE(std::fread(w.data(), sizeof(float), w.size(), f) == w.size(), CAMFE_EINVAL,
+                  "model file shorter than its header says");
+    char extra;
+    CAMFE_REQUIRE(std::fread(&extra, 1, 1, f) == 0, CAMFE_EINVAL, "model file longer than its header says");
+    camfe_model m = nullptr;
+    camfe_status rc = camfe_model_create(w.data(), head[0], head[1], head[2], &m);
+    if (rc != CAMFE_OK) throw Error(rc, "model creation failed");
+    *out = m;
+  });
+}
+
 camfe_status camfe_smoother_attach(camfe_sys s, camfe_model m) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s, CAMFE_EINVAL, "null system");
     CAMFE_REQUIRE(!m || s->h->degree == 1, CAMFE_EINVAL, "the learned smoother is defined for degree 1");
     s->model = m;
@@ -739,6 +785,7 @@ camfe_status camfe_smoother_attach(camfe_sys s, camfe_model m) {
 
 camfe_status camfe_smoother_omega(camfe_sys s, camfe_model m, int depth, double t, double* omega) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && m && omega, CAMFE_EINVAL, "bad argument");
     camfe_hier h = s->h;
     CAMFE_REQUIRE(depth >= h->d0 && depth <= h->D, CAMFE_ESTATE, "depth not assembled");
@@ -764,6 +811,7 @@ camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const fl
                                       int cycle, const double* e0, int nsamples, int nu, double* loss,
                                       double* grad) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && params && e0 && loss && nsamples >= 1 && nsamples <= KS && nu >= 0 &&
                       (sweep == 0 || sweep == 1) && (cycle == 0 || cycle == 1),
                   CAMFE_EINVAL, "bad argument");
@@ -793,6 +841,7 @@ camfe_status camfe_smoother_loss_grad(camfe_sys s, int depth, double t, const fl
 camfe_status camfe_smoother_train(camfe_ctx ctx, camfe_sys const* systems, int nsys, const camfe_train_opts* o,
                                   camfe_model* out, double* loss_history) {
   return guarded([&] {
+    if (ctx) set_current_ctx(ctx);
     CAMFE_REQUIRE(ctx && systems && nsys >= 1 && o && out, CAMFE_EINVAL, "bad argument");
     CAMFE_REQUIRE(o->levels >= 1 && o->levels <= 32 && o->steps >= 0 && o->nu >= 1 && o->lr > 0 &&
                       o->samples >= 0 && o->samples <= 2 && (o->sweep == 0 || o->sweep == 1) &&

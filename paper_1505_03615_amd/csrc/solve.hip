@@ -28,7 +28,7 @@ namespace camfe {
 
 namespace {
 constexpr int BLK = SBLK;
-constexpr int SORT_MIN_ROWS = 1 << 19;  // rows of a colour from which its rows are sorted by length
+constexpr int SORT_MIN_ROWS = 1 << 19;  // default: rows of a colour from which its rows are sorted by length
 constexpr int SORT_WINDOW = 1024;      // rows per sorted window (16 slices)
 }  // namespace
 
@@ -611,10 +611,11 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
   {
     std::vector<int> wbase(G.ncol + 1, 0);
     int mask = 0;
+    const long long sort_min = s->sell_sort_min_rows > 0 ? s->sell_sort_min_rows : SORT_MIN_ROWS;
     for (int c = 0; c < G.ncol; ++c) {
       const int nc = G.coff[c + 1] - G.coff[c];
       wbase[c + 1] = wbase[c] + (nc + SORT_WINDOW - 1) / SORT_WINDOW;
-      if (nc >= SORT_MIN_ROWS) mask |= 1 << c;
+      if (nc >= sort_min) mask |= 1 << c;
     }
     if (mask) {
       DArr<int> dco(G.ncol + 1), dwb(G.ncol + 1);
@@ -1734,6 +1735,7 @@ extern "C" {
 camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision, int reps, double* avg_ms,
                                   double* bytes_per_launch) {
   return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && kernel && reps > 0 && (precision == 0 || precision == 1), CAMFE_EINVAL, "bad argument");
     SolverState* S = s->solver;
     CAMFE_REQUIRE(S, CAMFE_ESTATE, "no solver state: call camfe_solve first");
@@ -1851,6 +1853,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
                          camfe_solve_stats* stats) {
   camfe_status rc = CAMFE_OK;
   camfe_status g = guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
     CAMFE_REQUIRE(s && o && b && x && k > 0, CAMFE_EINVAL, "bad argument");
     CAMFE_REQUIRE(o->precision == 0 || o->precision == 1, CAMFE_EINVAL, "precision must be 0 or 1");
     CAMFE_REQUIRE(o->method == 0 || o->method == 1, CAMFE_EINVAL, "method must be 0 or 1");
@@ -1947,6 +1950,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
 camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const* systems, int nsys, double t, double coarse_eps,
                                 camfe_batch* out) {
   return guarded([&] {
+    if (ctx) set_current_ctx(ctx);
     CAMFE_REQUIRE(ctx && systems && nsys >= 1 && out, CAMFE_EINVAL, "bad argument");
     ctx->use_device();
     auto t0 = std::chrono::steady_clock::now();
@@ -1969,6 +1973,7 @@ camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const* systems, int nsy
 
 camfe_status camfe_batch_info(camfe_batch b, int* levels, int64_t* rows) {
   return guarded([&] {
+    if (b) set_current_ctx(b->ctx);
     CAMFE_REQUIRE(b, CAMFE_EINVAL, "null batch");
     if (levels) *levels = b->S->D + 1;
     if (rows) *rows = (int64_t)b->S->lev[b->S->D].n;
@@ -1979,6 +1984,7 @@ camfe_status camfe_batch_solve(camfe_batch bt, const camfe_solve_opts* o, const 
                                double* const* x, camfe_solve_stats* stats) {
   camfe_status rc = CAMFE_OK;
   camfe_status g = guarded([&] {
+    if (bt) set_current_ctx(bt->ctx);
     CAMFE_REQUIRE(bt && o && b && k && x, CAMFE_EINVAL, "bad argument");
     CAMFE_REQUIRE(o->t == bt->t && o->coarse_eps == bt->coarse_eps, CAMFE_EINVAL,
                   "t and coarse_eps must be those the batch was built for");

@@ -14,6 +14,7 @@ import pytest
 
 from oracle import Oracle
 from paper_1505_03615_amd import meshgen
+from tests.test_oracle_assembly import sheet_fields_coeffs
 from tests.test_oracle_structure import dyadic_sheet
 
 pytestmark = pytest.mark.gpu
@@ -114,7 +115,7 @@ def test_matrices_match(cf, ctx, name):
         assert em <= 1e-12 and el <= 1e-12, (d, em, el)
 
 
-@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "knot", "dyadic"])
+@pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "knot", "dyadic", "sheets_split"])
 def test_load_vector_and_vertex_values(cf, ctx, name):
     h, s, o = built(cf, ctx, name)
     c = CASES[name]
@@ -125,6 +126,18 @@ def test_load_vector_and_vertex_values(cf, ctx, name):
     assert np.array_equal(X, o.linear_coeffs())
     ev = cf.camfe_eval_vertices(s, len(c["V"]), X)
     assert np.allclose(ev, o.eval_vertices(X), rtol=0, atol=1e-13)
+    # coefficients that differ between the components of a split support: a
+    # linear field per half of the triangle list, chosen by each function's
+    # representative triangle (on the two sheets, one field per sheet)
+    _, _, rep = o.functions(c["depth"])
+    fields = np.array([[0.7, -1.3, 0.4], [-0.9, 0.5, 1.6]])
+    xs = sheet_fields_coeffs(X, rep, len(c["F"]) // 2, fields)
+    ev = cf.camfe_eval_vertices(s, len(c["V"]), xs)
+    evo = o.eval_vertices(xs)
+    assert np.allclose(ev, evo, rtol=0, atol=1e-13)
+    if name == "sheets_split":
+        sheet = meshgen.two_sheets(64, 1.0 / 64)[3]
+        assert np.abs(ev[:, 0] - np.einsum("ij,ij->i", c["V"], fields[sheet])).max() <= 1e-13
 
 
 @pytest.mark.parametrize("name", ["sphere_deg1", "sphere_deg2", "sheets_split", "sheets_axis", "knot"])
@@ -150,11 +163,25 @@ def test_solve_residual(cf, ctx, name, precision, method):
         assert np.all(r <= 1e-6), r
         assert st["rel_residual"] <= rtol
     else:
-        # stationary cycles: same contraction as the oracle's over the first cycles
-        xo, io = o.solve(t, b, rtol=1e-30, max_iter=8, mode="vcycle")
-        assert st["iterations"] == iters
+        # stationary cycles: the residual after the same number of cycles as the
+        # oracle's.  FP64 cycles repeat the oracle's arithmetic up to summation
+        # order; FP32 sweeps (with the FP64 residual of every cycle) change each
+        # correction by about 1e-7 relative, and over 60 cycles of contraction
+        # 0.85-0.95 that moves the residual by well under 1 %.
+        xo, io = o.solve(t, b, rtol=1e-30, max_iter=iters, mode="vcycle")
+        assert st["iterations"] == iters and io["iterations"] == iters
         ro = io["history"][-1]
-        assert np.all(r <= 1.0), r
+        rg = float(r.max())
+        tol = 1e-9 if precision == 0 else 1e-2
+        say(f"[gpu] stationary {name} p{precision}: gpu {rg:.6e} oracle {ro:.6e}")
+        # (the singular axis-aligned sheets reach the FP64 rounding floor, about
+        # 1e-16 relative, within the 60 cycles: there both are noise)
+        assert abs(rg - ro) <= tol * ro + 1e-14, (rg, ro)
+        assert ro < io["history"][0]
+        if precision == 0 and name != "sheets_axis":
+            # (the axis-aligned sheets are singular: rounding moves x along the
+            # null space without changing the residual)
+            assert abs(x - xo).max() <= 1e-9 * abs(xo).max()
 
 
 def test_stationary_cycles_track_oracle(cf, ctx):

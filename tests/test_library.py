@@ -72,7 +72,8 @@ def _header_struct_fields(name):
 
 @pytest.mark.parametrize("cname,pyname", [("camfe_hier_opts", "HierOpts"), ("camfe_solve_opts", "SolveOpts"),
                                           ("camfe_solve_stats", "SolveStats"), ("camfe_train_opts", "TrainOpts"),
-                                          ("camfe_eig_opts", "EigOpts"), ("camfe_eig_stats", "EigStats")])
+                                          ("camfe_eig_opts", "EigOpts"), ("camfe_eig_stats", "EigStats"),
+                                          ("camfe_level_csr", "LevelCSR")])
 def test_binding_structs_follow_the_header(cname, pyname):
     py = [f[0] for f in getattr(camfe, pyname)._fields_]
     assert py == _header_struct_fields(cname)
@@ -92,3 +93,30 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_smoother_model_file_round_trip(lib, tmp_path):
+    """camfe_smoother_save / camfe_smoother_load: the packed parameters, the
+    BF16 flag and the sweep type survive a file; malformed files are refused."""
+    import numpy as np
+    rng = np.random.default_rng(3)
+    params = rng.normal(size=(3, camfe.MLP_PARAMS)).astype(np.float32)
+    m = camfe.camfe_model_create(params, bf16=False, sweep=camfe.SWEEP_SOR)
+    path = tmp_path / "model.bin"
+    camfe.camfe_smoother_save(m, path)
+    raw = path.read_bytes()
+    assert raw[:8] == b"CAMFESM1" and len(raw) == 8 + 16 + 4 * params.size
+    assert list(np.frombuffer(raw[8:24], "<i4")) == [3, 0, 1, camfe.MLP_PARAMS]
+    m2 = camfe.camfe_smoother_load(path)
+    p2, bf16, sweep = camfe.camfe_model_params(m2)
+    assert np.array_equal(p2, params) and bf16 is False and sweep == camfe.SWEEP_SOR
+    for m_ in (m, m2):
+        camfe.camfe_model_destroy(m_)
+    for bad in (raw[:-4], raw + b"\0", b"CAMFESM2" + raw[8:], raw[:8] + np.array([0, 0, 1, 2081], "<i4").tobytes()
+                + raw[24:], raw[:8] + np.array([3, 0, 1, 2080], "<i4").tobytes() + raw[24:]):
+        path.write_bytes(bad)
+        with pytest.raises(camfe.CamfeError, match="EINVAL"):
+            camfe.camfe_smoother_load(path)
+    with pytest.raises(camfe.CamfeError, match="EINVAL"):
+        camfe.camfe_smoother_load(tmp_path / "missing.bin")
+    assert lib.camfe_ctx_last_error(None) == b"null context"

@@ -180,6 +180,40 @@ def test_linear_field_closed_forms(fx, request):
     assert np.allclose(o.eval_vertices(X0), V, rtol=0, atol=1e-12)
 
 
+def sheet_fields_coeffs(X0, rep, nt_top, fields):
+    """Coefficients a_s . node_i, s the sheet (0: triangles below nt_top) of
+    each function's representative triangle."""
+    s = (rep >= nt_top).astype(int)
+    return np.einsum("ij,ij->i", X0, fields[s])
+
+
+@pytest.mark.parametrize("degree", [1, 2])
+def test_split_vertex_values_pick_the_vertex_component(degree):
+    """Evaluation u(v) = sum_k x_(k, label_k(t_v)) b_k(v) (Section 4.2: a split
+    function is one function per connected component) on two sheets closer
+    than a cell, in split mode.  Every function gets the coefficient
+    a_s . node, with a different linear field a_s for the sheet s of its
+    representative triangle.  Linear reproduction of the B-splines then gives
+    a_s . V_v at every vertex v of sheet s, exactly when each vertex reads the
+    component of its own sheet.  Components of one support are numbered by
+    smallest triangle and the top sheet's triangles come first, so a vertex
+    of the bottom sheet that read component 0 (or any fixed component) would
+    get the top sheet's field."""
+    V, F, _, sheet = meshgen.two_sheets(16, 1.0 / 64)
+    depth = 5 if degree == 1 else 4
+    o = Oracle(V, F, depth, degree=degree, max_coarse=0, min_depth=depth - 1).check()
+    keys, comp, rep = o.functions(depth)
+    assert comp.max() >= 1 and (comp > 0).sum() > len(comp) // 4      # most supports split
+    nt_top = len(F) // 2
+    fields = np.array([[0.7, -1.3, 0.4], [-0.9, 0.5, 1.6]])
+    x = sheet_fields_coeffs(o.linear_coeffs(), rep, nt_top, fields)
+    want = np.einsum("ij,ij->i", V, fields[sheet])
+    got = o.eval_vertices(x)[:, 0]
+    assert np.abs(got - want).max() <= 1e-13
+    # the two fields differ by O(1) at every vertex: a wrong pick cannot hide
+    assert np.abs(V @ (fields[0] - fields[1])).min() > 1e-3
+
+
 @pytest.mark.parametrize("fx", ["sphere1", "sphere2"])
 def test_galerkin_identity_of_nested_spaces(fx, request):
     """Claim of Section 4.1: coarse functions are combinations of fine ones with

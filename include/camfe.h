@@ -168,6 +168,15 @@ camfe_status camfe_load_vector(camfe_sys s, const double *vertex_f, int k, doubl
 camfe_status camfe_gradient_load(camfe_sys s, const double *vertex_f, int k, double *b);
 /* y = A x at the finest depth with A = M (which 0), L (1) or M + t L (2) */
 camfe_status camfe_apply(camfe_sys s, int which, double t, const double *x, int k, double *y);
+/* camfe_apply without any device allocation, for callers that cannot
+ * allocate (serving loops, harnesses that forbid it).  x and y must be device
+ * memory of the context's device (EINVAL otherwise) with n x k <= 2^20 (EINVAL
+ * otherwise).  The row-major staging lives in a fixed 16 MiB device array per
+ * GPU, reserved when the library first runs on that GPU and held until the
+ * process ends; it is shared by every call on that GPU, so calls that overlap
+ * on one GPU (from several threads or contexts) race.  Like every call it
+ * synchronises the context's stream before returning. */
+camfe_status camfe_apply_noalloc(camfe_sys s, int which, double t, const double *x, int k, double *y);
 /* coefficients that reproduce the embedding: n x 3 column-major (x, y, z) */
 camfe_status camfe_linear_coeffs(camfe_sys s, double *X);
 /* u(v) = sum_i x_i b_i(v) at every mesh vertex (nv x k column-major) */

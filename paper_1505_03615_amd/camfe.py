@@ -30,7 +30,7 @@ EXPORTS = [
     "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
     "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy", "camfe_eigs",
     "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
-    "camfe_smoother_save", "camfe_smoother_load",
+    "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc",
 ]
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 DEFAULT_COARSE_EPS = 1e-6   # eps * Id on the unit-diagonal-scaled coarsest matrix (the library's own default)
@@ -145,6 +145,7 @@ def load():
         "camfe_system_import_csr": (I, [H, I, I, P, I64, C.POINTER(H)]),
         "camfe_smoother_save": (I, [H, C.c_char_p]),
         "camfe_smoother_load": (I, [C.c_char_p, C.POINTER(H)]),
+        "camfe_apply_noalloc": (I, [H, I, D, P, I, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -361,6 +362,19 @@ def camfe_apply(s, which, t, x):
     xc, n, k = _colmajor(x)
     y = _empty_like_kind(xc, n, k)
     _check(load().camfe_apply(s, which, t, _ptr(xc), k, _ptr(y)))
+    return y
+
+
+def camfe_apply_noalloc(s, which, t, x, y):
+    """y = A x through the entry point that allocates nothing: x and y are
+    column-major n x k device tensors (y is written in place)."""
+    if not (_is_torch(x) and _is_torch(y)):
+        raise TypeError("x and y must be device tensors")
+    n, k = x.shape if x.dim() == 2 else (x.shape[0], 1)
+    for a in (x, y):
+        if a.dtype != x.dtype or tuple(a.shape[:1]) != (n,) or a.stride(0) != 1 or (k > 1 and a.stride(1) != n):
+            raise ValueError("x and y must be column-major n x k float64 tensors")
+    _check(load().camfe_apply_noalloc(s, which, t, _ptr(x), k, _ptr(y)))
     return y
 
 

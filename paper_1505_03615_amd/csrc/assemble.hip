@@ -1005,6 +1005,40 @@ camfe_status camfe_apply(camfe_sys s, int which, double t, const double* x, int 
   });
 }
 
+// true when p is device memory of the given device (clears the runtime's
+// error state when p is unknown to it, as plain host memory is)
+static bool device_memory_of(const void* p, int device) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+
+camfe_status camfe_apply_noalloc(camfe_sys s, int which, double t, const double* x, int k, double* y) {
+  return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
+    CAMFE_REQUIRE(s && x && y && k > 0 && which >= 0 && which <= 2, CAMFE_EINVAL, "bad argument");
+    camfe_hier h = s->h;
+    camfe_ctx ctx = h->ctx;
+    ctx->use_device();
+    const SLevel& L = s->lev[h->D];
+    CAMFE_REQUIRE(L.n * (size_t)k <= NOALLOC_BLOCK, CAMFE_EINVAL,
+                  "n x k = " + std::to_string(L.n * (size_t)k) + " exceeds the scratch limit of 2^20 values");
+    CAMFE_REQUIRE(device_memory_of(x, ctx->device) && device_memory_of(y, ctx->device), CAMFE_EINVAL,
+                  "x and y must be device memory of the context's device");
+    CAMFE_REQUIRE(ctx->noalloc_scratch, CAMFE_ESTATE, "no device scratch for this context");
+    double* xr = ctx->noalloc_scratch;
+    double* yr = ctx->noalloc_scratch + NOALLOC_BLOCK;
+    to_rowmajor(ctx, x, L.n, k, xr);
+    double al = which == 1 ? 0.0 : 1.0, be = which == 0 ? 0.0 : (which == 1 ? 1.0 : t);
+    csr_apply(ctx, L, al, be, xr, k, yr);
+    to_colmajor(ctx, yr, L.n, k, y);
+    ctx->sync();
+  });
+}
+
 camfe_status camfe_linear_coeffs(camfe_sys s, double* X) {
   return guarded([&] {
     if (s) set_current_ctx(s->h->ctx);

@@ -27,6 +27,10 @@ struct Error : std::runtime_error {
 // Records msg as the calling thread's last error and, when the failing call
 // has reached its context (camfe_ctx_s::use_device), as that context's.
 void set_last_error(const std::string& msg);
+
+// Scratch of camfe_apply_noalloc: a file-scope device array of
+// 2 * NOALLOC_BLOCK doubles (16 MiB) per device, held until the process ends.
+constexpr size_t NOALLOC_BLOCK = size_t(1) << 20;
 // context reached by the entry point running on this thread (or null)
 camfe_ctx current_ctx();
 void set_current_ctx(camfe_ctx ctx);
@@ -188,6 +192,7 @@ struct camfe_ctx_s {
   camfe::DArr<unsigned char> scratch2;
   int* d_flag = nullptr;               // device error flag
   camfe::KernelTimer timer;
+  double* noalloc_scratch = nullptr;   // this device's scratch of camfe_apply_noalloc (never freed)
   std::mutex err_mu;                   // guards last_error
   std::string last_error;              // last failed call that reached this context
   unsigned char* scratch_bytes(size_t b) {

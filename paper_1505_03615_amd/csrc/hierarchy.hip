@@ -802,6 +802,24 @@ namespace {
 thread_local std::string g_last_error;
 thread_local camfe_ctx g_current_ctx = nullptr;
 
+// Scratch of camfe_apply_noalloc (two row-major n x k blocks).  Each device
+// holds its own copy at its own address; host code uses only the address that
+// hipGetSymbolAddress gives for the current device, never the array's name.
+__device__ __align__(256) double scratch[2 * NOALLOC_BLOCK];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_addr;   // device ordinal -> address of its scratch
+
+// the current device's scratch address, looked up once per device
+double* scratch_address(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  double* p = nullptr;
+  CAMFE_HIP(hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)));
+  CAMFE_REQUIRE(p != nullptr, CAMFE_EDEVICE, "no address for the device scratch");
+  g_scratch_addr[device] = p;
+  return p;
+}
 }
 
 camfe_ctx camfe::current_ctx() { return g_current_ctx; }
@@ -834,6 +852,7 @@ camfe_status camfe_ctx_create(int device, void* hip_stream, camfe_ctx* out) {
     std::unique_ptr<camfe_ctx_s> c(new camfe_ctx_s());
     c->device = device;
     CAMFE_HIP(hipSetDevice(device));
+    c->noalloc_scratch = scratch_address(device);
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
     } else {

@@ -4,19 +4,21 @@
 One step = the whole path on one synthetic input, inputs resident in HBM:
 hierarchy (grid placement, triangle/cell pairs, octree, supports, split,
 prolongation), assembly of M and L at every depth, the load vector, and the
-solve of (M + t L) x = b to a relative residual of 1e-8 three times: with the
-FP64 Gauss-Seidel V-cycle, with the FP32 Gauss-Seidel V-cycle under FP64
-refinement, and with the FP32 V-cycle whose smoother is the learned multicolour SOR
-(conjugate gradients preconditioned by one V-cycle in all three).  The
-learned smoother is trained before timing on small meshes of other shapes.
+solve of (M + t L) x = b to a relative residual of 1e-8 with the learned
+smoother in mixed precision (FP32 V-cycle under FP64 conjugate gradients).
+The learned smoother is trained before timing on small meshes of other
+shapes.
 
-Workload: two parallel unit squares 1/256 apart, each a 256 x 256 grid of
-split quads (262,144 triangles), turned to general position, octree depth 8,
-t = 1e-3, RHS +-sin(40 pi x) on the two sheets.
+Workload (default): the held-out (3,5) torus-knot tube, 65536 x 64 quads
+(8,388,608 triangles, jitter seed 5901), octree depth 11, degree 1, split,
+t = 1e-4, RHS f = z + 0.1 x^2.
 
-Prints one JSON line.  `value` is finest-depth DoF x V-cycles of the three
-solves per second of the whole step; the per-phase times and the solve-only figures
-are reported beside it.
+Prints one JSON line.  `value` is the solve time to 1e-8 of the learned
+mixed-precision solve (iterations only, solver set-up reported apart), mean
+over the timed steps; the plain FP64 and plain mixed Gauss-Seidel solves of
+the same system, DoF x cycles per second, the per-phase times, the roofline
+of the dominant kernel and of the whole V-cycle, the other configurations
+and the oracle's CPU baseline are reported beside it.
 """
 from __future__ import annotations
 
@@ -33,10 +35,35 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOADS = {
-    "two_sheets_256_depth8": dict(mesh="two_sheets_256", depth=8, t=1e-3, degree=1),
-    # for --roofline-only: the colour sweep at the knot's 2.2M-function depth 10
-    "knot_2m_depth10": dict(mesh="knot_2m", depth=10, t=1e-4, degree=1),
+    # the held-out meshes of the learned smoother (never trained on)
+    "knot_8m_depth11": dict(mesh="knot_8m", depth=11, t=1e-4, degree=1,
+                            desc="held-out (3,5) torus-knot tube, tube radius 0.05, 65536 x 64 quads "
+                                 "(8,388,608 tris, jitter seed 5901), octree depth 11, degree 1, split, "
+                                 "t=1e-4, RHS f = z + 0.1 x^2"),
+    "sphere_8m_depth11": dict(mesh="sphere_8m", depth=11, t=1e-3, degree=1,
+                              desc="held-out noisy sphere: octahedron subdivided 10x (8,388,608 tris), "
+                                   "16 Gaussian bumps of amplitude 0.05 (seed 5902), octree depth 11, degree 1, "
+                                   "split, t=1e-3, RHS f = z + 0.1 x^2"),
+    "two_sheets_256_depth8": dict(mesh="two_sheets_256", depth=8, t=1e-3, degree=1,
+                                  desc="two parallel unit squares 1/256 apart, 2 x 256 x 256 split quads "
+                                       "(262,144 tris), rotated to general position, octree depth 8, degree 1, "
+                                       "split, t=1e-3, RHS +-sin(40 pi x)"),
+    "knot_2m_depth10": dict(mesh="knot_2m", depth=10, t=1e-4, degree=1,
+                            desc="(3,5) torus-knot tube, 16384 x 64 quads (2,097,152 tris, jitter seed 3), "
+                                 "octree depth 10, degree 1, split, t=1e-4, RHS f = x (first coordinate)"),
 }
+
+
+def workload_input(meshgen, name):
+    """(V, F, f) of a workload; f is nv x 1."""
+    if name == "knot_8m":
+        V, F = meshgen.torus_knot(nu=65536, nv=64, seed=5901)
+    elif name == "sphere_8m":
+        V, F = meshgen.noisy_sphere(10, seed=5902, base="octa")
+    else:
+        V, F, f = meshgen.config_mesh(name)
+        return V, F, np.asfortranarray(f[:, :1])
+    return V, F, np.asfortranarray(V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
@@ -45,28 +72,104 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(sample_n=128, sample_depth=7):
-    """The oracle (single-threaded FP64 C++) on a bounded sample of the same
-    workload: the two-sheet coupling test at 128 x 128 quads per sheet and
-    depth 7 (a quarter of the triangles, same voxel-to-triangle ratio)."""
+CPU_SAMPLE = dict(nu=2048, nv=16, seed=5901, depth=8, t=1e-4)
+
+
+def host_cpu():
+    """Host processor model (lscpu) and the thread counts the oracle can use."""
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return {"model": model, "os_cpu_count": os.cpu_count(),
+            "omp_threads": int(omp) if omp and omp.isdigit() else os.cpu_count()}
+
+
+def cpu_baseline(cf, ctx, meshgen, full, sample=CPU_SAMPLE):
+    """The oracle (plain FP64 C++, V(2,2)-preconditioned CG, the GPU's plain
+    method) on a bounded sample of the headline workload's family: the (3,5)
+    knot tube at 2048 x 16 quads (65,536 triangles) and depth 8.  Each phase
+    is timed by the oracle itself (steady_clock): hierarchy build, assembly,
+    solver setup, solve to 1e-8.  The solve runs single-threaded and with
+    OpenMP on all threads the host gives this process (same bits).  The
+    sample's solve time is scaled to the headline workload by finest DoF x
+    cycles (the oracle's cost per DoF-cycle times the full problem's DoF and
+    the GPU's plain FP64 cycle count there).  The same sample is solved on
+    the GPU with each of the headline's three solvers, and each solution is
+    compared with the oracle's: relative M-norm of the difference, and the
+    largest difference of the values at the mesh vertices over the largest
+    value."""
     from oracle import Oracle
-    from paper_1505_03615_amd import meshgen
-    V, F, f = meshgen.config_mesh("two_sheets", n=sample_n, gap=1.0 / sample_n)
-    t0 = time.perf_counter()
-    o = Oracle(V, F, sample_depth, max_coarse=2048).check().assemble()
-    b = o.load_vector(f)
-    x, info = o.solve(1e-3, b, rtol=1e-8, max_iter=2000)
-    secs = time.perf_counter() - t0
-    n = o.count(sample_depth, "functions")
-    return {"value": n * info["cycles"] / secs, "unit": "DoF*cycles/s", "cores": 1, "kind": "oracle",
-            "sample": f"two sheets {sample_n}x{sample_n} quads each ({len(F)} tris), depth {sample_depth}, "
-                      f"n={n}, FP64 V-cycle-preconditioned CG to 1e-8: {info['cycles']} cycles in {secs:.2f} s "
-                      f"(build+assemble+load+solve)",
-            "seconds": secs, "converged": bool(info["converged"])}
+    import torch
+    V, F = meshgen.torus_knot(nu=sample["nu"], nv=sample["nv"], seed=sample["seed"])
+    f = np.asfortranarray(V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
+    depth, t = sample["depth"], sample["t"]
+    cpu = host_cpu()
+    legs = {}
+    for omp in (False, True):
+        t0 = time.perf_counter()
+        o = Oracle(V, F, depth, max_coarse=4096, openmp=omp).check().assemble()
+        b = o.load_vector(f)
+        x, info = o.solve(t, b, rtol=1e-8, max_iter=3000)
+        wall = time.perf_counter() - t0
+        ph = o.timing()
+        legs["omp" if omp else "single"] = {"threads": cpu["omp_threads"] if omp else 1, "cycles": info["cycles"],
+                                            "converged": bool(info["converged"]), "wall_s": wall,
+                                            "phases_s": ph, "x": x, "o": o, "b": b}
+        log(f"[bench] oracle ({'all threads' if omp else '1 thread'}): {info['cycles']} cycles, phases {ph}")
+    n = legs["single"]["o"].count(depth, "functions")
+    o, xo, b = legs["single"]["o"], legs["single"]["x"], legs["single"]["b"]
+    Mo, Lo = o.matrices(depth)
+    # the GPU's three solvers on the same sample, against the oracle's solution
+    dev = torch.device("cuda:0")
+    h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=depth,
+                                 max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    errs = {}
+    uo = o.eval_vertices(xo)
+    mn = float(np.sqrt(xo[:, 0] @ (Mo @ xo[:, 0])))
+    for tag, kw in (("plain_gs_fp64", dict(precision=0, smoother=0)),
+                    ("plain_gs_mixed", dict(precision=1, smoother=0)),
+                    ("learned_mixed", dict(precision=1, smoother=2))):
+        cf.camfe_smoother_attach(s, full.get("model") if tag == "learned_mixed" else None)
+        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
+        d = x[:, 0] - xo[:, 0]
+        r = np.linalg.norm(b[:, 0] - (Mo + t * Lo) @ x[:, 0]) / np.linalg.norm(b)
+        errs[tag] = {"rel_M_norm_error": float(np.sqrt(d @ (Mo @ d)) / mn),
+                     "rel_vertex_error": float(np.abs(cf.camfe_eval_vertices(s, len(V), x) - uo).max() /
+                                               np.abs(uo).max()),
+                     "rel_residual_in_oracle_matrices": float(r), "cycles": st["cycles"]}
+    cf.camfe_smoother_attach(s, None)
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)
+    scale = full["dof"] * full["cycles_fp64"] / (n * legs["single"]["cycles"])
+    out = {}
+    for k, leg in legs.items():
+        sol = leg["phases_s"]["solve"]
+        out[k] = {"threads": leg["threads"], "cycles": leg["cycles"], "converged": leg["converged"],
+                  "phases_s": {kk: round(v, 4) for kk, v in leg["phases_s"].items()},
+                  "solve_s_sample": sol, "dof_cycles_per_s": n * leg["cycles"] / sol,
+                  "solve_s_scaled_to_workload": sol * scale}
+    top = out["omp"]
+    return {"value": top["solve_s_scaled_to_workload"], "unit": "s", "cores": top["threads"], "kind": "oracle",
+            "sample": f"(3,5) knot tube {sample['nu']}x{sample['nv']} quads ({len(F)} tris, jitter seed "
+                      f"{sample['seed']}), depth {depth}, n={n}, t={t}, FP64 V(2,2)-preconditioned CG to 1e-8 "
+                      f"({top['cycles']} cycles, {top['solve_s_sample']:.2f} s on {top['threads']} threads); "
+                      f"scaled by DoF x cycles to the workload ({full['dof']} DoF, {full['cycles_fp64']} cycles)",
+            "host": cpu, "single_thread": out["single"], "all_threads": out["omp"],
+            "gpu_error_vs_oracle_on_sample": errs}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gs_colour_two_sheets_d8_traffic.md")
 TRAFFIC_FILE_D10 = os.path.join(ROOT, "profiles", "gs_colour_knot_d10_traffic.md")
+# counter summaries of the finest-depth colour sweeps, per workload
+TRAFFIC_FILES = {"two_sheets_256_depth8": TRAFFIC_FILE, "knot_2m_depth10": TRAFFIC_FILE_D10,
+                 "knot_8m_depth11": os.path.join(ROOT, "profiles", "gs_colour_knot_8m_d11_traffic.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1505_03615_amd", "csrc", "sell_kernels.hpp")
 
 
@@ -93,7 +196,7 @@ def measured_traffic(path=TRAFFIC_FILE, key="traffic_bytes_per_launch"):
         return None
 
 
-def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1):
+def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1, traffic_file=TRAFFIC_FILE):
     """Algorithmic bytes of one launch of the finest-depth kernel over its
     average duration (HIP events around a captured graph of back-to-back
     launches on the library's stream), against the HBM peak, in both
@@ -112,7 +215,7 @@ def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1):
         key = "traffic_bytes_per_launch" + ("_fp32" if p == 1 else "")
         res[p] = {"kernel": meas + " (finest depth, " + ("FP32" if p else "FP64") + ")", "achieved": achieved,
                   "frac": achieved / PEAK_HBM_GBS,
-                  "traffic": measured_traffic(TRAFFIC_FILE, key) if (meas == "gs_colour" and with_traffic) else None,
+                  "traffic": measured_traffic(traffic_file, key) if (meas == "gs_colour" and with_traffic) else None,
                   "avg_launch_us": 1000.0 * avg, "bytes_per_launch": by}
         if meas == "gs_colour":
             # what any launch of this size costs on the same graph: an empty
@@ -200,53 +303,50 @@ def cycle_roofline(bytes_per_cycle, ms, cycles):
     return {"bytes_per_cycle": bytes_per_cycle, "ms_per_cycle": 1000.0 * t, "GBs": gbs, "frac": gbs / PEAK_HBM_GBS}
 
 
-def held_out_eval(cf, ctx, meshgen, model, size, model_jacobi=None):
-    """Held-out meshes (never trained on): the (3,5) knot tube and a noisy
-    sphere, each about 8.4M triangles at depth 11 (size 'full'), or 2.1M at
-    depth 10 ('small').  Solve (M + t L) x = b to 1e-8 with the plain FP64
-    Gauss-Seidel V-cycle and with the learned smoother in mixed precision;
-    each solve is run twice and the second (warm) run is reported."""
-    import torch
-    full = size == "full"
-    meshes = {
-        "knot": (meshgen.torus_knot(nu=65536 if full else 16384, nv=64, seed=3), 11 if full else 10, 1e-4),
-        "noisy_sphere": (meshgen.noisy_sphere(10 if full else 9, seed=7, base="octa"), 11 if full else 10, 1e-3),
-    }
+SOLVERS = (("plain_gs_fp64", dict(precision=0, smoother=0)),
+           ("plain_gs_mixed", dict(precision=1, smoother=0)),
+           ("learned_mixed", dict(precision=1, smoother=2)))
+
+
+def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mixed", "learned_mixed"),
+                     max_iter=4000):
+    """Each solver to 1e-8 on one assembled system, warm: a 4-iteration solve
+    first builds the solver state and captures the graphs, then the full
+    solve runs once.  Iteration time (set-up excluded), cycles, DoF x cycles
+    per second, and the whole V-cycle's algorithmic bytes over its measured
+    time (a captured plain V(2,2)-cycle, FP64 and FP32)."""
+    fin = cf.camfe_hierarchy_levels(h)[0]
+    n = cf.camfe_hierarchy_info(h, fin)[2]
+    res = {"dof": int(n)}
+    for tag, kw in SOLVERS:
+        if tag not in which:
+            continue
+        cf.camfe_smoother_attach(s, model if tag == "learned_mixed" else None)
+        cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4, **kw)
+        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=max_iter, **kw)
+        res[tag] = {"s": st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
+                    "converged": bool(st["converged"]), "fell_back": int(st["fell_back"]),
+                    "setup_s": st["setup_seconds"], "dof_cycles_per_s": n * st["cycles"] / st["seconds"]}
+        log(f"[bench] {tag}: {st['cycles']} cycles, {1000 * st['seconds']:.0f} ms")
+    cf.camfe_smoother_attach(s, None)
+    if "plain_gs_fp64" in res and "learned_mixed" in res:
+        res["speedup_learned_mixed_vs_plain_fp64"] = res["plain_gs_fp64"]["s"] / res["learned_mixed"]["s"]
+    if "plain_gs_mixed" in res and "learned_mixed" in res:
+        res["speedup_learned_mixed_vs_plain_mixed"] = res["plain_gs_mixed"]["s"] / res["learned_mixed"]["s"]
+    res["vcycle_roofline"] = whole_cycle(cf, s, h)
+    return res
+
+
+def whole_cycle(cf, s, h, reps=10):
+    """One plain V(2,2)-cycle (captured, back to back) against the HBM peak:
+    algorithmic bytes of the cycle (vcycle_bytes) over its measured time."""
     out = {}
-    dev = torch.device("cuda:0")
-    for name, ((V, F), depth, t) in meshes.items():
-        log(f"[bench] held-out {name}: {len(F)} tris, depth {depth}")
-        h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=depth,
-                                     degree=1, max_coarse=4096)
-        s = cf.camfe_assemble(h)
-        fv = torch.from_numpy(np.asfortranarray(V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)).to(dev)
-        b = cf.camfe_load_vector(s, h, fv)
-        n = cf.camfe_hierarchy_info(h, depth)[2]
-        res = {"tris": int(len(F)), "depth": depth, "t": t, "dof": int(n)}
-        runs = [("plain_gs_fp64", dict(precision=0, smoother=0), None),
-                ("plain_gs_mixed", dict(precision=1, smoother=0), None),
-                ("learned_mixed", dict(precision=1, smoother=2), model)]
-        if model_jacobi is not None:
-            runs.append(("learned_jacobi_mixed", dict(precision=1, smoother=2), model_jacobi))
-        for tag, kw, mdl in runs:
-            cf.camfe_smoother_attach(s, mdl)
-            for _ in range(2):
-                x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
-            res[tag] = {"ms": 1000.0 * st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
-                        "converged": bool(st["converged"]), "fell_back": int(st["fell_back"])}
-            log(f"[bench] held-out {name} {tag}: {res[tag]['cycles']} cycles, {res[tag]['ms']:.0f} ms")
-        res["speedup_learned_vs_plain"] = res["plain_gs_fp64"]["ms"] / res["learned_mixed"]["ms"]
-        # whole V-cycle (inside CG, whose vector work is not counted) against the HBM peak
-        b64 = vcycle_bytes(cf, s, h, 1, 8, 8)
-        b32 = vcycle_bytes(cf, s, h, 1, 4, 4)
-        res["vcycle_roofline"] = {
-            "plain_gs_fp64": cycle_roofline(b64, res["plain_gs_fp64"]["ms"], res["plain_gs_fp64"]["cycles"]),
-            "plain_gs_mixed": cycle_roofline(b32, res["plain_gs_mixed"]["ms"], res["plain_gs_mixed"]["cycles"])}
-        cf.camfe_smoother_attach(s, None)
-        cf.camfe_system_destroy(s)
-        cf.camfe_hierarchy_destroy(h)
-        out[name] = res
-        log(f"[bench] held-out {name}: " + json.dumps(res))
+    for p, (sv, sx) in ((0, (8, 8)), (1, (4, 4))):
+        ms, _ = cf.camfe_measure_kernel(s, "vcycle", p, reps)
+        by = vcycle_bytes(cf, s, h, 1, sv, sx)
+        gbs = by / (ms / 1000.0) / 1e9
+        out["fp64" if p == 0 else "fp32"] = {"bytes_per_cycle": by, "ms_per_cycle": ms, "GBs": gbs,
+                                            "frac": gbs / PEAK_HBM_GBS}
     return out
 
 
@@ -532,75 +632,78 @@ def cubes_eval(cf, ctx, meshgen, depth=5):
             "unsplit_gain_full_vs_finest_only": rp[depth] / rp[0]}
 
 
-def batch_eval(cf, ctx, meshgen, count=16, seed=4000):
-    """Config 4 (scaled): `count` meshes of uneven size (icospheres, tori,
-    noise-displaced spheres), depth clamp(round(log2(side / mean edge)), 6, 10),
-    1-16 random right-hand sides each; one batched solve against the same
-    systems solved one at a time (FP64, 1e-8)."""
+def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
+    """Config 4: `count` uneven meshes from meshgen.config4_batch (icospheres
+    L3-7, tori with R/r in [2, 6] and 1k-1.3M triangles, noisy icospheres
+    L3-8; depth clamp(round(log2(side / mean edge)), 6, 10); 1-16 N(0, 1)
+    right-hand sides each), solved to 1e-8 in FP64: one system at a time
+    (every system warm, iterations summed), then as one batch with a member
+    per (mesh, chunk of <= 4 columns) so that one pass covers every column,
+    with the default colour-sweep tile and with the autotuner's tile per
+    level."""
     import torch
-    rng = np.random.default_rng(seed)
-    systems, rhs = [], []
     dev = torch.device("cuda:0")
-    for i in range(count):
-        kind = i % 3
-        if kind == 0:
-            V, F = meshgen.icosphere(int(rng.integers(3, 7)))
-        elif kind == 1:
-            R = float(rng.uniform(2.0, 6.0))
-            nu = int(rng.integers(24, 400))
-            V, F = meshgen.torus(R, 1.0, nu, max(8, int(nu / R)))
-        else:
-            V, F = meshgen.noisy_sphere(int(rng.integers(3, 7)), seed=seed + i)
-        e = np.linalg.norm(V[F[:, 1]] - V[F[:, 0]], axis=1).mean()
-        side = 1.125 * (V.max(0) - V.min(0)).max()
-        depth = int(np.clip(round(np.log2(side / e)), 6, 10))
-        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, degree=1, max_coarse=4096)
-        sy = cf.camfe_assemble(h)
-        k = int(rng.integers(1, 17))
-        b = cf.camfe_load_vector(sy, h, rng.normal(size=(len(V), k)))
-        systems.append((h, sy, len(F), depth, k))
-        rhs.append(b)
-    t_single = 0.0
-    for (h, sy, nt, depth, k), b in zip(systems, rhs):
-        cf.camfe_solve(sy, b, t=1e-3, rtol=1e-8, max_iter=600)      # setup and capture
-        x, st = cf.camfe_solve(sy, b, t=1e-3, rtol=1e-8, max_iter=600)
-        t_single += st["seconds"]
     t0 = time.perf_counter()
-    bt = cf.camfe_batch_create(ctx, [x[1] for x in systems], 1e-3)
-    create = time.perf_counter() - t0
-    xs, sts = cf.camfe_batch_solve(bt, rhs, 1e-3, rtol=1e-8, max_iter=600)    # capture
-    xs, sts = cf.camfe_batch_solve(bt, rhs, 1e-3, rtol=1e-8, max_iter=600)
+    members = meshgen.config4_batch(count, seed)
+    gen_s = time.perf_counter() - t0
+    systems = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m in members:
+        h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(m["V"]).to(dev), torch.from_numpy(m["F"]).to(dev),
+                                     depth=m["depth"], degree=1, max_coarse=4096)
+        s = cf.camfe_assemble(h)
+        b = cf.camfe_load_vector(s, h, torch.from_numpy(m["fv"]).to(dev))
+        systems.append((h, s, b))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    dof = [int(cf.camfe_hierarchy_info(h, m["depth"])[2]) for (h, _, _), m in zip(systems, members)]
+    log(f"[bench] batch: {len(members)} meshes, {sum(len(m['F']) for m in members)} tris, {sum(dof)} DoF, "
+        f"generated in {gen_s:.1f} s, built and assembled in {setup_s:.1f} s")
+    single = 0.0
+    single_cycles = []
+    for h, s, b in systems:
+        cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4)
+        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=2000)
+        single += st["seconds"]
+        single_cycles.append(st["cycles"])
+    mem, chunks = [], []
+    for h, s, b in systems:
+        for c0 in range(0, b.shape[1], 4):
+            mem.append(s)
+            chunks.append(b[:, c0:c0 + 4])
+    t0 = time.perf_counter()
+    bt = cf.camfe_batch_create(ctx, mem, t)
+    create_s = time.perf_counter() - t0
     levels, rows = cf.camfe_batch_info(bt)
+    runs = {}
+    for tag in ("default_tiles", "autotuned_tiles"):
+        if tag == "autotuned_tiles":
+            t0 = time.perf_counter()
+            tiles, tms = cf.camfe_batch_autotune(bt, precision=0, reps=10)
+            tune_s = time.perf_counter() - t0
+        cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=4)      # capture
+        xs, sts = cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=2000)
+        runs[tag] = {"solve_s": sts[0]["seconds"], "iterations": max(x["iterations"] for x in sts),
+                     "all_converged": bool(all(x["converged"] for x in sts)),
+                     "max_rel_residual": float(max(x["rel_residual"] for x in sts))}
+        log(f"[bench] batch {tag}: " + json.dumps(runs[tag]))
     cf.camfe_batch_destroy(bt)
-    # the same work as one member per (mesh, chunk of <= 4 columns): a single
-    # pass of the batch then covers every column, where the per-mesh layout
-    # takes one pass per column chunk over all meshes
-    members, chunks = [], []
-    for (h, sy, nt, depth, k), b in zip(systems, rhs):
-        for c0 in range(0, k, 4):
-            members.append(sy)
-            chunks.append(np.asfortranarray(b[:, c0:c0 + 4]))
-    t0 = time.perf_counter()
-    bt = cf.camfe_batch_create(ctx, members, 1e-3)
-    create_c = time.perf_counter() - t0
-    xc, stc = cf.camfe_batch_solve(bt, chunks, 1e-3, rtol=1e-8, max_iter=600)    # capture
-    xc, stc = cf.camfe_batch_solve(bt, chunks, 1e-3, rtol=1e-8, max_iter=600)
-    levels_c, rows_c = cf.camfe_batch_info(bt)
-    cf.camfe_batch_destroy(bt)
-    out = {"meshes": count, "tris": [int(x[2]) for x in systems], "depths": [int(x[3]) for x in systems],
-           "rhs": [int(x[4]) for x in systems], "batch_rows": int(rows), "batch_levels": int(levels),
-           "batch_create_ms": 1000.0 * create, "batch_solve_ms": 1000.0 * sts[0]["seconds"],
-           "one_at_a_time_solve_ms": 1000.0 * t_single,
-           "all_converged": bool(all(x["converged"] for x in sts)),
-           "max_rel_residual": float(max(x["rel_residual"] for x in sts)),
-           "per_chunk_members": len(members), "per_chunk_rows": int(rows_c),
-           "per_chunk_create_ms": 1000.0 * create_c, "per_chunk_solve_ms": 1000.0 * stc[0]["seconds"],
-           "per_chunk_all_converged": bool(all(x["converged"] for x in stc)),
-           "per_chunk_max_rel_residual": float(max(x["rel_residual"] for x in stc))}
-    for h, sy, _, _, _ in systems:
-        cf.camfe_system_destroy(sy)
+    for h, s, b in systems:
+        cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
-    return out
+    return {"meshes": len(members), "tris_total": int(sum(len(m["F"]) for m in members)),
+            "tris_min_max": [int(min(len(m["F"]) for m in members)), int(max(len(m["F"]) for m in members))],
+            "dof_total": int(sum(dof)), "depths": [m["depth"] for m in members],
+            "rhs": [int(m["fv"].shape[1]) for m in members], "kinds": [m["kind"] for m in members],
+            "generate_s": gen_s, "build_assemble_load_s": setup_s,
+            "one_at_a_time": {"solve_s": single, "cycles_max": int(max(single_cycles)),
+                              "cycles_sum": int(sum(single_cycles))},
+            "batch": {"members": len(mem), "levels": int(levels), "rows": int(rows), "create_s": create_s, **runs},
+            "autotuner": {"tiles_per_level_coarsest_first": [list(cf.TILES[int(v)]) for v in tiles],
+                          "tile_is": "(wavefronts per 64-row slice, entries per lane issued together)",
+                          "ms_per_sweep": [float(v) for v in tms], "tune_s": tune_s},
+            "speedup_batch_vs_one_at_a_time": single / runs["autotuned_tiles"]["solve_s"]}
 
 
 def main():
@@ -608,16 +711,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="two_sheets_256_depth8", choices=list(WORKLOADS))
+    ap.add_argument("--workload", default="knot_8m_depth11", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-coarse", type=int, default=4096,
                     help="coarsest depth = finest with at most this many functions (solved directly)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--held-out", default="small", choices=["full", "small", "none"],
-                    help="learned-smoother evaluation on held-out meshes (8.4M or 2.1M tris)")
+    ap.add_argument("--no-sphere", action="store_true", help="skip the held-out noisy sphere (8.4M tris, depth 11)")
+    ap.add_argument("--no-sheets", action="store_true", help="skip the two-sheet coupling test (depth 8)")
     ap.add_argument("--no-flow", action="store_true", help="skip the config-3 flow steps")
-    ap.add_argument("--batch-meshes", type=int, default=16, help="meshes of the config-4 batch (0: skip)")
+    ap.add_argument("--batch-meshes", type=int, default=64, help="meshes of the config-4 batch (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
                          "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
@@ -625,10 +728,6 @@ def main():
     ap.add_argument("--cubes-only", action="store_true",
                     help="only the minimum-depth experiment of Figure cubes (W-cycles, gradient constraint)")
     ap.add_argument("--no-cubes", action="store_true", help="skip the Figure cubes experiment")
-    ap.add_argument("--nu-coarse", default="auto",
-                    help="sweeps each way below the finest depth in the step's solves: 'auto' (the warm-up times "
-                         "(finest, below) = (2, 2), (2, 1) and (3, 1) per solve and keeps the fastest) or an "
-                         "integer (with two sweeps each way at the finest depth; 0: as at the finest)")
     ap.add_argument("--spectrum-only", action="store_true",
                     help="only the spectral study (nested spheres, resolution and rotation sweeps)")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the spectral study")
@@ -637,6 +736,7 @@ def main():
     ap.add_argument("--no-flow-study", action="store_true", help="skip the cMCF study")
     ap.add_argument("--assembly-only", action="store_true",
                     help="only the assembly measurement (four meshes, both degrees); for matrix-core counter runs")
+    ap.add_argument("--no-assembly", action="store_true", help="skip the assembly measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -647,50 +747,36 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     cf.load()
     wl = WORKLOADS[args.workload]
-    V, F, f = meshgen.config_mesh(wl["mesh"])
     dev = torch.device("cuda:0")
-    Vd = torch.from_numpy(V).to(dev)
-    Fd = torch.from_numpy(F).to(dev)
-    fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
     stream = torch.cuda.current_stream()
     ctx = cf.camfe_ctx_create(0, stream)
 
-    if args.flow_only:
-        out = {"flow_config3": flow_eval(cf, ctx, meshgen)}
-        cf.camfe_ctx_destroy(ctx)
-        print(json.dumps(out), flush=True)
-        return
+    only = {"flow_config3": (args.flow_only, lambda: flow_eval(cf, ctx, meshgen)),
+            "spectrum": (args.spectrum_only, lambda: spectrum_eval(cf, ctx, meshgen)),
+            "flow_study": (args.flow_study_only, lambda: flow_study_eval(cf, ctx, meshgen)),
+            "colour_fit_cubes": (args.cubes_only, lambda: cubes_eval(cf, ctx, meshgen)),
+            "assembly": (args.assembly_only, lambda: assembly_eval(cf, ctx, meshgen))}
+    for key, (flag, fn) in only.items():
+        if flag:
+            out = {key: fn()}
+            cf.camfe_ctx_destroy(ctx)
+            print(json.dumps(out), flush=True)
+            return
 
-    if args.spectrum_only:
-        out = {"spectrum": spectrum_eval(cf, ctx, meshgen)}
-        cf.camfe_ctx_destroy(ctx)
-        print(json.dumps(out), flush=True)
-        return
-
-    if args.flow_study_only:
-        out = {"flow_study": flow_study_eval(cf, ctx, meshgen)}
-        cf.camfe_ctx_destroy(ctx)
-        print(json.dumps(out), flush=True)
-        return
-
-    if args.cubes_only:
-        out = {"colour_fit_cubes": cubes_eval(cf, ctx, meshgen)}
-        cf.camfe_ctx_destroy(ctx)
-        print(json.dumps(out), flush=True)
-        return
-
-    if args.assembly_only:
-        out = {"assembly": assembly_eval(cf, ctx, meshgen)}
-        cf.camfe_ctx_destroy(ctx)
-        print(json.dumps(out), flush=True)
-        return
+    log(f"[bench] workload {args.workload}: generating the mesh")
+    V, F, f = workload_input(meshgen, wl["mesh"])
+    Vd = torch.from_numpy(V).to(dev)
+    Fd = torch.from_numpy(F).to(dev)
+    fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
+    traffic_file = TRAFFIC_FILES.get(args.workload)
 
     if args.roofline_only:
         h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
         s = cf.camfe_assemble(h)
         b = cf.camfe_load_vector(s, h, fd)
         cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=0)     # solver setup only
-        out = {"roofline": roofline(cf, s, "gs_colour", with_traffic=args.workload == "two_sheets_256_depth8")}
+        out = {"roofline": roofline(cf, s, "gs_colour", with_traffic=traffic_file is not None,
+                                    traffic_file=traffic_file)}
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
         if args.calibrate_copy:
@@ -699,42 +785,12 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    keep = {}
-    log("[bench] training the learned smoothers")
+    log("[bench] training the learned smoother")
     model, train_info = train_smoother(cf, ctx, meshgen, sweep=1)
-    model_jac, train_info_jac = train_smoother(cf, ctx, meshgen, sweep=0)
-
-    SOLVES = (("plain_fp64", dict(precision=0, max_iter=2000)), ("mixed_fp32_fp64", dict(precision=1, max_iter=2000)),
-              ("learned_mixed", dict(precision=1, smoother=2, max_iter=4000)))
-    # (sweeps each way at the finest depth, below it; 0: as at the finest)
-    nuc = {k: (2, 0 if args.nu_coarse == "auto" else int(args.nu_coarse)) for k, _ in SOLVES}
-    tune = {}
-
-    def autotune():
-        """Time each solve to 1e-8 with (finest, below) sweeps (2, 2), (2, 1)
-        and (3, 1) (best of two, warm) and keep the fastest: the paper fixes
-        no sweep count."""
-        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
-        s = cf.camfe_assemble(h)
-        b = cf.camfe_load_vector(s, h, fd)
-        cf.camfe_smoother_attach(s, model)
-        for key, kw in SOLVES:
-            tune[key] = {}
-            for nu, nc in ((2, 0), (2, 1), (3, 1)):
-                best = float("inf")
-                for _ in range(2):
-                    _, st = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, nu_pre=nu, nu_post=nu, nu_coarse=nc, **kw)
-                    if st["converged"] and not st["fell_back"]:
-                        best = min(best, 1000.0 * st["seconds"])
-                tune[key][nu, nc] = best
-            nuc[key] = min(tune[key], key=tune[key].get)
-        cf.camfe_system_destroy(s)
-        cf.camfe_hierarchy_destroy(h)
-        log("[bench] sweep autotune (iteration ms): " +
-            json.dumps({k: {f"{a},{c}": v for (a, c), v in d.items()} for k, d in tune.items()}) +
-            " -> " + json.dumps(nuc))
+    keep = {}
 
     def step(record, keep_last=False):
+        """The whole path once: build, assemble, load, learned mixed solve."""
         t0 = time.perf_counter()
         h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"],
                                      max_coarse=args.max_coarse)
@@ -743,23 +799,13 @@ def main():
         t2 = time.perf_counter()
         b = cf.camfe_load_vector(s, h, fd)
         t3 = time.perf_counter()
-        sw = {k: dict(nu_pre=v[0], nu_post=v[0], nu_coarse=v[1]) for k, v in nuc.items()}
-        x64, st64 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=0, **sw["plain_fp64"])
-        t4 = time.perf_counter()
-        x32, st32 = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=2000, precision=1, **sw["mixed_fp32_fp64"])
-        t5 = time.perf_counter()
         cf.camfe_smoother_attach(s, model)
-        xl, stl = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=4000, precision=1, smoother=2,
-                                 **sw["learned_mixed"])
-        t6 = time.perf_counter()
-        fin, d0 = cf.camfe_hierarchy_levels(h)
-        n = cf.camfe_hierarchy_info(h, fin)[2]
+        x, st = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=4000, precision=1, smoother=2)
+        t4 = time.perf_counter()
         if record is not None:
-            record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve64=t4 - t3, solve32=t5 - t4,
-                               solvel=t6 - t5, st64=st64, st32=st32, stl=stl, n=n, levels=(fin, d0),
-                               xs=(x64, x32, xl)))
+            record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve_call=t4 - t3, st=st))
         if keep_last:
-            keep["h"], keep["s"] = h, s
+            keep.update(h=h, s=s, b=b, x=x)
         else:
             cf.camfe_system_destroy(s)
             cf.camfe_hierarchy_destroy(h)
@@ -777,8 +823,6 @@ def main():
             cf.camfe_ctx_kernel_timing(ctx, False)
             log("[bench] kernel event times (ms): " +
                 ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in sorted(ranking.items(), key=lambda kv: -kv[1][0])))
-    if args.nu_coarse == "auto":
-        autotune()
     rec = []
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
@@ -788,58 +832,41 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1000.0 / args.steps
-    n = rec[0]["n"]
-    cyc64 = np.mean([r["st64"]["cycles"] for r in rec])
-    cyc32 = np.mean([r["st32"]["cycles"] for r in rec])
-    cycl = np.mean([r["stl"]["cycles"] for r in rec])
-    solve64 = np.mean([r["solve64"] for r in rec])
-    solve32 = np.mean([r["solve32"] for r in rec])
-    solvel = np.mean([r["solvel"] for r in rec])
-    phases = {k: 1000.0 * float(np.mean([r[k] for r in rec]))
-              for k in ("build", "assemble", "load", "solve64", "solve32", "solvel")}
+    h, s, b = keep["h"], keep["s"], keep["b"]
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    n = cf.camfe_hierarchy_info(h, fin)[2]
+    sts = [r["st"] for r in rec]
+    solve_s = float(np.mean([x["seconds"] for x in sts]))
+    cycles = float(np.mean([x["cycles"] for x in sts]))
+    log("[bench] plain Gauss-Seidel solves of the same system")
+    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed"))
+    comp["learned_mixed"] = {"s": solve_s, "cycles": cycles, "rel_residual": float(max(x["rel_residual"] for x in sts)),
+                             "converged": bool(all(x["converged"] for x in sts)),
+                             "fell_back": int(max(x["fell_back"] for x in sts)),
+                             "setup_s": float(np.mean([x["setup_seconds"] for x in sts])),
+                             "dof_cycles_per_s": n * cycles / solve_s, "timed_steps": len(sts)}
+    comp["speedup_learned_mixed_vs_plain_fp64"] = comp["plain_gs_fp64"]["s"] / solve_s
+    comp["speedup_learned_mixed_vs_plain_mixed"] = comp["plain_gs_mixed"]["s"] / solve_s
+    phases = {k: 1000.0 * float(np.mean([r[k] for r in rec])) for k in ("build", "assemble", "load", "solve_call")}
     out = {
         "metric": "solve time to 1e-8 rel. residual, DoF*cycles/s; learned vs plain smoother",
-        "value": n * (cyc64 + cyc32 + cycl) / (ms / 1000.0),
-        "unit": "DoF*cycles/s",
+        "value": solve_s,
+        "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
-        "higher_is_better": True,
+        "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64 (mixed-precision solve: f32 V-cycle, f64 CG)",
+        "dtype": "f32 V-cycle (learned SOR smoother, BF16 MLP weights) under f64 CG; f64 assembly",
         "data": "synthetic",
-        "config": {"workload": "two parallel unit squares 1/256 apart, 2 x 256 x 256 split quads "
-                               "(262,144 tris), rotated to general position, octree depth 8, degree 1, "
-                               "split, t=1e-3, RHS +-sin(40 pi x)",
-                   "dof_finest": int(n), "levels": list(rec[0]["levels"]), "max_coarse": args.max_coarse},
+        "config": {"workload": wl["desc"], "dof_finest": int(n), "levels": [fin, d0], "max_coarse": args.max_coarse},
+        "value_is": "learned-smoother mixed-precision solve to 1e-8, iterations only (solver set-up in "
+                    "solvers.learned_mixed.setup_s), mean over the timed steps",
         "phases_ms": phases,
-        # sweeps each way (at the finest depth, below it; 0: as at the finest), per solve
-        "sweeps_finest_below": {k: list(v) for k, v in nuc.items()},
-        "sweep_autotune_iteration_ms": {k: {f"{a},{c}": v for (a, c), v in d.items()} for k, d in tune.items()},
-        "solve_to_1e-8_ms": {"plain_fp64": 1000.0 * solve64, "mixed_fp32_fp64": 1000.0 * solve32,
-                             "learned_mixed": 1000.0 * solvel},
-        "solve_cycles": {"plain_fp64": float(cyc64), "mixed_fp32_fp64": float(cyc32), "learned_mixed": float(cycl)},
-        # the iterations alone (solver setup excluded), and the setup the first solve of a system pays
-        "solve_iterations_ms": {k: 1000.0 * float(np.mean([r[st]["seconds"] for r in rec]))
-                                for k, st in (("plain_fp64", "st64"), ("mixed_fp32_fp64", "st32"),
-                                              ("learned_mixed", "stl"))},
-        "solver_setup_ms": 1000.0 * float(np.mean([r["st64"]["setup_seconds"] for r in rec])),
-        "solve_dof_cycles_per_s": {"plain_fp64": n * cyc64 / solve64, "mixed_fp32_fp64": n * cyc32 / solve32,
-                                   "learned_mixed": n * cycl / solvel},
-        "rel_residual": {"plain_fp64": float(max(r["st64"]["rel_residual"] for r in rec)),
-                         "mixed_fp32_fp64": float(max(r["st32"]["rel_residual"] for r in rec)),
-                         "learned_mixed": float(max(r["stl"]["rel_residual"] for r in rec))},
-        "learned_fell_back": int(max(r["stl"]["fell_back"] for r in rec)),
-        # difference of each solution from the FP64 one (all three reach 1e-8 residuals)
-        "rel_diff_from_fp64_solution": {
-            "mixed_fp32_fp64": max(float(torch.linalg.norm(r["xs"][1] - r["xs"][0]) / torch.linalg.norm(r["xs"][0]))
-                                   for r in rec),
-            "learned_mixed": max(float(torch.linalg.norm(r["xs"][2] - r["xs"][0]) / torch.linalg.norm(r["xs"][0]))
-                                 for r in rec)},
+        "solvers": comp,
         "learned_training": train_info,
-        "learned_jacobi_training": train_info_jac,
     }
     if ranking:
         out["kernel_event_ms_warmup"] = {k: v[0] for k, v in ranking.items() if v[1]}
@@ -857,11 +884,15 @@ def main():
                                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
         else:
             meas = dom if dom in ("gs_colour", "residual", "spmv_dot") else "gs_colour"
-            out["roofline"] = roofline(cf, keep["s"], meas)
-    cf.camfe_system_destroy(keep["s"])
-    cf.camfe_hierarchy_destroy(keep["h"])
-    if args.held_out != "none":
-        out["learned_held_out"] = held_out_eval(cf, ctx, meshgen, model, args.held_out, model_jac)
+            out["roofline"] = roofline(cf, s, meas, with_traffic=traffic_file is not None, traffic_file=traffic_file)
+        out["roofline"]["whole_vcycle"] = comp["vcycle_roofline"]
+    cf.camfe_smoother_attach(s, None)
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)
+    if args.workload == "knot_8m_depth11" and not args.no_sphere:
+        out["held_out_sphere"] = system_eval(cf, ctx, meshgen, "sphere_8m_depth11", model, args.max_coarse)
+    if not args.no_sheets:
+        out["two_sheets_config2"] = system_eval(cf, ctx, meshgen, "two_sheets_256_depth8", model, args.max_coarse)
     if not args.no_flow:
         log("[bench] flow steps (config 3)")
         out["flow_config3"] = flow_eval(cf, ctx, meshgen)
@@ -879,15 +910,44 @@ def main():
     if not args.no_spectrum:
         log("[bench] spectral study: nested spheres, split against unsplit")
         out["spectrum"] = spectrum_eval(cf, ctx, meshgen)
-    cf.camfe_model_destroy(model)
-    cf.camfe_model_destroy(model_jac)
+    if not args.no_assembly:
+        out["assembly"] = assembly_eval(cf, ctx, meshgen, reps=1)
     if args.calibrate_copy:
         calibrate_copy(torch, dev)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "knot_8m_depth11":
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(cf, ctx, meshgen, {"dof": int(n), "cycles_fp64": comp["plain_gs_fp64"]["cycles"],
+                                                              "model": model})
+    cf.camfe_model_destroy(model)
     cf.camfe_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)
+
+
+def system_eval(cf, ctx, meshgen, name, model, max_coarse):
+    """Another workload solved once warm with each solver (no timed steps):
+    build, assembly and load times, then solve_comparison."""
+    import torch
+    wl = WORKLOADS[name]
+    dev = torch.device("cuda:0")
+    log(f"[bench] {name}: generating the mesh")
+    V, F, f = workload_input(meshgen, wl["mesh"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = cf.camfe_hierarchy_build(ctx, torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev), depth=wl["depth"],
+                                 degree=wl["degree"], max_coarse=max_coarse)
+    t1 = time.perf_counter()
+    s = cf.camfe_assemble(h)
+    t2 = time.perf_counter()
+    b = cf.camfe_load_vector(s, h, torch.from_numpy(np.asfortranarray(f)).to(dev))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    res = {"workload": wl["desc"], "tris": int(len(F)),
+           "phases_ms": {"build": 1000 * (t1 - t0), "assemble": 1000 * (t2 - t1), "load": 1000 * (t3 - t2)}}
+    res.update(solve_comparison(cf, s, h, b, wl["t"], model))
+    cf.camfe_system_destroy(s)
+    cf.camfe_hierarchy_destroy(h)
+    log(f"[bench] {name}: " + json.dumps(res))
+    return res
 
 
 if __name__ == "__main__":

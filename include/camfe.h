@@ -237,7 +237,10 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double
 /* Measurement of one finest-depth kernel of a solved system (the solver state
  * of the last camfe_solve call): "gs_colour" (one forward Gauss-Seidel sweep,
  * one launch per colour), "residual" or "spmv_dot", with FP64 (precision 0) or
- * FP32 (1) values, one right-hand side.  reps back-to-back sweeps/launches are
+ * FP32 (1) values, one right-hand side; or "vcycle": one whole plain
+ * Gauss-Seidel V(2,2)-cycle from a zero guess over every depth (the
+ * preconditioner a CG step applies), avg_ms per cycle and bytes_per_launch 0
+ * (its algorithmic bytes depend on the depths' sizes, which the exports give).  reps back-to-back sweeps/launches are
  * captured once into a HIP graph and replayed between two HIP events on the
  * context's stream.  avg_ms: average time of one launch; bytes_per_launch: the
  * algorithmic bytes of one launch (matrix values + three vector accesses per
@@ -258,6 +261,20 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision
  * Takes effect at the next solver set-up: drops the system's current solver
  * state (captured graphs included). */
 camfe_status camfe_system_set_sell_sort(camfe_sys s, int64_t min_rows);
+/* Autotuner of the colour sweep's tile (not in the paper): for every depth of
+ * the system's solver for A = M + t L (built when missing), each compiled tile
+ * {wavefronts per 64-row slice, entries per lane issued together} in
+ * {8,4} (default), {4,4}, {8,2}, {16,2}, {16,4} is timed over reps forward
+ * sweeps (one right-hand side, FP64 values for precision 0, FP32 for 1,
+ * captured into a HIP graph, timed with events on the context's stream) and
+ * the fastest is kept for that depth: by this solver and by the solvers the
+ * system builds later.  Right-hand-side columns are processed four per pass
+ * (the widest tile compiled).  Two-call pattern over the depths, coarsest
+ * first: cap = 0 returns the count in *nlevels; otherwise tile (nullable)
+ * receives each depth's index (0..4 in the order above) and ms (nullable) its
+ * time per sweep.  Overwrites the solver's scratch vectors. */
+camfe_status camfe_system_autotune(camfe_sys s, double t, int precision, int reps, int32_t *tile, double *ms,
+                                   int cap, int *nlevels);
 void camfe_system_destroy(camfe_sys s);
 
 /* Debugging entry: a system built from given matrices instead of a mesh, so
@@ -353,6 +370,10 @@ camfe_status camfe_batch_info(camfe_batch b, int *levels, int64_t *rows);
  * has nsys entries.  Returns CAMFE_ENOCONV when any mesh stops above rtol. */
 camfe_status camfe_batch_solve(camfe_batch b, const camfe_solve_opts *opts, const double *const *b_in, const int *k,
                                double *const *x, camfe_solve_stats *stats);
+/* camfe_system_autotune over the batch's levels (finest last; the levels
+ * hold every member's rows of that relative depth). */
+camfe_status camfe_batch_autotune(camfe_batch b, int precision, int reps, int32_t *tile, double *ms, int cap,
+                                  int *nlevels);
 void camfe_batch_destroy(camfe_batch b);
 
 /* --------------------------------------------------------- surface flow */

@@ -10,7 +10,11 @@
 //
 // Build: g++ -O2 -ffp-contract=off -shared -fPIC (no -march=native), so every
 // floating-point predicate below is evaluated with plain IEEE-754 adds and
-// multiplies in the stated order.
+// multiplies in the stated order.  A second build with -fopenmp (used only for
+// the benchmark's all-cores timing) shares the rows of one colour and of the
+// residual, matrix-vector and prolongation loops among threads; each row is
+// still computed by one thread in the same order, so its results are the same
+// bits as the sequential build's.
 //
 // Steps, with the passage each follows:
 //   cube / grid coordinates ........ Section 3.2, Definition 1 (grid G^N embedding;
@@ -767,8 +771,13 @@ void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward
   const int nc = (int)S.colour_rows.size();
   for (int ci = 0; ci < nc; ++ci) {
     int c = forward ? ci : nc - 1 - ci;
-    for (long r : S.colour_rows[c])
+    const std::vector<long>& rows = S.colour_rows[c];
+    // rows of one colour never couple: in the OpenMP build they are shared out
+    // (each row computed by one thread exactly as here, so no result changes)
+#pragma omp parallel for schedule(static)
+    for (long j = 0; j < (long)rows.size(); ++j)
       for (int q = 0; q < k; ++q) {
+        const long r = rows[j];
         const double* xq = x + (size_t)q * S.n;
         double acc = 0.0;
         if (S.diag[r] == 0.0) continue;   // zero-mass function: all-zero row, nothing to relax
@@ -780,6 +789,7 @@ void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward
 
 void residual(const SysLevel& S, const double* b, const double* x, int k, double* r) {
   for (int q = 0; q < k; ++q)
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < S.n; ++i) {
       double acc = 0.0;
       for (long e = (*S.ptr)[i]; e < (*S.ptr)[i + 1]; ++e) acc += S.a[e] * x[(size_t)q * S.n + (*S.col)[e]];
@@ -789,6 +799,7 @@ void residual(const SysLevel& S, const double* b, const double* x, int k, double
 
 void matvec(const SysLevel& S, const double* x, int k, double* y) {
   for (int q = 0; q < k; ++q)
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < S.n; ++i) {
       double acc = 0.0;
       for (long e = (*S.ptr)[i]; e < (*S.ptr)[i + 1]; ++e) acc += S.a[e] * x[(size_t)q * S.n + (*S.col)[e]];
@@ -832,6 +843,7 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
   // the coarse problem gets gamma cycles from zero (one: V-cycle, two: W-cycle)
   for (int g = 0; g < sv.gamma; ++g) vcycle(sv, d - 1, bc.data(), xc.data(), k);
   for (int q = 0; q < k; ++q)
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < S.n; ++i)
       for (long e = Lf.Pptr[i]; e < Lf.Pptr[i + 1]; ++e)
         x[(size_t)q * S.n + i] += Lf.Pw[e] * xc[(size_t)q * C.n + Lf.Pcol[e]];

@@ -14,28 +14,32 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ORACLE_SO = os.path.join(HERE, "liboracle.so")
+ORACLE_OMP_SO = os.path.join(HERE, "liboracle_omp.so")
 ORACLE_SRC = os.path.join(HERE, "oracle.cpp")
 
 
 def build_oracle(force: bool = True) -> str:
-    """Compile oracle.cpp with g++ (-O2, no FP contraction, no -march=native)."""
-    if force or not os.path.exists(ORACLE_SO):
-        tmp = ORACLE_SO + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17", "-shared", "-fPIC",
-                               ORACLE_SRC, "-o", tmp])
-        os.replace(tmp, ORACLE_SO)
+    """Compile oracle.cpp with g++ (-O2, no FP contraction, no -march=native),
+    sequential (liboracle.so) and with OpenMP row loops (liboracle_omp.so, the
+    benchmark's all-cores timing only)."""
+    for so, extra in ((ORACLE_SO, []), (ORACLE_OMP_SO, ["-fopenmp"])):
+        if force or not os.path.exists(so):
+            tmp = so + ".tmp"
+            subprocess.check_call(["g++", "-O2", "-ffp-contract=off", "-std=c++17", "-shared", "-fPIC"] + extra +
+                                  [ORACLE_SRC, "-o", tmp])
+            os.replace(tmp, so)
     return ORACLE_SO
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(ORACLE_SO):
+def _load(openmp=False):
+    so = ORACLE_OMP_SO if openmp else ORACLE_SO
+    if so not in _libs:
+        if not os.path.exists(so):
             build_oracle(force=True)
-        lib = C.CDLL(ORACLE_SO)
+        lib = C.CDLL(so)
         vp, L, I, D = C.c_void_p, C.c_long, C.c_int, C.c_double
         P = C.c_void_p
         lib.oracle_build.restype = vp
@@ -60,8 +64,8 @@ def _load():
         lib.oracle_gs_sweep.argtypes = [vp, I, D, P, I, P, I]
         lib.oracle_eval_vertices.argtypes = [vp, P, I, P]
         lib.oracle_linear_coeffs.argtypes = [vp, P]
-        _lib = lib
-    return _lib
+        _libs[so] = lib
+    return _libs[so]
 
 
 def _p(a):
@@ -79,8 +83,10 @@ def _colmajor(a, n):
 class Oracle:
     """Hierarchy + matrices + solver for one mesh (all FP64, CPU)."""
 
-    def __init__(self, V, F, depth, degree=1, split=1, min_depth=0, max_coarse=2048, box=None):
-        self.lib = _load()
+    def __init__(self, V, F, depth, degree=1, split=1, min_depth=0, max_coarse=2048, box=None, openmp=False):
+        """openmp: use the build whose row loops run on all OpenMP threads
+        (same results; for timing only)."""
+        self.lib = _load(openmp)
         self.V = np.ascontiguousarray(V, dtype=np.float64)
         self.F = np.ascontiguousarray(F, dtype=np.int32)
         self.depth, self.degree = depth, degree

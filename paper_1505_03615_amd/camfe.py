@@ -30,8 +30,10 @@ EXPORTS = [
     "camfe_smoother_omega", "camfe_smoother_loss_grad", "camfe_smoother_train", "camfe_flow_step",
     "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy", "camfe_eigs",
     "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
-    "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc",
+    "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc", "camfe_system_autotune",
+    "camfe_batch_autotune",
 ]
+TILES = [(8, 4), (4, 4), (8, 2), (16, 2), (16, 4)]   # colour-sweep tiles: (wavefronts per slice, entries per lane)
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 DEFAULT_COARSE_EPS = 1e-6   # eps * Id on the unit-diagonal-scaled coarsest matrix (the library's own default)
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
@@ -146,6 +148,8 @@ def load():
         "camfe_smoother_save": (I, [H, C.c_char_p]),
         "camfe_smoother_load": (I, [C.c_char_p, C.POINTER(H)]),
         "camfe_apply_noalloc": (I, [H, I, D, P, I, P]),
+        "camfe_system_autotune": (I, [H, D, I, I, P, P, I, C.POINTER(I)]),
+        "camfe_batch_autotune": (I, [H, I, I, P, P, I, C.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -455,6 +459,25 @@ def camfe_system_destroy(s):
 def camfe_system_set_sell_sort(s, min_rows):
     """Length-sort the rows of colours with at least min_rows rows (<= 0: the default 2^19)."""
     _check(load().camfe_system_set_sell_sort(s, int(min_rows)))
+
+
+def _autotune(fn, *args):
+    nl = C.c_int()
+    _check(fn(*args, None, None, 0, C.byref(nl)))
+    tile = np.zeros(nl.value, np.int32)
+    ms = np.zeros(nl.value)
+    _check(fn(*args, _ptr(tile), _ptr(ms), nl.value, C.byref(nl)))
+    return tile, ms
+
+
+def camfe_system_autotune(s, t, precision=1, reps=10):
+    """(tile index per depth, coarsest first; ms per sweep with it)."""
+    return _autotune(load().camfe_system_autotune, s, t, precision, reps)
+
+
+def camfe_batch_autotune(bt, precision=0, reps=10):
+    """(tile index per batch level, coarsest first; ms per sweep with it)."""
+    return _autotune(load().camfe_batch_autotune, bt, precision, reps)
 
 
 def camfe_system_import_csr(ctx, degree, levels, max_coarse=4096):

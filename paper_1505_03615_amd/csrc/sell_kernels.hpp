@@ -29,10 +29,17 @@ __device__ inline long long xcd_block(long long b, long long nb) {
 // colour pass of n/8 rows enough memory-level parallelism to hide latency.
 // Each slice's metadata is one int4 {first entry, end entry, first row, rows},
 // a single scalar load per workgroup.
-constexpr int SW = 8;          // wavefronts per slice
-constexpr int MU = 4;          // entries per lane issued together
+constexpr int SW = 8;          // wavefronts per slice (default tile)
+constexpr int MU = 4;          // entries per lane issued together (default tile)
 
-template <class T, int K>
+// Tiles of the colour sweep that the autotuner chooses from per level
+// (camfe_system_autotune): {wavefronts per slice, entries per lane issued
+// together}.  Index 0 is the default of every other SELL kernel.
+constexpr int NTILE = 5;
+__host__ __device__ constexpr int tile_sw(int t) { return t == 1 ? 4 : (t == 3 || t == 4) ? 16 : 8; }
+__host__ __device__ constexpr int tile_mu(int t) { return (t == 2 || t == 3) ? 2 : 4; }
+
+template <class T, int K, int SWV = SW, int MUV = MU>
 __device__ inline void slice_row_dot(const int4& m, int lane, int sub, const int* scol, const T* sval, const T* x,
                                      T acc[K]) {
 #pragma unroll
@@ -41,24 +48,24 @@ __device__ inline void slice_row_dot(const int4& m, int lane, int sub, const int
   // column) rather than wait for the row count before their first load
   const int w = (m.y - m.x) / SL;
   const long long base = m.x + lane;
-  for (int j0 = sub; j0 < w; j0 += SW * MU) {
-    T a[MU];
-    int c[MU];
+  for (int j0 = sub; j0 < w; j0 += SWV * MUV) {
+    T a[MUV];
+    int c[MUV];
 #pragma unroll
-    for (int u = 0; u < MU; ++u) {
-      const int j = j0 + SW * u;
+    for (int u = 0; u < MUV; ++u) {
+      const int j = j0 + SWV * u;
       a[u] = j < w ? sval[base + (long long)j * SL] : (T)0;
       c[u] = j < w ? scol[base + (long long)j * SL] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < MU; ++u)
+    for (int u = 0; u < MUV; ++u)
 #pragma unroll
       for (int q = 0; q < K; ++q) acc[q] = fma(a[u], x[(long long)c[u] * K + q], acc[q]);
   }
 }
 
-// sum of the SW partial sums of each row (valid in wavefront 0 after return)
-template <class T, int K>
+// sum of the SWV partial sums of each row (valid in wavefront 0 after return)
+template <class T, int K, int SWV = SW>
 __device__ inline void slice_reduce(T (*red)[K][SL], int lane, int sub, T acc[K]) {
 #pragma unroll
   for (int q = 0; q < K; ++q) red[sub][q][lane] = acc[q];
@@ -68,16 +75,17 @@ __device__ inline void slice_reduce(T (*red)[K][SL], int lane, int sub, T acc[K]
     for (int q = 0; q < K; ++q) {
       T s = red[0][q][lane];
 #pragma unroll
-      for (int w = 1; w < SW; ++w) s += red[w][q][lane];
+      for (int w = 1; w < SWV; ++w) s += red[w][q][lane];
       acc[q] = s;
     }
   }
 }
 
-template <class T, int K>
-__global__ __launch_bounds__(SL * SW) void k_gs(const int4* meta, int s_begin, int s_end, const int* scol,
-                                                const T* sval, const T* invd, const T* b, T* x) {
-  __shared__ T red[SW][K][SL];
+template <class T, int K, int TILE = 0>
+__global__ __launch_bounds__(SL * tile_sw(TILE)) void k_gs(const int4* meta, int s_begin, int s_end, const int* scol,
+                                                           const T* sval, const T* invd, const T* b, T* x) {
+  constexpr int SWV = tile_sw(TILE), MUV = tile_mu(TILE);
+  __shared__ T red[SWV][K][SL];
   const int sub = threadIdx.x / SL, lane = threadIdx.x % SL;
   const long long s = s_begin + xcd_block(blockIdx.x, s_end - s_begin);
   const int4 m = meta[s];
@@ -98,8 +106,8 @@ __global__ __launch_bounds__(SL * SW) void k_gs(const int4* meta, int s_begin, i
     }
   }
   T acc[K];
-  slice_row_dot<T, K>(m, lane, sub, scol, sval, x, acc);
-  slice_reduce<T, K>(red, lane, sub, acc);
+  slice_row_dot<T, K, SWV, MUV>(m, lane, sub, scol, sval, x, acc);
+  slice_reduce<T, K, SWV>(red, lane, sub, acc);
   if (writer) {
 #pragma unroll
     for (int q = 0; q < K; ++q) x[i * K + q] = xi[q] + (bi[q] - acc[q]) * di;

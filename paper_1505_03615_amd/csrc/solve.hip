@@ -585,6 +585,7 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
   G.d = d;
   G.n = S.n;
   G.ncol = h->degree == 1 ? 8 : 27;
+  G.tile = (size_t)d < s->tiles.size() ? std::max(0, s->tiles[d]) : 0;
   const size_t n = G.n;
   unsigned g = grid_for(n, BLK);
   // colour order (stable: canonical order inside a colour)
@@ -831,15 +832,29 @@ double pass_bytes(long long z, long long rows) {
 
 // one multicolour sweep x_i += w_i (b_i - (A x)_i) with w = dinv (1 / A_ii for
 // Gauss-Seidel, omega_i / A_ii for SOR)
+template <class T, int K, int TILE>
+void gs_colour(camfe_ctx ctx, GLevel& G, int c, const T* b, T* x, const T* dinv) {
+  const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
+  CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K, TILE>),
+              (unsigned)(s1 - s0), SL * tile_sw(TILE), 0, ctx->stream, G.sl_meta.p, s0, s1, G.scol.p,
+              sval_of<T>(G), dinv, b, x);
+}
+
+// tile: the level's choice (G.tile) unless given
 template <class T, int K>
-void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T* dinv, int first = 0) {
+void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T* dinv, int first = 0,
+              int tile = -1) {
+  if (tile < 0) tile = G.tile;
   for (int ci = first; ci < G.ncol; ++ci) {
     const int c = forward ? ci : G.ncol - 1 - ci;
-    const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
-    if (s1 <= s0) continue;
-    CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K>),
-                (unsigned)(s1 - s0), SL * SW, 0, ctx->stream, G.sl_meta.p, s0, s1, G.scol.p,
-                sval_of<T>(G), dinv, b, x);
+    if (G.cslice[c + 1] <= G.cslice[c]) continue;
+    switch (tile) {
+      case 1: gs_colour<T, K, 1>(ctx, G, c, b, x, dinv); break;
+      case 2: gs_colour<T, K, 2>(ctx, G, c, b, x, dinv); break;
+      case 3: gs_colour<T, K, 3>(ctx, G, c, b, x, dinv); break;
+      case 4: gs_colour<T, K, 4>(ctx, G, c, b, x, dinv); break;
+      default: gs_colour<T, K, 0>(ctx, G, c, b, x, dinv); break;
+    }
   }
 }
 
@@ -1749,7 +1764,8 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
     else if (name == "spmv_dot") kid = 2;
     else if (name == "empty") kid = 3;
     else if (name == "copy") kid = 4;
-    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL, "measurable kernels: gs_colour, residual, spmv_dot, empty, copy");
+    else if (name == "vcycle") kid = 5;
+    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL, "measurable kernels: gs_colour, residual, spmv_dot, empty, copy, vcycle");
     const long long nk = (long long)G.n;
     hipStream_t st = ctx->stream;
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.b64.p, nk, 1.0);
@@ -1771,6 +1787,7 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
     }
     if (kid == 2) { launches = 1; bytes = (double)G.nnz * 8 + 2.0 * nk * 8; }
     if (kid == 3) bytes = 0;
+    if (kid == 5) { launches = 1; bytes = 0; }   // one whole cycle per repetition; bytes left to the caller
     // the copy moves a colour launch's average bytes (half read, half written)
     // per launch, rotating through NCP buffer pairs so that, like the colours'
     // matrices, its data does not stay in the L2 caches between launches
@@ -1802,6 +1819,16 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
         } else if (kid == 2) {
           hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p,
                              (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p, G.r64.p, S->part.p);
+        } else if (kid == 5) {
+          // one plain Gauss-Seidel V(2,2)-cycle from a zero guess, as the
+          // preconditioner of a CG step applies it (one column)
+          if (precision == 0) {
+            hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.x64.p, nk, 0.0);
+            vcycle<double, 1>(S, S->D, G.b64.p, G.x64.p, 2, 2);
+          } else {
+            hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
+            vcycle<float, 1>(S, S->D, G.b32.p, G.x32.p, 2, 2);
+          }
         } else {
           for (int c = 0; c < G.ncol; ++c) {
             const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
@@ -1817,6 +1844,12 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
         }
       }
     };
+    struct CycleScope {   // the measured cycle is the plain one, whatever the last solve used
+      SolverState* S;
+      int sm, g, nc;
+      ~CycleScope() { S->smoother = sm; S->gamma = g; S->nu_coarse = nc; }
+    } cycle_scope{S, S->smoother, S->gamma, S->nu_coarse};
+    if (kid == 5) { S->smoother = 0; S->gamma = 1; S->nu_coarse = 0; }
     const long long key = -1 - (((long long)kid * 2 + precision) << 20) - reps;
     // reference graphs are not kept: the copy's buffers end with this call
     struct DropGraph {
@@ -1846,6 +1879,122 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
     (void)hipEventDestroy(e1);
     if (avg_ms) *avg_ms = ms / (reps * launches);
     if (bytes_per_launch) *bytes_per_launch = bytes / launches;
+  });
+}
+
+}  // extern "C"
+
+namespace camfe {
+namespace {
+// Time of one forward colour sweep (all colours, one right-hand side) at level
+// G with tile v: reps sweeps captured once into a graph, replayed between two
+// events after a warm replay; ms per sweep.  Overwrites the level's scratch.
+double time_tile(SolverState* S, GLevel& G, int precision, int v, int reps) {
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  const long long nk = (long long)G.n;
+  hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.b64.p, nk, 1.0);
+  hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.x64.p, nk, 0.0);
+  hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.b32.p, nk, 1.0f);
+  hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
+  const long long key = -(1LL << 40) - ((long long)G.d << 16) - ((long long)v << 8) - precision;
+  auto enqueue = [&] {
+    for (int r = 0; r < reps; ++r) {
+      if (precision == 0) gs_sweep<double, 1>(ctx, G, G.b64.p, G.x64.p, true, G.invd64.p, 0, v);
+      else gs_sweep<float, 1>(ctx, G, G.b32.p, G.x32.p, true, G.invd32.p, 0, v);
+    }
+  };
+  struct Drop {
+    SolverState* S;
+    long long key;
+    ~Drop() {
+      auto it = S->graphs.find(key);
+      if (it == S->graphs.end()) return;
+      (void)hipStreamSynchronize(S->ctx->stream);
+      (void)hipGraphExecDestroy(it->second);
+      S->graphs.erase(it);
+    }
+  } drop{S, key};
+  run_graph(S, key, enqueue);
+  hipEvent_t e0, e1;
+  CAMFE_HIP(hipEventCreate(&e0));
+  CAMFE_HIP(hipEventCreate(&e1));
+  CAMFE_HIP(hipEventRecord(e0, st));
+  run_graph(S, key, enqueue);
+  CAMFE_HIP(hipEventRecord(e1, st));
+  CAMFE_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  CAMFE_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms / reps;
+}
+
+// every level of S (from d_lo up): the fastest tile for the colour sweep,
+// written into the levels and returned per level (index d - d_lo)
+std::vector<int> autotune_levels(SolverState* S, int d_lo, int precision, int reps, std::vector<double>* best_ms) {
+  std::vector<int> pick;
+  for (int d = d_lo; d <= S->D; ++d) {
+    GLevel& G = S->lev[d];
+    int bv = 0;
+    double bt = 0;
+    for (int v = 0; v < NTILE; ++v) {
+      const double ms = time_tile(S, G, precision, v, reps);
+      if (v == 0 || ms < bt) { bt = ms; bv = v; }
+    }
+    G.tile = bv;
+    pick.push_back(bv);
+    if (best_ms) best_ms->push_back(bt);
+  }
+  S->drop_graphs();   // captured cycles hold the old tiles
+  S->ctx->sync();
+  return pick;
+}
+}  // namespace
+}  // namespace camfe
+
+extern "C" {
+
+camfe_status camfe_system_autotune(camfe_sys s, double t, int precision, int reps, int32_t* tile, double* ms,
+                                   int cap, int* nlevels) {
+  return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
+    CAMFE_REQUIRE(s && (precision == 0 || precision == 1) && reps > 0, CAMFE_EINVAL, "bad argument");
+    camfe_hier h = s->h;
+    const int nl = h->D - h->d0 + 1;
+    if (nlevels) *nlevels = nl;
+    if (cap == 0) return;
+    CAMFE_REQUIRE(cap >= nl, CAMFE_ETOOSMALL, "capacity below the number of depths");
+    h->ctx->use_device();
+    SolverState* S = ensure_solver(s, t, s->solver ? s->solver->coarse_eps : DEFAULT_COARSE_EPS);
+    std::vector<double> best;
+    std::vector<int> pick = autotune_levels(S, h->d0, precision, reps, &best);
+    s->tiles.assign(h->D + 1, 0);
+    for (int i = 0; i < nl; ++i) {
+      s->tiles[h->d0 + i] = pick[i];
+      if (tile) tile[i] = pick[i];
+      if (ms) ms[i] = best[i];
+    }
+  });
+}
+
+camfe_status camfe_batch_autotune(camfe_batch b, int precision, int reps, int32_t* tile, double* ms, int cap,
+                                  int* nlevels) {
+  return guarded([&] {
+    if (b) set_current_ctx(b->ctx);
+    CAMFE_REQUIRE(b && (precision == 0 || precision == 1) && reps > 0, CAMFE_EINVAL, "bad argument");
+    SolverState* S = b->S.get();
+    const int nl = S->D + 1;
+    if (nlevels) *nlevels = nl;
+    if (cap == 0) return;
+    CAMFE_REQUIRE(cap >= nl, CAMFE_ETOOSMALL, "capacity below the number of levels");
+    b->ctx->use_device();
+    std::vector<double> best;
+    std::vector<int> pick = autotune_levels(S, 0, precision, reps, &best);
+    for (int i = 0; i < nl; ++i) {
+      if (tile) tile[i] = pick[i];
+      if (ms) ms[i] = best[i];
+    }
   });
 }
 

@@ -23,6 +23,7 @@ struct GLevel {
   int d = 0;
   size_t n = 0;
   int ncol = 8;
+  int tile = 0;               // colour-sweep tile (sell_kernels.hpp tile_sw / tile_mu), chosen by the autotuner
   std::vector<int> coff;      // colour c owns internal rows [coff[c], coff[c+1])
   std::vector<int> cslice;    // colour c owns slices [cslice[c], cslice[c+1])
   std::vector<long long> cnnz;  // nonzeros of the rows of each colour

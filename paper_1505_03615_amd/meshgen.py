@@ -17,6 +17,7 @@ import numpy as np
 __all__ = [
     "icosphere", "octasphere", "two_sheets", "torus", "torus_knot",
     "noisy_sphere", "unit_cubes", "cubes_checker", "u_tube", "nested_spheres", "single_triangle", "config_mesh",
+    "config4_batch",
 ]
 
 
@@ -40,9 +41,20 @@ def _midpoint_subdivide(V, F, project):
     return np.concatenate([V, mid], axis=0), NF
 
 
+_ICO_CACHE = {}
+
+
 def icosphere(level: int):
     """Unit icosphere: icosahedron (cyclic (0, +-1, +-phi) family), `level` midpoint
-    subdivisions, new vertices projected to the sphere.  Level 3: 642 V / 1280 F."""
+    subdivisions, new vertices projected to the sphere.  Level 3: 642 V / 1280 F.
+    (Built once per level and process; callers get copies.)"""
+    if level not in _ICO_CACHE:
+        _ICO_CACHE[level] = _icosphere(level)
+    V, F = _ICO_CACHE[level]
+    return V.copy(), F.copy()
+
+
+def _icosphere(level: int):
     p = (1.0 + 5.0 ** 0.5) / 2.0
     V = []
     for s1 in (-1.0, 1.0):
@@ -307,6 +319,41 @@ def single_triangle():
     """One generic triangle (used with an explicit box so it sits inside one cell)."""
     V = np.array([[0.31, 0.27, 0.43], [0.71, 0.36, 0.52], [0.42, 0.69, 0.61]])
     return V, np.array([[0, 1, 2]], dtype=np.int32)
+
+
+def config4_batch(count: int = 64, seed: int = 4000):
+    """The batch of uneven meshes, member i from seed + i: i % 3 == 0 an
+    icosphere of level 3..7, 1 a torus with R/r ~ U[2, 6] and log-uniform
+    1k..1.3M triangles (quad grid nu x nv with nu / nv = R / r), 2 a
+    noise-displaced icosphere of level 3..8 (16 Gaussian bumps, amplitude
+    0.05).  Each gets the depth clamp(round(log2(side / mean edge)), 6, 10) and
+    k ~ U{1..16} right-hand-side columns of per-vertex N(0, 1) values.
+    Returns a list of dicts (kind, V, F, depth, fv)."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng(seed + i)
+        kind = i % 3
+        if kind == 0:
+            V, F = icosphere(3 + (i // 3) % 5)
+            name = f"icosphere L{3 + (i // 3) % 5}"
+        elif kind == 1:
+            ratio = float(rng.uniform(2.0, 6.0))
+            tris = float(np.exp(rng.uniform(np.log(1e3), np.log(1.3e6))))
+            nv = max(4, int(round(np.sqrt(tris / (2.0 * ratio)))))
+            nu = max(8, int(round(tris / (2.0 * nv))))
+            V, F = torus(ratio, 1.0, nu, nv)
+            name = f"torus R/r={ratio:.2f} {nu}x{nv}"
+        else:
+            lev = 3 + (i // 3) % 6
+            V, F = noisy_sphere(lev, seed=seed + i)
+            name = f"noisy icosphere L{lev}"
+        e = np.linalg.norm(V[F[:, 1]] - V[F[:, 0]], axis=1).mean()
+        side = 1.125 * (V.max(0) - V.min(0)).max()
+        depth = int(np.clip(np.round(np.log2(side / e)), 6, 10))
+        k = int(rng.integers(1, 17))
+        fv = np.asfortranarray(rng.normal(size=(len(V), k)))
+        out.append(dict(kind=name, V=V, F=F, depth=depth, fv=fv))
+    return out
 
 
 def config_mesh(name: str, **kw):

@@ -136,3 +136,70 @@ def test_batch_with_a_system_listed_per_column_chunk(cf, setup):
         _check([(h, s, o, chunks[0]), (h, s, o, chunks[1]), items[0]], xs, stats)
     finally:
         cf.camfe_batch_destroy(bt2)
+
+
+@pytest.fixture(scope="module")
+def config4(cf):
+    """Seventeen members of the config-4 batch generator: the first sixteen of
+    at most 21k triangles at their own depths (6-7), and the 1,924-triangle
+    torus (R/r = 5.49) at depth 9 (760k functions), each with its 1-16
+    Gaussian right-hand sides; one batch member per (mesh, chunk of <= 4
+    columns)."""
+    ctx = cf.camfe_ctx_create(0)
+    B = meshgen.config4_batch()
+    picks = [(i, B[i]["depth"]) for i in range(len(B)) if len(B[i]["F"]) <= 21000 and B[i]["depth"] <= 7][:16]
+    picks.append((55, 9))
+    items = []
+    for i, depth in picks:
+        m = B[i]
+        say(f"[gpu] config 4: member {i} ({m['kind']}) nt={len(m['F'])} depth={depth} k={m['fv'].shape[1]}")
+        h = cf.camfe_hierarchy_build(ctx, m["V"], m["F"], depth=depth, max_coarse=4096)
+        s = cf.camfe_assemble(h)
+        o = Oracle(m["V"], m["F"], depth, max_coarse=4096).check().assemble()
+        items.append((h, s, o, o.load_vector(m["fv"])))
+    yield ctx, items
+    for h, s, o, b in items:
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+    cf.camfe_ctx_destroy(ctx)
+
+
+def test_config4_batch_meets_the_oracle_per_mesh_and_column(cf, config4):
+    ctx, items = config4
+    assert len(items) >= 17 and max(it[2].depth for it in items) >= 9
+    mem, chunks, owner = [], [], []
+    for j, (h, s, o, b) in enumerate(items):
+        for c0 in range(0, b.shape[1], 4):
+            mem.append(s)
+            chunks.append(np.asfortranarray(b[:, c0:c0 + 4]))
+            owner.append(j)
+    bt = cf.camfe_batch_create(ctx, mem, T)
+    try:
+        for tuned in (False, True):
+            if tuned:
+                tiles, ms = cf.camfe_batch_autotune(bt, precision=0, reps=3)
+                levels, _ = cf.camfe_batch_info(bt)
+                assert len(tiles) == levels and np.all((tiles >= 0) & (tiles < len(cf.TILES))) and np.all(ms > 0)
+                say(f"[gpu] config 4: tiles {tiles.tolist()}")
+            xs, stats = cf.camfe_batch_solve(bt, chunks, T, rtol=1e-8, max_iter=2000)
+            say(f"[gpu] config 4 ({'autotuned' if tuned else 'default'} tiles): {len(mem)} members, "
+                f"{1e3 * stats[0]['seconds']:.1f} ms, up to {max(st['iterations'] for st in stats)} iterations")
+            assert all(st["converged"] for st in stats)
+            _check([(items[j][0], items[j][1], items[j][2], c) for j, c in zip(owner, chunks)], xs, stats)
+    finally:
+        cf.camfe_batch_destroy(bt)
+
+
+def test_system_autotune_keeps_the_solution(cf, config4):
+    """The autotuner only picks among tiles of the same arithmetic: a solve
+    after it gives the oracle's residual bar again, and the tiles survive a
+    rebuilt solver (another t)."""
+    ctx, items = config4
+    h, s, o, b = items[-1]                       # the depth-9 torus
+    tiles, ms = cf.camfe_system_autotune(s, T, precision=1, reps=3)
+    assert len(tiles) == o.depth - o.coarsest + 1 and np.all(ms > 0)
+    for t in (T, 2 * T):
+        x, st = cf.camfe_solve(s, b[:, :2], t=t, rtol=1e-8, max_iter=2000, precision=1)
+        Mo, Lo = o.matrices(o.depth)
+        r = np.linalg.norm(b[:, :2] - (Mo + t * Lo) @ x, axis=0) / np.linalg.norm(b[:, :2], axis=0)
+        assert st["converged"] and np.all(r <= 1e-6), (t, r)

@@ -204,6 +204,53 @@ def test_train_then_solve_held_out(cf, ctx):
         cf.camfe_model_destroy(m)
 
 
+def test_learned_sor_against_gauss_seidel_on_a_held_out_knot(cf, ctx):
+    """What the learned smoother gains over the method without it (the paper's
+    Gauss-Seidel, Section 5.2), at equal precision (FP32 cycles under FP64 CG):
+    a SOR model trained as the benchmark trains it (icosphere L4 and two
+    sheets at depth 6, a (3,5) knot 2048 x 16 at depth 7), then the held-out
+    (3,5) knot of 262,144 triangles (seed 5901) at depth 9 solved to 1e-8 by
+    both.  Measured on this mesh: 85 against 93 cycles (0.91 of the time);
+    on the benchmark's depth-11 held-out knot and sphere and on the two
+    sheets the learned weights take more cycles than Gauss-Seidel.  The
+    test records both ratios and guards them without asserting a gain."""
+    fams = [(meshgen.icosphere(4)[:2], 6), (meshgen.two_sheets(64, 1.0 / 64)[:2], 6),
+            (meshgen.torus_knot(nu=2048, nv=16, seed=5), 7)]
+    made = []
+    for (V, F), depth in fams:
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, max_coarse=4096)
+        made.append((h, cf.camfe_assemble(h)))
+    say("[gpu] learned vs GS: train")
+    m, hist = cf.camfe_smoother_train(ctx, [x[1] for x in made], t=1e-3, levels=3, steps=150, nu=2, bf16=True,
+                                      lr=3e-3, seed=1, sweep=1)
+    V, F = meshgen.torus_knot(nu=4096, nv=32, seed=5901)
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=9, max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    made.append((h, s))
+    try:
+        b = cf.camfe_load_vector(s, h, V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
+        res = {}
+        for tag, sm, model in (("gs", 0, None), ("learned", 2, m)):
+            cf.camfe_smoother_attach(s, model)
+            cf.camfe_solve(s, b, t=1e-4, rtol=1e-8, max_iter=4, precision=1, smoother=sm)
+            x, st = cf.camfe_solve(s, b, t=1e-4, rtol=1e-8, max_iter=3000, precision=1, smoother=sm)
+            assert st["converged"] and not st["fell_back"], (tag, st)
+            res[tag] = st
+        cyc = res["learned"]["cycles"] / res["gs"]["cycles"]
+        tim = res["learned"]["seconds"] / res["gs"]["seconds"]
+        say(f"[gpu] learned vs GS (knot 262k, depth 9, mixed): cycles {res['learned']['cycles']} / "
+            f"{res['gs']['cycles']} = {cyc:.3f}, time {1e3 * res['learned']['seconds']:.1f} / "
+            f"{1e3 * res['gs']['seconds']:.1f} ms = {tim:.3f}")
+        # no gain is claimed; the weights must stay a usable smoother
+        assert cyc <= 1.5 and tim <= 1.6
+    finally:
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_model_destroy(m)
+        for hh, ss in made:
+            cf.camfe_system_destroy(ss)
+            cf.camfe_hierarchy_destroy(hh)
+
+
 def test_stalling_smoother_falls_back_to_gauss_seidel(cf, ctx):
     h, s, o = built(cf, ctx, "sphere")
     c = CASES["sphere"]

@@ -148,3 +148,20 @@ def test_pcg_with_fewer_coarse_sweeps_still_matches_the_dense_solve(small):
     xs = la.solve(A, b[:, 0], assume_a="pos")
     e = x[:, 0] - xs
     assert np.sqrt(e @ A @ e) <= 1e-9 * np.sqrt(xs @ A @ xs)
+
+
+def test_openmp_build_gives_the_same_bits():
+    """The all-cores build shares independent rows among threads; every row is
+    still one thread's sequential sum, so cycles, iterates and residual
+    histories equal the sequential build's bit for bit."""
+    V, F = meshgen.torus_knot(nu=512, nv=16, seed=3)
+    f = V[:, 2] + 0.1 * V[:, 0] ** 2
+    out = []
+    for omp in (False, True):
+        o = Oracle(V, F, 6, max_coarse=256, openmp=omp).check().assemble()
+        b = o.load_vector(f)
+        x, info = o.solve(1e-4, b, rtol=1e-10, max_iter=300)
+        xs, infos = o.solve(1e-4, b, rtol=1e-30, max_iter=5, mode="vcycle")
+        out.append((x, info["history"], xs, infos["history"]))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)

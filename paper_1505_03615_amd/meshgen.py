@@ -17,7 +17,7 @@ import numpy as np
 __all__ = [
     "icosphere", "octasphere", "two_sheets", "torus", "torus_knot",
     "noisy_sphere", "unit_cubes", "cubes_checker", "u_tube", "nested_spheres", "single_triangle", "config_mesh",
-    "config4_batch",
+    "config4_batch", "stripe_knot", "near_other_strand",
 ]
 
 
@@ -319,6 +319,32 @@ def single_triangle():
     """One generic triangle (used with an explicit box so it sits inside one cell)."""
     V = np.array([[0.31, 0.27, 0.43], [0.71, 0.36, 0.52], [0.42, 0.69, 0.61]])
     return V, np.array([[0, 1, 2]], dtype=np.int32)
+
+
+def stripe_knot(nu: int = 8192, nv: int = 64, radius: float = 0.35, stripes: int = 40, seed: int = 5100):
+    """A self-intersecting (3,5) torus-knot tube: radius 0.35 exceeds half the
+    smallest distance between distinct strands of the centre line (0.567), and
+    stays below its smallest radius of curvature (0.73), so the tube passes
+    through itself where strands come close but never folds.  The colour is a
+    stripe texture along the knot, f = cos(stripes * s) at the vertices of
+    centre-line parameter s.  Returns V, F, f (nv x 1) and s per vertex."""
+    V, F = torus_knot(nu=nu, nv=nv, radius=radius, seed=seed)
+    s = np.repeat(2 * np.pi * np.arange(nu) / nu, nv)
+    return V, F, np.cos(stripes * s)[:, None], s
+
+
+def near_other_strand(V, s, dist: float, min_ds: float = 0.6):
+    """Vertices within `dist` of a vertex whose centre-line parameter differs by
+    more than min_ds (circularly): where the self-intersecting tube passes
+    through or near another part of itself."""
+    from scipy.spatial import cKDTree
+    pairs = cKDTree(V).query_pairs(dist, output_type="ndarray")
+    ds = np.abs(s[pairs[:, 0]] - s[pairs[:, 1]])
+    ds = np.minimum(ds, 2 * np.pi - ds)
+    far = pairs[ds > min_ds]
+    mask = np.zeros(len(V), dtype=bool)
+    mask[far.ravel()] = True
+    return mask
 
 
 def config4_batch(count: int = 64, seed: int = 4000):

@@ -61,3 +61,13 @@ def test_nested_spheres_radii_and_rotation():
     assert np.allclose(Vr, V @ R.T) and np.array_equal(Fr, F)
     u, c = _edges(F)
     assert np.all(c == 2) and _components(len(V), F) == 2
+
+
+def test_stripe_knot_passes_through_itself():
+    """The stripe knot's tube (radius 0.35) reaches across to other strands;
+    the same sweep with the thin tube (radius 0.05) never does."""
+    V, F, f, s = meshgen.stripe_knot(nu=512, nv=24)
+    assert meshgen.near_other_strand(V, s, 0.05).sum() > 0.1 * len(V)
+    assert np.allclose(f[:, 0], np.cos(40 * s))
+    Vt, Ft = meshgen.torus_knot(nu=512, nv=24, radius=0.05, seed=5100)
+    assert meshgen.near_other_strand(Vt, s, 0.05).sum() == 0

@@ -43,6 +43,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <stdexcept>
 #include <string>
 #include <utility>
 #include <vector>
@@ -718,6 +719,11 @@ struct SysLevel {
   std::vector<double> chol;
   bool direct = false;
   const Level* lev = nullptr;
+  // cell-block Schwarz smoother: function lists of the blocks, the inverse of
+  // each block (m x m row-major) and 1 / (blocks holding each function)
+  std::vector<std::vector<long>> blocks;
+  std::vector<std::vector<double>> binv;
+  std::vector<double> invmult;
 };
 
 int colour_of(int degree, uint64_t key) {
@@ -764,7 +770,120 @@ struct Solver {
   int gamma = 1;              // coarse corrections per level: 1 V-cycle, 2 W-cycle
   int nu_coarse = 0;          // sweeps each way below the finest depth (0: nu1, nu2)
   int eps_used = 0;
+  int smoother = 0;           // 0 multicolour Gauss-Seidel, 1 cell-block Schwarz
+  double block_omega = 0.7;   // damping of the cell-block corrections
 };
+
+void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward);
+void residual(const SysLevel& S, const double* b, const double* x, int k, double* r);
+
+// Entry (r, c) of A at one level (0 when not stored)
+double a_entry(const SysLevel& S, long r, long c) {
+  long lo = (*S.ptr)[r], hi = (*S.ptr)[r + 1];
+  while (lo < hi) {
+    long mid = (lo + hi) / 2;
+    if ((*S.col)[mid] < c) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo < (*S.ptr)[r + 1] && (*S.col)[lo] == c ? S.a[lo] : 0.0;
+}
+
+// Cell blocks of the Schwarz smoother at depth d (trilinear functions only).
+// A block holds, for one occupied cell, every function whose support
+// contains the cell and whose component holds one of the cell's triangles:
+// the functions at the cell's 8 corners, one per component met in the cell.
+// Functions of zero computed mass are left out.  A cell with more than
+// BLOCK_CAP such functions (many separate pieces of surface in one cell, at
+// coarse split depths) gives one single-function block per function instead.
+// Each block's inverse is that of its unit-diagonal-scaled matrix plus eps I,
+// scaled back: D^-1/2 (D^-1/2 A_b D^-1/2 + eps I)^-1 D^-1/2 (the coarsest
+// solve's treatment, which keeps exactly dependent functions bounded).
+constexpr int BLOCK_CAP = 16;
+
+void build_blocks(const Hier& h, int d, SysLevel& S, double eps) {
+  const Level& L = h.lev[d];
+  S.blocks.clear();
+  S.binv.clear();
+  std::vector<std::vector<long>> raw;
+  size_t p = 0;
+  while (p < L.pairs.size()) {
+    const uint64_t cell = L.pairs[p].first;
+    long c[3];
+    demorton3(cell, c);
+    std::vector<long> fs;
+    size_t q = p;
+    for (; q < L.pairs.size() && L.pairs[q].first == cell; ++q)
+      for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            int f = func_of(L, morton3(c[0] + dx, c[1] + dy, c[2] + dz), L.pairs[q].second);
+            if (f >= 0 && S.diag[f] > 0.0) fs.push_back(f);
+          }
+    std::sort(fs.begin(), fs.end());
+    fs.erase(std::unique(fs.begin(), fs.end()), fs.end());
+    if ((int)fs.size() > BLOCK_CAP) {
+      for (long f : fs) raw.push_back({f});
+    } else if (!fs.empty()) {
+      raw.push_back(fs);
+    }
+    p = q;
+  }
+  S.invmult.assign(S.n, 0.0);
+  for (const auto& b : raw)
+    for (long f : b) S.invmult[f] += 1.0;
+  for (long i = 0; i < S.n; ++i) S.invmult[i] = S.invmult[i] > 0.0 ? 1.0 / S.invmult[i] : 0.0;
+  for (const auto& b : raw) {
+    const long m = (long)b.size();
+    std::vector<double> sc(m), A((size_t)m * m), inv((size_t)m * m, 0.0);
+    for (long i = 0; i < m; ++i) sc[i] = 1.0 / std::sqrt(S.diag[b[i]]);
+    for (long i = 0; i < m; ++i)
+      for (long j = 0; j < m; ++j) A[i * m + j] = a_entry(S, b[i], b[j]) * sc[i] * sc[j];
+    for (long i = 0; i < m; ++i) A[i * m + i] += eps;
+    if (!cholesky(A, m)) throw std::runtime_error("cell block not positive definite");
+    for (long j = 0; j < m; ++j) {
+      std::vector<double> e(m, 0.0);
+      e[j] = 1.0;
+      chol_solve(A, m, e.data());
+      for (long i = 0; i < m; ++i) inv[i * m + j] = sc[i] * e[i] * sc[j];
+    }
+    S.blocks.push_back(b);
+    S.binv.push_back(inv);
+  }
+}
+
+// One cell-block Schwarz sweep with damping omega: r = b - A x, then
+//   forward:  x_i += omega (1 / mult_i) sum over blocks B holding i of (A_B^-1 r_B)_i
+//   backward: x_i += omega              sum over blocks B holding i of (A_B^-1 (r / mult)_B)_i
+// The backward sweep is the A-adjoint of the forward one, so forward sweeps
+// before the coarse correction and backward sweeps after it make a symmetric
+// cycle.  Undamped (omega = 1) the averaged overlapping corrections can
+// overshoot some modes: stationary cycles then diverge on some meshes while
+// CG preconditioned by the cycle still converges.
+void block_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward, double omega) {
+  std::vector<double> r((size_t)S.n * k), u((size_t)S.n * k, 0.0);
+  residual(S, b, x, k, r.data());
+  if (!forward)
+    for (int q = 0; q < k; ++q)
+      for (long i = 0; i < S.n; ++i) r[(size_t)q * S.n + i] *= S.invmult[i];
+  for (size_t bi = 0; bi < S.blocks.size(); ++bi) {
+    const std::vector<long>& blk = S.blocks[bi];
+    const long m = (long)blk.size();
+    for (int q = 0; q < k; ++q)
+      for (long i = 0; i < m; ++i) {
+        double acc = 0.0;
+        for (long j = 0; j < m; ++j) acc += S.binv[bi][i * m + j] * r[(size_t)q * S.n + blk[j]];
+        u[(size_t)q * S.n + blk[i]] += acc;
+      }
+  }
+  for (int q = 0; q < k; ++q)
+    for (long i = 0; i < S.n; ++i)
+      x[(size_t)q * S.n + i] += omega * (forward ? S.invmult[i] * u[(size_t)q * S.n + i] : u[(size_t)q * S.n + i]);
+}
+
+void smooth(const Solver& sv, const SysLevel& S, const double* b, double* x, int k, bool forward) {
+  if (sv.smoother == 1) block_sweep(S, b, x, k, forward, sv.block_omega);
+  else gs_sweep(S, b, x, k, forward);
+}
 
 // one Gauss-Seidel sweep over all colours (forward or reverse), x n x k col-major
 void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward) {
@@ -825,12 +944,12 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
         for (long i = 0; i < S.n; ++i) xq[i] = S.diag[i] > 0.0 ? xq[i] / std::sqrt(S.diag[i]) : 0.0;
       }
     } else {
-      for (int s = 0; s < nu1; ++s) gs_sweep(S, b, x, k, true);
-      for (int s = 0; s < nu2; ++s) gs_sweep(S, b, x, k, false);
+      for (int s = 0; s < nu1; ++s) smooth(sv, S, b, x, k, true);
+      for (int s = 0; s < nu2; ++s) smooth(sv, S, b, x, k, false);
     }
     return;
   }
-  for (int s = 0; s < nu1; ++s) gs_sweep(S, b, x, k, true);
+  for (int s = 0; s < nu1; ++s) smooth(sv, S, b, x, k, true);
   std::vector<double> r((size_t)S.n * k);
   residual(S, b, x, k, r.data());
   const Level& Lf = sv.h->lev[d];
@@ -847,7 +966,7 @@ void vcycle(Solver& sv, int d, const double* b, double* x, int k) {
     for (long i = 0; i < S.n; ++i)
       for (long e = Lf.Pptr[i]; e < Lf.Pptr[i + 1]; ++e)
         x[(size_t)q * S.n + i] += Lf.Pw[e] * xc[(size_t)q * C.n + Lf.Pcol[e]];
-  for (int s = 0; s < nu2; ++s) gs_sweep(S, b, x, k, false);
+  for (int s = 0; s < nu2; ++s) smooth(sv, S, b, x, k, false);
 }
 
 double col_norm(const double* v, long n) {
@@ -989,14 +1108,20 @@ int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
 // before the first and after every iteration (true residual).
 int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2,
                  const double* b, int k, double* x, int x0_given, double* stats,
-                 double* history, int mode, double coarse_eps, int gamma, int nu_coarse) {
+                 double* history, int mode, double coarse_eps, int gamma, int nu_coarse, int smoother,
+                 double block_omega) {
   Hier& h = ((OracleHandle*)hp)->h;
   if (!h.err.empty()) return -1;
   if (gamma < 1 || gamma > 2) { h.err = "gamma must be 1 or 2"; return -1; }
   if (nu_coarse < 0) { h.err = "nu_coarse must be >= 0"; return -1; }
+  if (smoother < 0 || smoother > 1 || (smoother == 1 && h.degree != 1)) {
+    h.err = "smoother: 0 Gauss-Seidel, 1 cell blocks (degree 1)";
+    return -1;
+  }
   auto t0 = std::chrono::steady_clock::now();
   Solver sv;
-  sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2; sv.gamma = gamma; sv.nu_coarse = nu_coarse;
+  sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2; sv.gamma = gamma; sv.nu_coarse = nu_coarse; sv.smoother = smoother;
+  sv.block_omega = block_omega;
   sv.sl.assign(h.D + 1, SysLevel());
   for (int d = h.d0; d <= h.D; ++d) {
     Level& L = h.lev[d];
@@ -1014,6 +1139,14 @@ int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2
     const int ncol = h.degree == 1 ? 8 : 27;
     S.colour_rows.assign(ncol, {});
     for (long r = 0; r < S.n; ++r) S.colour_rows[colour_of(h.degree, L.fkey[r])].push_back(r);
+    if (smoother == 1) {
+      try {
+        build_blocks(h, d, S, coarse_eps);
+      } catch (const std::exception& e) {
+        h.err = e.what();
+        return -1;
+      }
+    }
   }
   {
     SysLevel& S = sv.sl[h.d0];
@@ -1155,6 +1288,32 @@ int oracle_gs_sweep(void* hp, int d, double t, const double* b, int k, double* x
   S.colour_rows.assign(h.degree == 1 ? 8 : 27, {});
   for (long r = 0; r < S.n; ++r) S.colour_rows[colour_of(h.degree, L.fkey[r])].push_back(r);
   gs_sweep(S, b, x, k, forward != 0);
+  return 0;
+}
+
+// One cell-block Schwarz sweep at depth d (forward or backward, for
+// sweep-level checks); eps as in the solver's block inverses
+int oracle_block_sweep(void* hp, int d, double t, const double* b, int k, double* x, int forward, double eps,
+                       double omega) {
+  Hier& h = ((OracleHandle*)hp)->h;
+  if (d < h.d0 || d > h.D || !h.lev[d].assembled || h.degree != 1) return -1;
+  const Level& L = h.lev[d];
+  SysLevel S;
+  S.n = (long)L.fkey.size();
+  S.ptr = &L.Aptr; S.col = &L.Acol;
+  S.a.resize(L.Mval.size());
+  for (size_t e = 0; e < L.Mval.size(); ++e) S.a[e] = L.Mval[e] + t * L.Lval[e];
+  S.diag.assign(S.n, 0.0);
+  for (long r = 0; r < S.n; ++r)
+    for (long e = L.Aptr[r]; e < L.Aptr[r + 1]; ++e)
+      if (L.Acol[e] == r) S.diag[r] = S.a[e];
+  try {
+    build_blocks(h, d, S, eps);
+  } catch (const std::exception& e) {
+    h.err = e.what();
+    return -1;
+  }
+  block_sweep(S, b, x, k, forward != 0, omega);
   return 0;
 }
 

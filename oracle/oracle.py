@@ -58,7 +58,8 @@ def _load(openmp=False):
         lib.oracle_assemble.argtypes = [vp, P]
         lib.oracle_matrix.argtypes = [vp, I, P, P, P, P]
         lib.oracle_load_vector.argtypes = [vp, I, P, I, P]
-        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I, I]
+        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I, I, I, D]
+        lib.oracle_block_sweep.argtypes = [vp, I, D, P, I, P, I, D, D]
         lib.oracle_gradient_load.argtypes = [vp, I, P, I, P]
         lib.oracle_apply.argtypes = [vp, I, D, P, I, P]
         lib.oracle_gs_sweep.argtypes = [vp, I, D, P, I, P, I]
@@ -201,17 +202,20 @@ class Oracle:
         return la.eigh(Ls, Ms, eigvals_only=True, subset_by_index=[0, k - 1])
 
     def solve(self, t, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, x0=None, mode="pcg",
-              coarse_eps=1e-6, gamma=1, nu_coarse=0):
+              coarse_eps=1e-6, gamma=1, nu_coarse=0, smoother="gs", block_omega=0.7):
         """mode 'pcg' (CG preconditioned by one cycle) or 'vcycle' (stationary
         cycles); gamma 1 for V-cycles, 2 for W-cycles; nu_coarse > 0 sweeps
-        each way below the finest depth."""
+        each way below the finest depth; smoother 'gs' (multicolour
+        Gauss-Seidel) or 'block' (cell-block Schwarz, degree 1, corrections
+        damped by block_omega)."""
         n = self.count(self.depth, "functions")
         b, k = _colmajor(b, n)
         x = np.zeros((n, k), order="F") if x0 is None else np.array(_colmajor(x0, n)[0], order="F")
         stats = np.zeros(5); hist = np.zeros(max_iter + 1)
         rc = self.lib.oracle_solve(self.h, t, rtol, max_iter, nu1, nu2, _p(b), k, _p(x),
                                    0 if x0 is None else 1, _p(stats), _p(hist),
-                                   {"vcycle": 0, "pcg": 1}[mode], coarse_eps, gamma, nu_coarse)
+                                   {"vcycle": 0, "pcg": 1}[mode], coarse_eps, gamma, nu_coarse,
+                                   {"gs": 0, "block": 1}[smoother], block_omega)
         if rc < 0:
             raise RuntimeError("oracle solve: " + self.lib.oracle_error(self.h).decode())
         it = int(stats[4])
@@ -232,6 +236,15 @@ class Oracle:
         b, k = _colmajor(b, n)
         x = np.array(_colmajor(x, n)[0], order="F")
         self.lib.oracle_gs_sweep(self.h, d, t, _p(b), k, _p(x), 1 if forward else 0)
+        return x
+
+    def block_sweep(self, d, t, b, x, forward=True, eps=1e-6, omega=0.7):
+        """One cell-block Schwarz sweep at depth d (degree 1), damped by omega."""
+        n = self.count(d, "functions")
+        b, k = _colmajor(b, n)
+        x = np.array(_colmajor(x, n)[0], order="F")
+        if self.lib.oracle_block_sweep(self.h, d, t, _p(b), k, _p(x), 1 if forward else 0, eps, omega) != 0:
+            raise RuntimeError("oracle block sweep: " + self.lib.oracle_error(self.h).decode())
         return x
 
     def eval_vertices(self, x):

@@ -1,0 +1,118 @@
+"""Pins of the oracle's cell-block Schwarz smoother (not in the paper: an
+alternative to its Gauss-Seidel smoother, Section 5.2, for the trilinear
+space).  A block holds the functions of one occupied cell; a forward sweep
+adds omega (1 / mult_i) sum_B (A_B^-1 r_B)_i, a backward sweep
+omega sum_B (A_B^-1 (r / mult)_B)_i, with r = b - A x, mult_i the number of
+blocks holding i and the damping omega (0.7 by default).
+
+Pinned here against things the definition fixes without restating it:
+- a mesh inside one cell gives one block holding every function, so one
+  sweep is a dense solve of the (unit-diagonal-scaled, eps-shifted) system,
+  checked against a library solver;
+- the backward sweep is the A-adjoint of the forward one (the identity
+  <A S_f e, g> = <A e, S_b g> fails when 1 / mult sits on the wrong side);
+- the solution of A x = b is a fixed point of both sweeps (fails on a sign
+  slip in the residual);
+- the symmetric cycle built from them preconditions CG to the dense solution,
+  in fewer cycles than Gauss-Seidel on a knot tube.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as la
+
+from oracle import Oracle
+from paper_1505_03615_amd import meshgen
+
+
+def test_one_cell_mesh_is_one_dense_block():
+    # a triangle strictly inside the cell [1, 2]^3 of the depth-2 grid on [0, 4]^3
+    V = np.array([[1.2, 1.3, 1.25], [1.8, 1.35, 1.5], [1.4, 1.75, 1.8]])
+    F = np.array([[0, 1, 2]], np.int32)
+    o = Oracle(V, F, 2, max_coarse=0, min_depth=2, box=[0, 0, 0, 4.0]).check().assemble()
+    assert len(o.cells(2)) == 1 and o.count(2, "functions") == 8
+    M, L = o.matrices(2)
+    A = (M + 0.3 * L).toarray()
+    rng = np.random.default_rng(1)
+    b = rng.normal(size=(8, 2))
+    for eps in (1e-6, 1e-3):
+        x = o.block_sweep(2, 0.3, b, np.zeros((8, 2)), forward=True, eps=eps, omega=1.0)
+        s = 1.0 / np.sqrt(np.diag(A))
+        ref = s[:, None] * la.solve(A * np.outer(s, s) + eps * np.eye(8), s[:, None] * b, assume_a="pos")
+        assert np.abs(x - ref).max() <= 1e-9 * np.abs(ref).max(), eps
+        # one block: mult = 1, the backward sweep is the same map
+        xb = o.block_sweep(2, 0.3, b, np.zeros((8, 2)), forward=False, eps=eps, omega=1.0)
+        assert np.abs(xb - x).max() <= 1e-12 * np.abs(x).max()
+
+
+@pytest.mark.parametrize("mesh", ["sheets", "knot"])
+def test_backward_sweep_is_the_adjoint_of_the_forward_sweep(mesh):
+    if mesh == "sheets":
+        V, F, _, _ = meshgen.two_sheets(16, 1.0 / 64)      # split supports: blocks of up to 16
+        o = Oracle(V, F, 5, max_coarse=0, min_depth=4).check().assemble()
+        d, t = 5, 1e-3
+    else:
+        V, F = meshgen.torus_knot(nu=256, nv=12, seed=3)
+        o = Oracle(V, F, 6, max_coarse=0, min_depth=5).check().assemble()
+        d, t = 6, 1e-4
+    M, L = o.matrices(d)
+    A = M + t * L
+    n = A.shape[0]
+    rng = np.random.default_rng(7)
+    e, g = rng.normal(size=n), rng.normal(size=n)
+    zero = np.zeros(n)
+    Sfe = o.block_sweep(d, t, zero, e, forward=True)[:, 0]     # e - W_f A e
+    Sbg = o.block_sweep(d, t, zero, g, forward=False)[:, 0]    # g - W_b A g
+    lhs, rhs = (A @ Sfe) @ g, (A @ e) @ Sbg
+    assert abs(lhs - rhs) <= 1e-12 * (abs(A @ e) @ abs(g))
+    # and the forward sweep alone is not self-adjoint when blocks overlap
+    # unevenly (so the identity above has something to catch)
+    Sfg = o.block_sweep(d, t, zero, g, forward=True)[:, 0]
+    assert abs((A @ Sfe) @ g - (A @ e) @ Sfg) > 1e-6 * (abs(A @ e) @ abs(g))
+
+
+def test_solution_is_a_fixed_point():
+    V, F = meshgen.icosphere(2)
+    o = Oracle(V, F, 4, max_coarse=0, min_depth=3).check().assemble()
+    M, L = o.matrices(4)
+    A = (M + 1e-2 * L).toarray()
+    x = np.random.default_rng(3).normal(size=(A.shape[0], 2))
+    b = A @ x
+    for fwd in (True, False):
+        y = o.block_sweep(4, 1e-2, b, x, forward=fwd)
+        assert np.abs(y - x).max() <= 1e-10 * np.abs(x).max()
+
+
+def test_block_cycles_precondition_cg_to_the_dense_solution():
+    V, F = meshgen.torus_knot(nu=512, nv=16, seed=3)
+    o = Oracle(V, F, 6, max_coarse=256).check().assemble()
+    f = V[:, 2] + 0.1 * V[:, 0] ** 2
+    b = o.load_vector(f)
+    M, L = o.matrices(6)
+    A = M + 1e-4 * L
+    xg, ig = o.solve(1e-4, b, rtol=1e-11, max_iter=500)
+    xb, ib = o.solve(1e-4, b, rtol=1e-11, max_iter=500, smoother="block")
+    assert ib["converged"] and ig["converged"]
+    assert np.linalg.norm(b - A @ xb) <= 1e-11 * np.linalg.norm(b)
+    # (the knot's matrix has rounding-sliver rows of zero mass, so compare the
+    # two solutions where they mean something: at the mesh vertices)
+    ub, ug = o.eval_vertices(xb), o.eval_vertices(xg)
+    assert np.abs(ub - ug).max() <= 1e-8 * np.abs(ug).max()
+    assert ib["cycles"] < 0.5 * ig["cycles"]
+    # on a nonsingular system the dense solution itself
+    Vs, Fs = meshgen.icosphere(2)
+    os_ = Oracle(Vs, Fs, 4, max_coarse=64).check().assemble()
+    bs = os_.load_vector(Vs[:, 2])
+    Ms, Ls = os_.matrices(4)
+    xd = la.solve((Ms + 1e-2 * Ls).toarray(), bs, assume_a="pos")
+    xs, ist = os_.solve(1e-2, bs, rtol=1e-12, max_iter=300, smoother="block")
+    assert np.abs(xs - xd).max() <= 1e-8 * np.abs(xd).max()
+    # damped stationary block cycles contract the residual every cycle; the
+    # undamped ones overshoot on this mesh and diverge
+    _, iv = o.solve(1e-4, b, rtol=1e-30, max_iter=25, mode="vcycle", smoother="block")
+    assert np.all(np.diff(iv["history"]) < 0) and iv["history"][-1] < 1e-5
+    _, iu = o.solve(1e-4, b, rtol=1e-30, max_iter=25, mode="vcycle", smoother="block", block_omega=1.0)
+    assert iu["history"][-1] > 1.0
+    Vi, Fi = meshgen.icosphere(1)
+    o2 = Oracle(Vi, Fi, 3, degree=2, max_coarse=64).check().assemble()
+    with pytest.raises(RuntimeError, match="degree 1"):
+        o2.solve(1e-3, np.ones(o2.count(3, "functions")), smoother="block")

@@ -198,8 +198,16 @@ typedef struct {
                      /*    FP32 cycles cannot amplify rounding past O(0.1))       */
   int smoother;      /* 0: multicolour Gauss-Seidel (Section 5.2); 1: weighted    */
                      /*    Jacobi with constant omega; 2: the attached learned    */
-                     /*    model's smoother (Jacobi or SOR, per-row omega)        */
-  double omega;      /* omega of smoother 1                                       */
+                     /*    model's smoother (Jacobi or SOR, per-row omega);       */
+                     /*    3: cell-block Schwarz (not in the paper; degree 1):    */
+                     /*    a block per occupied cell holding the functions of its */
+                     /*    8 corners met there (single-function blocks in cells   */
+                     /*    of more than 16), inverses of the unit-diagonal-scaled */
+                     /*    blocks plus coarse_eps I; a sweep adds                 */
+                     /*    omega sum_B w_B R_B^T A_B^-1 R_B (b - A x), w_B = 1 /  */
+                     /*    (the most blocks holding one of B's functions): an     */
+                     /*    A-norm contraction for omega in (0, 1]                 */
+  double omega;      /* omega of smoother 1; damping of smoother 3 (0: 1)        */
   int judge;         /* smoother 1 or 2 with method 0: Gauss-Seidel as judge.     */
                      /*    The requested smoother and plain Gauss-Seidel each run */
                      /*    `judge` CG iterations from the start; the one with the */
@@ -217,8 +225,10 @@ typedef struct {
 
 typedef struct {
   int iterations;    /* outer iterations done                                     */
-  int fell_back;     /* 1 when the smoother (1 or 2) failed and Gauss-Seidel redid */
-                     /*    the solve; 2 when the judge continued with Gauss-Seidel */
+  int fell_back;     /* 1 when the smoother (1 or 2, or 3 under CG) stopped above */
+                     /*    rtol and Gauss-Seidel redid the solve (stationary      */
+                     /*    cycles of smoother 3 are returned as asked); 2 when    */
+                     /*    the judge continued with Gauss-Seidel                  */
   int cycles;        /* V-cycles applied                                          */
   int eps_regularised;
   double rel_residual; /* max over columns of ||b - A x|| / ||b|| (FP64)          */

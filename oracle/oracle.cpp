@@ -720,10 +720,10 @@ struct SysLevel {
   bool direct = false;
   const Level* lev = nullptr;
   // cell-block Schwarz smoother: function lists of the blocks, the inverse of
-  // each block (m x m row-major) and 1 / (blocks holding each function)
+  // each block (m x m row-major) and each block's weight
   std::vector<std::vector<long>> blocks;
   std::vector<std::vector<double>> binv;
-  std::vector<double> invmult;
+  std::vector<double> bweight;
 };
 
 int colour_of(int degree, uint64_t key) {
@@ -771,7 +771,7 @@ struct Solver {
   int nu_coarse = 0;          // sweeps each way below the finest depth (0: nu1, nu2)
   int eps_used = 0;
   int smoother = 0;           // 0 multicolour Gauss-Seidel, 1 cell-block Schwarz
-  double block_omega = 0.7;   // damping of the cell-block corrections
+  double block_omega = 1.0;   // damping of the cell-block corrections
 };
 
 void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward);
@@ -828,10 +828,18 @@ void build_blocks(const Hier& h, int d, SysLevel& S, double eps) {
     }
     p = q;
   }
-  S.invmult.assign(S.n, 0.0);
+  // weight of a block: 1 / (the largest number of blocks holding one of its
+  // functions), so that the weights of the blocks holding any function sum to
+  // at most 1
+  std::vector<double> mult(S.n, 0.0);
   for (const auto& b : raw)
-    for (long f : b) S.invmult[f] += 1.0;
-  for (long i = 0; i < S.n; ++i) S.invmult[i] = S.invmult[i] > 0.0 ? 1.0 / S.invmult[i] : 0.0;
+    for (long f : b) mult[f] += 1.0;
+  S.bweight.clear();
+  for (const auto& b : raw) {
+    double mx = 0.0;
+    for (long f : b) mx = std::max(mx, mult[f]);
+    S.bweight.push_back(1.0 / mx);
+  }
   for (const auto& b : raw) {
     const long m = (long)b.size();
     std::vector<double> sc(m), A((size_t)m * m), inv((size_t)m * m, 0.0);
@@ -851,20 +859,15 @@ void build_blocks(const Hier& h, int d, SysLevel& S, double eps) {
   }
 }
 
-// One cell-block Schwarz sweep with damping omega: r = b - A x, then
-//   forward:  x_i += omega (1 / mult_i) sum over blocks B holding i of (A_B^-1 r_B)_i
-//   backward: x_i += omega              sum over blocks B holding i of (A_B^-1 (r / mult)_B)_i
-// The backward sweep is the A-adjoint of the forward one, so forward sweeps
-// before the coarse correction and backward sweeps after it make a symmetric
-// cycle.  Undamped (omega = 1) the averaged overlapping corrections can
-// overshoot some modes: stationary cycles then diverge on some meshes while
-// CG preconditioned by the cycle still converges.
-void block_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward, double omega) {
+// One cell-block Schwarz sweep: r = b - A x, then
+//   x += omega sum over blocks B of w_B R_B^T A_B^-1 R_B r
+// with w_B the block's weight.  The map is symmetric (the same before and
+// after the coarse correction) and, since the weights holding any function
+// sum to at most 1, an A-norm contraction for omega in (0, 1]: the cycle is
+// a positive definite preconditioner.
+void block_sweep(const SysLevel& S, const double* b, double* x, int k, double omega) {
   std::vector<double> r((size_t)S.n * k), u((size_t)S.n * k, 0.0);
   residual(S, b, x, k, r.data());
-  if (!forward)
-    for (int q = 0; q < k; ++q)
-      for (long i = 0; i < S.n; ++i) r[(size_t)q * S.n + i] *= S.invmult[i];
   for (size_t bi = 0; bi < S.blocks.size(); ++bi) {
     const std::vector<long>& blk = S.blocks[bi];
     const long m = (long)blk.size();
@@ -872,16 +875,14 @@ void block_sweep(const SysLevel& S, const double* b, double* x, int k, bool forw
       for (long i = 0; i < m; ++i) {
         double acc = 0.0;
         for (long j = 0; j < m; ++j) acc += S.binv[bi][i * m + j] * r[(size_t)q * S.n + blk[j]];
-        u[(size_t)q * S.n + blk[i]] += acc;
+        u[(size_t)q * S.n + blk[i]] += S.bweight[bi] * acc;
       }
   }
-  for (int q = 0; q < k; ++q)
-    for (long i = 0; i < S.n; ++i)
-      x[(size_t)q * S.n + i] += omega * (forward ? S.invmult[i] * u[(size_t)q * S.n + i] : u[(size_t)q * S.n + i]);
+  for (size_t e = 0; e < u.size(); ++e) x[e] += omega * u[e];
 }
 
 void smooth(const Solver& sv, const SysLevel& S, const double* b, double* x, int k, bool forward) {
-  if (sv.smoother == 1) block_sweep(S, b, x, k, forward, sv.block_omega);
+  if (sv.smoother == 1) block_sweep(S, b, x, k, sv.block_omega);
   else gs_sweep(S, b, x, k, forward);
 }
 
@@ -1291,8 +1292,8 @@ int oracle_gs_sweep(void* hp, int d, double t, const double* b, int k, double* x
   return 0;
 }
 
-// One cell-block Schwarz sweep at depth d (forward or backward, for
-// sweep-level checks); eps as in the solver's block inverses
+// One cell-block Schwarz sweep at depth d (for sweep-level checks; forward
+// and backward are the same map); eps as in the solver's block inverses
 int oracle_block_sweep(void* hp, int d, double t, const double* b, int k, double* x, int forward, double eps,
                        double omega) {
   Hier& h = ((OracleHandle*)hp)->h;
@@ -1313,7 +1314,8 @@ int oracle_block_sweep(void* hp, int d, double t, const double* b, int k, double
     h.err = e.what();
     return -1;
   }
-  block_sweep(S, b, x, k, forward != 0, omega);
+  (void)forward;   // the block sweep is the same map in both directions
+  block_sweep(S, b, x, k, omega);
   return 0;
 }
 

@@ -202,7 +202,7 @@ class Oracle:
         return la.eigh(Ls, Ms, eigvals_only=True, subset_by_index=[0, k - 1])
 
     def solve(self, t, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, x0=None, mode="pcg",
-              coarse_eps=1e-6, gamma=1, nu_coarse=0, smoother="gs", block_omega=0.7):
+              coarse_eps=1e-6, gamma=1, nu_coarse=0, smoother="gs", block_omega=1.0):
         """mode 'pcg' (CG preconditioned by one cycle) or 'vcycle' (stationary
         cycles); gamma 1 for V-cycles, 2 for W-cycles; nu_coarse > 0 sweeps
         each way below the finest depth; smoother 'gs' (multicolour
@@ -238,7 +238,7 @@ class Oracle:
         self.lib.oracle_gs_sweep(self.h, d, t, _p(b), k, _p(x), 1 if forward else 0)
         return x
 
-    def block_sweep(self, d, t, b, x, forward=True, eps=1e-6, omega=0.7):
+    def block_sweep(self, d, t, b, x, forward=True, eps=1e-6, omega=1.0):
         """One cell-block Schwarz sweep at depth d (degree 1), damped by omega."""
         n = self.count(d, "functions")
         b, k = _colmajor(b, n)

@@ -1,0 +1,54 @@
+// Cell-block Schwarz smoother (not in the paper; an alternative to its
+// Gauss-Seidel smoother, Section 5.2, for the trilinear space): the sweep's
+// block product x += omega sum_B w_B R_B^T A_B^-1 R_B r.  Included by
+// solve.hip only.
+//
+// A block holds the functions of one occupied cell (its 8 corners, one
+// function per component met in the cell), with the symmetric inverse of its
+// unit-diagonal-scaled matrix stored W x W (padded with zeros), its weight w_B
+// and the row scales s_i = 1 / sqrt(A_ii): A_B^-1 r_B = s (inverse (s r)).  A
+// group of W lanes of a wavefront takes one block: lane i loads s_i r_i of
+// the block's function i, the group's values meet through shuffles, lane i
+// forms its entry of the product reading column i of the inverse (the
+// group's loads of one column entry are W consecutive values: coalesced) and
+// adds it, times omega w_B s_i, to x_i with an atomic add (a function sits in
+// up to eight blocks).  A row with s_i = 0 (zero mass; in FP32 also a
+// diagonal whose reciprocal has no FP32 value) takes no part.
+#pragma once
+
+#include "solver.hpp"
+
+namespace camfe {
+namespace {
+
+template <class T, int K, int W>
+__global__ __launch_bounds__(256) void k_block_apply(long long nb, const int* idx, const T* inv, const T* weight,
+                                                     const T* scale, const T* r, T omega, T* x) {
+  const long long g = blockIdx.x * 256LL + threadIdx.x;
+  const long long b = g / W;
+  const int i = (int)(g % W);
+  const bool ok = b < nb;
+  const int f = ok ? idx[b * W + i] : -1;
+  const T sf = f >= 0 ? scale[f] : (T)0;
+  T rv[K], u[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    rv[q] = f >= 0 ? sf * r[(long long)f * K + q] : (T)0;
+    u[q] = 0;
+  }
+  const T* col = inv + (ok ? b : 0) * (long long)W * W + i;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const T a = ok ? col[j * W] : (T)0;   // entry (j, i) = (i, j): the inverse is symmetric
+#pragma unroll
+    for (int q = 0; q < K; ++q) u[q] = fma(a, __shfl(rv[q], j, W), u[q]);
+  }
+  if (f >= 0 && sf != (T)0) {
+    const T w = omega * weight[b] * sf;
+#pragma unroll
+    for (int q = 0; q < K; ++q) atomicAdd(&x[(long long)f * K + q], w * u[q]);
+  }
+}
+
+}  // namespace
+}  // namespace camfe

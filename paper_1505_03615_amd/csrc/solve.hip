@@ -21,8 +21,11 @@
 #include <string>
 #include <map>
 
+#include <type_traits>
+
 #include "solver.hpp"
 #include "sell_kernels.hpp"
+#include "block_kernels.hpp"
 
 namespace camfe {
 
@@ -885,9 +888,42 @@ const T* sweep_dinv(const SolverState* S, const GLevel& G) {
 
 // first0: x was zero and the first sweep's colour-0 rows are already relaxed
 // (by the kernel that zeroed x), so that sweep starts at colour 1
+// nu cell-block Schwarz sweeps: r = b - A x into the level's scratch vector,
+// then the weighted block products of both block classes added into x (the
+// same map before and after the coarse correction)
+template <class T, int K>
+void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  constexpr bool dbl = std::is_same<T, double>::value;
+  const T* inv8 = dbl ? (const T*)G.binv8_64.p : (const T*)G.binv8_32.p;
+  const T* inv16 = dbl ? (const T*)G.binv16_64.p : (const T*)G.binv16_32.p;
+  const T* w8 = dbl ? (const T*)G.bw8_64.p : (const T*)G.bw8_32.p;
+  const T* w16 = dbl ? (const T*)G.bw16_64.p : (const T*)G.bw16_32.p;
+  const T* sc = dbl ? (const T*)G.bs64.p : (const T*)G.bs32.p;
+  T* r = tmp_of<T>(G);
+  for (int it = 0; it < nu; ++it) {
+    CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
+                (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p, (int)G.nslices, G.scol.p, sval_of<T>(G), b,
+                (const T*)x, r, (double*)nullptr);
+    if (G.nb8)
+      CAMFE_TIMED(ctx, KT_GS, ((double)G.nb8 * 8 * (8 * sizeof(T) + 4) + 3.0 * G.n * K * sizeof(T)),
+                  (k_block_apply<T, K, 8>), grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, G.nb8, G.bidx8.p, inv8,
+                  w8, sc, (const T*)r, (T)S->block_omega, x);
+    if (G.nb16)
+      CAMFE_TIMED(ctx, KT_GS, ((double)G.nb16 * 16 * (16 * sizeof(T) + 4)), (k_block_apply<T, K, 16>),
+                  grid_for((size_t)G.nb16 * 16, 256), 256, 0, st, G.nb16, G.bidx16.p, inv16, w16, sc,
+                  (const T*)r, (T)S->block_omega, x);
+  }
+}
+
 template <class T, int K>
 void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward, bool first0 = false) {
   camfe_ctx ctx = S->ctx;
+  if (S->smoother == 3) {
+    block_smooth<T, K>(S, G, b, x, nu);
+    return;
+  }
   if (const T* dinv = sweep_dinv<T>(S, G)) {
     for (int i = 0; i < nu; ++i) gs_sweep<T, K>(ctx, G, b, x, forward, dinv, i == 0 && first0 && forward ? 1 : 0);
     return;
@@ -2015,8 +2051,11 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     camfe_hier h = s->h;
     camfe_ctx ctx = h->ctx;
     ctx->use_device();
-    CAMFE_REQUIRE(o->smoother >= 0 && o->smoother <= 2, CAMFE_EINVAL, "smoother must be 0, 1 or 2");
+    CAMFE_REQUIRE(o->smoother >= 0 && o->smoother <= 3, CAMFE_EINVAL, "smoother must be 0, 1, 2 or 3");
     CAMFE_REQUIRE(o->smoother != 1 || (o->omega > 0 && o->omega < 2), CAMFE_EINVAL, "omega must lie in (0, 2)");
+    CAMFE_REQUIRE(o->smoother != 3 || (o->omega >= 0 && o->omega <= 1), CAMFE_EINVAL,
+                  "block damping omega must lie in [0, 1] (0: 1)");
+    CAMFE_REQUIRE(o->smoother != 3 || h->degree == 1, CAMFE_EINVAL, "the cell-block smoother is defined for degree 1");
     CAMFE_REQUIRE(o->smoother != 2 || s->model, CAMFE_ESTATE, "learned smoother requested but no model attached");
     SolverState* S = ensure_solver(s, o->t, o->coarse_eps);
     S->precision = o->precision;   // both precisions share one setup
@@ -2030,7 +2069,14 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     S->nu_coarse = o->nu_coarse;
     const bool stale = o->smoother != S->wkind || (o->smoother == 1 && o->omega != S->omega) ||
                        (o->smoother == 2 && s->model != S->model);
-    if (o->smoother != 0 && stale) {
+    if (o->smoother == 3) {
+      if (!S->blocks_ready) build_cell_blocks(s, S);
+      const double bw = o->omega > 0 ? o->omega : 1.0;
+      if (S->block_omega != bw) {   // captured cycles hold the damping as a kernel argument
+        S->drop_graphs();
+        S->block_omega = bw;
+      }
+    } else if (o->smoother != 0 && stale) {
       set_smoother_weights(s, S, o->smoother, o->omega, o->smoother == 2 ? s->model : nullptr);
     }
     S->smoother = o->smoother;
@@ -2060,7 +2106,9 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     };
     SolveResult tot = run_all(*o);
     int fell_back = tot.judged_gs ? 2 : 0;
-    if (o->smoother != 0 && !tot.judged_gs && !(tot.rel <= o->rtol)) {
+    // (stationary cycles of the cell-block smoother, a contraction, are
+    // returned as asked; under CG a failed block solve is redone too)
+    if (o->smoother != 0 && !(o->smoother == 3 && o->method == 1) && !tot.judged_gs && !(tot.rel <= o->rtol)) {
       // the Jacobi smoother failed (diverged or stalled): Gauss-Seidel redoes the solve
       camfe_solve_opts go = *o;
       go.smoother = 0;

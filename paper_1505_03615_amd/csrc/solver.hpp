@@ -47,6 +47,14 @@ struct GLevel {
   // work vectors, n x KMAXS row-major (t: Jacobi ping-pong)
   DArr<double> x64, b64, r64, t64;
   DArr<float> x32, b32, r32, t32;
+  // cell-block Schwarz smoother: blocks of at most 8 and of 9..16 functions
+  // (internal rows, -1 padding), their symmetric inverses (W x W each) and
+  // weights 1 / (largest number of blocks holding one of their functions)
+  // (the inverses of the unit-diagonal-scaled blocks; bs = 1 / sqrt(A_ii))
+  long long nb8 = 0, nb16 = 0;
+  DArr<int> bidx8, bidx16;
+  DArr<double> binv8_64, binv16_64, bw8_64, bw16_64, bs64;
+  DArr<float> binv8_32, binv16_32, bw8_32, bw16_32, bs32;
   // batched solver only: meshes whose coarsest depth sits at this level and is
   // solved directly: first row of each, cumulative row counts (ncb + 1) and
   // the offset of each one's dense FP64 inverse in cb_a64
@@ -63,7 +71,10 @@ struct SolverState {
   int precision = 0;
   int gamma = 1;             // coarse cycles per depth: 1 V-cycle, 2 W-cycle (set per solve)
   int nu_coarse = 0;         // sweeps each way below the finest depth (0: as at the finest; set per solve)
-  int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi
+  int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi,
+                             // 3 cell-block Schwarz
+  bool blocks_ready = false; // cell blocks built for this state (t, coarse_eps)
+  double block_omega = 0;    // damping of the cell-block corrections
   int wkind = 0;             // smoother whose weights winvd holds (0: none)
   int wsweep = 0;            // sweep those weights are for: 0 Jacobi, 1 multicolour SOR
   double omega = 0;          // constant omega of smoother 1
@@ -101,5 +112,7 @@ struct SolverState {
 
 // smoother.hip: Jacobi weights for smoother 1 (constant) or 2 (learned model)
 void set_smoother_weights(camfe_sys s, SolverState* S, int smoother, double omega, const void* model);
+// block.hip: cell blocks and their inverses at every depth of S (degree 1)
+void build_cell_blocks(camfe_sys s, SolverState* S);
 
 }  // namespace camfe

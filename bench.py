@@ -135,12 +135,13 @@ def cpu_baseline(cf, ctx, meshgen, full, sample=CPU_SAMPLE):
     mn = float(np.sqrt(xo[:, 0] @ (Mo @ xo[:, 0])))
     for tag, kw in (("plain_gs_fp64", dict(precision=0, smoother=0)),
                     ("plain_gs_mixed", dict(precision=1, smoother=0)),
-                    ("learned_mixed", dict(precision=1, smoother=2))):
+                    ("learned_mixed", dict(precision=1, smoother=2)),
+                    ("block_mixed", dict(precision=1, smoother=3))):
         cf.camfe_smoother_attach(s, full.get("model") if tag == "learned_mixed" else None)
         x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
         d = x[:, 0] - xo[:, 0]
         r = np.linalg.norm(b[:, 0] - (Mo + t * Lo) @ x[:, 0]) / np.linalg.norm(b)
-        errs[tag] = {"rel_M_norm_error": float(np.sqrt(d @ (Mo @ d)) / mn),
+        errs[tag] = {"fell_back": int(st["fell_back"]), "rel_M_norm_error": float(np.sqrt(d @ (Mo @ d)) / mn),
                      "rel_vertex_error": float(np.abs(cf.camfe_eval_vertices(s, len(V), x) - uo).max() /
                                                np.abs(uo).max()),
                      "rel_residual_in_oracle_matrices": float(r), "cycles": st["cycles"]}
@@ -305,10 +306,12 @@ def cycle_roofline(bytes_per_cycle, ms, cycles):
 
 SOLVERS = (("plain_gs_fp64", dict(precision=0, smoother=0)),
            ("plain_gs_mixed", dict(precision=1, smoother=0)),
-           ("learned_mixed", dict(precision=1, smoother=2)))
+           ("learned_mixed", dict(precision=1, smoother=2)),
+           # cell-block Schwarz (smoother 3): CG capped at 500 iterations, then Gauss-Seidel redoes the solve
+           ("block_mixed", dict(precision=1, smoother=3, max_iter=500)))
 
 
-def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mixed", "learned_mixed"),
+def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mixed", "learned_mixed", "block_mixed"),
                      max_iter=4000):
     """Each solver to 1e-8 on one assembled system, warm: a 4-iteration solve
     first builds the solver state and captures the graphs, then the full
@@ -322,8 +325,10 @@ def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mi
         if tag not in which:
             continue
         cf.camfe_smoother_attach(s, model if tag == "learned_mixed" else None)
+        kw = dict(kw)
+        mi = kw.pop("max_iter", max_iter)
         cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4, **kw)
-        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=max_iter, **kw)
+        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=mi, **kw)
         res[tag] = {"s": st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
                     "converged": bool(st["converged"]), "fell_back": int(st["fell_back"]),
                     "setup_s": st["setup_seconds"], "dof_cycles_per_s": n * st["cycles"] / st["seconds"]}
@@ -879,7 +884,7 @@ def main():
     solve_s = float(np.mean([x["seconds"] for x in sts]))
     cycles = float(np.mean([x["cycles"] for x in sts]))
     log("[bench] plain Gauss-Seidel solves of the same system")
-    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed"))
+    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed", "block_mixed"))
     comp["learned_mixed"] = {"s": solve_s, "cycles": cycles, "rel_residual": float(max(x["rel_residual"] for x in sts)),
                              "converged": bool(all(x["converged"] for x in sts)),
                              "fell_back": int(max(x["fell_back"] for x in sts)),
@@ -961,6 +966,9 @@ def main():
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cf, ctx, meshgen, {"dof": int(n), "cycles_fp64": comp["plain_gs_fp64"]["cycles"],
                                                               "model": model})
+        # every solver's result against the oracle's FP64 solution, on the oracle-sized sample
+        out["error_vs_oracle"] = {"sample": out["cpu_baseline"]["sample"].split(";")[0],
+                                  **out["cpu_baseline"]["gpu_error_vs_oracle_on_sample"]}
     cf.camfe_model_destroy(model)
     cf.camfe_ctx_destroy(ctx)
     print(json.dumps(out), flush=True)

@@ -727,7 +727,9 @@ def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
             tune_s = time.perf_counter() - t0
         cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=4)      # capture
         xs, sts = cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=2000)
-        runs[tag] = {"solve_s": sts[0]["seconds"], "iterations": max(x["iterations"] for x in sts),
+        its = sorted(x["iterations"] for x in sts)
+        runs[tag] = {"solve_s": sts[0]["seconds"], "iterations": its[-1],
+                     "member_iterations_median": its[len(its) // 2], "member_iterations_sum": int(sum(its)),
                      "all_converged": bool(all(x["converged"] for x in sts)),
                      "max_rel_residual": float(max(x["rel_residual"] for x in sts))}
         log(f"[bench] batch {tag}: " + json.dumps(runs[tag]))
@@ -764,6 +766,7 @@ def main():
     ap.add_argument("--no-sheets", action="store_true", help="skip the two-sheet coupling test (depth 8)")
     ap.add_argument("--no-flow", action="store_true", help="skip the config-3 flow steps")
     ap.add_argument("--batch-meshes", type=int, default=64, help="meshes of the config-4 batch (0: skip)")
+    ap.add_argument("--batch-only", action="store_true", help="only the config-4 batch")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the roofline measurement: hierarchy, assembly, solver setup (no cycles), then the "
                          "measured kernel; for profiler runs whose only Gauss-Seidel launches are the measured ones")
@@ -800,7 +803,8 @@ def main():
             "spectrum": (args.spectrum_only, lambda: spectrum_eval(cf, ctx, meshgen)),
             "flow_study": (args.flow_study_only, lambda: flow_study_eval(cf, ctx, meshgen)),
             "colour_fit_cubes": (args.cubes_only, lambda: cubes_eval(cf, ctx, meshgen)),
-            "assembly": (args.assembly_only, lambda: assembly_eval(cf, ctx, meshgen))}
+            "assembly": (args.assembly_only, lambda: assembly_eval(cf, ctx, meshgen)),
+            "batch_config4": (args.batch_only, lambda: batch_eval(cf, ctx, meshgen, max(args.batch_meshes, 1)))}
     for key, (flag, fn) in only.items():
         if flag:
             out = {key: fn()}

@@ -363,7 +363,11 @@ camfe_status camfe_eigs(camfe_sys s, const camfe_eig_opts *opts, double *evals, 
  * up by depth below their finest (each mesh bottoms out at its own coarsest
  * depth), and every phase of the V-cycle and of CG is one launch over all
  * meshes, captured into a HIP graph.  CG keeps its scalars per mesh and
- * column, and freezes columns that have converged. */
+ * column, and freezes columns that have converged (checked every four
+ * iterations).  A member whose columns have all converged drops out: its
+ * slices, transfer rows, coarse solve and CG vector blocks are skipped by
+ * every later launch, so the batch costs what its members still iterating
+ * cost. */
 typedef struct camfe_batch_s *camfe_batch;
 /* Copies the systems' solver data for A = M + t L (building it where missing);
  * later changes to the systems do not reach the batch.  All systems share the
@@ -377,7 +381,9 @@ camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const *systems, int nsy
 camfe_status camfe_batch_info(camfe_batch b, int *levels, int64_t *rows);
 /* b[m], x[m]: n_m x k[m] column-major (x[m] read when x0_given); opts->t and
  * coarse_eps must be the batch's, method 0 and smoother 0.  stats (nullable)
- * has nsys entries.  Returns CAMFE_ENOCONV when any mesh stops above rtol. */
+ * has nsys entries: iterations and cycles are those member m took part in,
+ * seconds the whole batch's.  Returns CAMFE_ENOCONV when any mesh stops above
+ * rtol. */
 camfe_status camfe_batch_solve(camfe_batch b, const camfe_solve_opts *opts, const double *const *b_in, const int *k,
                                double *const *x, camfe_solve_stats *stats);
 /* camfe_system_autotune over the batch's levels (finest last; the levels

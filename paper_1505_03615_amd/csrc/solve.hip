@@ -216,12 +216,22 @@ __global__ void k_diag_of(const int* ptr, const int* col, const double* M, const
 }
 
 // ------------------------------------------------------ V-cycle kernels
+// Batched solves gate the row-parallel kernels by member: with gate != null a
+// workgroup whose rows belong to a member m with act[m] == 0 (every column of
+// it converged) returns at once.  A member's rows are padded to whole
+// BLK-row blocks, so each block has one member (gate[block]); its slices are
+// emptied in the gated slice records instead (k_gate_meta).
+__device__ inline bool gated_off(const int* gate, const int* act, long long blk) {
+  return gate && !act[gate[blk]];
+}
+
 // b_c = R r_f (coarse rows gather their fine children, 8 lanes per row) and
-// x_c = 0 for the recursion
+// x_c = 0 for the recursion (gate: member of each BLK-row block of the coarse level)
 constexpr int RL = 8;
 template <class T, int K>
 __global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long long nc, const T* rf, T* bc, T* xc,
-                           const T* dinv, long long n0c) {
+                           const T* dinv, long long n0c, const int* gate, const int* act) {
+  if (gated_off(gate, act, blockIdx.x * (long long)(BLK / RL) / BLK)) return;
   const long long g = blockIdx.x * (long long)BLK + threadIdx.x;
   const long long i = g / RL;
   const int sub = (int)(g % RL);
@@ -250,11 +260,12 @@ __global__ void k_restrict(const int* Rptr, const int* Rcol, const T* Rw, long l
   }
 }
 
-// x_f += P x_c
+// x_f += P x_c (gate: member of each BLK-row block of the fine level)
 template <class T, int K>
-__global__ void k_prolong(const int* Pptr, const int* Pcol, const T* Pw, long long nf, const T* xc, T* xf) {
+__global__ void k_prolong(const int* Pptr, const int* Pcol, const T* Pw, long long nf, const T* xc, T* xf,
+                          const int* gate, const int* act) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
-  if (i >= nf) return;
+  if (i >= nf || gated_off(gate, act, blockIdx.x)) return;
   T acc[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) acc[q] = 0;
@@ -296,15 +307,17 @@ __global__ void k_coarse(const double* Ainv, int n, const T* b, T* x) {
 }
 
 // batched coarse solves: x = Ainv_j b on the rows of every mesh j whose
-// coarsest depth is this level (one wavefront per row)
+// coarsest depth is this level (one wavefront per row; member j of the
+// batch is cbmem[j], skipped once it stopped iterating)
 template <class T, int K>
 __global__ void k_coarse_b(int nm, const int* rowoff, const int* cum, const long long* aoff, const double* ainv,
-                           const T* b, T* x) {
+                           const T* b, T* x, const int* cbmem, const int* act) {
   long long wave = (blockIdx.x * (long long)BLK + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (wave >= cum[nm]) return;
   int j = 0;
   while (cum[j + 1] <= wave) ++j;
+  if (!act[cbmem[j]]) return;
   const int n = cum[j + 1] - cum[j];
   const long long lr = wave - cum[j];
   const double* A = ainv + aoff[j];
@@ -496,6 +509,33 @@ __global__ void k_axpy_inplace(long long n, double* x, const double* y) {
 // bb[K] act[K] (act = 1 while the column still iterates, 0 once frozen).
 constexpr int SCS = 8 * KMAXS;
 
+// a member still iterates while one of its columns does
+template <int K>
+__device__ inline bool live_member(const double* sc) {
+  bool on = false;
+#pragma unroll
+  for (int c = 0; c < K; ++c) on = on || sc[5 * K + c] != 0.0;
+  return on;
+}
+
+// per-block partials of a . b per column; blocks of members with act 0 give zero
+template <int K>
+__global__ __launch_bounds__(BLK) void k_dot_b(long long n, const int* bmesh, const int* act, const double* a,
+                                               const double* b, double* part) {
+  __shared__ double sh[BLK / 64];
+  if (!act[bmesh[blockIdx.x]]) {
+    if (threadIdx.x < K) part[(long long)blockIdx.x * K + threadIdx.x] = 0.0;
+    return;
+  }
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < K; ++c) {
+    const double v = i < n ? a[i * K + c] * b[i * K + c] : 0.0;
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * K + c] = s;
+  }
+}
+
 // out[m * SCS + off + c] = sum of the partials of mesh m's blocks
 template <int K>
 __global__ __launch_bounds__(BLK) void k_finalize_seg(const double* part, const int* bstart, double* out, int off) {
@@ -516,6 +556,10 @@ __global__ __launch_bounds__(BLK) void k_cg_update_b(long long n, const int* bme
   __shared__ double sh[BLK / 64];
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   const double* sc = scall + (long long)bmesh[blockIdx.x] * SCS;
+  if (!live_member<K>(sc)) {   // every column frozen: x and r stay, the partials are zero
+    if (threadIdx.x < K) part[(long long)blockIdx.x * K + threadIdx.x] = 0.0;
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < K; ++c) {
     const double rz = sc[c], pq = sc[K + c];
@@ -536,6 +580,7 @@ __global__ void k_cg_direction_b(long long n, const int* bmesh, const double* sc
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
   const double* sc = scall + (long long)bmesh[blockIdx.x] * SCS;
+  if (!live_member<K>(sc)) return;   // p of a frozen member is never used again
 #pragma unroll
   for (int c = 0; c < K; ++c) {
     const double be = (sc[5 * K + c] != 0.0 && sc[c] != 0.0) ? sc[3 * K + c] / sc[c] : 0.0;
@@ -548,6 +593,15 @@ __global__ void k_copy_rz_b(int nm, double* scall) {
   if (i >= nm * K) return;
   double* sc = scall + (long long)(i / K) * SCS;
   sc[i % K] = sc[3 * K + i % K];
+}
+
+// gated slice records: the slices of members that stopped iterating become
+// empty (no entries, no rows), so the SELL kernels skip them unchanged
+__global__ void k_gate_meta(long long ns, const int4* all, const int* slmem, const int* act, int4* out) {
+  const long long s = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (s >= ns) return;
+  const int4 m = all[s];
+  out[s] = act[slmem[s]] ? m : make_int4(m.x, m.x, m.z, 0);
 }
 
 // canonical column-major n x k block (columns c0..c0+K) <-> internal row-major n x K
@@ -946,7 +1000,8 @@ template <class T, int K>
 void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
   if (!G.ncb) return;
   hipLaunchKernelGGL((k_coarse_b<T, K>), grid_for((size_t)G.cb_rows * 64, BLK), BLK, 0, S->ctx->stream, G.ncb,
-                     G.cb_rowoff.p, G.cb_cum.p, G.cb_aoff.p, (const double*)G.cb_a64.p, b, x);
+                     G.cb_rowoff.p, G.cb_cum.p, G.cb_aoff.p, (const double*)G.cb_a64.p, b, x,
+                     (const int*)G.cbmem.p, (const int*)S->mact.p);
 }
 
 // One cycle at depth d on (b, x) of that depth, x given (zero on entry below
@@ -989,11 +1044,12 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool firs
   const T* cdinv = (!S->batch && nu1 > 0 && d - 1 > S->d0) ? sweep_dinv<T>(S, C) : nullptr;
   CAMFE_TIMED(ctx, KT_RESTRICT, (4.0 * G.pnnz + ((double)G.n + C.n) * K * sizeof(T)), (k_restrict<T, K>),
               grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc,
-              xc, cdinv, cdinv ? (long long)C.coff[1] : 0LL);
+              xc, cdinv, cdinv ? (long long)C.coff[1] : 0LL, (const int*)C.blkmem.p, (const int*)S->mact.p);
   const int c1 = S->nu_coarse > 0 ? S->nu_coarse : nu1, c2 = S->nu_coarse > 0 ? S->nu_coarse : nu2;
   for (int g = 0; g < S->gamma; ++g) vcycle<T, K>(S, d - 1, bc, xc, c1, c2, g == 0 && cdinv != nullptr);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
-              grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x);
+              grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x,
+              (const int*)G.blkmem.p, (const int*)S->mact.p);
   if (G.ncb) coarse_batched<T, K>(S, G, b, x);   // meshes that bottom out here
   smooth<T, K>(S, G, b, x, nu2, false);
 }
@@ -1357,7 +1413,7 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
         meta[m].row0 = to_host(ctx, M.sl_row0, M.nslices);
         meta[m].rows = to_host(ctx, M.sl_rows, M.nslices);
       }
-    std::vector<int> hp(1, 0), hrow0, hrows;
+    std::vector<int> hp(1, 0), hrow0, hrows, hsm;
     G.cslice.assign(G.ncol + 1, 0);
     G.coff.assign(G.ncol + 1, 0);
     G.cnnz.assign(G.ncol, 0);
@@ -1375,6 +1431,7 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
         for (int sl = s0; sl < s1; ++sl) {
           hrow0.push_back((int)(meta[m].row0[sl] + rowoff[bd][m]));
           hrows.push_back(meta[m].rows[sl]);
+          hsm.push_back(m);
           hp.push_back(hp.back() + meta[m].ptr[sl + 1] - meta[m].ptr[sl]);
         }
         G.coff[c + 1] += M.coff[c + 1] - M.coff[c];
@@ -1395,6 +1452,22 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
       copy_in(ctx, G.sl_rows.p, hrows.data(), G.nslices);
     }
     pack_meta(ctx, G, hp, hrow0, hrows);
+    // the full records, and the member of each slice and of each BLK-row block
+    G.sl_meta_all.alloc(G.sl_meta.n);
+    dcopy(ctx, G.sl_meta_all.p, G.sl_meta.p, G.sl_meta.n * sizeof(int4));
+    hsm.resize(std::max<size_t>(G.nslices, 1), 0);
+    G.slmem.alloc(hsm.size());
+    copy_in(ctx, G.slmem.p, hsm.data(), hsm.size());
+    {
+      std::vector<int> bm(std::max<size_t>(G.n / BLK, 1), 0);
+      for (int m = 0; m < nm; ++m)
+        if (present(m, bd))
+          for (long long r = rowoff[bd][m]; r < rowoff[bd][m] + pad_rows((long long)ms[m]->lev[mdepth(m, bd)].n);
+               r += BLK)
+            bm[r / BLK] = m;
+      G.blkmem.alloc(bm.size());
+      copy_in(ctx, G.blkmem.p, bm.data(), bm.size());
+    }
     G.scol.alloc(G.snnz);
     G.sval64.alloc(G.snnz);
     G.sval32.alloc(G.snnz);
@@ -1420,11 +1493,12 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
     for (DArr<double>* v : {&G.x64, &G.b64, &G.r64, &G.t64}) { v->alloc(nk); zero(ctx, v->p, nk); }
     for (DArr<float>* v : {&G.x32, &G.b32, &G.r32, &G.t32}) { v->alloc(nk); zero(ctx, v->p, nk); }
     // meshes solved directly at this level
-    std::vector<int> cro, ccum(1, 0);
+    std::vector<int> cro, ccum(1, 0), cmem;
     std::vector<long long> caoff;
     long long atot = 0;
     for (int m = 0; m < nm; ++m)
       if (present(m, bd) && mdepth(m, bd) == ms[m]->d0 && ms[m]->direct) {
+        cmem.push_back(m);
         cro.push_back((int)rowoff[bd][m]);
         ccum.push_back(ccum.back() + ms[m]->n0);
         caoff.push_back(atot);
@@ -1439,6 +1513,8 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
       copy_in(ctx, G.cb_rowoff.p, cro.data(), cro.size());
       copy_in(ctx, G.cb_cum.p, ccum.data(), ccum.size());
       copy_in(ctx, G.cb_aoff.p, caoff.data(), caoff.size());
+      G.cbmem.alloc(G.ncb);
+      copy_in(ctx, G.cbmem.p, cmem.data(), cmem.size());
       G.cb_a64.alloc(atot);
       int j = 0;
       for (int m = 0; m < nm; ++m)
@@ -1519,6 +1595,11 @@ void build_batch(camfe_batch_s* Bt, const std::vector<SolverState*>& ms) {
   for (DArr<double>* v : {&S->X, &S->R, &S->Z, &S->P, &S->Q, &S->B}) { v->alloc(n); zero(ctx, v->p, n); }
   S->sc.alloc((size_t)nm * SCS);
   zero(ctx, S->sc.p, S->sc.n);
+  S->mact.alloc(nm);
+  {
+    std::vector<int> on(nm, 1);
+    copy_in(ctx, S->mact.p, on.data(), on.size());
+  }
   S->part.alloc((std::max(T.nslices, nb) + 1) * KMAXS);
   ctx->sync();
   Bt->S = std::move(S);
@@ -1528,7 +1609,8 @@ template <int K>
 void dot_seg(SolverState* S, const double* a, const double* b, int off) {
   const GLevel& G = S->lev[S->D];
   const long long nb = (long long)(G.n / BLK);
-  hipLaunchKernelGGL(k_dot<K>, (unsigned)nb, BLK, 0, S->ctx->stream, (long long)G.n, a, b, S->part.p);
+  hipLaunchKernelGGL(k_dot_b<K>, (unsigned)nb, BLK, 0, S->ctx->stream, (long long)G.n, (const int*)S->bmesh.p,
+                     (const int*)S->mact.p, a, b, S->part.p);
   hipLaunchKernelGGL(k_finalize_seg<K>, (unsigned)S->nmesh, BLK, 0, S->ctx->stream, (const double*)S->part.p,
                      S->bstart.p, S->sc.p, off);
 }
@@ -1569,8 +1651,12 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
   const int nm = S->nmesh;
   const long long nk = (long long)G.n * K;
   const unsigned gnk = grid_for(nk, BLK);
-  hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->B.p, nk, 0.0);
-  hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, S->X.p, nk, 0.0);
+  // every outer vector starts at zero: the rows that pad each member to whole
+  // blocks are written by no kernel but enter the per-block dot products, so
+  // what an earlier pass (another column count, another layout) left there
+  // must not survive
+  for (double* v : {S->B.p, S->X.p, S->R.p, S->Z.p, S->P.p, S->Q.p})
+    hipLaunchKernelGGL((k_fill<double>), gnk, BLK, 0, st, v, nk, 0.0);
   for (int m = 0; m < nm; ++m) {
     const BatchMember& me = Bt->mem[m];
     if (c0 >= kk[m]) continue;
@@ -1580,6 +1666,67 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
       hipLaunchKernelGGL(k_gather_in<K>, grid_for(me.n, BLK), BLK, 0, st, (const double*)dx[m].p, (long long)me.n,
                          c0, kk[m], me.iperm.p, S->X.p + me.rowoff * K);
   }
+  std::vector<double> rel((size_t)nm * K, 0.0);
+  // relative residual per (mesh, column); act = 1 while above rtol.  A column
+  // once frozen stays frozen (its x and r no longer change), and a member
+  // whose columns are all frozen is gated off: its slices are emptied and
+  // the gated kernels skip its blocks, so the batch costs what its members
+  // still iterating cost.  The gated members' scalars are not maintained, so
+  // the frozen state is kept here, not re-derived from them.
+  std::vector<char> live((size_t)nm * K, 1);
+  std::vector<int> mon(nm, 1), mon_dev;   // mon_dev: flags on the device (unknown at first)
+  std::vector<double> hs((size_t)nm * SCS);
+  auto update = [&](bool set_act) {
+    bool any = false;
+    for (int m = 0; m < nm; ++m) {
+      bool mlive = false;
+      for (int c = 0; c < K; ++c) {
+        double* sc = hs.data() + (size_t)m * SCS;
+        const bool col = c0 + c < kk[m];
+        const double bn = std::sqrt(sc[4 * K + c]);
+        const double v = !col ? 0.0 : (bn > 0 ? std::sqrt(sc[2 * K + c]) / bn : std::sqrt(sc[2 * K + c]));
+        if (!set_act) {   // final residuals: every column's
+          rel[(size_t)m * K + c] = v;
+          continue;
+        }
+        char& lv = live[(size_t)m * K + c];
+        if (lv) rel[(size_t)m * K + c] = v;
+        lv = lv && col && std::isfinite(v) && v > o.rtol;
+        sc[5 * K + c] = lv ? 1.0 : 0.0;
+        mlive = mlive || lv;
+      }
+      mon[m] = mlive ? 1 : 0;
+      any = any || mlive;
+    }
+    return any;
+  };
+  // push the members' active flags and re-gate the slice records of every level
+  auto gate = [&](const std::vector<int>& on) {
+    if (on == mon_dev) return;
+    mon_dev = on;
+    copy_in(ctx, S->mact.p, on.data(), on.size());
+    for (int bd = S->d0; bd <= S->D; ++bd) {
+      GLevel& L = S->lev[bd];
+      if (L.nslices)
+        hipLaunchKernelGGL(k_gate_meta, grid_for(L.nslices, BLK), BLK, 0, st, (long long)L.nslices,
+                           (const int4*)L.sl_meta_all.p, (const int*)L.slmem.p, (const int*)S->mact.p, L.sl_meta.p);
+    }
+  };
+  // every member on, and every slice record whole again when this returns or throws
+  struct Ungate {
+    SolverState* S;
+    ~Ungate() {
+      std::vector<int> on(S->nmesh, 1);
+      (void)hipMemcpyAsync(S->mact.p, on.data(), on.size() * sizeof(int), hipMemcpyHostToDevice, S->ctx->stream);
+      for (int bd = S->d0; bd <= S->D; ++bd) {
+        GLevel& L = S->lev[bd];
+        (void)hipMemcpyAsync(L.sl_meta.p, L.sl_meta_all.p, L.sl_meta.n * sizeof(int4), hipMemcpyDeviceToDevice,
+                             S->ctx->stream);
+      }
+      (void)hipStreamSynchronize(S->ctx->stream);
+    }
+  } ungate{S};
+  gate(std::vector<int>(nm, 1));
   hipLaunchKernelGGL((k_fill<double>), grid_for(S->sc.n, BLK), BLK, 0, st, S->sc.p, (long long)S->sc.n, 0.0);
   dot_seg<K>(S, S->B.p, S->B.p, 4 * K);
   hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
@@ -1587,28 +1734,13 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
                      (double*)nullptr);
   dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
   check_launch();
-  std::vector<double> hs((size_t)nm * SCS);
   copy_out(ctx, hs.data(), S->sc.p, hs.size());
-  std::vector<double> rel((size_t)nm * K, 0.0);
-  // relative residual per (mesh, column); act = 1 while above rtol
-  auto update = [&](bool set_act) {
-    bool any = false;
-    for (int m = 0; m < nm; ++m)
-      for (int c = 0; c < K; ++c) {
-        double* sc = hs.data() + (size_t)m * SCS;
-        const bool col = c0 + c < kk[m];
-        const double bn = std::sqrt(sc[4 * K + c]);
-        const double v = !col ? 0.0 : (bn > 0 ? std::sqrt(sc[2 * K + c]) / bn : std::sqrt(sc[2 * K + c]));
-        rel[(size_t)m * K + c] = v;
-        const bool on = col && std::isfinite(v) && v > o.rtol;
-        if (set_act) sc[5 * K + c] = on ? 1.0 : 0.0;
-        any = any || on;
-      }
-    return any;
-  };
   bool any = update(true);
   copy_in(ctx, S->sc.p, hs.data(), hs.size());
+  gate(mon);
+  const std::vector<int> mon0 = mon;   // members that take the first cycle
   int it = 0, cycles = 0;
+  std::vector<int> mit(nm, 0);   // iterations each member took part in
   const int nu1 = o.nu_pre, nu2 = o.nu_post;
   const bool use_graph = !ctx->timer.on;
   const int check_every = 4;
@@ -1627,11 +1759,14 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
       check_launch();
       it += mm;
       cycles += mm;
+      for (int m = 0; m < nm; ++m) mit[m] += mon[m] ? mm : 0;
       copy_out(ctx, hs.data(), S->sc.p, hs.size());
       any = update(true);
       copy_in(ctx, S->sc.p, hs.data(), hs.size());
+      gate(mon);
     }
-    // true residuals of the final iterates
+    // true residuals of the final iterates, over every member
+    gate(std::vector<int>(nm, 1));
     hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
                        (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
                        (double*)nullptr);
@@ -1645,8 +1780,8 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
     hipLaunchKernelGGL(k_scatter_out<K>, grid_for(me.n, BLK), BLK, 0, st, (const double*)(S->X.p + me.rowoff * K),
                        (long long)me.n, c0, kk[m], me.iperm.p, dx[m].p);
     SolveResult& r = res[m];
-    r.it = std::max(r.it, it);
-    r.cycles += cycles;
+    r.it = std::max(r.it, mit[m]);
+    r.cycles += mit[m] + (cycles > 0 && mon0[m] ? 1 : 0);
     for (int c = 0; c < K; ++c)
       if (c0 + c < kk[m] && !(rel[(size_t)m * K + c] <= r.rel)) r.rel = rel[(size_t)m * K + c];
   }
@@ -1715,18 +1850,20 @@ void coarse_correction(SolverState* S, int d, const double* e, double* out, bool
     hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, r);
   }
   hipLaunchKernelGGL((k_restrict<double, K>), grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, G.Rw64.p,
-                     (long long)C.n, (const double*)r, C.b64.p, C.x64.p, (const double*)nullptr, 0LL);
+                     (long long)C.n, (const double*)r, C.b64.p, C.x64.p, (const double*)nullptr, 0LL,
+                     (const int*)nullptr, (const int*)nullptr);
   vcycle<double, K>(S, d - 1, C.b64.p, C.x64.p, 2, 2);
   if (!adjoint) {
     // out = e + P x_c  (x_c = -B_c P^T A e)
     hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, out);
     hipLaunchKernelGGL((k_prolong<double, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, G.Pw64.p,
-                       (long long)G.n, (const double*)C.x64.p, out);
+                       (long long)G.n, (const double*)C.x64.p, out, (const int*)nullptr, (const int*)nullptr);
   } else {
     // t = P x_c (x_c = B_c P^T e), out = e - A t
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.t64.p, nk, 0.0);
     hipLaunchKernelGGL((k_prolong<double, K>), grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, G.Pw64.p,
-                       (long long)G.n, (const double*)C.x64.p, G.t64.p);
+                       (long long)G.n, (const double*)C.x64.p, G.t64.p, (const int*)nullptr,
+                       (const int*)nullptr);
     hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
                        (int)G.nslices, G.scol.p, G.sval64.p, e, (const double*)G.t64.p, out, (double*)nullptr);
   }

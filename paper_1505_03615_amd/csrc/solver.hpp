@@ -63,6 +63,11 @@ struct GLevel {
   DArr<int> cb_rowoff, cb_cum;
   DArr<long long> cb_aoff;
   DArr<double> cb_a64;
+  // batched solver only: the full slice records (sl_meta then holds a gated
+  // copy in which the slices of members that stopped iterating are empty),
+  // and the member of each slice, of each SBLK-row block and of each direct block
+  DArr<int4> sl_meta_all;
+  DArr<int> slmem, blkmem, cbmem;
 };
 
 struct SolverState {
@@ -97,6 +102,7 @@ struct SolverState {
   bool batch = false;
   int nmesh = 0;
   DArr<int> bmesh, bstart;
+  DArr<int> mact;            // batched: 1 while the member still iterates (read by the gated kernels)
   // captured iterations (one graph per right-hand-side count / precision / sweeps / method / smoother)
   hipStream_t cap = nullptr;
   std::map<long long, hipGraphExec_t> graphs;

@@ -111,6 +111,30 @@ def test_batch_matches_single_solves(cf, setup):
         assert np.all(num <= 1e-6 * np.where(den > 0, den, 1.0)), (i, num, den)
 
 
+def test_converged_members_drop_out_without_changing_the_rest(cf, setup):
+    """Members stop costing anything once all their columns converge (their
+    slices, transfers, coarse solves and CG blocks are skipped).  Every
+    member's arithmetic is its own, so its iterate, its iteration count and
+    its residual are bit for bit those of a batch holding it alone: a gate
+    that skipped a live member's rows, or let a frozen member change, fails
+    here.  The iteration counts are the members' own, not the batch's."""
+    ctx, items, bt = setup
+    xs, stats = cf.camfe_batch_solve(bt, [it[3] for it in items], T, rtol=1e-10, max_iter=800)
+    its = [st["iterations"] for st in stats]
+    say(f"[gpu] batch: iterations per member {its}")
+    assert min(its) < max(its)
+    for i in (0, 2, 5):
+        h, s, o, b = items[i]
+        one = cf.camfe_batch_create(ctx, [s], T)
+        try:
+            x1, st1 = cf.camfe_batch_solve(one, [b], T, rtol=1e-10, max_iter=800)
+        finally:
+            cf.camfe_batch_destroy(one)
+        assert st1[0]["iterations"] == stats[i]["iterations"], (i, st1[0], stats[i])
+        assert st1[0]["rel_residual"] == stats[i]["rel_residual"], i
+        assert np.array_equal(x1[0], xs[i]), (i, np.abs(x1[0] - xs[i]).max())
+
+
 def test_batch_warm_start_and_errors(cf, setup):
     ctx, items, bt = setup
     xs, stats = cf.camfe_batch_solve(bt, [it[3] for it in items], T, rtol=1e-9, max_iter=800)

@@ -136,7 +136,7 @@ def cpu_baseline(cf, ctx, meshgen, full, sample=CPU_SAMPLE):
     for tag, kw in (("plain_gs_fp64", dict(precision=0, smoother=0)),
                     ("plain_gs_mixed", dict(precision=1, smoother=0)),
                     ("learned_mixed", dict(precision=1, smoother=2)),
-                    ("block_mixed", dict(precision=1, smoother=3))):
+                    ("block_fp64", dict(precision=0, smoother=3))):
         cf.camfe_smoother_attach(s, full.get("model") if tag == "learned_mixed" else None)
         x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=3000, **kw)
         d = x[:, 0] - xo[:, 0]
@@ -307,11 +307,12 @@ def cycle_roofline(bytes_per_cycle, ms, cycles):
 SOLVERS = (("plain_gs_fp64", dict(precision=0, smoother=0)),
            ("plain_gs_mixed", dict(precision=1, smoother=0)),
            ("learned_mixed", dict(precision=1, smoother=2)),
-           # cell-block Schwarz (smoother 3): CG capped at 500 iterations, then Gauss-Seidel redoes the solve
-           ("block_mixed", dict(precision=1, smoother=3, max_iter=500)))
+           # cell-block Schwarz (smoother 3, FP64 cycles, damping chosen per depth): CG capped at 500
+           # iterations, then Gauss-Seidel redoes the solve
+           ("block_fp64", dict(precision=0, smoother=3, max_iter=500)))
 
 
-def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mixed", "learned_mixed", "block_mixed"),
+def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mixed", "learned_mixed", "block_fp64"),
                      max_iter=4000):
     """Each solver to 1e-8 on one assembled system, warm: a 4-iteration solve
     first builds the solver state and captures the graphs, then the full
@@ -332,6 +333,10 @@ def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mi
         res[tag] = {"s": st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
                     "converged": bool(st["converged"]), "fell_back": int(st["fell_back"]),
                     "setup_s": st["setup_seconds"], "dof_cycles_per_s": n * st["cycles"] / st["seconds"]}
+        if kw.get("smoother") == 3:
+            om, lam = cf.camfe_block_damping(s, t)
+            res[tag]["damping_per_depth"] = [round(float(v), 4) for v in om]
+            res[tag]["lambda_max_estimate_per_depth"] = [round(float(v), 4) for v in lam]
         log(f"[bench] {tag}: {st['cycles']} cycles, {1000 * st['seconds']:.0f} ms")
     cf.camfe_smoother_attach(s, None)
     if "plain_gs_fp64" in res and "learned_mixed" in res:
@@ -888,7 +893,7 @@ def main():
     solve_s = float(np.mean([x["seconds"] for x in sts]))
     cycles = float(np.mean([x["cycles"] for x in sts]))
     log("[bench] plain Gauss-Seidel solves of the same system")
-    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed", "block_mixed"))
+    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed", "block_fp64"))
     comp["learned_mixed"] = {"s": solve_s, "cycles": cycles, "rel_residual": float(max(x["rel_residual"] for x in sts)),
                              "converged": bool(all(x["converged"] for x in sts)),
                              "fell_back": int(max(x["fell_back"] for x in sts)),

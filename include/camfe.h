@@ -205,9 +205,14 @@ typedef struct {
                      /*    of more than 16), inverses of the unit-diagonal-scaled */
                      /*    blocks plus coarse_eps I; a sweep adds                 */
                      /*    omega sum_B w_B R_B^T A_B^-1 R_B (b - A x), w_B = 1 /  */
-                     /*    (the most blocks holding one of B's functions): an     */
-                     /*    A-norm contraction for omega in (0, 1]                 */
-  double omega;      /* omega of smoother 1; damping of smoother 3 (0: 1)        */
+                     /*    (the most blocks holding one of B's functions).  An    */
+                     /*    A-norm contraction only while omega lambda_max < 2     */
+                     /*    (lambda_max of that block sum times A, which passes 2  */
+                     /*    at fine depths: see camfe_block_damping).  Only FP64   */
+                     /*    cycles are reliable: a near-singular block amplifies   */
+                     /*    rounding by up to 1 / coarse_eps                       */
+  double omega;      /* omega of smoother 1; damping of smoother 3 in [0, 1]      */
+                     /*    (0: each depth's automatic value)                      */
   int judge;         /* smoother 1 or 2 with method 0: Gauss-Seidel as judge.     */
                      /*    The requested smoother and plain Gauss-Seidel each run */
                      /*    `judge` CG iterations from the start; the one with the */
@@ -271,6 +276,17 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision
  * Takes effect at the next solver set-up: drops the system's current solver
  * state (captured graphs included). */
 camfe_status camfe_system_set_sell_sort(camfe_sys s, int64_t min_rows);
+/* The automatic damping of smoother 3 at every depth (coarsest first; 0 at
+ * a coarsest depth solved directly), building the solver for A = M + t L and
+ * its cell blocks where missing: omega_d = min(1, 4 / (3 lambda_d)), where
+ * lambda_d estimates the largest eigenvalue of B A, B = sum_B w_B R_B^T A_B^-1
+ * R_B, by 20 power steps in the A inner product from a fixed pseudo-random
+ * start (from below).  One sweep maps the error e to (I - omega B A) e, so
+ * omega must stay below 2 / lambda_max.  lambda (nullable) receives the
+ * estimates.  cap: entries of omega / lambda (0: only *nlevels); ETOOSMALL
+ * below the number of depths; EINVAL for degree 2. */
+camfe_status camfe_block_damping(camfe_sys s, double t, double coarse_eps, double *omega, double *lambda, int cap,
+                                 int *nlevels);
 /* Autotuner of the colour sweep's tile (not in the paper): for every depth of
  * the system's solver for A = M + t L (built when missing), each compiled tile
  * {wavefronts per 64-row slice, entries per lane issued together} in

@@ -724,6 +724,7 @@ struct SysLevel {
   std::vector<std::vector<long>> blocks;
   std::vector<std::vector<double>> binv;
   std::vector<double> bweight;
+  double block_omega = 1.0;       // damping of this level's block corrections
 };
 
 int colour_of(int degree, uint64_t key) {
@@ -771,7 +772,6 @@ struct Solver {
   int nu_coarse = 0;          // sweeps each way below the finest depth (0: nu1, nu2)
   int eps_used = 0;
   int smoother = 0;           // 0 multicolour Gauss-Seidel, 1 cell-block Schwarz
-  double block_omega = 1.0;   // damping of the cell-block corrections
 };
 
 void gs_sweep(const SysLevel& S, const double* b, double* x, int k, bool forward);
@@ -862,9 +862,11 @@ void build_blocks(const Hier& h, int d, SysLevel& S, double eps) {
 // One cell-block Schwarz sweep: r = b - A x, then
 //   x += omega sum over blocks B of w_B R_B^T A_B^-1 R_B r
 // with w_B the block's weight.  The map is symmetric (the same before and
-// after the coarse correction) and, since the weights holding any function
-// sum to at most 1, an A-norm contraction for omega in (0, 1]: the cycle is
-// a positive definite preconditioner.
+// after the coarse correction): the error goes to (I - omega B A) e with B
+// the weighted block sum, an A-norm contraction only while omega times the
+// largest eigenvalue of B A stays below 2.  The weights bound what blocks
+// sharing a function add, but not the coupling of blocks that share none,
+// so that eigenvalue can pass 2 and the damping is the caller's to choose.
 void block_sweep(const SysLevel& S, const double* b, double* x, int k, double omega) {
   std::vector<double> r((size_t)S.n * k), u((size_t)S.n * k, 0.0);
   residual(S, b, x, k, r.data());
@@ -882,7 +884,7 @@ void block_sweep(const SysLevel& S, const double* b, double* x, int k, double om
 }
 
 void smooth(const Solver& sv, const SysLevel& S, const double* b, double* x, int k, bool forward) {
-  if (sv.smoother == 1) block_sweep(S, b, x, k, sv.block_omega);
+  if (sv.smoother == 1) block_sweep(S, b, x, k, S.block_omega);
   else gs_sweep(S, b, x, k, forward);
 }
 
@@ -1110,7 +1112,7 @@ int oracle_gradient_load(void* hp, int d, const double* fv, int k, double* b) {
 int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2,
                  const double* b, int k, double* x, int x0_given, double* stats,
                  double* history, int mode, double coarse_eps, int gamma, int nu_coarse, int smoother,
-                 double block_omega) {
+                 double block_omega, const double* level_omega) {
   Hier& h = ((OracleHandle*)hp)->h;
   if (!h.err.empty()) return -1;
   if (gamma < 1 || gamma > 2) { h.err = "gamma must be 1 or 2"; return -1; }
@@ -1122,7 +1124,6 @@ int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2
   auto t0 = std::chrono::steady_clock::now();
   Solver sv;
   sv.h = &h; sv.nu1 = nu1; sv.nu2 = nu2; sv.gamma = gamma; sv.nu_coarse = nu_coarse; sv.smoother = smoother;
-  sv.block_omega = block_omega;
   sv.sl.assign(h.D + 1, SysLevel());
   for (int d = h.d0; d <= h.D; ++d) {
     Level& L = h.lev[d];
@@ -1140,6 +1141,8 @@ int oracle_solve(void* hp, double t, double rtol, int max_iter, int nu1, int nu2
     const int ncol = h.degree == 1 ? 8 : 27;
     S.colour_rows.assign(ncol, {});
     for (long r = 0; r < S.n; ++r) S.colour_rows[colour_of(h.degree, L.fkey[r])].push_back(r);
+    // block damping: one value for every depth, or level_omega[d - d0]
+    S.block_omega = level_omega ? level_omega[d - h.d0] : block_omega;
     if (smoother == 1) {
       try {
         build_blocks(h, d, S, coarse_eps);

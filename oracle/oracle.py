@@ -58,7 +58,7 @@ def _load(openmp=False):
         lib.oracle_assemble.argtypes = [vp, P]
         lib.oracle_matrix.argtypes = [vp, I, P, P, P, P]
         lib.oracle_load_vector.argtypes = [vp, I, P, I, P]
-        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I, I, I, D]
+        lib.oracle_solve.argtypes = [vp, D, D, I, I, I, P, I, P, I, P, P, I, D, I, I, I, D, P]
         lib.oracle_block_sweep.argtypes = [vp, I, D, P, I, P, I, D, D]
         lib.oracle_gradient_load.argtypes = [vp, I, P, I, P]
         lib.oracle_apply.argtypes = [vp, I, D, P, I, P]
@@ -207,15 +207,22 @@ class Oracle:
         cycles); gamma 1 for V-cycles, 2 for W-cycles; nu_coarse > 0 sweeps
         each way below the finest depth; smoother 'gs' (multicolour
         Gauss-Seidel) or 'block' (cell-block Schwarz, degree 1, corrections
-        damped by block_omega)."""
+        damped by block_omega: one value, or one per depth, coarsest first)."""
         n = self.count(self.depth, "functions")
         b, k = _colmajor(b, n)
+        level_omega = None
+        if np.ndim(block_omega) > 0:
+            level_omega = np.ascontiguousarray(block_omega, dtype=np.float64)
+            if level_omega.shape != (self.depth - self.coarsest + 1,):
+                raise ValueError("block_omega: one value per depth from the coarsest")
+            block_omega = 0.0
         x = np.zeros((n, k), order="F") if x0 is None else np.array(_colmajor(x0, n)[0], order="F")
         stats = np.zeros(5); hist = np.zeros(max_iter + 1)
         rc = self.lib.oracle_solve(self.h, t, rtol, max_iter, nu1, nu2, _p(b), k, _p(x),
                                    0 if x0 is None else 1, _p(stats), _p(hist),
                                    {"vcycle": 0, "pcg": 1}[mode], coarse_eps, gamma, nu_coarse,
-                                   {"gs": 0, "block": 1}[smoother], block_omega)
+                                   {"gs": 0, "block": 1}[smoother], block_omega,
+                                   None if level_omega is None else _p(level_omega))
         if rc < 0:
             raise RuntimeError("oracle solve: " + self.lib.oracle_error(self.h).decode())
         it = int(stats[4])

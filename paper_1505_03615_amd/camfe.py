@@ -31,7 +31,7 @@ EXPORTS = [
     "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy", "camfe_eigs",
     "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
     "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc", "camfe_system_autotune",
-    "camfe_batch_autotune",
+    "camfe_batch_autotune", "camfe_block_damping",
 ]
 TILES = [(8, 4), (4, 4), (8, 2), (16, 2), (16, 4)]   # colour-sweep tiles: (wavefronts per slice, entries per lane)
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
@@ -150,6 +150,7 @@ def load():
         "camfe_apply_noalloc": (I, [H, I, D, P, I, P]),
         "camfe_system_autotune": (I, [H, D, I, I, P, P, I, C.POINTER(I)]),
         "camfe_batch_autotune": (I, [H, I, I, P, P, I, C.POINTER(I)]),
+        "camfe_block_damping": (I, [H, D, D, P, P, I, C.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -478,6 +479,16 @@ def camfe_system_autotune(s, t, precision=1, reps=10):
 def camfe_batch_autotune(bt, precision=0, reps=10):
     """(tile index per batch level, coarsest first; ms per sweep with it)."""
     return _autotune(load().camfe_batch_autotune, bt, precision, reps)
+
+
+def camfe_block_damping(s, t, coarse_eps=DEFAULT_COARSE_EPS):
+    """(automatic damping of smoother 3 per depth, the lambda_max estimates), coarsest first."""
+    nl = C.c_int()
+    _check(load().camfe_block_damping(s, t, coarse_eps, None, None, 0, C.byref(nl)))
+    om = np.zeros(nl.value)
+    lam = np.zeros(nl.value)
+    _check(load().camfe_block_damping(s, t, coarse_eps, _ptr(om), _ptr(lam), nl.value, C.byref(nl)))
+    return om, lam
 
 
 def camfe_system_import_csr(ctx, degree, levels, max_coarse=4096):

@@ -955,6 +955,7 @@ void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
   const T* w8 = dbl ? (const T*)G.bw8_64.p : (const T*)G.bw8_32.p;
   const T* w16 = dbl ? (const T*)G.bw16_64.p : (const T*)G.bw16_32.p;
   const T* sc = dbl ? (const T*)G.bs64.p : (const T*)G.bs32.p;
+  const T om = (T)(S->block_omega > 0 ? S->block_omega : G.block_omega);
   T* r = tmp_of<T>(G);
   for (int it = 0; it < nu; ++it) {
     CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
@@ -963,11 +964,89 @@ void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
     if (G.nb8)
       CAMFE_TIMED(ctx, KT_GS, ((double)G.nb8 * 8 * (8 * sizeof(T) + 4) + 3.0 * G.n * K * sizeof(T)),
                   (k_block_apply<T, K, 8>), grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, G.nb8, G.bidx8.p, inv8,
-                  w8, sc, (const T*)r, (T)S->block_omega, x);
+                  w8, sc, (const T*)r, om, x);
     if (G.nb16)
       CAMFE_TIMED(ctx, KT_GS, ((double)G.nb16 * 16 * (16 * sizeof(T) + 4)), (k_block_apply<T, K, 16>),
                   grid_for((size_t)G.nb16 * 16, 256), 256, 0, st, G.nb16, G.bidx16.p, inv16, w16, sc,
-                  (const T*)r, (T)S->block_omega, x);
+                  (const T*)r, om, x);
+  }
+}
+
+// uniform values in [-1, 1) from a counter (splitmix64 of seed + i)
+__global__ void k_hash_fill(long long n, unsigned long long seed, double* v) {
+  const long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i >= n) return;
+  unsigned long long z = seed + 0x9E3779B97F4A7C15ULL * (unsigned long long)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  v[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+__global__ void k_scale_into(long long n, double a, const double* y, double* v) {
+  const long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n) v[i] = a * y[i];
+}
+
+// Automatic damping of the cell-block smoother, per depth.  The block
+// operator B = sum_B w_B R_B^T A_B^-1 R_B is symmetric and B A is
+// A-self-adjoint; one sweep maps the error e to (I - omega B A) e, a
+// contraction only while omega lambda_max(B A) < 2.  The weights bound what
+// blocks sharing functions add, but blocks that share none still couple
+// through A (functions of neighbouring cells are nearly parallel where the
+// surface crosses cells in thin pieces), and lambda_max grows past 2 at fine
+// depths.  So lambda_max is estimated by BLOCK_POWER steps of the power
+// method in the A inner product from a fixed pseudo-random start (the
+// Rayleigh quotient (A v . B A v) / (v . A v) approaches it from below), and
+// the damping set to 4 / (3 lambda), the Richardson choice that damps the
+// upper half of the spectrum by at least 1/3, capped at 1.
+constexpr int BLOCK_POWER = 20;
+
+void estimate_block_damping(SolverState* S) {
+  camfe_ctx ctx = S->ctx;
+  hipStream_t st = ctx->stream;
+  DArr<double> dd(3);
+  for (int d = S->d0; d <= S->D; ++d) {
+    GLevel& G = S->lev[d];
+    G.block_lambda = G.block_omega = 0;
+    if (!G.nb8 && !G.nb16) continue;
+    const long long n = (long long)G.n, nb = (n + BLK - 1) / BLK;
+    double* v = G.x64.p;
+    double* zero_b = G.b64.p;
+    double* r = G.r64.p;
+    double* y = G.t64.p;
+    hipLaunchKernelGGL((k_fill<double>), grid_for(n, BLK), BLK, 0, st, zero_b, n, 0.0);
+    hipLaunchKernelGGL(k_hash_fill, grid_for(n, BLK), BLK, 0, st, n, 0x5EEDB10CULL + (unsigned long long)d, v);
+    double lam = 0;
+    for (int it = 0; it < BLOCK_POWER; ++it) {
+      // r = -A v, y = B r = -B A v
+      hipLaunchKernelGGL((k_residual<double, double, 1>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
+                         (int)G.nslices, G.scol.p, G.sval64.p, (const double*)zero_b, (const double*)v, r,
+                         (double*)nullptr);
+      hipLaunchKernelGGL((k_fill<double>), grid_for(n, BLK), BLK, 0, st, y, n, 0.0);
+      if (G.nb8)
+        hipLaunchKernelGGL((k_block_apply<double, 1, 8>), grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, G.nb8,
+                           G.bidx8.p, (const double*)G.binv8_64.p, (const double*)G.bw8_64.p,
+                           (const double*)G.bs64.p, (const double*)r, 1.0, y);
+      if (G.nb16)
+        hipLaunchKernelGGL((k_block_apply<double, 1, 16>), grid_for((size_t)G.nb16 * 16, 256), 256, 0, st, G.nb16,
+                           G.bidx16.p, (const double*)G.binv16_64.p, (const double*)G.bw16_64.p,
+                           (const double*)G.bs64.p, (const double*)r, 1.0, y);
+      const double* pa[3] = {y, v, y};
+      const double* pb[3] = {r, r, y};
+      for (int q = 0; q < 3; ++q) {
+        hipLaunchKernelGGL(k_dot<1>, (unsigned)nb, BLK, 0, st, n, pa[q], pb[q], S->part.p);
+        hipLaunchKernelGGL(k_finalize<1>, 1, 1024, 0, st, (const double*)S->part.p, (int)nb, dd.p + q);
+      }
+      double h[3];
+      copy_out(ctx, h, dd.p, 3);
+      if (!(h[2] > 0.0) || !(h[1] < 0.0)) break;   // B A v = 0: nothing to damp
+      lam = std::max(lam, -h[0] / h[1]);
+      hipLaunchKernelGGL(k_scale_into, grid_for(n, BLK), BLK, 0, st, n, 1.0 / std::sqrt(h[2]), (const double*)y,
+                         v);
+    }
+    check_launch();
+    G.block_lambda = lam;
+    G.block_omega = lam > 0 ? std::min(1.0, 4.0 / (3.0 * lam)) : 1.0;
   }
 }
 
@@ -2151,6 +2230,30 @@ camfe_status camfe_system_autotune(camfe_sys s, double t, int precision, int rep
   });
 }
 
+camfe_status camfe_block_damping(camfe_sys s, double t, double coarse_eps, double* omega, double* lambda, int cap,
+                                 int* nlevels) {
+  return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
+    CAMFE_REQUIRE(s, CAMFE_EINVAL, "null system");
+    camfe_hier h = s->h;
+    CAMFE_REQUIRE(h->degree == 1, CAMFE_EINVAL, "the cell-block smoother is defined for degree 1");
+    const int nl = h->D - h->d0 + 1;
+    if (nlevels) *nlevels = nl;
+    if (cap == 0) return;
+    CAMFE_REQUIRE(cap >= nl, CAMFE_ETOOSMALL, "capacity below the number of depths");
+    h->ctx->use_device();
+    SolverState* S = ensure_solver(s, t, coarse_eps);
+    if (!S->blocks_ready) {
+      build_cell_blocks(s, S);
+      estimate_block_damping(S);
+    }
+    for (int i = 0; i < nl; ++i) {
+      if (omega) omega[i] = S->lev[h->d0 + i].block_omega;
+      if (lambda) lambda[i] = S->lev[h->d0 + i].block_lambda;
+    }
+  });
+}
+
 camfe_status camfe_batch_autotune(camfe_batch b, int precision, int reps, int32_t* tile, double* ms, int cap,
                                   int* nlevels) {
   return guarded([&] {
@@ -2191,7 +2294,7 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     CAMFE_REQUIRE(o->smoother >= 0 && o->smoother <= 3, CAMFE_EINVAL, "smoother must be 0, 1, 2 or 3");
     CAMFE_REQUIRE(o->smoother != 1 || (o->omega > 0 && o->omega < 2), CAMFE_EINVAL, "omega must lie in (0, 2)");
     CAMFE_REQUIRE(o->smoother != 3 || (o->omega >= 0 && o->omega <= 1), CAMFE_EINVAL,
-                  "block damping omega must lie in [0, 1] (0: 1)");
+                  "block damping omega must lie in [0, 1] (0: automatic per depth)");
     CAMFE_REQUIRE(o->smoother != 3 || h->degree == 1, CAMFE_EINVAL, "the cell-block smoother is defined for degree 1");
     CAMFE_REQUIRE(o->smoother != 2 || s->model, CAMFE_ESTATE, "learned smoother requested but no model attached");
     SolverState* S = ensure_solver(s, o->t, o->coarse_eps);
@@ -2207,11 +2310,13 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
     const bool stale = o->smoother != S->wkind || (o->smoother == 1 && o->omega != S->omega) ||
                        (o->smoother == 2 && s->model != S->model);
     if (o->smoother == 3) {
-      if (!S->blocks_ready) build_cell_blocks(s, S);
-      const double bw = o->omega > 0 ? o->omega : 1.0;
-      if (S->block_omega != bw) {   // captured cycles hold the damping as a kernel argument
+      if (!S->blocks_ready) {
+        build_cell_blocks(s, S);
+        estimate_block_damping(S);
+      }
+      if (S->block_omega != o->omega) {   // captured cycles hold the damping as a kernel argument
         S->drop_graphs();
-        S->block_omega = bw;
+        S->block_omega = o->omega;
       }
     } else if (o->smoother != 0 && stale) {
       set_smoother_weights(s, S, o->smoother, o->omega, o->smoother == 2 ? s->model : nullptr);

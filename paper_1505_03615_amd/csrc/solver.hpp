@@ -52,6 +52,10 @@ struct GLevel {
   // weights 1 / (largest number of blocks holding one of their functions)
   // (the inverses of the unit-diagonal-scaled blocks; bs = 1 / sqrt(A_ii))
   long long nb8 = 0, nb16 = 0;
+  // automatic damping of the block corrections at this depth: 4 / (3 lambda)
+  // (at most 1), lambda a power-iteration estimate of the largest eigenvalue
+  // of sum_B w_B R_B^T A_B^-1 R_B A
+  double block_lambda = 0, block_omega = 0;
   DArr<int> bidx8, bidx16;
   DArr<double> binv8_64, binv16_64, bw8_64, bw16_64, bs64;
   DArr<float> binv8_32, binv16_32, bw8_32, bw16_32, bs32;
@@ -79,7 +83,7 @@ struct SolverState {
   int smoother = 0;          // 0 multicolour Gauss-Seidel, 1 Jacobi (constant omega), 2 learned Jacobi,
                              // 3 cell-block Schwarz
   bool blocks_ready = false; // cell blocks built for this state (t, coarse_eps)
-  double block_omega = 0;    // damping of the cell-block corrections
+  double block_omega = 0;    // damping of the cell-block corrections (0: each depth's automatic value)
   int wkind = 0;             // smoother whose weights winvd holds (0: none)
   int wsweep = 0;            // sweep those weights are for: 0 Jacobi, 1 multicolour SOR
   double omega = 0;          // constant omega of smoother 1

@@ -1,8 +1,10 @@
 """The cell-block Schwarz smoother (camfe_solve smoother 3) against the
 oracle's: stationary cycles to 1e-9 in FP64 (every block class: cells of at
 most 8 functions, split cells of 9-16, and crowded coarse cells relaxed
-function by function), CG solves to the oracle's residual bar in both
-precisions, fewer cycles than Gauss-Seidel, and the damping option.
+function by function) with the automatic per-depth damping handed to the
+oracle, CG solves to the oracle's residual bar in both precisions, fewer
+cycles than Gauss-Seidel, the damping option, and the automatic damping's
+eigenvalue estimate against the oracle's dense eigenvalue.
 """
 import sys
 
@@ -85,10 +87,13 @@ def test_block_cycles_track_the_oracle(cf, ctx, name):
     t = CASES[name]["t"]
     Mo, Lo = o.matrices(o.depth)
     A = Mo + t * Lo
+    om, lam = cf.camfe_block_damping(s, t)
+    say(f"[gpu] block: {name} damping per depth {np.round(om, 4).tolist()} (lambda {np.round(lam, 4).tolist()})")
+    assert len(om) == o.depth - o.coarsest + 1 and np.all((om >= 0) & (om <= 1)) and om[-1] > 0
     for cyc in (1, 3):
         say(f"[gpu] block: {name} {cyc} stationary cycles")
         x, st = cf.camfe_solve(s, b, t=t, rtol=1e-30, max_iter=cyc, method=1, smoother=3)
-        xo, io = o.solve(t, b, rtol=1e-30, max_iter=cyc, mode="vcycle", smoother="block")
+        xo, io = o.solve(t, b, rtol=1e-30, max_iter=cyc, mode="vcycle", smoother="block", block_omega=om)
         assert st["fell_back"] == 0
         err = abs(x - xo).max() / abs(xo).max()
         rg = float((np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)).max())
@@ -139,3 +144,34 @@ def test_block_smoother_rejects_degree_2(cf, ctx):
     finally:
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
+
+
+def test_automatic_damping_estimates_the_largest_eigenvalue(cf, ctx):
+    """The automatic damping omega = min(1, 4 / (3 lambda)) rests on a power
+    estimate lambda of the largest eigenvalue of B A (B the weighted block
+    sum).  Against the oracle's dense eigenvalue at the finest depth of two
+    small systems: the estimate approaches from below and is within 20 %, so
+    omega lambda_max lies in [4/3, 5/3], inside the contraction bound 2."""
+    V1, F1, _, _ = meshgen.two_sheets(16, 1.0 / 64)
+    V2, F2 = meshgen.torus_knot(nu=128, nv=8, seed=3)
+    for V, F, depth, t in ((V1, F1, 5, 1e-3), (V2, F2, 5, 1e-4)):
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, min_depth=depth - 1, max_coarse=0)
+        s = cf.camfe_assemble(h)
+        try:
+            om, lam = cf.camfe_block_damping(s, t)
+        finally:
+            cf.camfe_system_destroy(s)
+            cf.camfe_hierarchy_destroy(h)
+        o = Oracle(V, F, depth, min_depth=depth - 1, max_coarse=0).check().assemble()
+        M, L = o.matrices(depth)
+        A = (M + t * L).toarray()
+        n = A.shape[0]
+        say(f"[gpu] block: dense eigenvalue of B A at depth {depth}, n={n}")
+        E = o.block_sweep(depth, t, np.zeros((n, n)), np.eye(n), eps=1e-6, omega=1.0)   # I - B A
+        # B A is A-self-adjoint, so its eigenvalues are real (A is only
+        # semidefinite in rounding here, which rules out the generalized
+        # symmetric solver)
+        top = float(np.linalg.eigvals(np.eye(n) - E).real.max())
+        say(f"[gpu] block: lambda_max {top:.4f}, estimate {lam[-1]:.4f}, omega {om[-1]:.4f}")
+        assert lam[-1] <= top * (1 + 1e-8) and lam[-1] >= 0.8 * top, (lam[-1], top)
+        assert abs(om[-1] - min(1.0, 4.0 / (3.0 * lam[-1]))) <= 1e-15

@@ -12,10 +12,16 @@ Pinned here against things the definition fixes without restating it:
   applied on one side only breaks it);
 - the solution of A x = b is a fixed point (fails on a sign slip in the
   residual);
-- the weights of the blocks holding any function sum to at most 1, so the
-  sweep is an A-norm contraction: stationary cycles converge, and CG
-  preconditioned by the cycle reaches the dense solution in fewer cycles
-  than Gauss-Seidel on a knot tube.
+- the sweep is an A-norm contraction on these small cases at omega = 1
+  (the largest eigenvalue of the weighted block sum times A is 1.15 on the
+  sheets and 1.55 on the knot; it is not bounded by 2 in general, since
+  blocks that share no function still couple, so the damping is an input):
+  stationary cycles converge, and CG preconditioned by the cycle reaches the
+  dense solution in fewer cycles than Gauss-Seidel on a knot tube;
+- the damping scales the correction (the sweep is affine in omega), and a
+  per-depth damping list equal to one value everywhere gives that value's
+  cycles bit for bit, while changing only the finest depth's entry changes
+  them.
 """
 import numpy as np
 import pytest
@@ -110,3 +116,27 @@ def test_block_cycles_precondition_cg_to_the_dense_solution():
     o2 = Oracle(Vi, Fi, 3, degree=2, max_coarse=64).check().assemble()
     with pytest.raises(RuntimeError, match="degree 1"):
         o2.solve(1e-3, np.ones(o2.count(3, "functions")), smoother="block")
+
+
+def test_damping_scales_the_correction_and_applies_per_depth():
+    V, F = meshgen.torus_knot(nu=256, nv=12, seed=3)
+    o = Oracle(V, F, 6, max_coarse=0, min_depth=4).check().assemble()
+    d, t = 6, 1e-4
+    n = o.count(d, "functions")
+    rng = np.random.default_rng(11)
+    b, x = rng.normal(size=(n, 2)), rng.normal(size=(n, 2))
+    full = o.block_sweep(d, t, b, x, omega=1.0) - x
+    part = o.block_sweep(d, t, b, x, omega=0.37) - x
+    assert np.abs(part - 0.37 * full).max() <= 1e-12 * np.abs(full).max()
+    levels = d - o.coarsest + 1
+    assert levels == 3
+    f = V[:, 2:3] + 0.1 * V[:, 0:1] ** 2
+    bb = o.load_vector(f)
+    x1, _ = o.solve(t, bb, rtol=1e-30, max_iter=2, mode="vcycle", smoother="block", block_omega=0.5)
+    x2, _ = o.solve(t, bb, rtol=1e-30, max_iter=2, mode="vcycle", smoother="block", block_omega=[0.5] * levels)
+    assert np.array_equal(x1, x2)
+    x3, _ = o.solve(t, bb, rtol=1e-30, max_iter=2, mode="vcycle", smoother="block",
+                    block_omega=[0.5] * (levels - 1) + [0.3])
+    assert not np.array_equal(x1, x3)
+    with pytest.raises(ValueError):
+        o.solve(t, bb, max_iter=1, smoother="block", block_omega=[0.5] * (levels + 1))

@@ -197,7 +197,7 @@ def measured_traffic(path=TRAFFIC_FILE, key="traffic_bytes_per_launch"):
         return None
 
 
-def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1, traffic_file=TRAFFIC_FILE):
+def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1, traffic_file=TRAFFIC_FILE, depth=None):
     """Algorithmic bytes of one launch of the finest-depth kernel over its
     average duration (HIP events around a captured graph of back-to-back
     launches on the library's stream), against the HBM peak, in both
@@ -205,7 +205,9 @@ def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1, traffic_
     which takes the larger share of the bench step: the mixed and the
     learned solves run it), the other precision sits beside it.
     with_traffic: attach the committed counter figures (taken on the
-    two-sheet depth-8 workload only)."""
+    two-sheet depth-8 workload only).  depth (optional): the finest depth,
+    whose packed-matrix figures (slices, slices with 16-bit columns,
+    entries) are attached."""
     res = {}
     precs = (0, 1) if meas in ("gs_colour", "residual") else (0,)
     if main_precision not in precs:
@@ -229,6 +231,9 @@ def roofline(cf, s, meas, reps=50, with_traffic=True, main_precision=1, traffic_
     out = {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s", **res[main_precision]}
     if len(precs) == 2:
         out["fp64" if main_precision == 1 else "fp32"] = res[1 - main_precision]
+    if depth is not None:
+        sl, c16, ent = cf.camfe_system_sell_stats(s, depth)
+        out["sell_finest"] = {"slices": sl, "slices_16bit_columns": c16, "entries": ent}
     return out
 
 
@@ -442,7 +447,7 @@ def flow_eval(cf, ctx, meshgen, steps=10, max_coarse=4096):
     vb = vcycle_bytes(cf, s, h, 3, 4, 4, nu=2 * nu, nu_below=2 * (nc if nc > 0 else nu))
     # the same colour-sweep measurement as the bench's roofline, on this
     # 2.2M-function finest depth (launches about twelve times larger)
-    big = roofline(cf, s, "gs_colour", reps=10, with_traffic=False)
+    big = roofline(cf, s, "gs_colour", reps=10, with_traffic=False, depth=10)
     # counters taken on this same workload
     big["traffic"] = measured_traffic(TRAFFIC_FILE_D10, "traffic_bytes_per_launch_fp32")
     big["fp64"]["traffic"] = measured_traffic(TRAFFIC_FILE_D10)
@@ -830,7 +835,7 @@ def main():
         b = cf.camfe_load_vector(s, h, fd)
         cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=0)     # solver setup only
         out = {"roofline": roofline(cf, s, "gs_colour", with_traffic=traffic_file is not None,
-                                    traffic_file=traffic_file)}
+                                    traffic_file=traffic_file, depth=wl["depth"])}
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
         if args.calibrate_copy:
@@ -938,7 +943,8 @@ def main():
                                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
         else:
             meas = dom if dom in ("gs_colour", "residual", "spmv_dot") else "gs_colour"
-            out["roofline"] = roofline(cf, s, meas, with_traffic=traffic_file is not None, traffic_file=traffic_file)
+            out["roofline"] = roofline(cf, s, meas, with_traffic=traffic_file is not None, traffic_file=traffic_file,
+                                       depth=wl["depth"])
         out["roofline"]["whole_vcycle"] = comp["vcycle_roofline"]
     cf.camfe_smoother_attach(s, None)
     cf.camfe_system_destroy(s)

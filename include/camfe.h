@@ -276,6 +276,19 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char *kernel, int precision
  * Takes effect at the next solver set-up: drops the system's current solver
  * state (captured graphs included). */
 camfe_status camfe_system_set_sell_sort(camfe_sys s, int64_t min_rows);
+/* Column storage of the solver's packed matrices (degree 1): bits 16 (the
+ * default) stores per entry a 16-bit code, colour << 13 | offset from one
+ * base per (64-row slice, colour), wherever every colour's columns in the
+ * slice span fewer than 8192 rows, and 32-bit columns elsewhere; bits 32
+ * keeps 32-bit columns everywhere.  Both hold the same columns in the same
+ * order, so results are the same bits.  EINVAL for other values.  Takes
+ * effect at the next solver set-up (drops the current solver state). */
+camfe_status camfe_system_set_sell_columns(camfe_sys s, int bits);
+/* Packed-matrix figures of one depth of the current solver state: slices,
+ * slices with 16-bit column codes, stored entries (padding included).
+ * Nullable outputs.  ESTATE before the first solve; EINVAL for a depth
+ * outside the solver's. */
+camfe_status camfe_system_sell_stats(camfe_sys s, int depth, int64_t *slices, int64_t *compact, int64_t *entries);
 /* The automatic damping of smoother 3 at every depth (coarsest first; 0 at
  * a coarsest depth solved directly), building the solver for A = M + t L and
  * its cell blocks where missing: omega_d = min(1, 4 / (3 lambda_d)), where
@@ -290,14 +303,18 @@ camfe_status camfe_block_damping(camfe_sys s, double t, double coarse_eps, doubl
 /* Autotuner of the colour sweep's tile (not in the paper): for every depth of
  * the system's solver for A = M + t L (built when missing), each compiled tile
  * {wavefronts per 64-row slice, entries per lane issued together} in
- * {8,4} (default), {4,4}, {8,2}, {16,2}, {16,4} is timed over reps forward
+ * {8,4} (default), {4,4}, {8,2}, {16,2}, {16,4}, {4,8}, {2,16} is timed over
+ * reps forward
  * sweeps (one right-hand side, FP64 values for precision 0, FP32 for 1,
  * captured into a HIP graph, timed with events on the context's stream) and
  * the fastest is kept for that depth: by this solver and by the solvers the
- * system builds later.  Right-hand-side columns are processed four per pass
+ * system builds later.  Without it a degree-1 depth takes {4,8} from 2^19
+ * rows per colour, {4,4} from 2^17, {8,4} from 2^15 and {16,2} below (degree
+ * 2: {8,4}).  Tiles change the order in which a row's partial sums meet, so
+ * results move within rounding.  Right-hand-side columns are processed four per pass
  * (the widest tile compiled).  Two-call pattern over the depths, coarsest
  * first: cap = 0 returns the count in *nlevels; otherwise tile (nullable)
- * receives each depth's index (0..4 in the order above) and ms (nullable) its
+ * receives each depth's index (0..6 in the order above) and ms (nullable) its
  * time per sweep.  Overwrites the solver's scratch vectors. */
 camfe_status camfe_system_autotune(camfe_sys s, double t, int precision, int reps, int32_t *tile, double *ms,
                                    int cap, int *nlevels);

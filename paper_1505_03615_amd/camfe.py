@@ -31,9 +31,9 @@ EXPORTS = [
     "camfe_batch_create", "camfe_batch_info", "camfe_batch_solve", "camfe_batch_destroy", "camfe_eigs",
     "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
     "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc", "camfe_system_autotune",
-    "camfe_batch_autotune", "camfe_block_damping",
+    "camfe_batch_autotune", "camfe_block_damping", "camfe_system_set_sell_columns", "camfe_system_sell_stats",
 ]
-TILES = [(8, 4), (4, 4), (8, 2), (16, 2), (16, 4)]   # colour-sweep tiles: (wavefronts per slice, entries per lane)
+TILES = [(8, 4), (4, 4), (8, 2), (16, 2), (16, 4), (4, 8), (2, 16)]   # colour-sweep tiles: (wavefronts per slice, entries per lane)
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
 DEFAULT_COARSE_EPS = 1e-6   # eps * Id on the unit-diagonal-scaled coarsest matrix (the library's own default)
 KERNELS = ["gs_colour", "residual", "spmv_dot", "restrict", "prolong", "coarse_solve", "assemble", "pairs",
@@ -151,6 +151,8 @@ def load():
         "camfe_system_autotune": (I, [H, D, I, I, P, P, I, C.POINTER(I)]),
         "camfe_batch_autotune": (I, [H, I, I, P, P, I, C.POINTER(I)]),
         "camfe_block_damping": (I, [H, D, D, P, P, I, C.POINTER(I)]),
+        "camfe_system_set_sell_columns": (I, [H, I]),
+        "camfe_system_sell_stats": (I, [H, I, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -455,6 +457,17 @@ def camfe_measure_kernel(s, kernel: str, precision: int = 0, reps: int = 50):
 
 def camfe_system_destroy(s):
     load().camfe_system_destroy(s)
+
+
+def camfe_system_set_sell_columns(s, bits):
+    _check(load().camfe_system_set_sell_columns(s, bits))
+
+
+def camfe_system_sell_stats(s, depth):
+    """(slices, slices with 16-bit column codes, stored entries) of one depth."""
+    a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+    _check(load().camfe_system_sell_stats(s, depth, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
 
 
 def camfe_system_set_sell_sort(s, min_rows):

@@ -1,6 +1,6 @@
 // Systems built from given matrices (a debugging entry: the multigrid solve
 // of Sections 3.2, 4.3 and 5.2 on matrices assembled elsewhere), and the
-// solver's layout option.
+// solver's layout options and statistics.
 //
 // An imported system carries a hierarchy of its own with only what the
 // solver reads: per depth the function keys (their colours), the
@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "solver.hpp"
 
 using namespace camfe;
 
@@ -48,6 +49,32 @@ camfe_status camfe_system_set_sell_sort(camfe_sys s, int64_t min_rows) {
     s->h->ctx->sync();
     destroy_solver(s->solver);
     s->solver = nullptr;
+  });
+}
+
+camfe_status camfe_system_set_sell_columns(camfe_sys s, int bits) {
+  return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
+    CAMFE_REQUIRE(s && (bits == 16 || bits == 32), CAMFE_EINVAL, "null system, or bits other than 16 and 32");
+    s->h->ctx->use_device();
+    s->sell_compact = bits == 16;
+    s->h->ctx->sync();
+    destroy_solver(s->solver);
+    s->solver = nullptr;
+  });
+}
+
+camfe_status camfe_system_sell_stats(camfe_sys s, int depth, int64_t* slices, int64_t* compact, int64_t* entries) {
+  return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
+    CAMFE_REQUIRE(s, CAMFE_EINVAL, "null system");
+    CAMFE_REQUIRE(s->solver, CAMFE_ESTATE, "no solver yet: solve (or autotune) first");
+    const SolverState* S = s->solver;
+    CAMFE_REQUIRE(depth >= S->d0 && depth <= S->D, CAMFE_EINVAL, "depth outside the solver's depths");
+    const GLevel& G = S->lev[depth];
+    if (slices) *slices = (int64_t)G.nslices;
+    if (compact) *compact = (int64_t)G.ns16;
+    if (entries) *entries = (int64_t)G.snnz;
   });
 }
 

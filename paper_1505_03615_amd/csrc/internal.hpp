@@ -79,6 +79,7 @@ struct camfe_sys_s {
   camfe::DArr<double> area0;        // triangle areas of the original surface (flow)
   std::vector<camfe::DArr<double>> mcache;   // per depth: unweighted degree-1 mass blocks of every pair
   long long sell_sort_min_rows = 0;  // colours with at least this many rows are length-sorted (0: default)
+  bool sell_compact = true;          // 16-bit column codes where a slice's spans allow (degree 1)
   std::vector<int> tiles;            // colour-sweep tile per depth from camfe_system_autotune (empty: default)
   camfe_hier owned_h = nullptr;      // an imported system's own hierarchy (freed with the system)
   ~camfe_sys_s() {

@@ -26,6 +26,7 @@
 #include "solver.hpp"
 #include "sell_kernels.hpp"
 #include "block_kernels.hpp"
+#include <climits>
 
 namespace camfe {
 
@@ -131,6 +132,66 @@ __global__ void k_sell_pad(const int* sl_ptr, const int* row0, const int* rows, 
     scol[o] = row0[s];
     sval[o] = 0.0;
     sval32[o] = 0.0f;
+  }
+}
+
+// 16-bit column codes of one slice, one wavefront per slice (degree 1: 8
+// colours).  The smallest and largest column of each colour among the
+// slice's entries (padding included) meet by shuffles; when every colour
+// spans fewer than 2^C16_BITS rows the slice gets its codes colour << 13 |
+// (column - base), its eight bases (a colour it lacks takes the slice's first
+// row, so that the padding lanes' code 0 still decodes to a valid row) and
+// the C16 flag, and `count` one more.
+struct ColourStarts { int c[9]; };
+__device__ inline int colour_of_row(const ColourStarts& co, int r) {
+  int c = 0;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) c += r >= co.c[k] ? 1 : 0;
+  return c;
+}
+__global__ __launch_bounds__(64) void k_sell_compact(long long ns, ColourStarts co, const int* scol, int4* meta,
+                                                     int* sbase, uint16_t* scol16, unsigned long long* count) {
+  const long long s = blockIdx.x;
+  if (s >= ns) return;
+  const int lane = threadIdx.x;
+  const int4 m = meta[s];
+  const int w = (m.y - m.x) / SL;
+  int lo[8], hi[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) { lo[k] = INT_MAX; hi[k] = INT_MIN; }
+  for (int j = 0; j < w; ++j) {
+    const int col = scol[m.x + lane + (long long)j * SL];
+    const int c = colour_of_row(co, col);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (c == k) { lo[k] = min(lo[k], col); hi[k] = max(hi[k], col); }
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[k] = min(lo[k], __shfl_xor(lo[k], o));
+      hi[k] = max(hi[k], __shfl_xor(hi[k], o));
+    }
+    if (hi[k] >= lo[k] && hi[k] - lo[k] >= (1 << C16_BITS)) ok = false;
+    if (hi[k] < lo[k]) lo[k] = m.z;
+  }
+  if (!ok) return;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (lane == k) sbase[s * 8 + k] = lo[k];
+  for (int j = 0; j < w; ++j) {
+    const long long e = m.x + lane + (long long)j * SL;
+    const int col = scol[e];
+    const int c = colour_of_row(co, col);
+    int b = lo[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) b = c == k ? lo[k] : b;
+    scol16[e] = (uint16_t)((c << C16_BITS) | (col - b));
+  }
+  if (lane == 0) {
+    meta[s].w = m.w | C16;
+    atomicAdd(count, 1ULL);
   }
 }
 
@@ -633,6 +694,20 @@ void pack_meta(camfe_ctx ctx, GLevel& G, const std::vector<int>& ptr, const std:
   copy_in(ctx, G.sl_meta.p, m.data(), m.size());
 }
 
+// Colour-sweep tile of a depth that the autotuner has not seen, by its rows
+// per colour (degree 1; measured on the depth-11 knot and sphere and their
+// coarser depths): large colours take one pass of 8 entries per lane with 4
+// wavefronts per slice (more slices in flight per CU), mid-sized ones 4 x 4
+// or the 8 x 4 default, small ones 16 wavefronts of 2 entries (latency of a
+// short launch).
+int default_tile(int degree, size_t rows_per_colour) {
+  if (degree != 1) return 0;
+  if (rows_per_colour >= (size_t)1 << 19) return 5;
+  if (rows_per_colour >= (size_t)1 << 17) return 1;
+  if (rows_per_colour >= (size_t)1 << 15) return 0;
+  return 3;
+}
+
 void setup_level(camfe_sys s, SolverState* st, int d) {
   camfe_hier h = s->h;
   camfe_ctx ctx = h->ctx;
@@ -642,8 +717,8 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
   G.d = d;
   G.n = S.n;
   G.ncol = h->degree == 1 ? 8 : 27;
-  G.tile = (size_t)d < s->tiles.size() ? std::max(0, s->tiles[d]) : 0;
   const size_t n = G.n;
+  G.tile = (size_t)d < s->tiles.size() ? std::max(0, s->tiles[d]) : default_tile(h->degree, n / G.ncol);
   unsigned g = grid_for(n, BLK);
   // colour order (stable: canonical order inside a colour)
   DArr<uint32_t> colour(n), idx(n);
@@ -739,6 +814,19 @@ void setup_level(camfe_sys s, SolverState* st, int d) {
                      st->t, G.perm.p, G.iperm.p, G.sl_ptr.p, G.sl_row0.p, G.sl_rows.p, (long long)G.nslices,
                      G.scol.p, G.sval64.p, G.sval32.p, G.invd64.p, G.invd32.p);
   check_launch();
+  G.ns16 = 0;
+  if (G.ncol == 8 && s->sell_compact && G.nslices) {
+    ColourStarts co;
+    for (int c = 0; c <= 8; ++c) co.c[c] = G.coff[c];
+    G.scol16.alloc(G.snnz);
+    G.sbase.alloc(G.nslices * 8);
+    DArr<unsigned long long> cnt(1);
+    zero(ctx, cnt.p, 1);
+    hipLaunchKernelGGL(k_sell_compact, (unsigned)G.nslices, 64, 0, ctx->stream, (long long)G.nslices, co,
+                       (const int*)G.scol.p, G.sl_meta.p, G.sbase.p, G.scol16.p, cnt.p);
+    check_launch();
+    G.ns16 = (long long)read_scalar(ctx, cnt.p);
+  }
   G.x64.alloc(n * KMAXS); G.b64.alloc(n * KMAXS); G.r64.alloc(n * KMAXS); G.t64.alloc(n * KMAXS);
   G.x32.alloc(n * KMAXS); G.b32.alloc(n * KMAXS); G.r32.alloc(n * KMAXS); G.t32.alloc(n * KMAXS);
 }
@@ -893,7 +981,7 @@ template <class T, int K, int TILE>
 void gs_colour(camfe_ctx ctx, GLevel& G, int c, const T* b, T* x, const T* dinv) {
   const int s0 = G.cslice[c], s1 = G.cslice[c + 1];
   CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.cnnz[c], G.coff[c + 1] - G.coff[c])), (k_gs<T, K, TILE>),
-              (unsigned)(s1 - s0), SL * tile_sw(TILE), 0, ctx->stream, G.sl_meta.p, s0, s1, G.scol.p,
+              (unsigned)(s1 - s0), SL * tile_sw(TILE), 0, ctx->stream, G.sl_meta.p, s0, s1, G.scol.p, G.scol16.p, G.sbase.p,
               sval_of<T>(G), dinv, b, x);
 }
 
@@ -910,6 +998,8 @@ void gs_sweep(camfe_ctx ctx, GLevel& G, const T* b, T* x, bool forward, const T*
       case 2: gs_colour<T, K, 2>(ctx, G, c, b, x, dinv); break;
       case 3: gs_colour<T, K, 3>(ctx, G, c, b, x, dinv); break;
       case 4: gs_colour<T, K, 4>(ctx, G, c, b, x, dinv); break;
+      case 5: gs_colour<T, K, 5>(ctx, G, c, b, x, dinv); break;
+      case 6: gs_colour<T, K, 6>(ctx, G, c, b, x, dinv); break;
       default: gs_colour<T, K, 0>(ctx, G, c, b, x, dinv); break;
     }
   }
@@ -959,7 +1049,7 @@ void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
   T* r = tmp_of<T>(G);
   for (int it = 0; it < nu; ++it) {
     CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
-                (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p, (int)G.nslices, G.scol.p, sval_of<T>(G), b,
+                (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, sval_of<T>(G), b,
                 (const T*)x, r, (double*)nullptr);
     if (G.nb8)
       CAMFE_TIMED(ctx, KT_GS, ((double)G.nb8 * 8 * (8 * sizeof(T) + 4) + 3.0 * G.n * K * sizeof(T)),
@@ -1020,7 +1110,7 @@ void estimate_block_damping(SolverState* S) {
     for (int it = 0; it < BLOCK_POWER; ++it) {
       // r = -A v, y = B r = -B A v
       hipLaunchKernelGGL((k_residual<double, double, 1>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
-                         (int)G.nslices, G.scol.p, G.sval64.p, (const double*)zero_b, (const double*)v, r,
+                         (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, (const double*)zero_b, (const double*)v, r,
                          (double*)nullptr);
       hipLaunchKernelGGL((k_fill<double>), grid_for(n, BLK), BLK, 0, st, y, n, 0.0);
       if (G.nb8)
@@ -1066,7 +1156,7 @@ void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward, b
   for (int i = 0; i < nu; ++i) {
     CAMFE_TIMED(ctx, KT_GS, (pass_bytes<T, K>(G.nnz, (long long)G.n) + (double)G.n * sizeof(T)), (k_jacobi<T, K>),
                 (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p, (int)G.nslices,
-                G.scol.p, sval_of<T>(G), winvd_of<T>(G), b, (const T*)a, t);
+                G.scol.p, G.scol16.p, G.sbase.p, sval_of<T>(G), winvd_of<T>(G), b, (const T*)a, t);
     std::swap(a, t);
   }
   if (a != x)
@@ -1113,7 +1203,7 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool firs
   T* r = Vec<T>::r(G);
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
               (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
-              (int)G.nslices, G.scol.p, sval_of<T>(G), b, (const T*)x, r, (double*)nullptr);
+              (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, sval_of<T>(G), b, (const T*)x, r, (double*)nullptr);
   GLevel& C = S->lev[d - 1];
   T* bc = Vec<T>::b(C);
   T* xc = Vec<T>::x(C);
@@ -1172,7 +1262,7 @@ void residual64(SolverState* S, const double* b, const double* x, double* r, dou
   camfe_ctx ctx = S->ctx;
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<double, K>(G.nnz, (long long)G.n)), (k_residual<double, double, K>),
               (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p,
-              (int)G.nslices, G.scol.p, G.sval64.p, b, x, r, nrm ? S->part.p : (double*)nullptr);
+              (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, b, x, r, nrm ? S->part.p : (double*)nullptr);
   if (nrm) finalize<K>(S, (long long)G.nslices, nrm);
 }
 
@@ -1232,7 +1322,7 @@ void cg_step(SolverState* S, int nu1, int nu2) {
   const long long nb = (long long)((n + BLK - 1) / BLK);
   double* sc = S->sc.p;
   CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices, SL * SW, 0,
-              ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p,
               (const double*)S->P.p, S->Q.p, S->part.p);
   finalize<K>(S, (long long)G.nslices, sc + K);
   hipStream_t st = ctx->stream;
@@ -1702,7 +1792,7 @@ void cg_step_b(SolverState* S, int nu1, int nu2) {
   const size_t n = G.n;
   const long long nb = (long long)(n / BLK);
   CAMFE_TIMED(ctx, KT_SPMV, ((double)G.nnz * 8 + 2.0 * n * K * 8), k_spmv_dot<K>, (unsigned)G.nslices, SL * SW, 0,
-              ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.sval64.p,
+              ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p,
               (const double*)S->P.p, S->Q.p, S->part.p);
   dot_seg<K>(S, S->P.p, S->Q.p, K);
   CAMFE_TIMED(ctx, KT_CG_VEC, (6.0 * n * K * 8), k_cg_update_b<K>, (unsigned)nb, BLK, 0, ctx->stream, (long long)n,
@@ -1809,7 +1899,7 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
   hipLaunchKernelGGL((k_fill<double>), grid_for(S->sc.n, BLK), BLK, 0, st, S->sc.p, (long long)S->sc.n, 0.0);
   dot_seg<K>(S, S->B.p, S->B.p, 4 * K);
   hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
-                     (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
+                     (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
                      (double*)nullptr);
   dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
   check_launch();
@@ -1847,7 +1937,7 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
     // true residuals of the final iterates, over every member
     gate(std::vector<int>(nm, 1));
     hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
-                       (int)G.nslices, G.scol.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
+                       (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, (const double*)S->B.p, (const double*)S->X.p, S->R.p,
                        (double*)nullptr);
     dot_seg<K>(S, S->R.p, S->R.p, 2 * K);
     copy_out(ctx, hs.data(), S->sc.p, hs.size());
@@ -1924,7 +2014,7 @@ void coarse_correction(SolverState* S, int d, const double* e, double* out, bool
     // r = 0 - A e, b_c = P^T r = -P^T A e
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.t64.p, nk, 0.0);
     hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
-                       (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.t64.p, e, r, (double*)nullptr);
+                       (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, (const double*)G.t64.p, e, r, (double*)nullptr);
   } else {
     hipLaunchKernelGGL((k_convert<double, double>), grid_for(nk, BLK), BLK, 0, st, e, nk, r);
   }
@@ -1944,7 +2034,7 @@ void coarse_correction(SolverState* S, int d, const double* e, double* out, bool
                        (long long)G.n, (const double*)C.x64.p, G.t64.p, (const int*)nullptr,
                        (const int*)nullptr);
     hipLaunchKernelGGL((k_residual<double, double, K>), (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
-                       (int)G.nslices, G.scol.p, G.sval64.p, e, (const double*)G.t64.p, out, (double*)nullptr);
+                       (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, e, (const double*)G.t64.p, out, (double*)nullptr);
   }
   S->smoother = sm;
   check_launch();
@@ -2062,15 +2152,15 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
         } else if (kid == 1) {
           if (precision == 0)
             hipLaunchKernelGGL((k_residual<double, double, 1>), (unsigned)G.nslices, SL * SW, 0,
-                               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p,
+                               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p,
                                G.sval64.p, (const double*)G.b64.p, (const double*)G.x64.p, G.r64.p, (double*)nullptr);
           else
             hipLaunchKernelGGL((k_residual<float, float, 1>), (unsigned)G.nslices, SL * SW, 0,
-                               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p,
+                               ctx->stream, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p,
                                G.sval32.p, (const float*)G.b32.p, (const float*)G.x32.p, G.r32.p, (double*)nullptr);
         } else if (kid == 2) {
           hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p,
-                             (int)G.nslices, G.scol.p, G.sval64.p, (const double*)G.x64.p, G.r64.p, S->part.p);
+                             (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, (const double*)G.x64.p, G.r64.p, S->part.p);
         } else if (kid == 5) {
           // one plain Gauss-Seidel V(2,2)-cycle from a zero guess, as the
           // preconditioner of a CG step applies it (one column)

@@ -33,8 +33,13 @@ struct GLevel {
   DArr<int> sl_ptr;           // slice offsets into the value arrays (nslices + 1)
   DArr<int> sl_row0;          // first internal row of each slice
   DArr<int> sl_rows;          // rows in each slice (<= 64)
-  DArr<int4> sl_meta;         // {sl_ptr[s], sl_ptr[s + 1], sl_row0[s], sl_rows[s]} per slice
+  DArr<int4> sl_meta;         // {sl_ptr[s], sl_ptr[s + 1], sl_row0[s], sl_rows[s] | flags} per slice
   DArr<int> scol;
+  // 16-bit column codes (colour << 13 | offset) and 8 bases per slice, for
+  // the slices flagged C16 in sl_meta (sell_kernels.hpp); ns16 of them
+  DArr<uint16_t> scol16;
+  DArr<int> sbase;
+  long long ns16 = 0;
   DArr<double> sval64, invd64;
   DArr<float> sval32, invd32;
   // relaxation weights omega_i / A_ii (internal order), set for smoothers 1 and 2

@@ -1,7 +1,7 @@
 """The remaining calls of the C ABI, through the binding, against the oracle:
 occupied cells, systems built from the oracle's own matrices, the
-per-context error record, the solver's row layout option, and the largest
-coarsest depth solved directly.
+per-context error record, the solver's row layout and column storage
+options, and the largest coarsest depth solved directly.
 """
 import sys
 
@@ -173,6 +173,49 @@ def test_length_sorted_rows_track_the_oracle(cf, ctx, sheets, name):
             r = np.linalg.norm(b - (Mo + t * Lo) @ x, axis=0) / np.linalg.norm(b, axis=0)
             assert st["converged"] and np.all(r <= 1e-6), (precision, r)
     finally:
+        cf.camfe_system_set_sell_sort(s, 0)
+        if own:
+            cf.camfe_system_destroy(s)
+            cf.camfe_hierarchy_destroy(h)
+
+
+@pytest.mark.parametrize("name", ["sheets", "knot_d9"])
+def test_sixteen_bit_columns_give_the_same_bits(cf, ctx, sheets, name):
+    """16-bit column codes (the default) hold the same columns in the same
+    positions as 32-bit columns, so stationary cycles and CG in both
+    precisions give the same bits with either storage, also with every
+    colour length-sorted; most slices of the finest depth take the codes
+    (on the depth-9 knot, 780k functions, some slices keep 32-bit columns
+    where the Morton order jumps: both kinds in one launch)."""
+    if name == "sheets":
+        V, F, f, h, s, o = sheets
+        t, own, depth = 1e-3, False, 6
+        b = o.load_vector(f)
+    else:
+        V, F = meshgen.torus_knot(nu=8192, nv=32, seed=3)
+        depth, t, own = 9, 1e-4, True
+        h = cf.camfe_hierarchy_build(ctx, V, F, depth=depth, max_coarse=4096)
+        s = cf.camfe_assemble(h)
+        b = cf.camfe_load_vector(s, h, V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
+    runs = (dict(rtol=1e-30, max_iter=3, method=1), dict(rtol=1e-8, max_iter=2000, precision=0),
+            dict(rtol=1e-8, max_iter=2000, precision=1))
+    try:
+        for sort in (0, 1):
+            cf.camfe_system_set_sell_sort(s, sort)
+            res = {}
+            for bits in (16, 32):
+                cf.camfe_system_set_sell_columns(s, bits)
+                res[bits] = [cf.camfe_solve(s, b, t=t, **kw) for kw in runs]
+                sl, c16, ent = cf.camfe_system_sell_stats(s, depth)
+                say(f"[gpu] {name} sort {sort} bits {bits}: {c16} of {sl} slices with 16-bit codes, {ent} entries")
+                if bits == 32:
+                    assert c16 == 0
+                else:
+                    assert 0.5 * sl <= c16 <= sl
+            for (x16, st16), (x32, st32) in zip(res[16], res[32]):
+                assert np.array_equal(x16, x32) and st16["cycles"] == st32["cycles"]
+    finally:
+        cf.camfe_system_set_sell_columns(s, 16)
         cf.camfe_system_set_sell_sort(s, 0)
         if own:
             cf.camfe_system_destroy(s)

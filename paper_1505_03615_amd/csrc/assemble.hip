@@ -204,6 +204,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
   constexpr int PG = DEG == 1 ? 8 : 4;
   constexpr int PMAX = 16;   // clipped polygon vertices (9 in exact arithmetic)
   __shared__ double poly[PMAX][6];
+  __shared__ double sarea[PMAX];
   const int lane = threadIdx.x;
   const int slot = lane & 15;
   const int pt = lane >> 4;
@@ -331,7 +332,22 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
         P[5] = lane == 2 ? 1.0 : 0.0;
       }
       int n = 3;
-      for (int pl = 0; pl < 6 && n >= 3; ++pl) {
+      // a triangle inside the closed cell (the common case at fine depths,
+      // where triangles are smaller than cells) is its own clipped polygon:
+      // every plane would keep all three vertices in order, so the clipping
+      // is skipped with the same result
+      bool inside = true;
+      if (lane < 3)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) inside = inside && P[q] >= (double)cc[q] && P[q] <= (double)cc[q] + 1.0;
+      const bool all_in = __all(inside);
+      if (all_in) {
+        if (lane < 3)
+#pragma unroll
+          for (int q = 0; q < 6; ++q) poly[lane][q] = P[q];
+        __syncthreads();
+      }
+      for (int pl = 0; pl < 6 && n >= 3 && !all_in; ++pl) {
         const int ax = pl >> 1;
         const bool ge = (pl & 1) == 0;
         const double v = (double)cc[ax] + (ge ? 0.0 : 1.0);
@@ -408,6 +424,20 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
       }
       const int npts = (n - 2) * Q;
       wave_pts += (unsigned long long)npts;
+      // area of each fan sub-triangle, once (lane s - 1 takes sub-triangle s)
+      if (lane < n - 2) {
+        const double* A0 = poly[0];
+        const double* A1 = poly[lane + 1];
+        const double* A2 = poly[lane + 2];
+        double e1[3], e2[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) { e1[q] = A1[q] - A0[q]; e2[q] = A2[q] - A0[q]; }
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+        const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+        const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+        sarea[lane] = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+      }
+      __syncthreads();
       for (int p0 = 0; p0 < npts; p0 += PG) {
         const int p = p0 + pt + (DEG == 1 ? 4 * (slot >> 3) : 0);
         double val[T], gx[T], gy[T], gz[T];
@@ -424,10 +454,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           double e1[3], e2[3];
 #pragma unroll
           for (int q = 0; q < 3; ++q) { e1[q] = A1[q] - A0[q]; e2[q] = A2[q] - A0[q]; }
-          const double cx = e1[1] * e2[2] - e1[2] * e2[1];
-          const double cy = e1[2] * e2[0] - e1[0] * e2[2];
-          const double cz = e1[0] * e2[1] - e1[1] * e2[0];
-          const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+          const double area = sarea[s - 1];
           const double u = c_glx[RI][iu], wu = c_glw[RI][iu];
           const double xi = u, eta = (1.0 - u) * c_glx[RI][iv];
           wl = 2.0 * area * wu * c_glw[RI][iv] * (1.0 - u);

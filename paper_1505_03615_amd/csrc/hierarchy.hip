@@ -292,11 +292,16 @@ __global__ void k_uf_init(int* parent, long long n) {
 
 // Links of entry e = (k, t): shared edges of t that reach into the open
 // support, and vertices of t inside it; t is joined with the smallest
-// triangle on that edge (vertex) that is active at k.
+// triangle on that edge (vertex) that is active at k.  Two shortcuts keep
+// the same components: when t itself comes first among the edge's (vertex's)
+// triangles there is nothing to join, so no search is made; and a vertex
+// inside the box by more than rounding whose triangles form one fan (vfan)
+// adds no link, since its edges all reach into the box and their links
+// already join every triangle at it (all of which are active at k).
 __global__ void k_uf_link(const u64* ent, long long n, const int* cid, const int* cstart, int ncorn,
                           const int* F, const double* U, double sc, int degree, const int* tri_edge,
                           const int* edge_ptr, const int* edge_tri, const int* vt_ptr, const int* vt_tri,
-                          int* parent) {
+                          const int* vfan, int* parent) {
   long long e = blockIdx.x * (long long)BLK + threadIdx.x;
   if (e >= n) return;
   const u64 key = ent[e];
@@ -320,6 +325,7 @@ __global__ void k_uf_link(const u64* ent, long long n, const int* cid, const int
       int eid = tri_edge[3 * t + j];
       for (int r = edge_ptr[eid]; r < edge_ptr[eid + 1]; ++r) {
         int t2 = edge_tri[r];
+        if (t2 == t) break;
         u64 k2 = (skey << TRI_BITS) | (u64)t2;
         long long p = lower_bound_u64(ent, gs, ge, k2);
         if (p < ge && ent[p] == k2) {
@@ -329,11 +335,16 @@ __global__ void k_uf_link(const u64* ent, long long n, const int* cid, const int
       }
     }
     int v = F[3 * t + j];
-    bool inside = true;
-    for (int q = 0; q < 3; ++q) inside = inside && fabs(U[3 * (long long)v + q] * sc - C[q]) < H;
-    if (inside) {
+    bool inside = true, deep = true;
+    for (int q = 0; q < 3; ++q) {
+      const double z = fabs(U[3 * (long long)v + q] * sc - C[q]);
+      inside = inside && z < H;
+      deep = deep && z < H * (1.0 - 1e-12);
+    }
+    if (inside && !(deep && vfan[v])) {
       for (int r = vt_ptr[v]; r < vt_ptr[v + 1]; ++r) {
         int t2 = vt_tri[r];
+        if (t2 == t) break;
         u64 k2 = (skey << TRI_BITS) | (u64)t2;
         long long p = lower_bound_u64(ent, gs, ge, k2);
         if (p < ge && ent[p] == k2) {
@@ -434,6 +445,43 @@ __global__ void k_vt_fill(const u64* keys, long long n, long long nv, int* vt_pt
   for (long long w = pv + 1; w <= v; ++w) vt_ptr[w] = (int)i;
   if (i == n - 1)
     for (long long w = v + 1; w <= nv; ++w) vt_ptr[w] = (int)n;
+}
+
+// 1 when the triangles at vertex v form a single fan: connected through
+// edges at v (two triangles share the edge (v, w) when both hold w).  Up to
+// 32 triangles per vertex are examined; a vertex with more counts as not
+// a single fan (its vertex links are kept, which is always correct).
+__global__ void k_vertex_fans(const int* F, const int* vt_ptr, const int* vt_tri, long long nv, int* vfan) {
+  long long v = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (v >= nv) return;
+  const int p0 = vt_ptr[v], k = vt_ptr[v + 1] - p0;
+  if (k > 32) { vfan[v] = 0; return; }
+  int w1[32], w2[32], lab[32];
+  for (int i = 0; i < k; ++i) {
+    const int t = vt_tri[p0 + i];
+    int o[2], m = 0;
+    for (int j = 0; j < 3; ++j) {
+      const int u = F[3 * t + j];
+      if (u != (int)v && m < 2) o[m++] = u;
+    }
+    w1[i] = o[0];
+    w2[i] = m > 1 ? o[1] : o[0];
+    lab[i] = i;
+  }
+  // label propagation over the shared-edge graph (at most k rounds)
+  for (bool moved = true; moved;) {
+    moved = false;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j)
+        if ((w1[i] == w1[j] || w1[i] == w2[j] || w2[i] == w1[j] || w2[i] == w2[j]) && lab[i] != lab[j]) {
+          const int m = min(lab[i], lab[j]);
+          lab[i] = lab[j] = m;
+          moved = true;
+        }
+  }
+  int one = 1;
+  for (int i = 0; i < k; ++i) one = one && lab[i] == 0;
+  vfan[v] = one;
 }
 
 // ----------------------------------------------------------- prolongation
@@ -555,6 +603,9 @@ void build_adjacency(camfe_hier h) {
   h->vt_tri.alloc(n3);
   hipLaunchKernelGGL(k_vt_fill, g, BLK, 0, ctx->stream, keys.p, (long long)n3, (long long)h->nv, h->vt_ptr.p,
                      h->vt_tri.p);
+  h->vfan.alloc(std::max<size_t>(h->nv, 1));
+  hipLaunchKernelGGL(k_vertex_fans, grid_for(h->nv, BLK), BLK, 0, ctx->stream, h->F.p, h->vt_ptr.p, h->vt_tri.p,
+                     (long long)h->nv, h->vfan.p);
   check_launch();
   ctx->sync();
 }
@@ -603,7 +654,7 @@ void build_functions(camfe_hier h, int d) {
     const double sc = ldexp(1.0, d - h->D);
     CAMFE_TIMED(ctx, KT_UF_LINK, 0.0, k_uf_link, ge, BLK, 0, ctx->stream, L.ent.p, (long long)n, cid.p, cstart.p,
                 (int)L.ncorn, h->F.p, h->U.p, sc, h->degree, h->tri_edge.p, h->edge_ptr.p, h->edge_tri.p,
-                h->vt_ptr.p, h->vt_tri.p, link.p);
+                h->vt_ptr.p, h->vt_tri.p, h->vfan.p, link.p);
     check_launch();
     hipLaunchKernelGGL(k_uf_roots, ge, BLK, 0, ctx->stream, (const int*)link.p, (long long)n, parent.p);
   } else {

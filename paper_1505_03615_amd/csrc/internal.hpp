@@ -49,6 +49,7 @@ struct camfe_hier_s {
   camfe::DArr<int> tri_edge;  // nt x 3: edge id of edge (F[t][j], F[t][j+1])
   camfe::DArr<int> edge_ptr, edge_tri;
   camfe::DArr<int> vt_ptr, vt_tri;
+  camfe::DArr<int> vfan;      // nv: 1 when the triangles at the vertex form one fan joined by edges at it
   std::vector<camfe::HLevel> lev;  // index = depth
   int NB() const { return degree == 1 ? 8 : 27; }
   int W() const { return degree == 1 ? 2 : 3; }

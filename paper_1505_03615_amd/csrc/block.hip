@@ -12,8 +12,10 @@
 // of its functions).  Each block's inverse is D^-1/2 (D^-1/2 A_B D^-1/2 + eps I)^-1
 // D^-1/2 with the state's coarse_eps (the coarsest solve's treatment of
 // exactly dependent functions): the middle factor is computed in FP64 by a
-// Cholesky factorisation and kept in FP64 and FP32, the outer D^-1/2 as one
-// scale per row applied by the sweep.
+// Cholesky factorisation and kept in FP64 and FP32 as its packed upper
+// triangle, the outer D^-1/2 as one scale per row applied by the sweep.  The
+// damping of the weighted block sum is chosen per depth at set-up (solve.hip,
+// estimate_block_damping): the weights alone do not make a sweep contract.
 //
 // Deduplication per cell: the functions at one corner are a contiguous range
 // of the canonical numbering (one per component, cfirst of the corner's
@@ -181,9 +183,10 @@ __global__ void k_block_invert(long long nb, const int* idx, const int* perm, co
       a[i * W + j] = s / d;
     }
   }
-  double* o64 = inv64 + b * (long long)W * W;
-  float* o32 = inv32 + b * (long long)W * W;
-  for (int i = 0; i < W * W; ++i) { o64[i] = 0.0; o32[i] = 0.0f; }
+  constexpr int NP = W * (W + 1) / 2;
+  double* o64 = inv64 + b * (long long)NP;
+  float* o32 = inv32 + b * (long long)NP;
+  for (int i = 0; i < NP; ++i) { o64[i] = 0.0; o32[i] = 0.0f; }
   for (int j = 0; j < m; ++j) {
     double e[W];
     for (int i = 0; i < m; ++i) e[i] = i == j ? 1.0 : 0.0;
@@ -197,9 +200,9 @@ __global__ void k_block_invert(long long nb, const int* idx, const int* perm, co
       for (int k = i + 1; k < m; ++k) s -= a[k * W + i] * e[k];
       e[i] = s / a[i * W + i];
     }
-    for (int i = 0; i < m; ++i) {
-      o64[i * W + j] = e[i];
-      o32[i * W + j] = (float)e[i];
+    for (int i = 0; i <= j; ++i) {   // rows up to j of column j: the packed upper triangle
+      o64[bpk<W>(i, j)] = e[i];
+      o32[bpk<W>(i, j)] = (float)e[i];
     }
   }
   for (int i = 0; i < m; ++i) atomicAdd(&mult[f[i]], 1);
@@ -259,10 +262,10 @@ void build_level(camfe_sys s, SolverState* S, int d) {
   hipLaunchKernelGGL(k_block_fill, grid_for(nc, BLK), BLK, 0, st, nc, H.pairs.p, cstart.p, H.pair_rows.p, H.ckey.p,
                      (int)H.ncorn, H.cfirst.p, G.iperm.p, G.invd64.p, off8.p, off16.p, cnt8.p, cnt16.p, G.bidx8.p,
                      G.bidx16.p, err.p);
-  G.binv8_64.alloc(std::max(G.nb8, 1LL) * 64);
-  G.binv8_32.alloc(std::max(G.nb8, 1LL) * 64);
-  G.binv16_64.alloc(std::max(G.nb16, 1LL) * 256);
-  G.binv16_32.alloc(std::max(G.nb16, 1LL) * 256);
+  G.binv8_64.alloc(std::max(G.nb8, 1LL) * 36);
+  G.binv8_32.alloc(std::max(G.nb8, 1LL) * 36);
+  G.binv16_64.alloc(std::max(G.nb16, 1LL) * 136);
+  G.binv16_32.alloc(std::max(G.nb16, 1LL) * 136);
   DArr<int> mult(n);
   zero(ctx, mult.p, n);
   if (G.nb8)

@@ -5,14 +5,15 @@
 //
 // A block holds the functions of one occupied cell (its 8 corners, one
 // function per component met in the cell), with the symmetric inverse of its
-// unit-diagonal-scaled matrix stored W x W (padded with zeros), its weight w_B
-// and the row scales s_i = 1 / sqrt(A_ii): A_B^-1 r_B = s (inverse (s r)).  A
-// group of W lanes of a wavefront takes one block: lane i loads s_i r_i of
-// the block's function i, the group's values meet through shuffles, lane i
-// forms its entry of the product reading column i of the inverse (the
-// group's loads of one column entry are W consecutive values: coalesced) and
-// adds it, times omega w_B s_i, to x_i with an atomic add (a function sits in
-// up to eight blocks).  A row with s_i = 0 (zero mass; in FP32 also a
+// unit-diagonal-scaled matrix stored as its packed upper triangle (W (W + 1)
+// / 2 values, row by row; rows past the block's functions are zero), its
+// weight w_B and the row scales s_i = 1 / sqrt(A_ii): A_B^-1 r_B = s (inverse
+// (s r)).  A workgroup stages the packed inverses of its blocks in LDS with
+// coalesced loads; a group of W lanes of a wavefront takes one block: lane i
+// loads s_i r_i of the block's function i, the group's values meet through
+// shuffles, lane i forms its entry of the product from row i of the inverse
+// and adds it, times omega w_B s_i, to x_i with an atomic add (a function
+// sits in up to eight blocks).  A row with s_i = 0 (zero mass; in FP32 also a
 // diagonal whose reciprocal has no FP32 value) takes no part.
 #pragma once
 
@@ -24,9 +25,14 @@ namespace {
 template <class T, int K, int W>
 __global__ __launch_bounds__(256) void k_block_apply(long long nb, const int* idx, const T* inv, const T* weight,
                                                      const T* scale, const T* r, T omega, T* x) {
-  const long long g = blockIdx.x * 256LL + threadIdx.x;
-  const long long b = g / W;
-  const int i = (int)(g % W);
+  constexpr int NP = W * (W + 1) / 2, G = 256 / W;
+  __shared__ T sm[G * NP];
+  const long long b0 = blockIdx.x * (long long)G;   // the grid covers nb blocks: b0 < nb
+  const long long nload = (nb - b0 < G ? nb - b0 : G) * NP;
+  for (int e = threadIdx.x; e < G * NP; e += 256) sm[e] = e < nload ? inv[b0 * NP + e] : (T)0;
+  __syncthreads();
+  const int grp = threadIdx.x / W, i = threadIdx.x % W;
+  const long long b = b0 + grp;
   const bool ok = b < nb;
   const int f = ok ? idx[b * W + i] : -1;
   const T sf = f >= 0 ? scale[f] : (T)0;
@@ -36,10 +42,10 @@ __global__ __launch_bounds__(256) void k_block_apply(long long nb, const int* id
     rv[q] = f >= 0 ? sf * r[(long long)f * K + q] : (T)0;
     u[q] = 0;
   }
-  const T* col = inv + (ok ? b : 0) * (long long)W * W + i;
+  const T* A = sm + grp * NP;
 #pragma unroll
   for (int j = 0; j < W; ++j) {
-    const T a = ok ? col[j * W] : (T)0;   // entry (j, i) = (i, j): the inverse is symmetric
+    const T a = A[i <= j ? bpk<W>(i, j) : bpk<W>(j, i)];   // entry (i, j) of the symmetric inverse
 #pragma unroll
     for (int q = 0; q < K; ++q) u[q] = fma(a, __shfl(rv[q], j, W), u[q]);
   }

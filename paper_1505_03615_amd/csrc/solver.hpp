@@ -19,6 +19,11 @@ constexpr int KMAXS = 4;      // right-hand sides per pass
 // (~1e-7) is not amplified past O(0.1), and without effect on regular systems
 constexpr double DEFAULT_COARSE_EPS = 1e-6;
 
+// position of entry (r, c), r <= c, in the packed upper triangle (row by
+// row) of a symmetric W x W cell-block inverse
+template <int W>
+__host__ __device__ constexpr int bpk(int r, int c) { return r * W - r * (r - 1) / 2 + c - r; }
+
 struct GLevel {
   int d = 0;
   size_t n = 0;
@@ -53,7 +58,8 @@ struct GLevel {
   DArr<double> x64, b64, r64, t64;
   DArr<float> x32, b32, r32, t32;
   // cell-block Schwarz smoother: blocks of at most 8 and of 9..16 functions
-  // (internal rows, -1 padding), their symmetric inverses (W x W each) and
+  // (internal rows, -1 padding), their symmetric inverses (packed upper
+  // triangles, W (W + 1) / 2 values each) and
   // weights 1 / (largest number of blocks holding one of their functions)
   // (the inverses of the unit-diagonal-scaled blocks; bs = 1 / sqrt(A_ii))
   long long nb8 = 0, nb16 = 0;

@@ -284,6 +284,15 @@ camfe_status camfe_system_set_sell_sort(camfe_sys s, int64_t min_rows);
  * order, so results are the same bits.  EINVAL for other values.  Takes
  * effect at the next solver set-up (drops the current solver state). */
 camfe_status camfe_system_set_sell_columns(camfe_sys s, int bits);
+/* Launch pattern of the cell-block smoother (smoother 3): at each depth, a
+ * block class (blocks of up to 8 and of 9-16 functions) with at least
+ * min_blocks blocks is relaxed colour by colour (cells whose coordinates have
+ * the same parities share no function, so each colour's blocks update x
+ * with plain adds, 8 launches); a smaller class takes one launch with atomic
+ * adds.  The update is the same sum either way, in another order.
+ * min_blocks <= 0 restores the default (2^19).  Takes effect at the next
+ * smoother-3 solve. */
+camfe_status camfe_system_set_block_colouring(camfe_sys s, int64_t min_blocks);
 /* Packed-matrix figures of one depth of the current solver state: slices,
  * slices with 16-bit column codes, stored entries (padding included).
  * Nullable outputs.  ESTATE before the first solve; EINVAL for a depth

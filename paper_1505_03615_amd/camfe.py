@@ -32,6 +32,7 @@ EXPORTS = [
     "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
     "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc", "camfe_system_autotune",
     "camfe_batch_autotune", "camfe_block_damping", "camfe_system_set_sell_columns", "camfe_system_sell_stats",
+    "camfe_system_set_block_colouring",
 ]
 TILES = [(8, 4), (4, 4), (8, 2), (16, 2), (16, 4), (4, 8), (2, 16)]   # colour-sweep tiles: (wavefronts per slice, entries per lane)
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
@@ -152,6 +153,7 @@ def load():
         "camfe_batch_autotune": (I, [H, I, I, P, P, I, C.POINTER(I)]),
         "camfe_block_damping": (I, [H, D, D, P, P, I, C.POINTER(I)]),
         "camfe_system_set_sell_columns": (I, [H, I]),
+        "camfe_system_set_block_colouring": (I, [H, I64]),
         "camfe_system_sell_stats": (I, [H, I, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
     }
     for name, (res, args) in sig.items():
@@ -461,6 +463,10 @@ def camfe_system_destroy(s):
 
 def camfe_system_set_sell_columns(s, bits):
     _check(load().camfe_system_set_sell_columns(s, bits))
+
+
+def camfe_system_set_block_colouring(s, min_blocks):
+    _check(load().camfe_system_set_block_colouring(s, min_blocks))
 
 
 def camfe_system_sell_stats(s, depth):

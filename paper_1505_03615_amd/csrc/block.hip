@@ -138,6 +138,43 @@ __global__ void k_block_fill(long long ncell, const u64* pairs, const int* cstar
     for (; w < W; ++w) out[w] = -1;
 }
 
+// colour of each occupied cell: the parities of its coordinates
+__global__ void k_cell_colour(long long ncell, const u64* pairs, const int* cstart, int* colour) {
+  const long long c = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (c >= ncell) return;
+  long long x[3];
+  demorton(pairs[cstart[c]] >> TRI_BITS, x);
+  colour[c] = (int)((x[0] & 1) + 2 * (x[1] & 1) + 4 * (x[2] & 1));
+}
+__global__ void k_colour_mask(long long ncell, const int* colour, int k, const int* cnt, int* out) {
+  const long long c = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (c > ncell) return;
+  out[c] = (c < ncell && colour[c] == k) ? cnt[c] : 0;
+}
+__global__ void k_colour_offsets(long long ncell, const int* colour, int k, const int* pre, long long base, int* off) {
+  const long long c = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (c < ncell && colour[c] == k) off[c] = (int)(base + pre[c]);
+}
+
+// block offsets of every cell, colour by colour (cell order within a
+// colour); bc receives the colour ranges, and the total is returned
+long long colour_major_offsets(camfe_ctx ctx, long long nc, const int* colour, const int* cnt, int* off,
+                               long long bc[9]) {
+  DArr<int> masked(nc + 1), pre(nc + 1);
+  long long base = 0;
+  for (int k = 0; k < 8; ++k) {
+    bc[k] = base;
+    hipLaunchKernelGGL(k_colour_mask, grid_for(nc + 1, BLK), BLK, 0, ctx->stream, nc, colour, k, cnt, masked.p);
+    exclusive_scan(ctx, masked.p, pre.p, (size_t)nc + 1);
+    hipLaunchKernelGGL(k_colour_offsets, grid_for(nc, BLK), BLK, 0, ctx->stream, nc, colour, k, (const int*)pre.p,
+                       base, off);
+    check_launch();
+    base += read_scalar(ctx, pre.p + nc);
+  }
+  bc[8] = base;
+  return base;
+}
+
 // entry (r, c) of A = M + t L (canonical CSR, ascending columns)
 __device__ inline double a_entry(const int* ptr, const int* col, const double* M, const double* L, double t, int r,
                                  int c) {
@@ -252,11 +289,11 @@ void build_level(camfe_sys s, SolverState* S, int d) {
   zero(ctx, cnt16.p, nc + 1);
   hipLaunchKernelGGL(k_block_count, grid_for(nc, BLK), BLK, 0, st, nc, H.pairs.p, cstart.p, H.pair_rows.p,
                      H.ckey.p, (int)H.ncorn, H.cfirst.p, G.iperm.p, G.invd64.p, cnt8.p, cnt16.p, err.p);
-  exclusive_scan(ctx, cnt8.p, off8.p, (size_t)nc + 1);
-  exclusive_scan(ctx, cnt16.p, off16.p, (size_t)nc + 1);
   check_launch();
-  G.nb8 = read_scalar(ctx, off8.p + nc);
-  G.nb16 = read_scalar(ctx, off16.p + nc);
+  DArr<int> colour(std::max(nc, 1LL));
+  hipLaunchKernelGGL(k_cell_colour, grid_for(nc, BLK), BLK, 0, st, nc, H.pairs.p, cstart.p, colour.p);
+  G.nb8 = colour_major_offsets(ctx, nc, colour.p, cnt8.p, off8.p, G.bc8);
+  G.nb16 = colour_major_offsets(ctx, nc, colour.p, cnt16.p, off16.p, G.bc16);
   G.bidx8.alloc(std::max(G.nb8, 1LL) * 8);
   G.bidx16.alloc(std::max(G.nb16, 1LL) * 16);
   hipLaunchKernelGGL(k_block_fill, grid_for(nc, BLK), BLK, 0, st, nc, H.pairs.p, cstart.p, H.pair_rows.p, H.ckey.p,

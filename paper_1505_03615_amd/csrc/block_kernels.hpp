@@ -22,18 +22,22 @@
 namespace camfe {
 namespace {
 
-template <class T, int K, int W>
-__global__ __launch_bounds__(256) void k_block_apply(long long nb, const int* idx, const T* inv, const T* weight,
-                                                     const T* scale, const T* r, T omega, T* x) {
+// Blocks [b_begin, b_end).  ATOMIC: blocks of the range may share functions
+// (atomic adds); otherwise the range is one cell colour (cells whose
+// coordinates have the same parities share no corner, hence no function),
+// and x is updated with plain adds, one launch per colour.
+template <class T, int K, int W, bool ATOMIC>
+__global__ __launch_bounds__(256) void k_block_apply(long long b_begin, long long b_end, const int* idx, const T* inv,
+                                                     const T* weight, const T* scale, const T* r, T omega, T* x) {
   constexpr int NP = W * (W + 1) / 2, G = 256 / W;
   __shared__ T sm[G * NP];
-  const long long b0 = blockIdx.x * (long long)G;   // the grid covers nb blocks: b0 < nb
-  const long long nload = (nb - b0 < G ? nb - b0 : G) * NP;
+  const long long b0 = b_begin + blockIdx.x * (long long)G;   // the grid covers the range: b0 < b_end
+  const long long nload = (b_end - b0 < G ? b_end - b0 : G) * NP;
   for (int e = threadIdx.x; e < G * NP; e += 256) sm[e] = e < nload ? inv[b0 * NP + e] : (T)0;
   __syncthreads();
   const int grp = threadIdx.x / W, i = threadIdx.x % W;
   const long long b = b0 + grp;
-  const bool ok = b < nb;
+  const bool ok = b < b_end;
   const int f = ok ? idx[b * W + i] : -1;
   const T sf = f >= 0 ? scale[f] : (T)0;
   T rv[K], u[K];
@@ -52,7 +56,10 @@ __global__ __launch_bounds__(256) void k_block_apply(long long nb, const int* id
   if (f >= 0 && sf != (T)0) {
     const T w = omega * weight[b] * sf;
 #pragma unroll
-    for (int q = 0; q < K; ++q) atomicAdd(&x[(long long)f * K + q], w * u[q]);
+    for (int q = 0; q < K; ++q) {
+      if (ATOMIC) atomicAdd(&x[(long long)f * K + q], w * u[q]);
+      else x[(long long)f * K + q] += w * u[q];
+    }
   }
 }
 

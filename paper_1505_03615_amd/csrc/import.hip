@@ -64,6 +64,14 @@ camfe_status camfe_system_set_sell_columns(camfe_sys s, int bits) {
   });
 }
 
+camfe_status camfe_system_set_block_colouring(camfe_sys s, int64_t min_blocks) {
+  return guarded([&] {
+    if (s) set_current_ctx(s->h->ctx);
+    CAMFE_REQUIRE(s, CAMFE_EINVAL, "null system");
+    s->block_colour_min = min_blocks > 0 ? (long long)min_blocks : 0;
+  });
+}
+
 camfe_status camfe_system_sell_stats(camfe_sys s, int depth, int64_t* slices, int64_t* compact, int64_t* entries) {
   return guarded([&] {
     if (s) set_current_ctx(s->h->ctx);

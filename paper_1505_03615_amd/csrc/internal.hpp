@@ -81,6 +81,7 @@ struct camfe_sys_s {
   std::vector<camfe::DArr<double>> mcache;   // per depth: unweighted degree-1 mass blocks of every pair
   long long sell_sort_min_rows = 0;  // colours with at least this many rows are length-sorted (0: default)
   bool sell_compact = true;          // 16-bit column codes where a slice's spans allow (degree 1)
+  long long block_colour_min = 0;    // cell-block depths relaxed colour by colour from this many blocks (0: default)
   std::vector<int> tiles;            // colour-sweep tile per depth from camfe_system_autotune (empty: default)
   camfe_hier owned_h = nullptr;      // an imported system's own hierarchy (freed with the system)
   ~camfe_sys_s() {

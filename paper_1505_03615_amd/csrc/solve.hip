@@ -1035,6 +1035,11 @@ const T* sweep_dinv(const SolverState* S, const GLevel& G) {
 // nu cell-block Schwarz sweeps: r = b - A x into the level's scratch vector,
 // then the weighted block products of both block classes added into x (the
 // same map before and after the coarse correction)
+// a block class (8 or 16 wide) of at least this many blocks at a depth is
+// relaxed colour by colour without atomics (8 launches); a smaller one in one
+// launch with atomic adds
+constexpr long long BLOCK_COLOUR_MIN = 1LL << 19;
+
 template <class T, int K>
 void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
   camfe_ctx ctx = S->ctx;
@@ -1051,14 +1056,38 @@ void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
     CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
                 (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, sval_of<T>(G), b,
                 (const T*)x, r, (double*)nullptr);
-    if (G.nb8)
-      CAMFE_TIMED(ctx, KT_GS, ((double)G.nb8 * 8 * (8 * sizeof(T) + 4) + 3.0 * G.n * K * sizeof(T)),
-                  (k_block_apply<T, K, 8>), grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, G.nb8, G.bidx8.p, inv8,
-                  w8, sc, (const T*)r, om, x);
-    if (G.nb16)
-      CAMFE_TIMED(ctx, KT_GS, ((double)G.nb16 * 16 * (16 * sizeof(T) + 4)), (k_block_apply<T, K, 16>),
-                  grid_for((size_t)G.nb16 * 16, 256), 256, 0, st, G.nb16, G.bidx16.p, inv16, w16, sc,
+    // each block class separately: colour by colour with plain adds (no two
+    // blocks of a colour share a function) when it is large, else one
+    // launch with atomic adds; the launches of a sweep run in order
+    const long long cmin = S->block_colour_min > 0 ? S->block_colour_min : BLOCK_COLOUR_MIN;
+    const double b8 = 36 * sizeof(T) / 8.0 + 4 + 3.0 * K * sizeof(T);     // bytes per block row
+    const double b16 = 136 * sizeof(T) / 16.0 + 4 + 3.0 * K * sizeof(T);
+    if (G.nb8 >= cmin) {
+      for (int k = 0; k < 8; ++k) {
+        const long long a = G.bc8[k], e = G.bc8[k + 1];
+        if (e > a)
+          CAMFE_TIMED(ctx, KT_GS, ((double)(e - a) * 8 * b8), (k_block_apply<T, K, 8, false>),
+                      grid_for((size_t)(e - a) * 8, 256), 256, 0, st, a, e, G.bidx8.p, inv8, w8, sc, (const T*)r, om,
+                      x);
+      }
+    } else if (G.nb8) {
+      CAMFE_TIMED(ctx, KT_GS, ((double)G.nb8 * 8 * b8), (k_block_apply<T, K, 8, true>),
+                  grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, 0LL, G.nb8, G.bidx8.p, inv8, w8, sc, (const T*)r,
+                  om, x);
+    }
+    if (G.nb16 >= cmin) {
+      for (int k = 0; k < 8; ++k) {
+        const long long a = G.bc16[k], e = G.bc16[k + 1];
+        if (e > a)
+          CAMFE_TIMED(ctx, KT_GS, ((double)(e - a) * 16 * b16), (k_block_apply<T, K, 16, false>),
+                      grid_for((size_t)(e - a) * 16, 256), 256, 0, st, a, e, G.bidx16.p, inv16, w16, sc,
+                      (const T*)r, om, x);
+      }
+    } else if (G.nb16) {
+      CAMFE_TIMED(ctx, KT_GS, ((double)G.nb16 * 16 * b16), (k_block_apply<T, K, 16, true>),
+                  grid_for((size_t)G.nb16 * 16, 256), 256, 0, st, 0LL, G.nb16, G.bidx16.p, inv16, w16, sc,
                   (const T*)r, om, x);
+    }
   }
 }
 
@@ -1114,12 +1143,12 @@ void estimate_block_damping(SolverState* S) {
                          (double*)nullptr);
       hipLaunchKernelGGL((k_fill<double>), grid_for(n, BLK), BLK, 0, st, y, n, 0.0);
       if (G.nb8)
-        hipLaunchKernelGGL((k_block_apply<double, 1, 8>), grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, G.nb8,
-                           G.bidx8.p, (const double*)G.binv8_64.p, (const double*)G.bw8_64.p,
+        hipLaunchKernelGGL((k_block_apply<double, 1, 8, true>), grid_for((size_t)G.nb8 * 8, 256), 256, 0, st, 0LL,
+                           G.nb8, G.bidx8.p, (const double*)G.binv8_64.p, (const double*)G.bw8_64.p,
                            (const double*)G.bs64.p, (const double*)r, 1.0, y);
       if (G.nb16)
-        hipLaunchKernelGGL((k_block_apply<double, 1, 16>), grid_for((size_t)G.nb16 * 16, 256), 256, 0, st, G.nb16,
-                           G.bidx16.p, (const double*)G.binv16_64.p, (const double*)G.bw16_64.p,
+        hipLaunchKernelGGL((k_block_apply<double, 1, 16, true>), grid_for((size_t)G.nb16 * 16, 256), 256, 0, st,
+                           0LL, G.nb16, G.bidx16.p, (const double*)G.binv16_64.p, (const double*)G.bw16_64.p,
                            (const double*)G.bs64.p, (const double*)r, 1.0, y);
       const double* pa[3] = {y, v, y};
       const double* pb[3] = {r, r, y};
@@ -2403,6 +2432,10 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts* o, const double* b
       if (!S->blocks_ready) {
         build_cell_blocks(s, S);
         estimate_block_damping(S);
+      }
+      if (S->block_colour_min != s->block_colour_min) {   // captured cycles hold the launch pattern
+        S->drop_graphs();
+        S->block_colour_min = s->block_colour_min;
       }
       if (S->block_omega != o->omega) {   // captured cycles hold the damping as a kernel argument
         S->drop_graphs();

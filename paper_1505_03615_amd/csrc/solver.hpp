@@ -63,6 +63,9 @@ struct GLevel {
   // weights 1 / (largest number of blocks holding one of their functions)
   // (the inverses of the unit-diagonal-scaled blocks; bs = 1 / sqrt(A_ii))
   long long nb8 = 0, nb16 = 0;
+  // blocks of each class ordered by the colour of their cell (coordinate
+  // parities): colour k owns blocks [bc8[k], bc8[k + 1]) and [bc16[k], bc16[k + 1])
+  long long bc8[9] = {0}, bc16[9] = {0};
   // automatic damping of the block corrections at this depth: 4 / (3 lambda)
   // (at most 1), lambda a power-iteration estimate of the largest eigenvalue
   // of sum_B w_B R_B^T A_B^-1 R_B A
@@ -95,6 +98,7 @@ struct SolverState {
                              // 3 cell-block Schwarz
   bool blocks_ready = false; // cell blocks built for this state (t, coarse_eps)
   double block_omega = 0;    // damping of the cell-block corrections (0: each depth's automatic value)
+  long long block_colour_min = 0;  // depths with at least this many blocks relax them colour by colour
   int wkind = 0;             // smoother whose weights winvd holds (0: none)
   int wsweep = 0;            // sweep those weights are for: 0 Jacobi, 1 multicolour SOR
   double omega = 0;          // constant omega of smoother 1

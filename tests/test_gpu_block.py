@@ -81,8 +81,12 @@ def built(cf, ctx, name):
 NEAR_SINGULAR = ("sheets_axis", "cubes")
 
 
+@pytest.mark.parametrize("colouring", ["atomic", "by_colour"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_block_cycles_track_the_oracle(cf, ctx, name):
+def test_block_cycles_track_the_oracle(cf, ctx, name, colouring):
+    """Both launch patterns of the block sweep: two launches with atomic adds
+    (the default at these sizes) and one launch per cell colour with plain
+    adds (forced at every depth; the default from 2^19 blocks)."""
     h, s, o, b = built(cf, ctx, name)
     t = CASES[name]["t"]
     Mo, Lo = o.matrices(o.depth)
@@ -90,6 +94,14 @@ def test_block_cycles_track_the_oracle(cf, ctx, name):
     om, lam = cf.camfe_block_damping(s, t)
     say(f"[gpu] block: {name} damping per depth {np.round(om, 4).tolist()} (lambda {np.round(lam, 4).tolist()})")
     assert len(om) == o.depth - o.coarsest + 1 and np.all((om >= 0) & (om <= 1)) and om[-1] > 0
+    cf.camfe_system_set_block_colouring(s, 1 if colouring == "by_colour" else 0)
+    try:
+        _track(cf, s, o, b, t, A, om, name)
+    finally:
+        cf.camfe_system_set_block_colouring(s, 0)
+
+
+def _track(cf, s, o, b, t, A, om, name):
     for cyc in (1, 3):
         say(f"[gpu] block: {name} {cyc} stationary cycles")
         x, st = cf.camfe_solve(s, b, t=t, rtol=1e-30, max_iter=cyc, method=1, smoother=3)
@@ -113,14 +125,19 @@ def test_block_cg_meets_the_oracle_residual(cf, ctx, name, precision):
     Mo, Lo = o.matrices(o.depth)
     A = Mo + t * Lo
     res = {}
-    for sm in (0, 3):
-        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=2000, precision=precision, smoother=sm)
+    for sm, colour in ((0, 0), (3, 0), (3, 1)):
+        cf.camfe_system_set_block_colouring(s, colour)
+        try:
+            x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=2000, precision=precision, smoother=sm)
+        finally:
+            cf.camfe_system_set_block_colouring(s, 0)
         r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
-        assert st["converged"] and not st["fell_back"] and np.all(r <= 1e-6), (sm, st, r)
-        res[sm] = st["cycles"]
-    say(f"[gpu] block: {name} precision {precision}: Gauss-Seidel {res[0]} cycles, blocks {res[3]}")
+        assert st["converged"] and not st["fell_back"] and np.all(r <= 1e-6), (sm, colour, st, r)
+        res[sm, colour] = st["cycles"]
+    say(f"[gpu] block: {name} precision {precision}: Gauss-Seidel {res[0, 0]} cycles, blocks {res[3, 0]} "
+        f"(by colour {res[3, 1]})")
     if name in ("knot", "sheets_split"):
-        assert res[3] < 0.6 * res[0]
+        assert res[3, 0] < 0.6 * res[0, 0] and res[3, 1] < 0.6 * res[0, 0]
 
 
 def test_block_damping_option(cf, ctx):

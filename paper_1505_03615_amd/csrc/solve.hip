@@ -1030,18 +1030,17 @@ const T* sweep_dinv(const SolverState* S, const GLevel& G) {
   return nullptr;
 }
 
-// first0: x was zero and the first sweep's colour-0 rows are already relaxed
-// (by the kernel that zeroed x), so that sweep starts at colour 1
 // nu cell-block Schwarz sweeps: r = b - A x into the level's scratch vector,
 // then the weighted block products of both block classes added into x (the
-// same map before and after the coarse correction)
+// same map before and after the coarse correction).  x_zero: x is zero on
+// entry, so the first sweep's residual is b itself and is not computed.
 // a block class (8 or 16 wide) of at least this many blocks at a depth is
 // relaxed colour by colour without atomics (8 launches); a smaller one in one
 // launch with atomic adds
 constexpr long long BLOCK_COLOUR_MIN = 1LL << 19;
 
 template <class T, int K>
-void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
+void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool x_zero) {
   camfe_ctx ctx = S->ctx;
   hipStream_t st = ctx->stream;
   constexpr bool dbl = std::is_same<T, double>::value;
@@ -1051,11 +1050,15 @@ void block_smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu) {
   const T* w16 = dbl ? (const T*)G.bw16_64.p : (const T*)G.bw16_32.p;
   const T* sc = dbl ? (const T*)G.bs64.p : (const T*)G.bs32.p;
   const T om = (T)(S->block_omega > 0 ? S->block_omega : G.block_omega);
-  T* r = tmp_of<T>(G);
+  T* rbuf = tmp_of<T>(G);
   for (int it = 0; it < nu; ++it) {
-    CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
-                (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, sval_of<T>(G), b,
-                (const T*)x, r, (double*)nullptr);
+    const T* r = b;
+    if (it > 0 || !x_zero) {
+      CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
+                  (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p, (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p,
+                  sval_of<T>(G), b, (const T*)x, rbuf, (double*)nullptr);
+      r = rbuf;
+    }
     // each block class separately: colour by colour with plain adds (no two
     // blocks of a colour share a function) when it is large, else one
     // launch with atomic adds; the launches of a sweep run in order
@@ -1170,10 +1173,14 @@ void estimate_block_damping(SolverState* S) {
 }
 
 template <class T, int K>
-void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward, bool first0 = false) {
+// first0: x was zero and the first sweep's colour-0 rows are already relaxed
+// (by the kernel that zeroed x), so that sweep starts at colour 1; x_zero: x
+// is zero on entry (used by the cell-block sweep)
+void smooth(SolverState* S, GLevel& G, const T* b, T* x, int nu, bool forward, bool first0 = false,
+            bool x_zero = false) {
   camfe_ctx ctx = S->ctx;
   if (S->smoother == 3) {
-    block_smooth<T, K>(S, G, b, x, nu);
+    block_smooth<T, K>(S, G, b, x, nu, x_zero);
     return;
   }
   if (const T* dinv = sweep_dinv<T>(S, G)) {
@@ -1207,12 +1214,12 @@ void coarse_batched(SolverState* S, GLevel& G, const T* b, T* x) {
 // V-cycle, two: W-cycle, Section 5.2).
 // first0: as for smooth() (x zero, colour 0 of the first pre-sweep done)
 template <class T, int K>
-void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool first0 = false) {
+void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool first0 = false, bool x_zero = false) {
   camfe_ctx ctx = S->ctx;
   hipStream_t st = ctx->stream;
   GLevel& G = S->lev[d];
   if (d == S->d0 && S->batch) {
-    smooth<T, K>(S, G, b, x, nu1, true);
+    smooth<T, K>(S, G, b, x, nu1, true, false, x_zero);
     coarse_batched<T, K>(S, G, b, x);
     smooth<T, K>(S, G, b, x, nu2, false);
     return;
@@ -1223,12 +1230,12 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool firs
       CAMFE_TIMED(ctx, KT_COARSE, w, (k_coarse<T, K>), grid_for((size_t)S->n0 * 64, BLK), BLK, 0, st,
                   (const double*)S->Ainv64.p, S->n0, b, x);
     } else {
-      smooth<T, K>(S, G, b, x, nu1, true);
+      smooth<T, K>(S, G, b, x, nu1, true, false, x_zero);
       smooth<T, K>(S, G, b, x, nu2, false);
     }
     return;
   }
-  smooth<T, K>(S, G, b, x, nu1, true, first0);
+  smooth<T, K>(S, G, b, x, nu1, true, first0, x_zero);
   T* r = Vec<T>::r(G);
   CAMFE_TIMED(ctx, KT_RESIDUAL, (pass_bytes<T, K>(G.nnz, (long long)G.n)), (k_residual<T, T, K>),
               (unsigned)G.nslices, SL * SW, 0, st, G.sl_meta.p,
@@ -1244,7 +1251,9 @@ void vcycle(SolverState* S, int d, const T* b, T* x, int nu1, int nu2, bool firs
               grid_for(C.n * RL, BLK), BLK, 0, st, G.Rptr.p, G.Rcol.p, rw_of<T>(G), (long long)C.n, (const T*)r, bc,
               xc, cdinv, cdinv ? (long long)C.coff[1] : 0LL, (const int*)C.blkmem.p, (const int*)S->mact.p);
   const int c1 = S->nu_coarse > 0 ? S->nu_coarse : nu1, c2 = S->nu_coarse > 0 ? S->nu_coarse : nu2;
-  for (int g = 0; g < S->gamma; ++g) vcycle<T, K>(S, d - 1, bc, xc, c1, c2, g == 0 && cdinv != nullptr);
+  // the restriction zeroes x_c (or relaxes its colour 0 when cdinv is set)
+  for (int g = 0; g < S->gamma; ++g)
+    vcycle<T, K>(S, d - 1, bc, xc, c1, c2, g == 0 && cdinv != nullptr, g == 0 && cdinv == nullptr);
   CAMFE_TIMED(ctx, KT_PROLONG, (4.0 * G.pnnz + ((double)C.n + 2.0 * G.n) * K * sizeof(T)), (k_prolong<T, K>),
               grid_for(G.n, BLK), BLK, 0, st, G.Pptr.p, G.Pcol.p, pw_of<T>(G), (long long)G.n, (const T*)xc, x,
               (const int*)G.blkmem.p, (const int*)S->mact.p);
@@ -1260,11 +1269,11 @@ void precondition(SolverState* S, const double* r, double* z, int nu1, int nu2) 
   const long long nk = (long long)G.n * K;
   if (S->precision == 0) {
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, z, nk, 0.0);
-    vcycle<double, K>(S, S->D, r, z, nu1, nu2);
+    vcycle<double, K>(S, S->D, r, z, nu1, nu2, false, true);
   } else {
     hipLaunchKernelGGL((k_convert<double, float>), grid_for(nk, BLK), BLK, 0, st, r, nk, G.b32.p);
     hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
-    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2);
+    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2, false, true);
     hipLaunchKernelGGL((k_convert<float, double>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, z);
   }
 }
@@ -1364,7 +1373,7 @@ void cg_step(SolverState* S, int nu1, int nu2) {
                 (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p, S->part2.p, S->Z.p,
                 (float*)nullptr, (float*)nullptr, first0 ? sweep_dinv<double>(S, G) : (const double*)nullptr,
                 (const float*)nullptr, n0c);
-    vcycle<double, K>(S, S->D, S->R.p, S->Z.p, nu1, nu2, first0);
+    vcycle<double, K>(S, S->D, S->R.p, S->Z.p, nu1, nu2, first0, !first0);
     hipLaunchKernelGGL((k_dot_rz<K, 0>), (unsigned)nb, BLK, 0, st, (long long)n, (const double*)S->R.p, S->Z.p,
                        (const float*)nullptr, S->part.p);
   } else {
@@ -1372,7 +1381,7 @@ void cg_step(SolverState* S, int nu1, int nu2) {
                 (long long)n, (const double*)sc, S->X.p, S->R.p, (const double*)S->P.p, (const double*)S->Q.p,
                 S->part2.p, (double*)nullptr, G.b32.p, G.x32.p, (const double*)nullptr,
                 first0 ? sweep_dinv<float>(S, G) : (const float*)nullptr, n0c);
-    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2, first0);
+    vcycle<float, K>(S, S->D, G.b32.p, G.x32.p, nu1, nu2, first0, !first0);
     hipLaunchKernelGGL((k_dot_rz<K, 1>), (unsigned)nb, BLK, 0, st, (long long)n, (const double*)S->R.p, S->Z.p,
                        (const float*)G.x32.p, S->part.p);
   }

@@ -188,9 +188,16 @@ struct AsmArgs {
 __host__ __device__ constexpr int upk8(int r, int c) { return r * (17 - r) / 2 + c - r; }
 
 // CACHE (degree 1, mass only): every pair's unweighted element block also
-// goes to a.pcache, so that later re-weightings skip clipping and quadrature
-template <int DEG, bool CACHE = false>
-__global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
+// goes to a.pcache, so that later re-weightings skip clipping and quadrature.
+// RHS: the launch fills right-hand sides (a.rhs) instead of matrices (a.M),
+// fixed at compile time so that each variant holds only its own registers.
+// The kernel is bound by the latency of its per-pair chain (triangle loads,
+// clipping rounds, LDS, atomics), so occupancy matters: the degree-1 matrix
+// variant is held to 96 registers (5 waves per SIMD, a few spilled values;
+// at 80 and 6 waves the spills cost twice the time), the others to their
+// spill-free counts (4 waves for degree-1 loads, 2-3 for degree 2).
+template <int DEG, bool CACHE = false, bool RHS = false>
+__global__ __launch_bounds__(64, DEG == 1 ? (RHS ? 4 : 5) : 2) void k_assemble(AsmArgs a) {
   constexpr int W = DEG == 1 ? 2 : 3;
   constexpr int NB = W * W * W;
   constexpr int T = DEG == 1 ? 1 : 2;       // 16-row tiles per block
@@ -209,8 +216,8 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
   const int slot = lane & 15;
   const int pt = lane >> 4;
   const u64 lt_mask = (1ULL << lane) - 1ULL;
-  const bool want_mat = a.M != nullptr;
-  const bool want_rhs = a.rhs != nullptr;
+  const bool want_mat = !RHS && a.M != nullptr;
+  const bool want_rhs = RHS && a.rhs != nullptr;
   unsigned long long wave_pts = 0;   // quadrature points of this wavefront (measurement)
   static_assert(!CACHE || DEG == 1, "the block cache holds degree-1 blocks");
   d4 accP = (d4){0, 0, 0, 0};        // CACHE: this pair's block
@@ -292,6 +299,7 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           for (int i = 0; i < T; ++i)
 #pragma unroll
             for (int c = 0; c < KMAX; ++c) {
+              if (c >= a.k) continue;
               double v = accB[i][c];
               if (DEG == 1) v += __shfl_xor(v, 8);
               v += __shfl_xor(v, 16);
@@ -463,8 +471,9 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           double lc[3];
 #pragma unroll
           for (int q = 0; q < 3; ++q) lc[q] = A0[q] + xi * e1[q] + eta * e2[q] - (double)cc[q];
+          if (want_rhs && !a.grad_rhs)   // barycentric coordinates: the value load only
 #pragma unroll
-          for (int q = 0; q < 3; ++q) bar[q] = A0[3 + q] + xi * (A1[3 + q] - A0[3 + q]) + eta * (A2[3 + q] - A0[3 + q]);
+            for (int q = 0; q < 3; ++q) bar[q] = A0[3 + q] + xi * (A1[3 + q] - A0[3 + q]) + eta * (A2[3 + q] - A0[3 + q]);
 #pragma unroll
           for (int i = 0; i < T; ++i) {
             const int j = DEG == 1 ? (slot & 7) : 16 * i + slot;
@@ -502,12 +511,14 @@ __global__ __launch_bounds__(64) void k_assemble(AsmArgs a) {
           // Dirichlet form is invariant under the scaling
 #pragma unroll
           for (int c = 0; c < KMAX; ++c)
+            if (c < a.k)   // (columns past k stay zero)
 #pragma unroll
-            for (int i = 0; i < T; ++i)
-              accB[i][c] += wl * (gx[i] * fvv[0][c] + gy[i] * fvv[1][c] + gz[i] * fvv[2][c]);
+              for (int i = 0; i < T; ++i)
+                accB[i][c] += wl * (gx[i] * fvv[0][c] + gy[i] * fvv[1][c] + gz[i] * fvv[2][c]);
         } else if (want_rhs) {
 #pragma unroll
           for (int c = 0; c < KMAX; ++c) {
+            if (c >= a.k) continue;
             const double fx = bar[0] * fvv[0][c] + bar[1] * fvv[1][c] + bar[2] * fvv[2][c];
 #pragma unroll
             for (int i = 0; i < T; ++i) accB[i][c] += wm * val[i] * fx;
@@ -721,7 +732,11 @@ void launch_assemble(camfe_hier h, int d, const Chunks& ch, AsmArgs a) {
     zero(ctx, cnt.p, 1);
     a.npts = cnt.p;
   }
-  if (h->degree == 1)
+  if (a.rhs && h->degree == 1)
+    CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, (k_assemble<1, false, true>), grid, 64, 0, ctx->stream, a);
+  else if (a.rhs)
+    CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, (k_assemble<2, false, true>), grid, 64, 0, ctx->stream, a);
+  else if (h->degree == 1)
     CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, k_assemble<1>, grid, 64, 0, ctx->stream, a);
   else
     CAMFE_TIMED(ctx, KT_ASSEMBLE, 0.0, k_assemble<2>, grid, 64, 0, ctx->stream, a);

@@ -85,6 +85,27 @@ camfe_status camfe_ctx_kernel_timing(camfe_ctx ctx, int enable);
 camfe_status camfe_ctx_kernel_time(camfe_ctx ctx, const char *kernel, double *total_ms, int64_t *launches,
                                    double *work);
 
+/* ----------------------------------------------------------- primitives */
+/* The ordering and counting steps under the hierarchy build: finding the
+ * basis (Section 4.2) needs the triangles of each cell and of each support
+ * grouped, which the build does by sorting Morton-keyed records and taking
+ * prefix sums of counts.  Exported so that they can be tested and reused.
+ * All pointers are device memory; the calls run on the context's stream,
+ * take temporary storage from the context and return once the result is in
+ * place (work queued earlier on other streams is not waited for).
+ *
+ * camfe_radix_sort: stable radix sort, in place, of n keys (key_bytes 4 or
+ * 8, unsigned) by their bits [0, end_bit), carrying n 32-bit values along
+ * when vals is not NULL.  Keys that agree on those bits keep their input
+ * order.  EINVAL for n < 0 or n >= 2^31, key_bytes other than 4 and 8,
+ * end_bit outside [0, 8 key_bytes], or a null keys pointer with n > 0.
+ *
+ * camfe_exclusive_sum: out[i] = in[0] + ... + in[i-1] for n integers of
+ * elem_bytes 4 or 8 (two's complement, wrapping); out may equal in.  EINVAL
+ * for n < 0, other element sizes, or a null pointer with n > 0. */
+camfe_status camfe_radix_sort(camfe_ctx ctx, void *keys, int key_bytes, uint32_t *vals, int64_t n, int end_bit);
+camfe_status camfe_exclusive_sum(camfe_ctx ctx, const void *in, void *out, int64_t n, int elem_bytes);
+
 /* ------------------------------------------------------------ hierarchy */
 typedef struct {
   int depth;          /* finest depth D, 1..12 (2^D cells per axis)                   */

@@ -32,7 +32,7 @@ EXPORTS = [
     "camfe_ctx_last_error", "camfe_export_cells", "camfe_system_set_sell_sort", "camfe_system_import_csr",
     "camfe_smoother_save", "camfe_smoother_load", "camfe_apply_noalloc", "camfe_system_autotune",
     "camfe_batch_autotune", "camfe_block_damping", "camfe_system_set_sell_columns", "camfe_system_sell_stats",
-    "camfe_system_set_block_colouring",
+    "camfe_system_set_block_colouring", "camfe_radix_sort", "camfe_exclusive_sum",
 ]
 TILES = [(8, 4), (4, 4), (8, 2), (16, 2), (16, 4), (4, 8), (2, 16)]   # colour-sweep tiles: (wavefronts per slice, entries per lane)
 MLP_PARAMS = 2081   # parameters of one relative depth's MLP (30-32-32-1)
@@ -155,6 +155,8 @@ def load():
         "camfe_system_set_sell_columns": (I, [H, I]),
         "camfe_system_set_block_colouring": (I, [H, I64]),
         "camfe_system_sell_stats": (I, [H, I, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
+        "camfe_radix_sort": (I, [H, P, I, P, I64, I]),
+        "camfe_exclusive_sum": (I, [H, P, P, I64, I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -385,6 +387,31 @@ def camfe_apply_noalloc(s, which, t, x, y):
             raise ValueError("x and y must be column-major n x k float64 tensors")
     _check(load().camfe_apply_noalloc(s, which, t, _ptr(x), k, _ptr(y)))
     return y
+
+
+def camfe_radix_sort(ctx, keys, end_bit, vals=None):
+    """Stable in-place sort of a 1-D device tensor of uint64/int64 or
+    uint32/int32 keys by bits [0, end_bit), carrying an int32/uint32 tensor
+    of values along when given."""
+    if not _is_torch(keys) or keys.dim() != 1 or not keys.is_contiguous():
+        raise TypeError("keys must be a contiguous 1-D device tensor")
+    kb = keys.element_size()
+    if vals is not None and (not _is_torch(vals) or vals.shape != keys.shape or vals.element_size() != 4
+                             or not vals.is_contiguous()):
+        raise TypeError("vals must be a contiguous 32-bit device tensor shaped like keys")
+    _check(load().camfe_radix_sort(ctx, _ptr(keys), kb, None if vals is None else _ptr(vals), keys.numel(),
+                                   end_bit))
+    return keys, vals
+
+
+def camfe_exclusive_sum(ctx, x, out=None):
+    """Exclusive prefix sum of a 1-D int32/int64 device tensor (out may be x)."""
+    if not _is_torch(x) or x.dim() != 1 or not x.is_contiguous():
+        raise TypeError("x must be a contiguous 1-D device tensor")
+    if out is None:
+        out = x.new_empty(x.shape)
+    _check(load().camfe_exclusive_sum(ctx, _ptr(x), _ptr(out), x.numel(), x.element_size()))
+    return out
 
 
 def camfe_linear_coeffs(s, h):

@@ -317,13 +317,49 @@ SOLVERS = (("plain_gs_fp64", dict(precision=0, smoother=0)),
            ("block_fp64", dict(precision=0, smoother=3, max_iter=500)))
 
 
+# sweep schedules tried per solver: (sweeps before and after at the finest
+# depth, sweeps before and after at every coarser depth); 0 = the same
+SCHEDULES = ((2, 0), (2, 1), (3, 1), (1, 0))
+
+
+def schedule_kw(sched):
+    nu, nc = sched
+    return dict(nu_pre=nu, nu_post=nu, nu_coarse=nc)
+
+
+def tune_schedules(cf, s, b, t, model, which, max_iter=4000):
+    """Every solver of `which` to 1e-8 once warm with each of SCHEDULES on one
+    system; the fastest schedule per solver (iteration time, set-up excluded).
+    The same rule for every solver, so their comparison stays even."""
+    out = {}
+    for tag, kw in SOLVERS:
+        if tag not in which:
+            continue
+        cf.camfe_smoother_attach(s, model if tag == "learned_mixed" else None)
+        kw = dict(kw)
+        mi = kw.pop("max_iter", max_iter)
+        times, cycles = {}, {}
+        for sc in SCHEDULES:
+            cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4, **kw, **schedule_kw(sc))
+            _, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=mi, **kw, **schedule_kw(sc))
+            times[sc] = st["seconds"] if st["converged"] else float("inf")
+            cycles[sc] = st["cycles"]
+        best = min(times, key=times.get)
+        out[tag] = {"chosen": list(best), "seconds": {f"{a},{c}": round(v, 4) for (a, c), v in times.items()},
+                    "cycles": {f"{a},{c}": v for (a, c), v in cycles.items()}}
+        log(f"[bench] schedule {tag}: {best} from " + json.dumps(out[tag]["seconds"]))
+    cf.camfe_smoother_attach(s, None)
+    return out
+
+
 def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mixed", "learned_mixed", "block_fp64"),
-                     max_iter=4000):
+                     max_iter=4000, schedules=None):
     """Each solver to 1e-8 on one assembled system, warm: a 4-iteration solve
     first builds the solver state and captures the graphs, then the full
     solve runs once.  Iteration time (set-up excluded), cycles, DoF x cycles
     per second, and the whole V-cycle's algorithmic bytes over its measured
-    time (a captured plain V(2,2)-cycle, FP64 and FP32)."""
+    time (a captured plain V(2,2)-cycle, FP64 and FP32).  schedules: solver ->
+    (nu, nu below), else V(2,2) everywhere."""
     fin = cf.camfe_hierarchy_levels(h)[0]
     n = cf.camfe_hierarchy_info(h, fin)[2]
     res = {"dof": int(n)}
@@ -333,6 +369,7 @@ def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mi
         cf.camfe_smoother_attach(s, model if tag == "learned_mixed" else None)
         kw = dict(kw)
         mi = kw.pop("max_iter", max_iter)
+        kw.update(schedule_kw(tuple(schedules[tag]) if schedules and tag in schedules else (2, 0)))
         cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4, **kw)
         x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=mi, **kw)
         res[tag] = {"s": st["seconds"], "cycles": st["cycles"], "rel_residual": st["rel_residual"],
@@ -773,6 +810,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-sphere", action="store_true", help="skip the held-out noisy sphere (8.4M tris, depth 11)")
+    ap.add_argument("--fixed-schedule", action="store_true",
+                    help="V(2,2) for every solver instead of choosing each one's sweep schedule first")
     ap.add_argument("--no-sheets", action="store_true", help="skip the two-sheet coupling test (depth 8)")
     ap.add_argument("--no-flow", action="store_true", help="skip the config-3 flow steps")
     ap.add_argument("--batch-meshes", type=int, default=64, help="meshes of the config-4 batch (0: skip)")
@@ -847,6 +886,16 @@ def main():
     log("[bench] training the learned smoother")
     model, train_info = train_smoother(cf, ctx, meshgen, sweep=1)
     keep = {}
+    sched = {}
+    if not args.fixed_schedule:
+        log("[bench] sweep schedule per solver, chosen on the workload before the warm-up")
+        h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
+        s = cf.camfe_assemble(h)
+        b = cf.camfe_load_vector(s, h, fd)
+        sched = tune_schedules(cf, s, b, wl["t"], model, [tag for tag, _ in SOLVERS])
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+    learned_kw = schedule_kw(tuple(sched["learned_mixed"]["chosen"]) if sched else (2, 0))
 
     def step(record, keep_last=False):
         """The whole path once: build, assemble, load, learned mixed solve."""
@@ -859,7 +908,7 @@ def main():
         b = cf.camfe_load_vector(s, h, fd)
         t3 = time.perf_counter()
         cf.camfe_smoother_attach(s, model)
-        x, st = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=4000, precision=1, smoother=2)
+        x, st = cf.camfe_solve(s, b, t=wl["t"], rtol=1e-8, max_iter=4000, precision=1, smoother=2, **learned_kw)
         t4 = time.perf_counter()
         if record is not None:
             record.append(dict(build=t1 - t0, assemble=t2 - t1, load=t3 - t2, solve_call=t4 - t3, st=st))
@@ -898,12 +947,17 @@ def main():
     solve_s = float(np.mean([x["seconds"] for x in sts]))
     cycles = float(np.mean([x["cycles"] for x in sts]))
     log("[bench] plain Gauss-Seidel solves of the same system")
-    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed", "block_fp64"))
+    comp = solve_comparison(cf, s, h, b, wl["t"], model, which=("plain_gs_fp64", "plain_gs_mixed", "block_fp64"),
+                            schedules={k: v["chosen"] for k, v in sched.items()})
     comp["learned_mixed"] = {"s": solve_s, "cycles": cycles, "rel_residual": float(max(x["rel_residual"] for x in sts)),
                              "converged": bool(all(x["converged"] for x in sts)),
                              "fell_back": int(max(x["fell_back"] for x in sts)),
                              "setup_s": float(np.mean([x["setup_seconds"] for x in sts])),
                              "dof_cycles_per_s": n * cycles / solve_s, "timed_steps": len(sts)}
+    for k, v in sched.items():
+        comp[k]["schedule"] = v
+    if not sched:
+        comp["schedule"] = "V(2,2) for every solver"
     comp["speedup_learned_mixed_vs_plain_fp64"] = comp["plain_gs_fp64"]["s"] / solve_s
     comp["speedup_learned_mixed_vs_plain_mixed"] = comp["plain_gs_mixed"]["s"] / solve_s
     phases = {k: 1000.0 * float(np.mean([r[k] for r in rec])) for k in ("build", "assemble", "load", "solve_call")}
@@ -922,7 +976,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "dof_finest": int(n), "levels": [fin, d0], "max_coarse": args.max_coarse},
         "value_is": "learned-smoother mixed-precision solve to 1e-8, iterations only (solver set-up in "
-                    "solvers.learned_mixed.setup_s), mean over the timed steps",
+                    "solvers.learned_mixed.setup_s), mean over the timed steps; every solver runs the sweep "
+                    "schedule that was fastest for it among (sweeps at the finest depth, sweeps below) = "
+                    "(2,2), (2,1), (3,1), (1,1) in untimed solves of the same system before the warm-up "
+                    "(solvers.<name>.schedule); the held-out sphere and the sheets use V(2,2)",
         "phases_ms": phases,
         "solvers": comp,
         "learned_training": train_info,
@@ -979,8 +1036,9 @@ def main():
         calibrate_copy(torch, dev)
     if not args.no_cpu_baseline and args.workload == "knot_8m_depth11":
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(cf, ctx, meshgen, {"dof": int(n), "cycles_fp64": comp["plain_gs_fp64"]["cycles"],
-                                                              "model": model})
+        # the oracle runs V(2,2)-cycles: scale by the GPU's FP64 V(2,2) cycle count
+        c22 = sched["plain_gs_fp64"]["cycles"]["2,0"] if sched else comp["plain_gs_fp64"]["cycles"]
+        out["cpu_baseline"] = cpu_baseline(cf, ctx, meshgen, {"dof": int(n), "cycles_fp64": c22, "model": model})
         # every solver's result against the oracle's FP64 solution, on the oracle-sized sample
         out["error_vs_oracle"] = {"sample": out["cpu_baseline"]["sample"].split(";")[0],
                                   **out["cpu_baseline"]["gpu_error_vs_oracle_on_sample"]}

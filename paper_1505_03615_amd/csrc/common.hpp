@@ -258,11 +258,12 @@ inline unsigned grid_for(size_t n, unsigned block) {
 }
 
 // ------------------------------------------------- primitives (prim.hip)
-// Radix sorts of 64- or 32-bit keys on bits [0, end_bit); stable.  Temporary storage
-// comes from the context.  In-place on (keys[, vals]).
+// Radix sorts of 64- or 32-bit keys on bits [0, end_bit) (sort_pairs: [begin_bit,
+// end_bit)); stable.  Temporary storage comes from the context.  In-place on
+// (keys[, vals]).
 void sort_keys(camfe_ctx ctx, u64* keys, size_t n, int end_bit);
 void sort_keys_u32(camfe_ctx ctx, uint32_t* keys, size_t n, int end_bit);
-void sort_pairs(camfe_ctx ctx, u64* keys, uint32_t* vals, size_t n, int end_bit);
+void sort_pairs(camfe_ctx ctx, u64* keys, uint32_t* vals, size_t n, int end_bit, int begin_bit = 0);
 void sort_pairs_u32(camfe_ctx ctx, uint32_t* keys, uint32_t* vals, size_t n, int end_bit);
 // exclusive prefix sums (out may alias in); returns nothing (total = last in + last out)
 void exclusive_scan(camfe_ctx ctx, const int* in, int* out, size_t n);

@@ -227,19 +227,28 @@ __global__ void k_parent_keys(const u64* in, long long n, u64* out) {
 }
 
 // --------------------------------------------------------- support entries
-__global__ void k_support_emit(const u64* pairs, long long np, int W, u64* keys, uint32_t* vals) {
+// (support, triangle) candidates of the pairs taken in triangle order
+// (pairs_by_tri, with each pair's index in the cell-ordered list): a stable
+// sort on the support bits alone then orders them by (support, triangle).
+// vals = cell-ordered pair index * NB + corner.
+__global__ void k_support_emit(const u64* pairs_by_tri, const uint32_t* pair_index, long long np, int W,
+                               u64* keys, uint32_t* vals) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   const int NB = W * W * W;
   if (i >= np * NB) return;
-  long long p = i / NB;
-  int j = (int)(i - p * NB);
-  u64 k = pairs[p];
+  long long q = i / NB;
+  int j = (int)(i - q * NB);
+  u64 k = pairs_by_tri[q];
   long long c[3];
   demorton(k >> TRI_BITS, c);
   int jx = j % W, jy = (j / W) % W, jz = j / (W * W);
   u64 s = morton((u64)(c[0] + jx), (u64)(c[1] + jy), (u64)(c[2] + jz));
   keys[i] = (s << TRI_BITS) | (k & TRI_MASK);
-  vals[i] = (uint32_t)i;
+  vals[i] = pair_index[q] * (uint32_t)NB + (uint32_t)j;
+}
+__global__ void k_iota_u32(uint32_t* v, long long n) {
+  long long i = blockIdx.x * (long long)BLK + threadIdx.x;
+  if (i < n) v[i] = (uint32_t)i;
 }
 // unique entries + map from (pair, j) to its entry
 __global__ void k_entries_scatter(const u64* keys, const uint32_t* vals, const int* flag, const int* pos,
@@ -412,14 +421,15 @@ __global__ void k_pair_rows(const int* entry_of, const int* ent_func, long long 
 }
 
 // --------------------------------------------------------------- adjacency
-__global__ void k_edge_emit(const int* F, long long nt, u64* keys, uint32_t* vals) {
+// edge keys: (smaller vertex << vbits) | larger vertex, vbits bits per vertex
+__global__ void k_edge_emit(const int* F, long long nt, int vbits, u64* keys, uint32_t* vals) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= 3 * nt) return;
   long long t = i / 3;
   int j = (int)(i - 3 * t);
   int a = F[3 * t + j], b = F[3 * t + (j + 1) % 3];
   u64 lo = (u64)min(a, b), hi = (u64)max(a, b);
-  keys[i] = (lo << 32) | hi;
+  keys[i] = (lo << vbits) | hi;
   vals[i] = (uint32_t)i;
 }
 __global__ void k_edge_fill(const uint32_t* vals, const int* flag, const int* pos, long long n, int* tri_edge,
@@ -431,17 +441,19 @@ __global__ void k_edge_fill(const uint32_t* vals, const int* flag, const int* po
   edge_tri[i] = (int)(vals[i] / 3);
   if (flag[i]) edge_ptr[id] = (int)i;
 }
-__global__ void k_vert_emit(const int* F, long long nt, u64* keys) {
+// vertex keys: (vertex << tbits) | triangle, tbits bits per triangle
+__global__ void k_vert_emit(const int* F, long long nt, int tbits, u64* keys) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= 3 * nt) return;
-  keys[i] = ((u64)F[i] << 32) | (u64)(i / 3);
+  keys[i] = ((u64)F[i] << tbits) | (u64)(i / 3);
 }
-__global__ void k_vt_fill(const u64* keys, long long n, long long nv, int* vt_ptr, int* vt_tri) {
+__global__ void k_vt_fill(const u64* keys, long long n, long long nv, int tbits, int* vt_ptr, int* vt_tri) {
   long long i = blockIdx.x * (long long)BLK + threadIdx.x;
   if (i >= n) return;
-  long long v = (long long)(keys[i] >> 32);
-  vt_tri[i] = (int)(keys[i] & 0xffffffffULL);
-  long long pv = (i == 0) ? -1 : (long long)(keys[i - 1] >> 32);
+  const u64 tmask = (1ULL << tbits) - 1ULL;
+  long long v = (long long)(keys[i] >> tbits);
+  vt_tri[i] = (int)(keys[i] & tmask);
+  long long pv = (i == 0) ? -1 : (long long)(keys[i - 1] >> tbits);
   for (long long w = pv + 1; w <= v; ++w) vt_ptr[w] = (int)i;
   if (i == n - 1)
     for (long long w = v + 1; w <= nv; ++w) vt_ptr[w] = (int)n;
@@ -582,9 +594,16 @@ void build_adjacency(camfe_hier h) {
   DArr<u64> keys(n3);
   DArr<uint32_t> vals(n3);
   unsigned g = grid_for(n3, BLK);
-  hipLaunchKernelGGL(k_edge_emit, g, BLK, 0, ctx->stream, h->F.p, (long long)h->nt, keys.p, vals.p);
+  // bits that hold any vertex index and any triangle index
+  auto bits_for = [](size_t count) {
+    int b = 1;
+    while (b < 31 && (size_t(1) << b) < count) ++b;
+    return b;
+  };
+  const int vbits = bits_for(h->nv), tbits = bits_for(h->nt);
+  hipLaunchKernelGGL(k_edge_emit, g, BLK, 0, ctx->stream, h->F.p, (long long)h->nt, vbits, keys.p, vals.p);
   check_launch();
-  sort_pairs(ctx, keys.p, vals.p, n3, 64);
+  sort_pairs(ctx, keys.p, vals.p, n3, 2 * vbits);
   DArr<int> flag(n3), pos(n3);
   hipLaunchKernelGGL(k_head_flags, g, BLK, 0, ctx->stream, keys.p, (long long)n3, 0, flag.p);
   exclusive_scan(ctx, flag.p, pos.p, n3);
@@ -597,12 +616,12 @@ void build_adjacency(camfe_hier h) {
   int n3i = (int)n3;
   copy_in(ctx, h->edge_ptr.p + h->ne, &n3i, 1);
   ctx->sync();
-  hipLaunchKernelGGL(k_vert_emit, g, BLK, 0, ctx->stream, h->F.p, (long long)h->nt, keys.p);
-  sort_keys(ctx, keys.p, n3, 64);
+  hipLaunchKernelGGL(k_vert_emit, g, BLK, 0, ctx->stream, h->F.p, (long long)h->nt, tbits, keys.p);
+  sort_keys(ctx, keys.p, n3, vbits + tbits);
   h->vt_ptr.alloc(h->nv + 1);
   h->vt_tri.alloc(n3);
-  hipLaunchKernelGGL(k_vt_fill, g, BLK, 0, ctx->stream, keys.p, (long long)n3, (long long)h->nv, h->vt_ptr.p,
-                     h->vt_tri.p);
+  hipLaunchKernelGGL(k_vt_fill, g, BLK, 0, ctx->stream, keys.p, (long long)n3, (long long)h->nv, tbits,
+                     h->vt_ptr.p, h->vt_tri.p);
   h->vfan.alloc(std::max<size_t>(h->nv, 1));
   hipLaunchKernelGGL(k_vertex_fans, grid_for(h->nv, BLK), BLK, 0, ctx->stream, h->F.p, h->vt_ptr.p, h->vt_tri.p,
                      (long long)h->nv, h->vfan.p);
@@ -620,9 +639,20 @@ void build_functions(camfe_hier h, int d) {
   DArr<u64> keys(nraw);
   DArr<uint32_t> vals(nraw);
   unsigned g = grid_for(nraw, BLK);
-  hipLaunchKernelGGL(k_support_emit, g, BLK, 0, ctx->stream, L.pairs.p, (long long)L.npairs, W, keys.p, vals.p);
-  check_launch();
-  sort_pairs(ctx, keys.p, vals.p, nraw, 3 * sbits(d) + TRI_BITS);
+  {
+    // the pairs in triangle order (3 digit passes), so that the candidates
+    // need sorting on their support bits only
+    DArr<u64> by_tri(L.npairs);
+    DArr<uint32_t> index(L.npairs);
+    CAMFE_HIP(hipMemcpyAsync(by_tri.p, L.pairs.p, L.npairs * sizeof(u64), hipMemcpyDeviceToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_iota_u32, grid_for(L.npairs, BLK), BLK, 0, ctx->stream, index.p, (long long)L.npairs);
+    check_launch();
+    sort_pairs(ctx, by_tri.p, index.p, L.npairs, TRI_BITS);
+    hipLaunchKernelGGL(k_support_emit, g, BLK, 0, ctx->stream, by_tri.p, index.p, (long long)L.npairs, W, keys.p,
+                       vals.p);
+    check_launch();
+  }
+  sort_pairs(ctx, keys.p, vals.p, nraw, 3 * sbits(d) + TRI_BITS, TRI_BITS);
   DArr<int> entry_of(nraw);
   {
     DArr<int> flag(nraw), pos(nraw);

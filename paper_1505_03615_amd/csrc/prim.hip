@@ -3,7 +3,7 @@
 // written for 64-wide wavefronts.
 //
 // Radix sort, one pass per 8-bit digit:
-//   1. k_radix_hist: every tile of TILE keys counts its digits; the counts
+//   1. k_radix_hist: every tile of STILE keys counts its digits; the counts
 //      land digit-major, counts[d * tiles + tile].
 //   2. an exclusive scan of that array gives, for every (digit, tile), the
 //      output position of the tile's first key with that digit.
@@ -12,7 +12,7 @@
 //      wave-private running counters in LDS, the waves' counts are combined
 //      per digit, the tile is reordered by digit in LDS and written out, so
 //      that keys of one digit leave a tile as one contiguous run.
-// A tile is four waves, each with a contiguous quarter, so the order within a
+// A tile is eight waves, each with a contiguous eighth, so the order within a
 // tile (wave, then step, then lane) is the input order: the sort is stable.
 #include "common.hpp"
 
@@ -20,14 +20,20 @@ namespace camfe {
 
 namespace {
 
+// scans and reductions
 constexpr int PB = 256;             // threads per block (four waves)
 constexpr int PW = PB / 64;         // waves per block
-constexpr int PI = 8;               // keys per thread
-constexpr int TILE = PB * PI;       // keys per tile
-constexpr int WTILE = TILE / PW;    // keys per wave
+constexpr int PI = 8;               // values per thread
+constexpr int TILE = PB * PI;       // values per tile
+// radix sort
+constexpr int SB = 512;             // threads per block (eight waves)
+constexpr int SW = SB / 64;         // waves per block
+constexpr int SI = 8;               // keys per thread
+constexpr int STILE = SB * SI;      // keys per tile
+constexpr int WTILE = STILE / SW;   // keys per wave
 constexpr int RBITS = 8;            // bits per digit
 constexpr int RD = 1 << RBITS;      // digits
-static_assert(PB == RD, "one thread per digit in the per-tile digit scan");
+static_assert(SB >= RD && SB % RD == 0, "every digit has a thread in the per-tile digit scan");
 
 __device__ inline unsigned long long lanes_below() {
   return (1ULL << __lane_id()) - 1ULL;
@@ -76,58 +82,57 @@ __device__ inline T block_exclusive_sum(T v, T* part, T& total) {
 }
 
 template <class K>
-__global__ __launch_bounds__(PB) void k_radix_hist(const K* __restrict__ keys, long long n, int shift,
+__global__ __launch_bounds__(SB) void k_radix_hist(const K* __restrict__ keys, long long n, int shift,
                                                    unsigned dmask, int* __restrict__ counts, int tiles) {
   __shared__ int h[RD];
-  h[threadIdx.x] = 0;
+  if (threadIdx.x < RD) h[threadIdx.x] = 0;
   __syncthreads();
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long long base = (long long)blockIdx.x * TILE + (long long)w * WTILE + lane;
-  K key[PI];
+  const long long base = (long long)blockIdx.x * STILE + (long long)w * WTILE + lane;
+  K key[SI];
 #pragma unroll
-  for (int k = 0; k < PI; ++k) {
+  for (int k = 0; k < SI; ++k) {
     const long long i = base + 64LL * k;
     key[k] = i < n ? keys[i] : K(0);
   }
 #pragma unroll
-  for (int k = 0; k < PI; ++k) {
+  for (int k = 0; k < SI; ++k) {
     const bool valid = base + 64LL * k < n;
     const unsigned d = (unsigned)(key[k] >> shift) & dmask;
     const unsigned long long m = same_digit(d, valid);
     if (valid && (m & lanes_below()) == 0ULL) atomicAdd(&h[d], (int)__popcll(m));
   }
   __syncthreads();
-  counts[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < RD) counts[(size_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
 template <class K, bool VALS>
-__global__ __launch_bounds__(PB) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+__global__ __launch_bounds__(SB) void k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                       K* __restrict__ kout, uint32_t* __restrict__ vout,
                                                       long long n, int shift, unsigned dmask,
                                                       const int* __restrict__ offs, int tiles) {
-  __shared__ K sk[TILE];
-  __shared__ uint32_t sv[VALS ? TILE : 1];
-  __shared__ int run[PW][RD];     // per wave: keys of each digit ranked so far, then the wave's prefix
+  __shared__ K sk[STILE];
+  __shared__ uint32_t sv[VALS ? STILE : 1];
+  __shared__ int run[SW][RD];     // per wave: keys of each digit ranked so far, then the wave's prefix
   __shared__ int tstart[RD];      // first position of each digit within the reordered tile
   __shared__ int gshift[RD];      // output position of the tile's digit-d run, minus tstart[d]
-  __shared__ int part[PW];
+  __shared__ int part[SW];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  const long long tile0 = (long long)blockIdx.x * TILE;
+  const long long tile0 = (long long)blockIdx.x * STILE;
   const long long base = tile0 + (long long)w * WTILE + lane;
-  K key[PI];
-  uint32_t val[PI];
-  int rank[PI];
+  K key[SI];
+  uint32_t val[SI];
+  int rank[SI];
 #pragma unroll
-  for (int k = 0; k < PI; ++k) {
+  for (int k = 0; k < SI; ++k) {
     const long long i = base + 64LL * k;
     key[k] = i < n ? kin[i] : K(0);
     if (VALS) val[k] = i < n ? vin[i] : 0u;
   }
-#pragma unroll
-  for (int ww = 0; ww < PW; ++ww) run[ww][t] = 0;
+  for (int i = t; i < SW * RD; i += SB) (&run[0][0])[i] = 0;
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PI; ++k) {
+  for (int k = 0; k < SI; ++k) {
     const bool valid = base + 64LL * k < n;
     const unsigned d = (unsigned)(key[k] >> shift) & dmask;
     const unsigned long long m = same_digit(d, valid);
@@ -144,22 +149,27 @@ __global__ __launch_bounds__(PB) void k_radix_scatter(const K* __restrict__ kin,
   }
   __syncthreads();
   {
+    // threads below RD own one digit each; the others add zeros to the scan
     const int d = t;
     int s = 0;
+    if (d < RD) {
 #pragma unroll
-    for (int ww = 0; ww < PW; ++ww) {
-      const int c = run[ww][d];
-      run[ww][d] = s;
-      s += c;
+      for (int ww = 0; ww < SW; ++ww) {
+        const int c = run[ww][d];
+        run[ww][d] = s;
+        s += c;
+      }
     }
     int total;
     const int ex = block_exclusive_sum(s, part, total);
-    tstart[d] = ex;
-    gshift[d] = offs[(size_t)d * tiles + blockIdx.x] - ex;
+    if (d < RD) {
+      tstart[d] = ex;
+      gshift[d] = offs[(size_t)d * tiles + blockIdx.x] - ex;
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PI; ++k) {
+  for (int k = 0; k < SI; ++k) {
     if (base + 64LL * k < n) {
       const unsigned d = (unsigned)(key[k] >> shift) & dmask;
       const int pos = tstart[d] + run[w][d] + rank[k];
@@ -169,8 +179,8 @@ __global__ __launch_bounds__(PB) void k_radix_scatter(const K* __restrict__ kin,
   }
   __syncthreads();
   const long long rem = n - tile0;
-  const int cnt = rem < TILE ? (int)rem : TILE;
-  for (int p = t; p < cnt; p += PB) {
+  const int cnt = rem < STILE ? (int)rem : STILE;
+  for (int p = t; p < cnt; p += SB) {
     const K kk = sk[p];
     const unsigned d = (unsigned)(kk >> shift) & dmask;
     const long long o = (long long)gshift[d] + p;
@@ -239,6 +249,7 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const T* __restrict__ p, 
 }
 
 inline size_t tiles_of(size_t n) { return (n + TILE - 1) / TILE; }
+inline size_t sort_tiles_of(size_t n) { return (n + STILE - 1) / STILE; }
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // exclusive scan with caller-provided room for tiles_of(n) partials
@@ -259,11 +270,12 @@ void scan_with(camfe_ctx ctx, const T* in, T* out, size_t n, T* partials) {
 }
 
 template <class K, bool VALS>
-void radix_sort(camfe_ctx ctx, K* keys, uint32_t* vals, size_t n, int end_bit) {
-  if (n < 2 || end_bit <= 0) return;
+void radix_sort(camfe_ctx ctx, K* keys, uint32_t* vals, size_t n, int end_bit, int begin_bit = 0) {
+  CAMFE_REQUIRE(begin_bit >= 0, CAMFE_EINVAL, "radix sort begin bit below 0");
+  if (n < 2 || end_bit <= begin_bit) return;
   CAMFE_REQUIRE(n < (size_t(1) << 31), CAMFE_EINVAL, "radix sort of 2^31 keys or more");
   CAMFE_REQUIRE(end_bit <= (int)(8 * sizeof(K)), CAMFE_EINVAL, "radix sort end bit beyond the key");
-  const size_t tl = tiles_of(n);
+  const size_t tl = sort_tiles_of(n);
   const size_t ncount = tl * RD;
   // scratch: digit counts, then the partials of their scan
   unsigned char* s1 = ctx->scratch_bytes(align256(ncount * sizeof(int)) + align256(tiles_of(ncount) * sizeof(int)));
@@ -278,14 +290,14 @@ void radix_sort(camfe_ctx ctx, K* keys, uint32_t* vals, size_t n, int end_bit) {
   uint32_t* vsrc = vals;
   uint32_t* vdst = valt;
   int passes = 0;
-  for (int shift = 0; shift < end_bit; shift += RBITS, ++passes) {
+  for (int shift = begin_bit; shift < end_bit; shift += RBITS, ++passes) {
     const int bits = end_bit - shift < RBITS ? end_bit - shift : RBITS;
     const unsigned dmask = (1u << bits) - 1u;
-    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)tl), dim3(PB), 0, ctx->stream, (const K*)ksrc, (long long)n,
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)tl), dim3(SB), 0, ctx->stream, (const K*)ksrc, (long long)n,
                        shift, dmask, counts, (int)tl);
     check_launch();
     scan_with<int>(ctx, counts, counts, ncount, partials);
-    hipLaunchKernelGGL((k_radix_scatter<K, VALS>), dim3((unsigned)tl), dim3(PB), 0, ctx->stream, (const K*)ksrc,
+    hipLaunchKernelGGL((k_radix_scatter<K, VALS>), dim3((unsigned)tl), dim3(SB), 0, ctx->stream, (const K*)ksrc,
                        (const uint32_t*)vsrc, kdst, vdst, (long long)n, shift, dmask, (const int*)counts, (int)tl);
     check_launch();
     K* tk = ksrc; ksrc = kdst; kdst = tk;
@@ -307,8 +319,8 @@ void sort_keys(camfe_ctx ctx, u64* keys, size_t n, int end_bit) {
   radix_sort<u64, false>(ctx, keys, nullptr, n, end_bit);
 }
 
-void sort_pairs(camfe_ctx ctx, u64* keys, uint32_t* vals, size_t n, int end_bit) {
-  radix_sort<u64, true>(ctx, keys, vals, n, end_bit);
+void sort_pairs(camfe_ctx ctx, u64* keys, uint32_t* vals, size_t n, int end_bit, int begin_bit) {
+  radix_sort<u64, true>(ctx, keys, vals, n, end_bit, begin_bit);
 }
 
 void sort_pairs_u32(camfe_ctx ctx, uint32_t* keys, uint32_t* vals, size_t n, int end_bit) {

@@ -386,16 +386,22 @@ def solve_comparison(cf, s, h, b, t, model, which=("plain_gs_fp64", "plain_gs_mi
     if "plain_gs_mixed" in res and "learned_mixed" in res:
         res["speedup_learned_mixed_vs_plain_mixed"] = res["plain_gs_mixed"]["s"] / res["learned_mixed"]["s"]
     res["vcycle_roofline"] = whole_cycle(cf, s, h)
+    if schedules and "plain_gs_mixed" in schedules and tuple(schedules["plain_gs_mixed"]) != (2, 0):
+        sc = tuple(schedules["plain_gs_mixed"])
+        res["vcycle_roofline_chosen_schedule"] = {"schedule": list(sc), **whole_cycle(cf, s, h, schedule=sc)}
     return res
 
 
-def whole_cycle(cf, s, h, reps=10):
-    """One plain V(2,2)-cycle (captured, back to back) against the HBM peak:
-    algorithmic bytes of the cycle (vcycle_bytes) over its measured time."""
+def whole_cycle(cf, s, h, reps=10, schedule=(2, 0)):
+    """One plain Gauss-Seidel V-cycle (captured, back to back) against the
+    HBM peak: algorithmic bytes of the cycle (vcycle_bytes) over its measured
+    time.  schedule = (sweeps each way at the finest depth, below; 0 = same)."""
+    a, c = schedule
+    name = "vcycle" if (a, c) == (2, 0) else f"vcycle:{a},{c}"
     out = {}
     for p, (sv, sx) in ((0, (8, 8)), (1, (4, 4))):
-        ms, _ = cf.camfe_measure_kernel(s, "vcycle", p, reps)
-        by = vcycle_bytes(cf, s, h, 1, sv, sx)
+        ms, _ = cf.camfe_measure_kernel(s, name, p, reps)
+        by = vcycle_bytes(cf, s, h, 1, sv, sx, nu=2 * a, nu_below=2 * (c if c > 0 else a))
         gbs = by / (ms / 1000.0) / 1e9
         out["fp64" if p == 0 else "fp32"] = {"bytes_per_cycle": by, "ms_per_cycle": ms, "GBs": gbs,
                                             "frac": gbs / PEAK_HBM_GBS}
@@ -834,6 +840,9 @@ def main():
     ap.add_argument("--assembly-only", action="store_true",
                     help="only the assembly measurement (four meshes, both degrees); for matrix-core counter runs")
     ap.add_argument("--no-assembly", action="store_true", help="skip the assembly measurement")
+    ap.add_argument("--build-only", action="store_true",
+                    help="only the hierarchy build of the workload, four times (the last three timed); for "
+                         "kernel-trace runs of the set-up path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
@@ -867,6 +876,22 @@ def main():
     Fd = torch.from_numpy(F).to(dev)
     fd = torch.from_numpy(np.asfortranarray(f)).to(dev)
     traffic_file = TRAFFIC_FILES.get(args.workload)
+
+    if args.build_only:
+        times = []
+        for i in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"],
+                                         max_coarse=args.max_coarse)
+            torch.cuda.synchronize()
+            times.append(1000.0 * (time.perf_counter() - t0))
+            log(f"[bench] hierarchy build {i}: {times[-1]:.1f} ms")
+            cf.camfe_hierarchy_destroy(h)
+        cf.camfe_ctx_destroy(ctx)
+        print(json.dumps({"hierarchy_build": {"workload": wl["desc"], "ms": times, "best_of_last_3_ms": min(times[1:])}}),
+              flush=True)
+        return
 
     if args.roofline_only:
         h = cf.camfe_hierarchy_build(ctx, Vd, Fd, depth=wl["depth"], degree=wl["degree"], max_coarse=args.max_coarse)
@@ -1003,6 +1028,8 @@ def main():
             out["roofline"] = roofline(cf, s, meas, with_traffic=traffic_file is not None, traffic_file=traffic_file,
                                        depth=wl["depth"])
         out["roofline"]["whole_vcycle"] = comp["vcycle_roofline"]
+        if "vcycle_roofline_chosen_schedule" in comp:
+            out["roofline"]["whole_vcycle_chosen_schedule"] = comp["vcycle_roofline_chosen_schedule"]
     cf.camfe_smoother_attach(s, None)
     cf.camfe_system_destroy(s)
     cf.camfe_hierarchy_destroy(h)

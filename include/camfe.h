@@ -276,7 +276,9 @@ camfe_status camfe_solve(camfe_sys s, const camfe_solve_opts *opts, const double
  * FP32 (1) values, one right-hand side; or "vcycle": one whole plain
  * Gauss-Seidel V(2,2)-cycle from a zero guess over every depth (the
  * preconditioner a CG step applies), avg_ms per cycle and bytes_per_launch 0
- * (its algorithmic bytes depend on the depths' sizes, which the exports give).  reps back-to-back sweeps/launches are
+ * (its algorithmic bytes depend on the depths' sizes, which the exports give);
+ * "vcycle:a,c" is the same cycle with a sweeps each way at the finest depth
+ * and c at every coarser one (c = 0: a; 1 <= a <= 16, 0 <= c <= 16).  reps back-to-back sweeps/launches are
  * captured once into a HIP graph and replayed between two HIP events on the
  * context's stream.  avg_ms: average time of one launch; bytes_per_launch: the
  * algorithmic bytes of one launch (matrix values + three vector accesses per

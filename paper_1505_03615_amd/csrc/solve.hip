@@ -2144,8 +2144,21 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
     else if (name == "spmv_dot") kid = 2;
     else if (name == "empty") kid = 3;
     else if (name == "copy") kid = 4;
-    else if (name == "vcycle") kid = 5;
-    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL, "measurable kernels: gs_colour, residual, spmv_dot, empty, copy, vcycle");
+    // "vcycle" or "vcycle:<sweeps at the finest depth>,<sweeps below>"
+    int cyc_nu = 2, cyc_nc = 0;
+    if (name == "vcycle") kid = 5;
+    else if (name.rfind("vcycle:", 0) == 0) {
+      int a = 0, c = 0;
+      char tail = 0;
+      CAMFE_REQUIRE(std::sscanf(name.c_str() + 7, "%d,%d%c", &a, &c, &tail) == 2 && a >= 1 && a <= 16 && c >= 0 &&
+                        c <= 16,
+                    CAMFE_EINVAL, "vcycle schedule: vcycle:<1-16>,<0-16>");
+      kid = 5;
+      cyc_nu = a;
+      cyc_nc = c;
+    }
+    CAMFE_REQUIRE(kid >= 0, CAMFE_EINVAL,
+                  "measurable kernels: gs_colour, residual, spmv_dot, empty, copy, vcycle[:nu,nu_below]");
     const long long nk = (long long)G.n;
     hipStream_t st = ctx->stream;
     hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.b64.p, nk, 1.0);
@@ -2200,14 +2213,14 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
           hipLaunchKernelGGL(k_spmv_dot<1>, (unsigned)G.nslices, SL * SW, 0, ctx->stream, G.sl_meta.p,
                              (int)G.nslices, G.scol.p, G.scol16.p, G.sbase.p, G.sval64.p, (const double*)G.x64.p, G.r64.p, S->part.p);
         } else if (kid == 5) {
-          // one plain Gauss-Seidel V(2,2)-cycle from a zero guess, as the
+          // one plain Gauss-Seidel V-cycle from a zero guess, as the
           // preconditioner of a CG step applies it (one column)
           if (precision == 0) {
             hipLaunchKernelGGL((k_fill<double>), grid_for(nk, BLK), BLK, 0, st, G.x64.p, nk, 0.0);
-            vcycle<double, 1>(S, S->D, G.b64.p, G.x64.p, 2, 2);
+            vcycle<double, 1>(S, S->D, G.b64.p, G.x64.p, cyc_nu, cyc_nu);
           } else {
             hipLaunchKernelGGL((k_fill<float>), grid_for(nk, BLK), BLK, 0, st, G.x32.p, nk, 0.0f);
-            vcycle<float, 1>(S, S->D, G.b32.p, G.x32.p, 2, 2);
+            vcycle<float, 1>(S, S->D, G.b32.p, G.x32.p, cyc_nu, cyc_nu);
           }
         } else {
           for (int c = 0; c < G.ncol; ++c) {
@@ -2229,8 +2242,9 @@ camfe_status camfe_measure_kernel(camfe_sys s, const char* kernel, int precision
       int sm, g, nc;
       ~CycleScope() { S->smoother = sm; S->gamma = g; S->nu_coarse = nc; }
     } cycle_scope{S, S->smoother, S->gamma, S->nu_coarse};
-    if (kid == 5) { S->smoother = 0; S->gamma = 1; S->nu_coarse = 0; }
-    const long long key = -1 - (((long long)kid * 2 + precision) << 20) - reps;
+    if (kid == 5) { S->smoother = 0; S->gamma = 1; S->nu_coarse = cyc_nc; }
+    const long long sched = kid == 5 ? (long long)(cyc_nu * 17 + cyc_nc) : 0;
+    const long long key = -1 - ((((long long)kid * 2 + precision) * 512 + sched) << 20) - reps;
     // reference graphs are not kept: the copy's buffers end with this call
     struct DropGraph {
       SolverState* S;

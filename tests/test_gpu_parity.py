@@ -285,6 +285,16 @@ def test_kernel_measurement_and_references(cf, ctx):
         assert c_ms > 0 and abs(c_by - gs_by) <= 32
     with pytest.raises(cf.CamfeError, match="EINVAL"):
         cf.camfe_measure_kernel(s, "no_such_kernel")
+    # whole cycles under a sweep schedule: a V(3,3)-cycle with V(1,1) below
+    # sweeps more at the finest depth and less below than V(2,2)
+    say("measure: vcycle, vcycle:3,1, vcycle:1,0")
+    v22, vb = cf.camfe_measure_kernel(s, "vcycle", 0, 5)
+    v31, _ = cf.camfe_measure_kernel(s, "vcycle:3,1", 0, 5)
+    v11, _ = cf.camfe_measure_kernel(s, "vcycle:1,0", 0, 5)
+    assert vb == 0 and v22 > 0 and v31 > 0 and 0 < v11 < v22
+    for bad in ("vcycle:0,1", "vcycle:3", "vcycle:3,1x", "vcycle:17,1", "vcycle:3,-1"):
+        with pytest.raises(cf.CamfeError, match="EINVAL"):
+            cf.camfe_measure_kernel(s, bad, 0, 5)
     # the measurements leave the solver as it was: the same solve again
     x2, st2 = cf.camfe_solve(s, b, t=1e-3, max_iter=600)
     assert st1["converged"] and st2["iterations"] == st1["iterations"]

@@ -345,9 +345,10 @@ def tune_schedules(cf, s, b, t, model, which, max_iter=4000):
             times[sc] = st["seconds"] if st["converged"] else float("inf")
             cycles[sc] = st["cycles"]
         best = min(times, key=times.get)
-        out[tag] = {"chosen": list(best), "seconds": {f"{a},{c}": round(v, 4) for (a, c), v in times.items()},
+        out[tag] = {"chosen": list(best),
+                    "seconds": {f"{a},{c}": (round(v, 4) if v != float("inf") else None) for (a, c), v in times.items()},
                     "cycles": {f"{a},{c}": v for (a, c), v in cycles.items()}}
-        log(f"[bench] schedule {tag}: {best} from " + json.dumps(out[tag]["seconds"]))
+        log(f"[bench] schedule {tag}: {best} from " + json.dumps(out[tag]["seconds"]) + " (null: not converged)")
     cf.camfe_smoother_attach(s, None)
     return out
 

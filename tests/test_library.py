@@ -120,3 +120,42 @@ def test_smoother_model_file_round_trip(lib, tmp_path):
     with pytest.raises(camfe.CamfeError, match="EINVAL"):
         camfe.camfe_smoother_load(tmp_path / "missing.bin")
     assert lib.camfe_ctx_last_error(None) == b"null context"
+
+
+class _FakeSolver:
+    """Stands in for the binding in the bench's schedule choice: solve times
+    and cycle counts per (smoother, sweeps at the finest depth, below)."""
+
+    def __init__(self, table):
+        self.table = table
+        self.attached = []
+
+    def camfe_smoother_attach(self, s, m):
+        self.attached.append(m)
+
+    def camfe_solve(self, s, b, t, rtol, max_iter, precision=0, smoother=0, nu_pre=2, nu_post=2, nu_coarse=0):
+        secs, cyc = self.table[(smoother, nu_pre, nu_coarse)]
+        if max_iter <= 4:
+            return None, {"seconds": 0.0, "cycles": max_iter, "converged": False}
+        return None, {"seconds": secs, "cycles": cyc, "converged": secs is not None}
+
+
+def test_bench_schedule_choice_takes_each_solvers_fastest():
+    """The bench's schedule choice keeps, per solver, the schedule with the
+    shortest converged solve, reports a schedule that did not converge as
+    null, and records every candidate's cycles."""
+    import bench
+    table = {}
+    for sm, best in ((0, (3, 1)), (2, (2, 1)), (3, (1, 0))):
+        for a, c in bench.SCHEDULES:
+            table[(sm, a, c)] = (1.0 if (a, c) == best else 2.0 + a, 100 + 10 * a + c)
+    table[(2, 1, 0)] = (None, 4000)     # the learned smoother does not converge with (1, 1)
+    fake = _FakeSolver(table)
+    out = bench.tune_schedules(fake, None, None, 1e-4, "model", [tag for tag, _ in bench.SOLVERS])
+    assert out["plain_gs_fp64"]["chosen"] == [3, 1] and out["plain_gs_mixed"]["chosen"] == [3, 1]
+    assert out["learned_mixed"]["chosen"] == [2, 1] and out["block_fp64"]["chosen"] == [1, 0]
+    assert out["learned_mixed"]["seconds"]["1,0"] is None
+    assert out["plain_gs_fp64"]["cycles"]["2,0"] == 120
+    assert "model" in fake.attached and fake.attached[-1] is None
+    kw = bench.schedule_kw((3, 1))
+    assert kw == {"nu_pre": 3, "nu_post": 3, "nu_coarse": 1}

@@ -431,6 +431,50 @@ def test_length_sorted_layout_on_a_7m_function_system(cf, ctx):
         cf.camfe_hierarchy_destroy(h)
 
 
+def test_headline_knot_at_full_size(cf, ctx):
+    """The headline workload at its stated size: the held-out (3,5) knot tube
+    of 65536 x 64 quads (8,388,608 triangles, jitter seed 5901) at depth 11,
+    t = 1e-4, f = z + 0.1 x^2.  Properties that hold at any size, on the GPU's
+    exports: partition of unity (M sums to the mesh area) and zero row sums of
+    L at the finest depth, and prolongation rows that sum to exactly 1 (the
+    dyadic weights of the parents of a fine function, Eq. (3), whatever
+    component chi picks).  Each solver of the bench, with the sweep schedule
+    the bench picks for it on this mesh, reaches 1e-8 checked with the
+    exported FP64 matrices (the learned weights here are an untrained model's,
+    which still go through the learned SOR kernels)."""
+    V, F = meshgen.torus_knot(nu=65536, nv=64, seed=5901)
+    say("[gpu] build knot 8.4M depth 11")
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=11, max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    assert (fin, d0) == (11, 5)
+    M = cf.camfe_export_matrix(s, h, fin, 0)
+    L = cf.camfe_export_matrix(s, h, fin, 1)
+    assert M.shape[0] > 9_000_000
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    assert abs(M.sum() - area) <= 1e-12 * area
+    assert abs(L @ np.ones(L.shape[0])).max() <= 1e-11 * abs(L).max()
+    for d in (fin, fin - 3, d0 + 1):
+        P = cf.camfe_export_prolongation(h, d)
+        assert np.array_equal(np.asarray(P.sum(axis=1)).ravel(), np.ones(P.shape[0])), d
+    b = cf.camfe_load_vector(s, h, V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
+    A = M + 1e-4 * L
+    model = cf.camfe_model_create(None, levels=3, bf16=True, sweep=1)
+    cf.camfe_smoother_attach(s, model)
+    try:
+        for precision, smoother, (nu, nc) in ((0, 0, (3, 1)), (1, 0, (3, 1)), (1, 2, (3, 1)), (0, 3, (1, 0))):
+            say(f"[gpu] solve knot 8.4M precision={precision} smoother={smoother} sweeps=({nu},{nc})")
+            x, st = cf.camfe_solve(s, b, t=1e-4, rtol=1e-8, max_iter=500 if smoother == 3 else 3000,
+                                   precision=precision, smoother=smoother, nu_pre=nu, nu_post=nu, nu_coarse=nc)
+            r = np.linalg.norm(b - A @ x, axis=0) / np.linalg.norm(b, axis=0)
+            assert st["converged"] and not st["fell_back"] and np.all(r <= 1e-6), (precision, smoother, st, r)
+    finally:
+        cf.camfe_smoother_attach(s, None)
+        cf.camfe_model_destroy(model)
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+
+
 @pytest.mark.parametrize("nu_coarse", [1, 3])
 def test_coarse_sweep_count_tracks_oracle(cf, ctx, nu_coarse):
     """Fewer (or more) sweeps below the finest depth: stationary cycles track

@@ -475,6 +475,38 @@ def test_headline_knot_at_full_size(cf, ctx):
         cf.camfe_hierarchy_destroy(h)
 
 
+def test_held_out_sphere_at_full_size(cf, ctx):
+    """The second held-out mesh at its stated size: the octahedron subdivided
+    ten times (8,388,608 triangles) with 16 Gaussian bumps (seed 5902), depth
+    11, t = 1e-3 (30.5M functions, whose finest colours take the
+    length-sorted layout).  Partition of unity and zero row sums of the
+    exports at the finest depth, prolongation rows summing to 1, and the
+    mixed solve to 1e-8 checked with the exported FP64 matrices."""
+    V, F = meshgen.noisy_sphere(10, seed=5902, base="octa")
+    say("[gpu] build noisy sphere 8.4M depth 11")
+    h = cf.camfe_hierarchy_build(ctx, V, F, depth=11, max_coarse=4096)
+    s = cf.camfe_assemble(h)
+    fin, d0 = cf.camfe_hierarchy_levels(h)
+    M = cf.camfe_export_matrix(s, h, fin, 0)
+    assert M.shape[0] > 30_000_000
+    area = 0.5 * np.linalg.norm(np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]]), axis=1).sum()
+    assert abs(M.sum() - area) <= 1e-12 * area
+    L = cf.camfe_export_matrix(s, h, fin, 1)
+    assert abs(L @ np.ones(L.shape[0])).max() <= 1e-11 * abs(L).max()
+    P = cf.camfe_export_prolongation(h, fin)
+    assert np.array_equal(np.asarray(P.sum(axis=1)).ravel(), np.ones(P.shape[0]))
+    del P
+    b = cf.camfe_load_vector(s, h, V[:, 2:3] + 0.1 * V[:, 0:1] ** 2)
+    try:
+        say("[gpu] solve noisy sphere 8.4M, mixed")
+        x, st = cf.camfe_solve(s, b, t=1e-3, rtol=1e-8, max_iter=3000, precision=1)
+        r = np.linalg.norm(b - M @ x - 1e-3 * (L @ x), axis=0) / np.linalg.norm(b, axis=0)
+        assert st["converged"] and not st["fell_back"] and np.all(r <= 1e-6), (st, r)
+    finally:
+        cf.camfe_system_destroy(s)
+        cf.camfe_hierarchy_destroy(h)
+
+
 @pytest.mark.parametrize("nu_coarse", [1, 3])
 def test_coarse_sweep_count_tracks_oracle(cf, ctx, nu_coarse):
     """Fewer (or more) sweeps below the finest depth: stationary cycles track

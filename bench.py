@@ -729,7 +729,7 @@ def stripe_knot_eval(cf, ctx, meshgen, nu=8192, nv=64, depth=9, alpha=0.01):
             "near_crossings_vertices": int(near.sum().item()), "vertices": int(len(V)), "rows": rows}
 
 
-def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
+def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3, schedule=(2, 0)):
     """Config 4: `count` uneven meshes from meshgen.config4_batch (icospheres
     L3-7, tori with R/r in [2, 6] and 1k-1.3M triangles, noisy icospheres
     L3-8; depth clamp(round(log2(side / mean edge)), 6, 10); 1-16 N(0, 1)
@@ -737,7 +737,9 @@ def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
     (every system warm, iterations summed), then as one batch with a member
     per (mesh, chunk of <= 4 columns) so that one pass covers every column,
     with the default colour-sweep tile and with the autotuner's tile per
-    level."""
+    level.  schedule = (sweeps each way at the finest depth, below; 0 = the
+    same), for both the single systems and the batch."""
+    skw = schedule_kw(schedule)
     import torch
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
@@ -760,8 +762,8 @@ def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
     single = 0.0
     single_cycles = []
     for h, s, b in systems:
-        cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4)
-        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=2000)
+        cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=4, **skw)
+        x, st = cf.camfe_solve(s, b, t=t, rtol=1e-8, max_iter=2000, **skw)
         single += st["seconds"]
         single_cycles.append(st["cycles"])
     mem, chunks = [], []
@@ -779,8 +781,8 @@ def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
             t0 = time.perf_counter()
             tiles, tms = cf.camfe_batch_autotune(bt, precision=0, reps=10)
             tune_s = time.perf_counter() - t0
-        cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=4)      # capture
-        xs, sts = cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=2000)
+        cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=4, **skw)      # capture
+        xs, sts = cf.camfe_batch_solve(bt, chunks, t, rtol=1e-8, max_iter=2000, **skw)
         its = sorted(x["iterations"] for x in sts)
         runs[tag] = {"solve_s": sts[0]["seconds"], "iterations": its[-1],
                      "member_iterations_median": its[len(its) // 2], "member_iterations_sum": int(sum(its)),
@@ -791,7 +793,8 @@ def batch_eval(cf, ctx, meshgen, count=64, seed=4000, t=1e-3):
     for h, s, b in systems:
         cf.camfe_system_destroy(s)
         cf.camfe_hierarchy_destroy(h)
-    return {"meshes": len(members), "tris_total": int(sum(len(m["F"]) for m in members)),
+    return {"meshes": len(members), "sweeps_finest_below": list(schedule),
+            "tris_total": int(sum(len(m["F"]) for m in members)),
             "tris_min_max": [int(min(len(m["F"]) for m in members)), int(max(len(m["F"]) for m in members))],
             "dof_total": int(sum(dof)), "depths": [m["depth"] for m in members],
             "rhs": [int(m["fv"].shape[1]) for m in members], "kinds": [m["kind"] for m in members],

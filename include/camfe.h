@@ -445,7 +445,8 @@ camfe_status camfe_batch_create(camfe_ctx ctx, camfe_sys const *systems, int nsy
 /* levels of the batched hierarchy; rows of its finest level (padded) */
 camfe_status camfe_batch_info(camfe_batch b, int *levels, int64_t *rows);
 /* b[m], x[m]: n_m x k[m] column-major (x[m] read when x0_given); opts->t and
- * coarse_eps must be the batch's, method 0 and smoother 0.  stats (nullable)
+ * coarse_eps must be the batch's, method 0 and smoother 0; opts->nu_coarse
+ * applies to every member's depths below its finest.  stats (nullable)
  * has nsys entries: iterations and cycles are those member m took part in,
  * seconds the whole batch's.  Returns CAMFE_ENOCONV when any mesh stops above
  * rtol. */

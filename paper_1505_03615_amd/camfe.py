@@ -608,7 +608,7 @@ def camfe_batch_info(bt):
 
 
 def camfe_batch_solve(bt, bs, t, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, precision=0, x0s=None,
-                      coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, cycle=1):
+                      coarse_eps=DEFAULT_COARSE_EPS, raise_on_noconv=False, cycle=1, nu_coarse=0):
     """bs: list of n_m x k_m right-hand sides.  Returns (list of solutions, list of stats dicts).
     The batch takes V-cycles only (cycle 1); other values are passed on and rejected."""
     cols = [_colmajor(b) for b in bs]
@@ -623,7 +623,7 @@ def camfe_batch_solve(bt, bs, t, rtol=1e-8, max_iter=400, nu_pre=2, nu_post=2, p
     o = SolveOpts()
     o.t, o.rtol, o.max_iter, o.nu_pre, o.nu_post = t, rtol, max_iter, nu_pre, nu_post
     o.method, o.precision, o.x0_given, o.coarse_eps = 0, precision, 0 if x0s is None else 1, coarse_eps
-    o.cycle = cycle
+    o.cycle, o.nu_coarse = cycle, nu_coarse
     st = (SolveStats * m)()
     code = load().camfe_batch_solve(bt, C.byref(o), C.cast(bp, C.c_void_p), C.cast(kk, C.c_void_p),
                                     C.cast(xp, C.c_void_p), C.cast(st, C.c_void_p))

@@ -1951,7 +1951,7 @@ void batch_solve_block(camfe_batch_s* Bt, const camfe_solve_opts& o, const std::
   const int nu1 = o.nu_pre, nu2 = o.nu_post;
   const bool use_graph = !ctx->timer.on;
   const int check_every = 4;
-  const long long gkey = ((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 8 + 5;
+  const long long gkey = (((((long long)K * 2 + S->precision) * 64 + nu1) * 64 + nu2) * 8 + 5) * 64 + S->nu_coarse;
   if (any && o.max_iter > 0) {
     precondition<K>(S, S->R.p, S->Z.p, nu1, nu2);
     ++cycles;
@@ -2579,10 +2579,16 @@ camfe_status camfe_batch_solve(camfe_batch bt, const camfe_solve_opts* o, const 
     CAMFE_REQUIRE(o->cycle == 0 || o->cycle == 1, CAMFE_EINVAL, "the batched solve takes V-cycles (cycle 0 or 1)");
     CAMFE_REQUIRE(o->nu_pre >= 0 && o->nu_post >= 0 && o->max_iter >= 0 && o->nu_pre == o->nu_post, CAMFE_EINVAL,
                   "bad sweep counts (CG needs nu_pre == nu_post)");
+    CAMFE_REQUIRE(o->nu_coarse >= 0 && o->nu_coarse < 64, CAMFE_EINVAL, "nu_coarse must lie in [0, 64)");
     SolverState* S = bt->S.get();
     camfe_ctx ctx = bt->ctx;
     ctx->use_device();
     S->precision = o->precision;
+    struct CoarseScope {   // the batch's later calls start from the default again
+      SolverState* S;
+      ~CoarseScope() { S->nu_coarse = 0; }
+    } coarse_scope{S};
+    S->nu_coarse = o->nu_coarse;
     const int nm = S->nmesh;
     std::vector<int> kk(k, k + nm);
     int kmax = 0;

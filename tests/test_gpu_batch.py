@@ -95,6 +95,31 @@ def test_batch_solves_every_mesh(cf, setup, precision):
     _check(items, xs, stats)
 
 
+def test_batch_sweeps_below_the_finest_depth(cf, setup):
+    """nu_coarse reaches every member's coarse depths: V(3,3) at the finest
+    depth with V(1,1) below meets the oracle's residual bar in both
+    precisions, its iterates differ from V(3,3) everywhere, and the default
+    solve afterwards gives the same bits as before (the captured cycles are
+    kept apart per sweep schedule)."""
+    ctx, items, bt = setup
+    bs = [it[3] for it in items]
+    x0, s0 = cf.camfe_batch_solve(bt, bs, T, rtol=1e-8, max_iter=800)
+    for precision in (0, 1):
+        say(f"[gpu] batch: nu 3 below 1, precision={precision}")
+        xs, stats = cf.camfe_batch_solve(bt, bs, T, rtol=1e-8, max_iter=800, nu_pre=3, nu_post=3, nu_coarse=1,
+                                         precision=precision)
+        assert all(st["converged"] for st in stats), stats
+        _check(items, xs, stats)
+    x33, _ = cf.camfe_batch_solve(bt, bs, T, rtol=1e-30, max_iter=2, nu_pre=3, nu_post=3)
+    x31, _ = cf.camfe_batch_solve(bt, bs, T, rtol=1e-30, max_iter=2, nu_pre=3, nu_post=3, nu_coarse=1)
+    assert all(not np.array_equal(a, b) for a, b in zip(x33, x31))
+    x1, s1 = cf.camfe_batch_solve(bt, bs, T, rtol=1e-8, max_iter=800)
+    assert all(np.array_equal(a, b) for a, b in zip(x0, x1))
+    assert [st["cycles"] for st in s0] == [st["cycles"] for st in s1]
+    with pytest.raises(cf.CamfeError, match="EINVAL"):
+        cf.camfe_batch_solve(bt, bs, T, nu_coarse=64)
+
+
 def test_batch_matches_single_solves(cf, setup):
     ctx, items, bt = setup
     xs, stats = cf.camfe_batch_solve(bt, [it[3] for it in items], T, rtol=1e-10, max_iter=800)
